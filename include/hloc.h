@@ -1,0 +1,205 @@
+/*
+ * hloc — hierarchical L2 retrieval and 2-D candidate aggregation for indoor
+ * localization, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Hu, Zhu, Zhang, "GPU-accelerated Hierarchical Panoramic Image Feature
+ * Retrieval for Indoor Localization", ICMR 2016.
+ *   - Database of feature vectors with a geo-referenced (x, y) per entry:
+ *     Section 3 (environment modeling) and Section 3.2 (mapping table).
+ *   - Subspaces searched in parallel, each frame compared with every database
+ *     frame by Euclidean distance, top-N candidates per frame: Section 3.1,
+ *     Algorithm 1, Section 4. Here the database is split into regions with a
+ *     coarse representative each; a frame searches every row of its best
+ *     `n_regions` regions (all regions = the paper's exhaustive search).
+ *   - Multi-frame requests and 2-D density aggregation: Section 3.1 and
+ *     Section 3.2, Algorithm 2.
+ *
+ * Conventions for every call:
+ *   - Return value: HLOC_OK (0) or a negative hloc_status. On error the
+ *     outputs are unspecified and hloc_last_error() describes the failure.
+ *   - Ownership: the caller owns every buffer it passes. The library copies
+ *     database inputs during the call and keeps no caller pointer afterwards.
+ *   - Threads: calls on one hloc_db must not overlap (the database owns one
+ *     workspace). Distinct databases are independent.
+ *   - Devices: a database lives on the HIP device that was current when it
+ *     was built; later calls make that device current.
+ */
+#ifndef HLOC_H
+#define HLOC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hloc_db hloc_db; /* opaque; owns all of its device memory */
+
+typedef enum {
+  HLOC_OK = 0,
+  HLOC_EINVAL = -1,      /* an argument is out of range or malformed */
+  HLOC_ENOMEM = -2,      /* device or host allocation failed */
+  HLOC_ESTATE = -3,      /* call order violated (e.g. query before set_regions) */
+  HLOC_EDEVICE = -4,     /* a HIP call failed; the message names it */
+  HLOC_EUNSUPPORTED = -5 /* the requested screen precision is not available */
+} hloc_status;
+
+/* Screen precision of the fine (and coarse) screen. Whatever the screen, the
+ * returned top-k is decided by an FP64 rerank of the survivors. */
+typedef enum { HLOC_FP32 = 0, HLOC_BF16 = 1, HLOC_FP8 = 2 } hloc_precision;
+
+/* Per-request flags written by the aggregation (bit set). */
+enum {
+  HLOC_FLAG_LOW_CONFIDENCE = 1, /* no TopC tile passed the threshold; rank-1 tile returned */
+  HLOC_FLAG_EMPTY = 2,          /* request had no candidate; position is NaN */
+  HLOC_FLAG_BAD_REQUEST = 4     /* offsets not monotone / out of range, or too many candidates */
+};
+
+/* Limits. */
+#define HLOC_MAX_DIM 1024            /* d */
+#define HLOC_MAX_K 256               /* k */
+#define HLOC_MAX_REQUEST_CANDIDATES 4096 /* frames of one request x k */
+#define HLOC_MAX_TOP_C 64
+
+/*
+ * Build a database from n feature vectors (Section 3: one omnidirectional
+ * feature per modeled frame) and their floor-plan positions (Section 3.2: the
+ * geo-referenced mapping table).
+ *   feats : host, n x d float32, row-major, every value finite.
+ *   xy    : host, n x 2 float64 metres (x west->east, y south->north), finite.
+ *   n     : 1 .. 2^31-1 rows;  d : 1 .. HLOC_MAX_DIM.
+ *   mirrors: reserved for low-precision copies; pass 0.
+ *   out   : receives the new handle (set to NULL on error).
+ * Errors: EINVAL (sizes, NULL pointers, non-finite values), ENOMEM, EDEVICE.
+ * The database is not queryable until hloc_set_regions() succeeds.
+ */
+int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, uint32_t mirrors,
+                  hloc_db **out);
+
+/*
+ * Partition the rows into regions (the subspaces of Section 3.1) and compute
+ * each region's representative.
+ *   region_of : host, n int32 in [0, n_regions_total).
+ *   reps      : host, n_regions_total x d float32 representatives, or NULL to
+ *               use each region's mean row (computed in FP64 on the device).
+ * Regions with no row are never selected. Rows are re-laid out
+ * region-contiguously on the device. Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_total,
+                     const float *reps);
+
+/*
+ * Aggregation constants of Algorithm 2 (Section 3.2): tile edge cell_m > 0,
+ * top_c in 1 .. HLOC_MAX_TOP_C, tolerance-circle radius radius_m >= 0 (in
+ * whole tiles: rho = round(radius_m / cell_m)), threshold toler_pct in
+ * 0 .. 100. The paper uses 0.30 m, 10, 3 m, 20 %. Default until called:
+ * argmax of a 0.5 m grid (0.5, 1, 0, 0). Errors: EINVAL (also when a
+ * position is beyond 2^30 tiles from the origin), EDEVICE.
+ */
+int hloc_set_aggregation(hloc_db *db, double cell_m, int32_t top_c, double radius_m,
+                         int32_t toler_pct);
+
+/*
+ * Localize a batch (host pointers; blocks until done).
+ *   q           : nq x d float32 query frames, row-major (nq >= 0).
+ *   k           : 1 .. HLOC_MAX_K candidates per frame.
+ *   n_regions   : >= 1 regions searched per frame; clamped to the number of
+ *                 non-empty regions.
+ *   req_offsets : nreq + 1 int32, non-decreasing, from 0 to nq: request i owns
+ *                 frames [req_offsets[i], req_offsets[i+1]). NULL means one
+ *                 frame per request (nreq must equal nq).
+ *   precision   : hloc_precision of the screen.
+ * Outputs (row-major):
+ *   idx   : nq x k int64 original row indices by (squared distance, index)
+ *           ascending; -1 where fewer than k candidates exist.
+ *   dist  : nq x k float32 squared L2 distances (FP64 rounded), +inf padding.
+ *   xy    : nreq x 2 float64 estimate (tile centre), or NULL.
+ *   tile  : nreq x 2 int32 (ix, iy) of the estimate, or NULL.
+ *   flags : nreq int32 HLOC_FLAG_* bits, or NULL.
+ * If xy, tile and flags are all NULL the aggregation is skipped.
+ * Errors: EINVAL, ESTATE (no regions yet), EUNSUPPORTED, ENOMEM, EDEVICE.
+ */
+int hloc_query_batch(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t n_regions,
+                     const int32_t *req_offsets, int32_t nreq, int32_t precision, int64_t *idx,
+                     float *dist, double *xy, int32_t *tile, int32_t *flags);
+
+/*
+ * Same as hloc_query_batch, but every pointer is device memory on the
+ * database's device and the work is enqueued on `stream` (a hipStream_t; NULL
+ * is the null stream); the call returns without waiting. Pointers must stay
+ * valid until the stream passes the call. Malformed req_offsets are not
+ * detected on the host: the affected requests get HLOC_FLAG_BAD_REQUEST.
+ * The call may allocate (grow the workspace) unless hloc_reserve() sized it
+ * beforehand.
+ */
+int hloc_query_batch_async(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t n_regions,
+                           const int32_t *req_offsets, int32_t nreq, int32_t precision,
+                           int64_t *idx, float *dist, double *xy, int32_t *tile, int32_t *flags,
+                           void *stream);
+
+/*
+ * Pre-size the workspace for batches up to nq_max frames, nreq_max requests,
+ * k_max and n_regions_max, so that later query calls within these limits
+ * allocate nothing. Errors: EINVAL, ESTATE, ENOMEM, EDEVICE.
+ */
+int hloc_reserve(hloc_db *db, int32_t nq_max, int32_t nreq_max, int32_t k_max,
+                 int32_t n_regions_max);
+
+/*
+ * Per-database counters of the last query call (waits for it): out[0] work
+ * items of the fine screen, out[1] frames whose coarse selection needed the
+ * exact FP64 fallback, out[2] frames whose top-k needed it, out[3] largest
+ * candidate count of a frame, out[4] survivors per frame (k'), out[5] total
+ * candidates screened. Writes min(n, 6) values. Errors: EINVAL, EDEVICE.
+ */
+int hloc_query_info(hloc_db *db, int64_t *out, int32_t n);
+
+/*
+ * Region ids chosen for each frame by the last query call (waits for it):
+ * nq x n_regions_eff int32, sorted by (distance to representative, id); in
+ * id order when every non-empty region was searched. *nq and *n_regions_eff
+ * receive the sizes; `out` may be NULL to get only the sizes.
+ * Errors: EINVAL, ESTATE, EDEVICE.
+ */
+int hloc_last_regions(hloc_db *db, int32_t *out, int32_t *nq, int32_t *n_regions_eff);
+
+/*
+ * Device-time profile of the query path, measured with HIP events recorded on
+ * the query's stream around each phase:
+ *   HLOC_PHASE_PREP      query norms and padded copy
+ *   HLOC_PHASE_COARSE    coarse screen, select, FP64 rerank, exact fallback
+ *   HLOC_PHASE_SCHED     region -> frames lists and work items
+ *   HLOC_PHASE_SCREEN    fine screen (one kernel launch)
+ *   HLOC_PHASE_SELECT    per-frame selection of the survivors
+ *   HLOC_PHASE_RERANK    FP64 rerank, certificate, exact fallback
+ *   HLOC_PHASE_AGGREGATE aggregation of each request
+ * hloc_profile(db, 1) clears the record and starts recording for later query
+ * calls; hloc_profile(db, 0) stops. hloc_profile_read() waits for the device,
+ * writes for each of min(n, HLOC_NUM_PHASES) phases the summed milliseconds
+ * and the number of calls recorded, and clears the record.
+ * Errors: EINVAL, EDEVICE.
+ */
+enum {
+  HLOC_PHASE_PREP = 0,
+  HLOC_PHASE_COARSE = 1,
+  HLOC_PHASE_SCHED = 2,
+  HLOC_PHASE_SCREEN = 3,
+  HLOC_PHASE_SELECT = 4,
+  HLOC_PHASE_RERANK = 5,
+  HLOC_PHASE_AGGREGATE = 6,
+  HLOC_NUM_PHASES = 7
+};
+int hloc_profile(hloc_db *db, int32_t enable);
+int hloc_profile_read(hloc_db *db, double *ms, int64_t *calls, int32_t n);
+
+/* Release every resource of the database (NULL is ignored). */
+void hloc_free_db(hloc_db *db);
+
+/* Message of the last non-OK return on this thread ("" if none). */
+const char *hloc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HLOC_H */

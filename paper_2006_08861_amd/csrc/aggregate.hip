@@ -1,0 +1,164 @@
+// Multi-frame candidate aggregation (Section 3.2, Algorithm 2), one block per
+// request, integer arithmetic throughout:
+//   1. the request's frames pool their k candidates each (duplicates count,
+//      padding -1 is dropped) and every candidate becomes its tile key
+//      (iy, ix) from the precomputed floor(coord / cell) table;
+//   2. the keys are sorted; runs give each distinct tile and its count
+//      (the 2-D binning of the location distribution array);
+//   3. tiles are ranked by (count desc, iy asc, ix asc): a tile's position in
+//      the (iy, ix)-sorted run list carries the (iy, ix) order, so a single
+//      64-bit key ((2^32-1-count) << 32 | position) ranks them;
+//   4. for the first TopC ranked tiles, the tolerance circle sums the counts
+//      of the tiles within rho tiles (dx^2 + dy^2 <= rho^2);
+//   5. the first tile with 100 * circle > pct * total wins; if none does, the
+//      rank-1 tile is returned with HLOC_FLAG_LOW_CONFIDENCE.
+// The estimate is the tile centre ((ix + 0.5) * cell, (iy + 0.5) * cell) with
+// one rounded FP64 add and one rounded multiply, so it is reproducible bit
+// for bit from the tile.
+#include "hloc_device.h"
+#include "hloc_internal.h"
+
+namespace hloc {
+
+constexpr int kAggMax = 4096;  // pooled candidates of one request
+constexpr int kFlagLow = 1, kFlagEmpty = 2, kFlagBad = 4;
+
+__device__ __forceinline__ uint32_t flip(int32_t v) { return (uint32_t)v ^ 0x80000000u; }
+__device__ __forceinline__ int32_t unflip(uint32_t v) { return (int32_t)(v ^ 0x80000000u); }
+
+__global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
+  extern __shared__ uint64_t lds[];
+  uint64_t *s_key = lds;               // kAggMax sorted tile keys
+  uint64_t *s_rank = lds + kAggMax;    // kAggMax rank keys
+  int *s_pos = reinterpret_cast<int *>(lds + 2 * kAggMax);  // kAggMax + 1 run starts
+  __shared__ int scratch[16];
+  __shared__ int s_circle[64];
+  const int req = blockIdx.x;
+  if (req >= a.nreq) return;
+  const int tid = threadIdx.x;
+  int f0, f1;
+  if (a.req_offsets) {
+    f0 = a.req_offsets[req];
+    f1 = a.req_offsets[req + 1];
+  } else {
+    f0 = req;
+    f1 = req + 1;
+  }
+  const bool bad = f0 < 0 || f1 < f0 || f1 > a.nq ||
+                   (int64_t)(f1 - f0) * a.k > (int64_t)kAggMax;
+  if (bad) {
+    if (tid == 0) {
+      a.tile[2 * req] = 0;
+      a.tile[2 * req + 1] = 0;
+      a.xy[2 * req] = __builtin_nan("");
+      a.xy[2 * req + 1] = __builtin_nan("");
+      a.flags[req] = kFlagBad;
+    }
+    return;
+  }
+  const int P = (f1 - f0) * a.k;
+  const int Pp = next_pow2(P > 0 ? P : 1);
+  const int64_t *idx = a.idx + (int64_t)f0 * a.k;
+  int valid_local = 0;
+  for (int p = tid; p < Pp; p += blockDim.x) {
+    uint64_t key = kKeyNone;
+    if (p < P) {
+      const int64_t j = idx[p];
+      if (j >= 0) {
+        const int2 t = a.tile_of[j];
+        key = ((uint64_t)flip(t.y) << 32) | flip(t.x);
+        ++valid_local;
+      }
+    }
+    s_key[p] = key;
+  }
+  if (tid == 0) s_circle[0] = 0;
+  __syncthreads();
+  if (valid_local) atomicAdd(&s_circle[0], valid_local);
+  __syncthreads();
+  const int total = s_circle[0];
+  if (total == 0) {
+    if (tid == 0) {
+      a.tile[2 * req] = 0;
+      a.tile[2 * req + 1] = 0;
+      a.xy[2 * req] = __builtin_nan("");
+      a.xy[2 * req + 1] = __builtin_nan("");
+      a.flags[req] = kFlagEmpty;
+    }
+    return;
+  }
+  block_sort_u64(s_key, Pp);  // valid keys form the prefix [0, total)
+  // run starts -> tile list in (iy, ix) order
+  int ntiles = 0;
+  for (int base = 0; base < total; base += blockDim.x) {
+    const int p = base + tid;
+    const bool start = p < total && (p == 0 || s_key[p] != s_key[p - 1]);
+    int tot;
+    const int pos = block_excl_count(start, scratch, &tot);
+    if (start) s_pos[ntiles + pos] = p;
+    ntiles += tot;
+  }
+  if (tid == 0) s_pos[ntiles] = total;
+  __syncthreads();
+  const int Tp = next_pow2(ntiles);
+  for (int t = tid; t < Tp; t += blockDim.x) {
+    uint64_t rk = kKeyNone;
+    if (t < ntiles) {
+      const uint32_t cnt = (uint32_t)(s_pos[t + 1] - s_pos[t]);
+      rk = ((uint64_t)(0xFFFFFFFFu - cnt) << 32) | (uint32_t)t;
+    }
+    s_rank[t] = rk;
+  }
+  block_sort_u64(s_rank, Tp);
+  const int C = min(a.top_c, ntiles);
+  for (int c = tid; c < C; c += blockDim.x) s_circle[c] = 0;
+  __syncthreads();
+  const int64_t rho2 = (int64_t)a.rho * a.rho;
+  for (int e = tid; e < C * ntiles; e += blockDim.x) {
+    const int c = e / ntiles, u = e - c * ntiles;
+    const int tc = (int)(uint32_t)s_rank[c];
+    const uint64_t kc = s_key[s_pos[tc]], ku = s_key[s_pos[u]];
+    const int64_t dx = (int64_t)unflip((uint32_t)ku) - unflip((uint32_t)kc);
+    const int64_t dy = (int64_t)unflip((uint32_t)(ku >> 32)) - unflip((uint32_t)(kc >> 32));
+    if (dx <= a.rho && dx >= -a.rho && dy <= a.rho && dy >= -a.rho && dx * dx + dy * dy <= rho2)
+      atomicAdd(&s_circle[c], s_pos[u + 1] - s_pos[u]);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int chosen = 0, flag = kFlagLow;
+    for (int c = 0; c < C; ++c) {
+      if ((int64_t)100 * s_circle[c] > (int64_t)a.toler_pct * total) {
+        chosen = c;
+        flag = 0;
+        break;
+      }
+    }
+    const uint64_t kt = s_key[s_pos[(int)(uint32_t)s_rank[chosen]]];
+    const int32_t ix = unflip((uint32_t)kt), iy = unflip((uint32_t)(kt >> 32));
+    a.tile[2 * req] = ix;
+    a.tile[2 * req + 1] = iy;
+    a.xy[2 * req] = __dmul_rn(__dadd_rn((double)ix, 0.5), a.cell);
+    a.xy[2 * req + 1] = __dmul_rn(__dadd_rn((double)iy, 0.5), a.cell);
+    a.flags[req] = flag;
+  }
+}
+
+hipError_t launch_aggregate(const AggArgs &a, hipStream_t s) {
+  if (a.nreq <= 0) return hipSuccess;
+  if (a.top_c < 1 || a.top_c > 64) return hipErrorInvalidValue;
+  const size_t lds = 2 * kAggMax * sizeof(uint64_t) + (kAggMax + 1) * sizeof(int);
+  static int attr_dev = -1;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (attr_dev != dev) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_aggregate),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_dev = dev;
+  }
+  hipLaunchKernelGGL(k_aggregate, dim3(a.nreq), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace hloc

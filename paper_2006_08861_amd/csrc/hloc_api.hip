@@ -1,0 +1,800 @@
+// Host side of the hloc C ABI (include/hloc.h): argument checks, device
+// layout of the database, the per-database workspace and the sequence of
+// kernels that localizes a batch.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hloc.h"
+#include "hloc_internal.h"
+
+using namespace hloc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(HLOC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHK(expr)            \
+  do {                       \
+    int rc_ = (expr);        \
+    if (rc_ != HLOC_OK) return rc_; \
+  } while (0)
+
+struct DeviceGuard {
+  int old = -1;
+  hipError_t err;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old) != hipSuccess) old = -1;
+    err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (old >= 0) (void)hipSetDevice(old);
+  }
+};
+
+struct WsBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+};
+
+constexpr int kRegionMargin = 8;    // extra regions re-scored in FP64 by the coarse stage
+constexpr int kOversample = 16;     // extra rows re-scored in FP64 by the fine stage
+constexpr int kRowsCoarse = 64;     // rows (representatives) per coarse work item
+constexpr int kRowsFine = 128;      // rows per fine work item
+constexpr double kUnit32 = 5.9604644775390625e-08;  // 2^-24
+
+template <class T>
+T *as(WsBuf &b) {
+  return reinterpret_cast<T *>(b.p);
+}
+
+}  // namespace
+
+struct hloc_db {
+  int device = 0;
+  int num_cu = 256;
+  hipStream_t stream = nullptr;
+  hipStream_t last_stream = nullptr;
+  int64_t n = 0;
+  int32_t d = 0, dp = 0;
+  float *rows = nullptr;      // n x dp fp32, region-contiguous once regions are set
+  float *row_n2 = nullptr;    // n squared norms
+  int32_t *perm = nullptr;    // device row -> original index
+  double *xy = nullptr;       // n x 2 by original index
+  int2 *tiles = nullptr;      // n by original index
+  float *norm_max = nullptr;  // [0] rows, [1] representatives
+  float h_row_max = 0.f, h_rep_max = 0.f;
+  std::vector<int32_t> h_perm;
+  double max_abs_coord = 0.0;
+  bool has_regions = false;
+  int32_t R = 0, R_nonempty = 0;
+  int64_t max_region = 0;
+  int64_t *reg_start = nullptr;
+  std::vector<int64_t> h_reg_start;
+  std::vector<int64_t> h_desc_prefix;  // sum of the j largest region sizes, j = 0..R
+  int64_t chunks_fine = 0;             // sum over regions of ceil(size / kRowsFine)
+  int32_t *nonempty_ids = nullptr;
+  double *rep64 = nullptr;
+  float *rep32 = nullptr;
+  float *rep_n2 = nullptr;
+  double cell = 0.5, radius = 0.0;
+  int32_t top_c = 1, rho = 0, pct = 0;
+  // workspace
+  WsBuf qp, qn2, cand1, sel1, regions, flag1, flag2, rcount, rfill, rq_off, item_off, cand_off,
+      n_cand, misc, rq, items, cand2, sel2, agg_xy, agg_tile, agg_flags;
+  WsBuf s_q, s_off, s_idx, s_dist, s_xy, s_tile, s_flags;
+  // last query
+  int32_t last_nq = 0, last_nr = 0, last_kp = 0;
+  // profiling: phase boundaries recorded as HIP events on the query stream
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct ProfRec {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfRec> prof;
+};
+
+namespace {
+
+void free_buf(WsBuf &b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+int ensure(WsBuf &b, size_t bytes) {
+  if (bytes <= b.cap && b.p) return HLOC_OK;
+  HIPCHK(hipDeviceSynchronize());  // the old buffer may still be in use
+  free_buf(b);
+  size_t want = std::max<size_t>(bytes + bytes / 4, 256);
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(HLOC_ENOMEM, "device allocation of %zu bytes failed", want);
+  }
+  b.cap = want;
+  return HLOC_OK;
+}
+
+template <class T>
+int dev_alloc(T **p, size_t count) {
+  if (hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(count, 1) * sizeof(T)) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(HLOC_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
+  }
+  return HLOC_OK;
+}
+
+template <class T>
+void dev_free(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+struct Plan {
+  int32_t nq, k, nr, L1, want1, kp, want2, nreq;
+  bool exhaustive;
+  int64_t cap2, items_bound;
+  int32_t grid1, grid2;
+};
+
+int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32_t nreq,
+              Plan *pl) {
+  if (!db->has_regions) return fail(HLOC_ESTATE, "hloc_set_regions has not been called");
+  if (nq < 0) return fail(HLOC_EINVAL, "nq must be >= 0 (got %d)", nq);
+  if (k < 1 || k > HLOC_MAX_K) return fail(HLOC_EINVAL, "k must be in 1..%d (got %d)", HLOC_MAX_K, k);
+  if (n_regions < 1) return fail(HLOC_EINVAL, "n_regions must be >= 1 (got %d)", n_regions);
+  Plan p{};
+  p.nq = nq;
+  p.k = k;
+  p.nreq = nreq;
+  p.nr = std::min(n_regions, db->R_nonempty);
+  p.exhaustive = p.nr == db->R_nonempty;
+  if (!p.exhaustive) {
+    p.L1 = std::min(p.nr + kRegionMargin, db->R_nonempty);
+    if (p.L1 > kMaxSurvivors)
+      return fail(HLOC_EINVAL,
+                  "n_regions %d is above %d and below the %d non-empty regions; pass "
+                  "n_regions >= %d to search every region",
+                  n_regions, kMaxSurvivors - kRegionMargin, db->R_nonempty, db->R_nonempty);
+    p.want1 = p.L1 + 1;
+  }
+  p.kp = std::min(k + kOversample, kMaxSurvivors);
+  p.want2 = p.kp + 1;
+  p.cap2 = db->h_desc_prefix[p.nr];
+  const int64_t maxch = (db->max_region + kRowsFine - 1) / kRowsFine;
+  const int64_t b1 = (int64_t)nq * p.nr * maxch;
+  const int64_t b2 = db->chunks_fine * (((int64_t)nq + kGroup - 1) / kGroup);
+  p.items_bound = std::min(b1, b2);
+  if (p.items_bound > INT32_MAX || (int64_t)nq * p.cap2 > ((int64_t)1 << 40))
+    return fail(HLOC_EINVAL, "batch too large for one call (nq %d)", nq);
+  const int64_t blocks = (int64_t)db->num_cu * 4;
+  p.grid2 = (int32_t)std::max<int64_t>(1, std::min(p.items_bound, blocks));
+  const int64_t dense_items =
+      (((int64_t)db->R + kRowsCoarse - 1) / kRowsCoarse) * (((int64_t)nq + kGroup - 1) / kGroup);
+  p.grid1 = (int32_t)std::max<int64_t>(1, std::min(dense_items, blocks));
+  *pl = p;
+  return HLOC_OK;
+}
+
+int ensure_workspace(hloc_db *db, const Plan &p, bool agg_internal) {
+  const int64_t nq = std::max(p.nq, 1), nr = std::max(p.nr, 1);
+  CHK(ensure(db->qp, (size_t)nq * db->dp * sizeof(float)));
+  CHK(ensure(db->qn2, (size_t)nq * sizeof(float)));
+  if (!p.exhaustive) {
+    CHK(ensure(db->cand1, (size_t)nq * db->R * sizeof(uint64_t)));
+    CHK(ensure(db->sel1, (size_t)nq * p.want1 * sizeof(uint64_t)));
+  }
+  CHK(ensure(db->regions, (size_t)nq * nr * sizeof(int32_t)));
+  CHK(ensure(db->flag1, (size_t)nq * sizeof(int32_t)));
+  CHK(ensure(db->flag2, (size_t)nq * sizeof(int32_t)));
+  CHK(ensure(db->rcount, (size_t)db->R * sizeof(int32_t)));
+  CHK(ensure(db->rfill, (size_t)db->R * sizeof(int32_t)));
+  CHK(ensure(db->rq_off, (size_t)db->R * sizeof(int32_t)));
+  CHK(ensure(db->item_off, (size_t)db->R * sizeof(int32_t)));
+  CHK(ensure(db->cand_off, (size_t)nq * nr * sizeof(int32_t)));
+  CHK(ensure(db->n_cand, (size_t)nq * sizeof(int32_t)));
+  CHK(ensure(db->misc, 16 * sizeof(int32_t)));
+  CHK(ensure(db->rq, (size_t)nq * nr * sizeof(int2)));
+  CHK(ensure(db->items, (size_t)std::max<int64_t>(p.items_bound, 1) * sizeof(Item)));
+  CHK(ensure(db->cand2, (size_t)nq * std::max<int64_t>(p.cap2, 1) * sizeof(uint64_t)));
+  CHK(ensure(db->sel2, (size_t)nq * p.want2 * sizeof(uint64_t)));
+  if (agg_internal) {
+    const int64_t nreq = std::max(p.nreq, 1);
+    CHK(ensure(db->agg_xy, (size_t)nreq * 2 * sizeof(double)));
+    CHK(ensure(db->agg_tile, (size_t)nreq * 2 * sizeof(int32_t)));
+    CHK(ensure(db->agg_flags, (size_t)nreq * sizeof(int32_t)));
+  }
+  return HLOC_OK;
+}
+
+// Records an event on s when profiling; returns it (or nullptr).
+int prof_mark(hloc_db *db, hipStream_t s, hipEvent_t *ev) {
+  *ev = nullptr;
+  if (!db->prof_on) return HLOC_OK;
+  if (db->ev_used == db->ev_pool.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    db->ev_pool.push_back(e);
+  }
+  *ev = db->ev_pool[db->ev_used++];
+  HIPCHK(hipEventRecord(*ev, s));
+  return HLOC_OK;
+}
+
+// Closes the phase opened by *t (a mark) and opens the next one.
+int prof_phase(hloc_db *db, int phase, hipStream_t s, hipEvent_t *t) {
+  if (!db->prof_on) return HLOC_OK;
+  hipEvent_t e;
+  CHK(prof_mark(db, s, &e));
+  db->prof.push_back({phase, *t, e});
+  *t = e;
+  return HLOC_OK;
+}
+
+int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req_offsets,
+                  int64_t *idx, float *dist, double *xy, int32_t *tile, int32_t *flags,
+                  hipStream_t s) {
+  const bool want_agg = xy || tile || flags;
+  CHK(ensure_workspace(db, p, want_agg && !(xy && tile && flags)));
+  db->last_stream = s;
+  db->last_nq = p.nq;
+  db->last_nr = p.nr;
+  db->last_kp = p.kp;
+  int32_t *misc = as<int32_t>(db->misc);
+  HIPCHK(launch_fill_i32(misc, 16, 0, s));
+  if (p.nq == 0) return HLOC_OK;
+  float *qp = as<float>(db->qp), *qn2 = as<float>(db->qn2);
+  int32_t *regions = as<int32_t>(db->regions);
+  hipEvent_t t;
+  CHK(prof_mark(db, s, &t));
+  HIPCHK(launch_prep_queries(q, p.nq, db->d, db->dp, qp, qn2, s));
+  CHK(prof_phase(db, HLOC_PHASE_PREP, s, &t));
+  const double coef = (db->dp + 16) * kUnit32 * 1.001;
+  if (!p.exhaustive) {
+    ScreenF32Args sa{};
+    sa.rows = db->rep32;
+    sa.row_n2 = db->rep_n2;
+    sa.dp = db->dp;
+    sa.qp = qp;
+    sa.qn2 = qn2;
+    sa.cand = as<uint64_t>(db->cand1);
+    sa.cap = db->R;
+    sa.rows_per_item = kRowsCoarse;
+    sa.dense = 1;
+    sa.nrows = db->R;
+    sa.nq = p.nq;
+    HIPCHK(launch_screen_f32(sa, p.grid1, s));
+    HIPCHK(launch_select(as<uint64_t>(db->cand1), db->R, nullptr, db->R, p.nq, p.want1,
+                         as<uint64_t>(db->sel1), nullptr, s));
+    RerankArgs ra{};
+    ra.sel = as<uint64_t>(db->sel1);
+    ra.want = p.want1;
+    ra.m = p.nr;
+    ra.n_fixed = db->R_nonempty;
+    ra.src64 = db->rep64;
+    ra.dp = db->dp;
+    ra.qp = qp;
+    ra.qn2 = qn2;
+    ra.err_coef = coef;
+    ra.max_norm = (double)db->h_rep_max * (1.0 + 1e-6);
+    ra.nq = p.nq;
+    ra.reg_out = regions;
+    ra.flag = as<int32_t>(db->flag1);
+    ra.stat_fallback = misc + 1;
+    HIPCHK(launch_rerank(ra, s));
+    ExactArgs ea{};
+    ea.flag = as<int32_t>(db->flag1);
+    ea.nq = p.nq;
+    ea.m = p.nr;
+    ea.dp = db->dp;
+    ea.qp = qp;
+    ea.src64 = db->rep64;
+    ea.R = db->R;
+    ea.reg_start = db->reg_start;
+    ea.reg_out = regions;
+    HIPCHK(launch_exact(ea, s));
+  } else {
+    HIPCHK(launch_broadcast_ids(db->nonempty_ids, p.nr, p.nq, regions, s));
+  }
+  CHK(prof_phase(db, HLOC_PHASE_COARSE, s, &t));
+  int32_t *cand_off = as<int32_t>(db->cand_off), *n_cand = as<int32_t>(db->n_cand);
+  HIPCHK(launch_sched(regions, p.nq, p.nr, db->R, db->reg_start, kRowsFine,
+                      as<int32_t>(db->rcount), as<int32_t>(db->rfill), as<int32_t>(db->rq_off),
+                      as<int32_t>(db->item_off), cand_off, n_cand, misc + 0, as<int2>(db->rq),
+                      as<Item>(db->items), s));
+  CHK(prof_phase(db, HLOC_PHASE_SCHED, s, &t));
+  ScreenF32Args sb{};
+  sb.rows = db->rows;
+  sb.row_n2 = db->row_n2;
+  sb.dp = db->dp;
+  sb.qp = qp;
+  sb.qn2 = qn2;
+  sb.cand = as<uint64_t>(db->cand2);
+  sb.cap = p.cap2;
+  sb.rows_per_item = kRowsFine;
+  sb.dense = 0;
+  sb.items = as<Item>(db->items);
+  sb.n_items = misc + 0;
+  sb.rq = as<int2>(db->rq);
+  sb.reg_start = db->reg_start;
+  HIPCHK(launch_screen_f32(sb, p.grid2, s));
+  CHK(prof_phase(db, HLOC_PHASE_SCREEN, s, &t));
+  HIPCHK(launch_select(as<uint64_t>(db->cand2), p.cap2, n_cand, 0, p.nq, p.want2,
+                       as<uint64_t>(db->sel2), misc + 3, s));
+  CHK(prof_phase(db, HLOC_PHASE_SELECT, s, &t));
+  RerankArgs rb{};
+  rb.sel = as<uint64_t>(db->sel2);
+  rb.want = p.want2;
+  rb.m = p.k;
+  rb.n_cand = n_cand;
+  rb.src32 = db->rows;
+  rb.dp = db->dp;
+  rb.tie_of = db->perm;
+  rb.qp = qp;
+  rb.qn2 = qn2;
+  rb.err_coef = coef;
+  rb.max_norm = (double)db->h_row_max * (1.0 + 1e-6);
+  rb.nq = p.nq;
+  rb.idx_out = idx;
+  rb.dist_out = dist;
+  rb.flag = as<int32_t>(db->flag2);
+  rb.stat_fallback = misc + 2;
+  HIPCHK(launch_rerank(rb, s));
+  ExactArgs eb{};
+  eb.flag = as<int32_t>(db->flag2);
+  eb.nq = p.nq;
+  eb.m = p.k;
+  eb.dp = db->dp;
+  eb.qp = qp;
+  eb.src32 = db->rows;
+  eb.regions = regions;
+  eb.nr = p.nr;
+  eb.cand_off = cand_off;
+  eb.n_cand = n_cand;
+  eb.reg_start = db->reg_start;
+  eb.tie_of = db->perm;
+  eb.idx_out = idx;
+  eb.dist_out = dist;
+  HIPCHK(launch_exact(eb, s));
+  CHK(prof_phase(db, HLOC_PHASE_RERANK, s, &t));
+  if (want_agg && p.nreq > 0) {
+    AggArgs ag{};
+    ag.idx = idx;
+    ag.k = p.k;
+    ag.nq = p.nq;
+    ag.req_offsets = req_offsets;
+    ag.nreq = p.nreq;
+    ag.tile_of = db->tiles;
+    ag.cell = db->cell;
+    ag.top_c = db->top_c;
+    ag.rho = db->rho;
+    ag.toler_pct = db->pct;
+    ag.xy = xy ? xy : as<double>(db->agg_xy);
+    ag.tile = tile ? tile : as<int32_t>(db->agg_tile);
+    ag.flags = flags ? flags : as<int32_t>(db->agg_flags);
+    HIPCHK(launch_aggregate(ag, s));
+    CHK(prof_phase(db, HLOC_PHASE_AGGREGATE, s, &t));
+  }
+  return HLOC_OK;
+}
+
+int check_query_args(const hloc_db *db, const float *q, int32_t nq, const int32_t *req_offsets,
+                     int32_t nreq, int32_t precision, const int64_t *idx, const float *dist) {
+  if (!db) return fail(HLOC_EINVAL, "db is NULL");
+  if (precision != HLOC_FP32) {
+    if (precision == HLOC_BF16 || precision == HLOC_FP8)
+      return fail(HLOC_EUNSUPPORTED, "screen precision %d is not available in this build",
+                  precision);
+    return fail(HLOC_EINVAL, "unknown precision %d", precision);
+  }
+  if (nq > 0 && (!q || !idx || !dist)) return fail(HLOC_EINVAL, "q, idx and dist must be non-NULL");
+  if (nreq < 0) return fail(HLOC_EINVAL, "nreq must be >= 0");
+  if (!req_offsets && nreq != nq)
+    return fail(HLOC_EINVAL, "without req_offsets nreq must equal nq (%d vs %d)", nreq, nq);
+  return HLOC_OK;
+}
+
+void free_all(hloc_db *db) {
+  WsBuf *bufs[] = {&db->qp,     &db->qn2,      &db->cand1,    &db->sel1,    &db->regions,
+                   &db->flag1,  &db->flag2,    &db->rcount,   &db->rfill,   &db->rq_off,
+                   &db->item_off, &db->cand_off, &db->n_cand, &db->misc,    &db->rq,
+                   &db->items,  &db->cand2,    &db->sel2,     &db->agg_xy,  &db->agg_tile,
+                   &db->agg_flags, &db->s_q,   &db->s_off,    &db->s_idx,   &db->s_dist,
+                   &db->s_xy,   &db->s_tile,   &db->s_flags};
+  for (WsBuf *b : bufs) free_buf(*b);
+  dev_free(db->rows);
+  dev_free(db->row_n2);
+  dev_free(db->perm);
+  dev_free(db->xy);
+  dev_free(db->tiles);
+  dev_free(db->norm_max);
+  dev_free(db->reg_start);
+  dev_free(db->nonempty_ids);
+  dev_free(db->rep64);
+  dev_free(db->rep32);
+  dev_free(db->rep_n2);
+  for (hipEvent_t e : db->ev_pool) (void)hipEventDestroy(e);
+  db->ev_pool.clear();
+  db->ev_used = 0;
+  db->prof.clear();
+  if (db->stream) (void)hipStreamDestroy(db->stream);
+  db->stream = nullptr;
+}
+
+int compute_tiles(hloc_db *db) {
+  HIPCHK(launch_tiles(db->xy, db->n, db->cell, db->tiles, db->stream));
+  HIPCHK(hipStreamSynchronize(db->stream));
+  return HLOC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hloc_last_error(void) { return g_err.c_str(); }
+
+int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, uint32_t mirrors,
+                  hloc_db **out) {
+  if (!out) return fail(HLOC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!feats || !xy) return fail(HLOC_EINVAL, "feats and xy must be non-NULL");
+  if (n < 1 || n > INT32_MAX) return fail(HLOC_EINVAL, "n must be in 1..2^31-1 (got %lld)", (long long)n);
+  if (d < 1 || d > HLOC_MAX_DIM) return fail(HLOC_EINVAL, "d must be in 1..%d (got %d)", HLOC_MAX_DIM, d);
+  if (mirrors != 0) return fail(HLOC_EUNSUPPORTED, "low-precision mirrors are not available in this build");
+  const int64_t nd = n * (int64_t)d;
+  for (int64_t i = 0; i < nd; ++i)
+    if (!std::isfinite(feats[i]))
+      return fail(HLOC_EINVAL, "feature value %lld (row %lld) is not finite", (long long)i,
+                  (long long)(i / d));
+  double max_abs = 0.0;
+  for (int64_t i = 0; i < 2 * n; ++i) {
+    if (!std::isfinite(xy[i]))
+      return fail(HLOC_EINVAL, "position value %lld is not finite", (long long)i);
+    max_abs = std::max(max_abs, std::fabs(xy[i]));
+  }
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hloc_db *db = new (std::nothrow) hloc_db();
+  if (!db) return fail(HLOC_ENOMEM, "host allocation failed");
+  db->device = dev;
+  db->n = n;
+  db->d = d;
+  db->dp = (d + 31) / 32 * 32;
+  db->max_abs_coord = max_abs;
+  auto bail = [&](int rc) {
+    free_all(db);
+    delete db;
+    return rc;
+  };
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return bail(fail(HLOC_EDEVICE, "hipGetDeviceProperties failed"));
+  db->num_cu = std::max(1, prop.multiProcessorCount);
+  if (hipStreamCreateWithFlags(&db->stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(HLOC_EDEVICE, "hipStreamCreateWithFlags failed"));
+  int rc;
+  if ((rc = dev_alloc(&db->rows, (size_t)n * db->dp)) || (rc = dev_alloc(&db->row_n2, (size_t)n)) ||
+      (rc = dev_alloc(&db->perm, (size_t)n)) || (rc = dev_alloc(&db->xy, (size_t)n * 2)) ||
+      (rc = dev_alloc(&db->tiles, (size_t)n)) || (rc = dev_alloc(&db->norm_max, 2)))
+    return bail(rc);
+  float *tmp = nullptr;
+  if ((rc = dev_alloc(&tmp, (size_t)nd))) return bail(rc);
+  db->h_perm.resize(n);
+  std::iota(db->h_perm.begin(), db->h_perm.end(), 0);
+  hipError_t e = hipMemcpy(tmp, feats, (size_t)nd * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(db->perm, db->h_perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(db->xy, xy, (size_t)n * 2 * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemsetAsync(db->norm_max, 0, 2 * sizeof(float), db->stream);
+  if (e == hipSuccess) e = launch_gather_rows(tmp, db->perm, n, d, d, db->rows, db->dp, db->stream);
+  if (e == hipSuccess) e = launch_row_norms(db->rows, n, db->dp, db->row_n2, db->norm_max, db->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(db->stream);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return bail(fail(HLOC_EDEVICE, "database upload failed: %s", hipGetErrorString(e)));
+  if ((rc = compute_tiles(db))) return bail(rc);
+  *out = db;
+  return HLOC_OK;
+}
+
+int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_total,
+                     const float *reps) {
+  if (!db || !region_of) return fail(HLOC_EINVAL, "db and region_of must be non-NULL");
+  if (n_regions_total < 1) return fail(HLOC_EINVAL, "n_regions_total must be >= 1");
+  const int64_t n = db->n;
+  const int32_t R = n_regions_total;
+  std::vector<int64_t> sizes(R, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t r = region_of[i];
+    if (r < 0 || r >= R)
+      return fail(HLOC_EINVAL, "region_of[%lld] = %d is outside [0, %d)", (long long)i, r, R);
+    ++sizes[r];
+  }
+  if (reps) {
+    for (int64_t i = 0; i < (int64_t)R * db->d; ++i)
+      if (!std::isfinite(reps[i])) return fail(HLOC_EINVAL, "representative value %lld is not finite", (long long)i);
+  }
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  HIPCHK(hipDeviceSynchronize());
+  // counting sort of the rows by region, stable in the original index
+  std::vector<int64_t> start(R + 1, 0);
+  for (int32_t r = 0; r < R; ++r) start[r + 1] = start[r] + sizes[r];
+  std::vector<int32_t> new_perm(n), src_row(n), inv_cur(n);
+  {
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    for (int64_t i = 0; i < n; ++i) new_perm[fill[region_of[i]]++] = (int32_t)i;
+  }
+  for (int64_t i = 0; i < n; ++i) inv_cur[db->h_perm[i]] = (int32_t)i;
+  for (int64_t i = 0; i < n; ++i) src_row[i] = inv_cur[new_perm[i]];
+  // release the old region data
+  dev_free(db->reg_start);
+  dev_free(db->nonempty_ids);
+  dev_free(db->rep64);
+  dev_free(db->rep32);
+  dev_free(db->rep_n2);
+  db->has_regions = false;
+  int rc;
+  float *new_rows = nullptr;
+  int32_t *d_src = nullptr;
+  if ((rc = dev_alloc(&new_rows, (size_t)n * db->dp))) return rc;
+  if ((rc = dev_alloc(&d_src, (size_t)n))) {
+    dev_free(new_rows);
+    return rc;
+  }
+  hipError_t e = hipMemcpy(d_src, src_row.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_gather_rows(db->rows, d_src, n, db->dp, db->dp, new_rows, db->dp, db->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(db->stream);
+  dev_free(d_src);
+  if (e != hipSuccess) {
+    dev_free(new_rows);
+    return fail(HLOC_EDEVICE, "row re-layout failed: %s", hipGetErrorString(e));
+  }
+  dev_free(db->rows);
+  db->rows = new_rows;
+  db->h_perm = new_perm;
+  std::vector<int32_t> ids;
+  for (int32_t r = 0; r < R; ++r)
+    if (sizes[r] > 0) ids.push_back(r);
+  if ((rc = dev_alloc(&db->reg_start, (size_t)R + 1)) || (rc = dev_alloc(&db->nonempty_ids, ids.size())) ||
+      (rc = dev_alloc(&db->rep64, (size_t)R * db->dp)) || (rc = dev_alloc(&db->rep32, (size_t)R * db->dp)) ||
+      (rc = dev_alloc(&db->rep_n2, (size_t)R)))
+    return rc;
+  HIPCHK(hipMemcpy(db->perm, new_perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(db->reg_start, start.data(), (size_t)(R + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(db->nonempty_ids, ids.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemsetAsync(db->norm_max, 0, 2 * sizeof(float), db->stream));
+  HIPCHK(launch_row_norms(db->rows, n, db->dp, db->row_n2, db->norm_max, db->stream));
+  if (reps) {
+    std::vector<double> r64((size_t)R * db->dp, 0.0);
+    for (int32_t r = 0; r < R; ++r)
+      for (int32_t c = 0; c < db->d; ++c) r64[(size_t)r * db->dp + c] = reps[(size_t)r * db->d + c];
+    HIPCHK(hipMemcpy(db->rep64, r64.data(), r64.size() * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    HIPCHK(launch_region_means(db->rows, db->reg_start, R, db->dp, db->rep64, db->stream));
+  }
+  HIPCHK(launch_rep_finish(db->rep64, db->reg_start, R, db->dp, db->rep32, db->rep_n2,
+                           db->norm_max + 1, db->stream));
+  float mx[2];
+  HIPCHK(hipMemcpyAsync(mx, db->norm_max, sizeof mx, hipMemcpyDeviceToHost, db->stream));
+  HIPCHK(hipStreamSynchronize(db->stream));
+  db->h_row_max = mx[0];
+  db->h_rep_max = mx[1];
+  db->R = R;
+  db->R_nonempty = (int32_t)ids.size();
+  db->h_reg_start = start;
+  std::vector<int64_t> desc(sizes);
+  std::sort(desc.begin(), desc.end(), std::greater<int64_t>());
+  db->h_desc_prefix.assign(R + 1, 0);
+  for (int32_t r = 0; r < R; ++r) db->h_desc_prefix[r + 1] = db->h_desc_prefix[r] + desc[r];
+  db->max_region = desc.empty() ? 0 : desc[0];
+  db->chunks_fine = 0;
+  for (int32_t r = 0; r < R; ++r) db->chunks_fine += (sizes[r] + kRowsFine - 1) / kRowsFine;
+  db->has_regions = true;
+  return HLOC_OK;
+}
+
+int hloc_set_aggregation(hloc_db *db, double cell_m, int32_t top_c, double radius_m,
+                         int32_t toler_pct) {
+  if (!db) return fail(HLOC_EINVAL, "db is NULL");
+  if (!(cell_m > 0.0) || !std::isfinite(cell_m)) return fail(HLOC_EINVAL, "cell_m must be > 0");
+  if (top_c < 1 || top_c > HLOC_MAX_TOP_C) return fail(HLOC_EINVAL, "top_c must be in 1..%d", HLOC_MAX_TOP_C);
+  if (!(radius_m >= 0.0) || !std::isfinite(radius_m)) return fail(HLOC_EINVAL, "radius_m must be >= 0");
+  if (toler_pct < 0 || toler_pct > 100) return fail(HLOC_EINVAL, "toler_pct must be in 0..100");
+  if (db->max_abs_coord / cell_m >= 1073741824.0)
+    return fail(HLOC_EINVAL, "a position lies 2^30 or more tiles from the origin at cell %g m", cell_m);
+  const double rr = std::floor(radius_m / cell_m + 0.5);
+  if (rr > 1073741824.0) return fail(HLOC_EINVAL, "radius_m / cell_m is too large");
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  HIPCHK(hipDeviceSynchronize());
+  db->cell = cell_m;
+  db->top_c = top_c;
+  db->radius = radius_m;
+  db->rho = (int32_t)rr;
+  db->pct = toler_pct;
+  return compute_tiles(db);
+}
+
+int hloc_reserve(hloc_db *db, int32_t nq_max, int32_t nreq_max, int32_t k_max,
+                 int32_t n_regions_max) {
+  if (!db) return fail(HLOC_EINVAL, "db is NULL");
+  if (nreq_max < 0) return fail(HLOC_EINVAL, "nreq_max must be >= 0");
+  Plan p;
+  CHK(make_plan(db, nq_max, k_max, n_regions_max, nreq_max, &p));
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  CHK(ensure_workspace(db, p, true));
+  // a smaller n_regions can need more coarse survivors than the largest one
+  if (!p.exhaustive) CHK(ensure(db->sel1, (size_t)std::max(nq_max, 1) * p.want1 * sizeof(uint64_t)));
+  return HLOC_OK;
+}
+
+int hloc_query_batch_async(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t n_regions,
+                           const int32_t *req_offsets, int32_t nreq, int32_t precision,
+                           int64_t *idx, float *dist, double *xy, int32_t *tile, int32_t *flags,
+                           void *stream) {
+  CHK(check_query_args(db, q, nq, req_offsets, nreq, precision, idx, dist));
+  Plan p;
+  CHK(make_plan(db, nq, k, n_regions, nreq, &p));
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  return enqueue_query(db, p, q, req_offsets, idx, dist, xy, tile, flags,
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+int hloc_query_batch(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t n_regions,
+                     const int32_t *req_offsets, int32_t nreq, int32_t precision, int64_t *idx,
+                     float *dist, double *xy, int32_t *tile, int32_t *flags) {
+  CHK(check_query_args(db, q, nq, req_offsets, nreq, precision, idx, dist));
+  if (req_offsets) {
+    if (req_offsets[0] != 0 || req_offsets[nreq] != nq)
+      return fail(HLOC_EINVAL, "req_offsets must run from 0 to nq");
+    for (int32_t i = 0; i < nreq; ++i) {
+      if (req_offsets[i + 1] < req_offsets[i])
+        return fail(HLOC_EINVAL, "req_offsets decreases at %d", i);
+      if ((int64_t)(req_offsets[i + 1] - req_offsets[i]) * k > HLOC_MAX_REQUEST_CANDIDATES)
+        return fail(HLOC_EINVAL, "request %d has more than %d candidates", i,
+                    HLOC_MAX_REQUEST_CANDIDATES);
+    }
+  } else if ((int64_t)k > HLOC_MAX_REQUEST_CANDIDATES) {
+    return fail(HLOC_EINVAL, "k is above the request candidate limit");
+  }
+  Plan p;
+  CHK(make_plan(db, nq, k, n_regions, nreq, &p));
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  const bool want_agg = xy || tile || flags;
+  const int64_t nqk = (int64_t)nq * k;
+  CHK(ensure(db->s_q, (size_t)std::max<int64_t>((int64_t)nq * db->d, 1) * sizeof(float)));
+  CHK(ensure(db->s_off, (size_t)(nreq + 1) * sizeof(int32_t)));
+  CHK(ensure(db->s_idx, (size_t)std::max<int64_t>(nqk, 1) * sizeof(int64_t)));
+  CHK(ensure(db->s_dist, (size_t)std::max<int64_t>(nqk, 1) * sizeof(float)));
+  if (want_agg) {
+    CHK(ensure(db->s_xy, (size_t)std::max(nreq, 1) * 2 * sizeof(double)));
+    CHK(ensure(db->s_tile, (size_t)std::max(nreq, 1) * 2 * sizeof(int32_t)));
+    CHK(ensure(db->s_flags, (size_t)std::max(nreq, 1) * sizeof(int32_t)));
+  }
+  hipStream_t s = db->stream;
+  if (nq > 0)
+    HIPCHK(hipMemcpyAsync(db->s_q.p, q, (size_t)nq * db->d * sizeof(float), hipMemcpyHostToDevice, s));
+  if (req_offsets)
+    HIPCHK(hipMemcpyAsync(db->s_off.p, req_offsets, (size_t)(nreq + 1) * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s));
+  CHK(enqueue_query(db, p, as<float>(db->s_q), req_offsets ? as<int32_t>(db->s_off) : nullptr,
+                    as<int64_t>(db->s_idx), as<float>(db->s_dist),
+                    want_agg ? as<double>(db->s_xy) : nullptr,
+                    want_agg ? as<int32_t>(db->s_tile) : nullptr,
+                    want_agg ? as<int32_t>(db->s_flags) : nullptr, s));
+  if (nqk > 0) {
+    HIPCHK(hipMemcpyAsync(idx, db->s_idx.p, (size_t)nqk * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(dist, db->s_dist.p, (size_t)nqk * sizeof(float), hipMemcpyDeviceToHost, s));
+  }
+  if (want_agg && nreq > 0) {
+    if (xy) HIPCHK(hipMemcpyAsync(xy, db->s_xy.p, (size_t)nreq * 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (tile) HIPCHK(hipMemcpyAsync(tile, db->s_tile.p, (size_t)nreq * 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (flags) HIPCHK(hipMemcpyAsync(flags, db->s_flags.p, (size_t)nreq * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return HLOC_OK;
+}
+
+int hloc_query_info(hloc_db *db, int64_t *out, int32_t n) {
+  if (!db || !out || n < 0) return fail(HLOC_EINVAL, "db and out must be non-NULL, n >= 0");
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  HIPCHK(hipDeviceSynchronize());
+  int32_t misc[16] = {0};
+  if (db->misc.p) HIPCHK(hipMemcpy(misc, db->misc.p, sizeof misc, hipMemcpyDeviceToHost));
+  int64_t total = 0;
+  if (db->last_nq > 0 && db->n_cand.p) {
+    std::vector<int32_t> nc(db->last_nq);
+    HIPCHK(hipMemcpy(nc.data(), db->n_cand.p, nc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int32_t v : nc) total += v;
+  }
+  const int64_t vals[6] = {misc[0], misc[1], misc[2], misc[3], db->last_kp, total};
+  for (int32_t i = 0; i < std::min(n, 6); ++i) out[i] = vals[i];
+  return HLOC_OK;
+}
+
+int hloc_last_regions(hloc_db *db, int32_t *out, int32_t *nq, int32_t *n_regions_eff) {
+  if (!db || !nq || !n_regions_eff) return fail(HLOC_EINVAL, "db, nq and n_regions_eff must be non-NULL");
+  if (!db->has_regions) return fail(HLOC_ESTATE, "no regions");
+  *nq = db->last_nq;
+  *n_regions_eff = db->last_nr;
+  if (!out || db->last_nq == 0) return HLOC_OK;
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(out, db->regions.p, (size_t)db->last_nq * db->last_nr * sizeof(int32_t),
+                   hipMemcpyDeviceToHost));
+  return HLOC_OK;
+}
+
+int hloc_profile(hloc_db *db, int32_t enable) {
+  if (!db) return fail(HLOC_EINVAL, "db is NULL");
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  HIPCHK(hipDeviceSynchronize());
+  db->prof.clear();
+  db->ev_used = 0;
+  db->prof_on = enable != 0;
+  return HLOC_OK;
+}
+
+int hloc_profile_read(hloc_db *db, double *ms, int64_t *calls, int32_t n) {
+  if (!db || !ms || !calls || n < 0) return fail(HLOC_EINVAL, "db, ms and calls must be non-NULL");
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  HIPCHK(hipDeviceSynchronize());
+  double acc[HLOC_NUM_PHASES] = {0};
+  int64_t cnt[HLOC_NUM_PHASES] = {0};
+  for (const auto &r : db->prof) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+    acc[r.phase] += t;
+    cnt[r.phase] += 1;
+  }
+  for (int32_t i = 0; i < std::min<int32_t>(n, HLOC_NUM_PHASES); ++i) {
+    ms[i] = acc[i];
+    calls[i] = cnt[i];
+  }
+  db->prof.clear();
+  db->ev_used = 0;
+  return HLOC_OK;
+}
+
+void hloc_free_db(hloc_db *db) {
+  if (!db) return;
+  {
+    DeviceGuard g(db->device);
+    (void)hipDeviceSynchronize();
+    free_all(db);
+  }
+  delete db;
+}
+
+}  // extern "C"

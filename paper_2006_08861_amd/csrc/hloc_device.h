@@ -1,0 +1,98 @@
+// Device helpers: block-wide bitonic sorts in LDS, block scans and wave
+// reductions with a fixed order (results never depend on timing).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hloc {
+
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Ascending bitonic sort of n (power of two) keys in LDS by the whole block.
+__device__ inline void block_sort_u64(uint64_t *a, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < (n >> 1); t += blockDim.x) {
+        const int i = 2 * t - (t & (stride - 1));
+        const int j = i + stride;
+        const bool up = (i & size) == 0;
+        const uint64_t x = a[i], y = a[j];
+        if ((x > y) == up) {
+          a[i] = y;
+          a[j] = x;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Ascending bitonic sort of n (power of two) pairs (hi, lo) by hi, then lo.
+__device__ inline void block_sort_pairs(uint64_t *hi, uint32_t *lo, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < (n >> 1); t += blockDim.x) {
+        const int i = 2 * t - (t & (stride - 1));
+        const int j = i + stride;
+        const bool up = (i & size) == 0;
+        const uint64_t xh = hi[i], yh = hi[j];
+        const uint32_t xl = lo[i], yl = lo[j];
+        const bool gt = (xh > yh) || (xh == yh && xl > yl);
+        if (gt == up) {
+          hi[i] = yh;
+          hi[j] = xh;
+          lo[i] = yl;
+          lo[j] = xl;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Exclusive prefix count of `pred` over the block (blockDim.x multiple of 64,
+// at most 1024). `scratch` holds 16 ints of LDS. Returns the thread's offset;
+// *total receives the block count. Contains barriers: call from all threads.
+__device__ inline int block_excl_count(bool pred, int *scratch, int *total) {
+  const uint64_t mask = __ballot(pred);
+  const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
+  const int below = __popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+  __syncthreads();
+  if (lane == 0) scratch[w] = __popcll(mask);
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int i = 0; i < nw; ++i) {
+    const int c = scratch[i];
+    if (i < w) base += c;
+    tot += c;
+  }
+  *total = tot;
+  return base + below;
+}
+
+// Sum over the wave in a fixed butterfly order; lane 0 holds the result.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t dist_key(float d, uint32_t row) {
+  return ((uint64_t)__float_as_uint(d) << 32) | row;
+}
+
+}  // namespace hloc

@@ -1,0 +1,166 @@
+// FP32 distance screen on MFMA (gfx950 v_mfma_f32_16x16x4_f32).
+//
+// Squared L2 distance of each frame to each candidate row, written as
+// |q|^2 + |d|^2 - 2 q.d with the dot products on the matrix cores (the
+// comparison of a frame with every row of a subspace, Section 3.1 /
+// Algorithm 1). A block of four waves takes one work item: up to 16 frames
+// (one MFMA column block, staged in LDS) against a chunk of rows; each wave
+// walks 16-row blocks of the chunk. Lane l holds row (l % 16) and the k-slice
+// 4 * (l / 16) + 16 s + {0..3}, so one 16-byte load feeds four MFMAs and the
+// 16 rows of a block are read as 64-byte runs. The frame operand uses the
+// same k-slice, so the k order of the sum is identical for every frame slot:
+// a frame's distances do not depend on which frames share its item.
+#include "hloc_device.h"
+#include "hloc_internal.h"
+
+namespace hloc {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_prep_queries(const float *__restrict__ q, int nq, int d,
+                                                      int dp, float *__restrict__ qp,
+                                                      float *__restrict__ qn2) {
+  const int f = blockIdx.x * 4 + wave_id();
+  const int lane = lane_id();
+  if (f >= nq) return;
+  const float *src = q + (int64_t)f * d;
+  float *dst = qp + (int64_t)f * dp;
+  float acc = 0.f;
+  for (int c = lane; c < dp; c += 64) {
+    const float v = c < d ? src[c] : 0.f;
+    dst[c] = v;
+    acc = fmaf(v, v, acc);
+  }
+  acc = wave_sum_f32(acc);
+  if (lane == 0) qn2[f] = acc;
+}
+
+hipError_t launch_prep_queries(const float *q, int32_t nq, int32_t d, int32_t dp, float *qp,
+                               float *qn2, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prep_queries, dim3((nq + 3) / 4), dim3(256), 0, s, q, nq, d, dp, qp, qn2);
+  return hipGetLastError();
+}
+
+template <bool DENSE>
+__global__ __launch_bounds__(256) void k_screen_f32(ScreenF32Args a) {
+  extern __shared__ float4 qs4[];  // kGroup x (dp + 4) floats, 16-byte aligned
+  float *qs = reinterpret_cast<float *>(qs4);
+  __shared__ int s_q[kGroup];
+  __shared__ int64_t s_off[kGroup];
+  __shared__ float s_qn[kGroup];
+  const int tid = threadIdx.x, wave = wave_id(), lane = lane_id();
+  const int dp = a.dp, ldq = dp + 4, dp4 = dp >> 2;
+  int n_items, nchunks = 1;
+  if (DENSE) {
+    nchunks = (a.nrows + a.rows_per_item - 1) / a.rows_per_item;
+    n_items = nchunks * ((a.nq + kGroup - 1) / kGroup);
+  } else {
+    n_items = *a.n_items;
+  }
+  const int i = lane & 15, g = lane >> 4;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    int64_t row_begin;
+    int nrows, gq;
+    if (DENSE) {
+      const int c = it % nchunks, grp = it / nchunks;
+      row_begin = (int64_t)c * a.rows_per_item;
+      nrows = min(a.rows_per_item, a.nrows - c * a.rows_per_item);
+      gq = min(kGroup, a.nq - grp * kGroup);
+      if (tid < kGroup) {
+        const int f = grp * kGroup + tid;
+        s_q[tid] = tid < gq ? f : 0;
+        s_off[tid] = (int64_t)f * a.cap + row_begin;
+        s_qn[tid] = tid < gq ? a.qn2[f] : 0.f;
+      }
+    } else {
+      const Item itm = a.items[it];
+      const int64_t rs = a.reg_start[itm.region], re = a.reg_start[itm.region + 1];
+      row_begin = rs + itm.chunk_row;
+      nrows = (int)min((int64_t)a.rows_per_item, re - row_begin);
+      gq = itm.gq;
+      if (tid < kGroup) {
+        if (tid < gq) {
+          const int2 e = a.rq[itm.q0 + tid];
+          s_q[tid] = e.x;
+          s_off[tid] = (int64_t)e.x * a.cap + e.y + itm.chunk_row;
+          s_qn[tid] = a.qn2[e.x];
+        } else {
+          s_q[tid] = 0;
+          s_off[tid] = 0;
+          s_qn[tid] = 0.f;
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < kGroup * dp4; e += blockDim.x) {
+      const int j = e / dp4, c = e - j * dp4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (j < gq) v = reinterpret_cast<const float4 *>(a.qp + (int64_t)s_q[j] * dp)[c];
+      *reinterpret_cast<float4 *>(qs + j * ldq + 4 * c) = v;
+    }
+    __syncthreads();
+    const float4 *qrow = reinterpret_cast<const float4 *>(qs + i * ldq) + g;
+    const int nrb = (nrows + 15) >> 4;
+    for (int rb = wave; rb < nrb; rb += 4) {
+      int rl = rb * 16 + i;
+      rl = rl < nrows ? rl : nrows - 1;
+      const float4 *rp = reinterpret_cast<const float4 *>(a.rows + (row_begin + rl) * dp) + g;
+      v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+      for (int s = 0; s < (dp >> 4); ++s) {
+        const float4 av = rp[4 * s];
+        const float4 bv = qrow[4 * s];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc, 0, 0, 0);
+      }
+      // lane l holds dot(row 4*(l/16)+r of the block, frame l%16)
+      if (i < gq) {
+        const float qn = s_qn[i];
+        const int64_t off = s_off[i];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rb * 16 + 4 * g + r;
+          if (row < nrows) {
+            const int64_t grow = row_begin + row;
+            const float rn = a.row_n2[grow];
+            uint64_t key = kKeyNone;
+            if (!__builtin_isinf(rn)) {
+              float dd = (qn + rn) - 2.f * acc[r];
+              dd = dd > 0.f ? dd : 0.f;
+              key = dist_key(dd, (uint32_t)grow);
+            }
+            a.cand[off + row] = key;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <bool DENSE>
+hipError_t launch_screen_t(const ScreenF32Args &a, int32_t grid, hipStream_t s) {
+  const size_t lds = (size_t)kGroup * (a.dp + 4) * sizeof(float);
+  static int attr_dev = -1;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (attr_dev != dev) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_screen_f32<DENSE>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    if (e != hipSuccess) return e;
+    attr_dev = dev;
+  }
+  hipLaunchKernelGGL(k_screen_f32<DENSE>, dim3(grid), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_screen_f32(const ScreenF32Args &a, int32_t grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  return a.dense ? launch_screen_t<true>(a, grid, s) : launch_screen_t<false>(a, grid, s);
+}
+
+}  // namespace hloc

@@ -1,0 +1,235 @@
+"""Python binding of libhloc.so (include/hloc.h) — argument marshalling only.
+
+Every step of the localization runs in the library's HIP kernels. PyTorch is
+used for device memory and streams: a query given as a CUDA tensor runs on
+torch's current stream and returns CUDA tensors; a query given as a NumPy
+array goes through the blocking host-pointer entry point and returns NumPy
+arrays. If the library has not been built, loading raises HlocError; there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhloc.so")
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "hloc.h")
+
+OK, EINVAL, ENOMEM, ESTATE, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", ESTATE: "ESTATE",
+                EDEVICE: "EDEVICE", EUNSUPPORTED: "EUNSUPPORTED"}
+FP32, BF16, FP8 = 0, 1, 2
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8}
+FLAG_LOW_CONFIDENCE, FLAG_EMPTY, FLAG_BAD_REQUEST = 1, 2, 4
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32, _I64, _U32, _F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
+_SIGNATURES = {
+    "hloc_build_db": (ctypes.c_int, [_P, _I64, _I32, _P, _U32, ctypes.POINTER(_P)]),
+    "hloc_set_regions": (ctypes.c_int, [_P, _P, _I32, _P]),
+    "hloc_set_aggregation": (ctypes.c_int, [_P, _F64, _I32, _F64, _I32]),
+    "hloc_query_batch": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _P, _P, _P,
+                                        _P]),
+    "hloc_query_batch_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _P,
+                                              _P, _P, _P, _P]),
+    "hloc_reserve": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32]),
+    "hloc_query_info": (ctypes.c_int, [_P, _P, _I32]),
+    "hloc_last_regions": (ctypes.c_int, [_P, _P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "hloc_profile": (ctypes.c_int, [_P, _I32]),
+    "hloc_profile_read": (ctypes.c_int, [_P, _P, _P, _I32]),
+    "hloc_free_db": (None, [_P]),
+    "hloc_last_error": (ctypes.c_char_p, []),
+}
+
+
+class HlocError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions include/hloc.h declares."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(hloc_\w+)\s*\(", text,
+                                 flags=re.M)))
+
+
+def load_library():
+    """Load libhloc.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise HlocError(EDEVICE, f"{LIB_PATH} is not built; run `python -m "
+                                 "paper_2006_08861_amd.build`")
+    import torch  # noqa: F401  (binds libamdhip64 before the library does)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise HlocError(rc, load_library().hloc_last_error().decode())
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _is_torch_cuda(x) -> bool:
+    try:
+        import torch
+    except ImportError:
+        return False
+    return isinstance(x, torch.Tensor) and x.is_cuda
+
+
+class HlocDB:
+    """A feature database on the current HIP device (see include/hloc.h)."""
+
+    def __init__(self, feats, xy, mirrors: int = 0):
+        lib = load_library()
+        feats = np.ascontiguousarray(feats, dtype=np.float32)
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        if feats.ndim != 2 or xy.shape != (feats.shape[0], 2):
+            raise HlocError(EINVAL, "feats must be n x d and xy n x 2")
+        h = ctypes.c_void_p()
+        _check(lib.hloc_build_db(_np_ptr(feats), feats.shape[0], feats.shape[1], _np_ptr(xy),
+                                 mirrors, ctypes.byref(h)))
+        self._h = h
+        self.n, self.d = feats.shape
+        self.n_regions_total = 0
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().hloc_free_db(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_regions(self, region_of, n_regions_total: int, reps=None):
+        region_of = np.ascontiguousarray(region_of, dtype=np.int32)
+        if region_of.shape != (self.n,):
+            raise HlocError(EINVAL, "region_of must have one entry per row")
+        if reps is not None:
+            reps = np.ascontiguousarray(reps, dtype=np.float32)
+            if reps.shape != (n_regions_total, self.d):
+                raise HlocError(EINVAL, "reps must be n_regions_total x d")
+        _check(load_library().hloc_set_regions(self._h, _np_ptr(region_of), n_regions_total,
+                                               _np_ptr(reps)))
+        self.n_regions_total = n_regions_total
+
+    def set_aggregation(self, cell: float, top_c: int, radius: float, toler_pct: int):
+        _check(load_library().hloc_set_aggregation(self._h, cell, top_c, radius, toler_pct))
+
+    def reserve(self, nq_max: int, nreq_max: int, k_max: int, n_regions_max: int):
+        _check(load_library().hloc_reserve(self._h, nq_max, nreq_max, k_max, n_regions_max))
+
+    def query(self, q, k: int, n_regions: int, req_offsets=None, precision="fp32",
+              aggregate: bool = True, stream=None) -> dict:
+        """Localize a batch. Returns idx, dist (per frame) and, with
+        aggregate=True, xy, tile and flags (per request)."""
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        if _is_torch_cuda(q):
+            return self._query_device(q, k, n_regions, req_offsets, prec, aggregate, stream)
+        return self._query_host(q, k, n_regions, req_offsets, prec, aggregate)
+
+    def _query_host(self, q, k, n_regions, req_offsets, prec, aggregate):
+        lib = load_library()
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        if q.ndim != 2 or q.shape[1] != self.d:
+            raise HlocError(EINVAL, f"q must be nq x {self.d}")
+        nq = q.shape[0]
+        offs = None if req_offsets is None else np.ascontiguousarray(req_offsets, dtype=np.int32)
+        nreq = nq if offs is None else len(offs) - 1
+        idx = np.empty((nq, k), np.int64)
+        dist = np.empty((nq, k), np.float32)
+        out = dict(idx=idx, dist=dist)
+        xy = tile = flags = None
+        if aggregate:
+            xy = np.empty((nreq, 2), np.float64)
+            tile = np.empty((nreq, 2), np.int32)
+            flags = np.empty(nreq, np.int32)
+            out.update(xy=xy, tile=tile, flags=flags)
+        _check(lib.hloc_query_batch(self._h, _np_ptr(q), nq, k, n_regions, _np_ptr(offs), nreq,
+                                    prec, _np_ptr(idx), _np_ptr(dist), _np_ptr(xy),
+                                    _np_ptr(tile), _np_ptr(flags)))
+        return out
+
+    def _query_device(self, q, k, n_regions, req_offsets, prec, aggregate, stream):
+        import torch
+        lib = load_library()
+        if q.dtype != torch.float32 or q.dim() != 2 or q.shape[1] != self.d:
+            raise HlocError(EINVAL, f"q must be an nq x {self.d} float32 tensor")
+        q = q.contiguous()
+        dev = q.device
+        nq = q.shape[0]
+        offs = None
+        if req_offsets is not None:
+            offs = torch.as_tensor(req_offsets, dtype=torch.int32, device=dev).contiguous()
+        nreq = nq if offs is None else offs.numel() - 1
+        idx = torch.empty((nq, k), dtype=torch.int64, device=dev)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        out = dict(idx=idx, dist=dist)
+        xy = tile = flags = None
+        if aggregate:
+            xy = torch.empty((nreq, 2), dtype=torch.float64, device=dev)
+            tile = torch.empty((nreq, 2), dtype=torch.int32, device=dev)
+            flags = torch.empty(nreq, dtype=torch.int32, device=dev)
+            out.update(xy=xy, tile=tile, flags=flags)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+
+        def p(t):
+            return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+        _check(lib.hloc_query_batch_async(self._h, p(q), nq, k, n_regions, p(offs), nreq, prec,
+                                          p(idx), p(dist), p(xy), p(tile), p(flags),
+                                          ctypes.c_void_p(s.cuda_stream)))
+        return out
+
+    def info(self) -> dict:
+        out = (ctypes.c_int64 * 6)()
+        _check(load_library().hloc_query_info(self._h, out, 6))
+        keys = ("items", "coarse_fallbacks", "fine_fallbacks", "max_candidates", "survivors",
+                "candidates")
+        return dict(zip(keys, list(out)))
+
+    PHASES = ("prep", "coarse", "sched", "screen", "select", "rerank", "aggregate")
+
+    def profile(self, enable: bool = True):
+        """Start (clearing) or stop the per-phase event record."""
+        _check(load_library().hloc_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{phase: (milliseconds summed, calls)} since the last read; clears."""
+        ms = (ctypes.c_double * len(self.PHASES))()
+        calls = (ctypes.c_int64 * len(self.PHASES))()
+        _check(load_library().hloc_profile_read(self._h, ms, calls, len(self.PHASES)))
+        return {p: (ms[i], calls[i]) for i, p in enumerate(self.PHASES)}
+
+    def last_regions(self) -> np.ndarray:
+        """Regions searched by each frame of the last query (nq x n_regions)."""
+        lib = load_library()
+        nq, nr = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.hloc_last_regions(self._h, None, ctypes.byref(nq), ctypes.byref(nr)))
+        out = np.empty((nq.value, nr.value), np.int32)
+        if out.size:
+            _check(lib.hloc_last_regions(self._h, _np_ptr(out), ctypes.byref(nq), ctypes.byref(nr)))
+        return out

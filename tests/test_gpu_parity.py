@@ -1,0 +1,306 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Each test builds a database on cuda:0, runs a batch through
+hloc_query_batch[_async] and judges every frame and request with the
+acceptance rule of tests/parity.py.
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from parity import judge_frames, judge_requests
+from paper_2006_08861_amd import hloc, workload
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if not os.path.exists(hloc.LIB_PATH):
+        pytest.fail("libhloc.so is not built")
+    return torch
+
+
+def make_db(feats, xy, region_of, R, agg=None, reps=None):
+    db = hloc.HlocDB(feats, xy)
+    db.set_regions(region_of, R, reps)
+    if agg is not None:
+        db.set_aggregation(*agg)
+    return db
+
+
+def run_device(torch, db, q, k, n_reg, offs=None):
+    qd = torch.from_numpy(np.ascontiguousarray(q, np.float32)).to("cuda:0")
+    od = None if offs is None else torch.from_numpy(np.asarray(offs, np.int32)).to("cuda:0")
+    out = db.query(qd, k, n_reg, od)
+    torch.cuda.synchronize()
+    return {key: v.cpu().numpy() for key, v in out.items()}
+
+
+def check_all(torch, feats, xy, region_of, R, q, k, n_reg, offs=None, agg=(0.5, 1, 0.0, 0),
+              reps=None, name=""):
+    say(f"[case] {name}: n={len(feats)} d={feats.shape[1]} R={R} nq={len(q)} k={k} n_reg={n_reg}")
+    db = make_db(feats, xy, region_of, R, agg, reps)
+    offs = np.arange(len(q) + 1) if offs is None else np.asarray(offs)
+    out = run_device(torch, db, q, k, n_reg, offs)
+    regs = db.last_regions()
+    info = db.info()
+    ora = oracle.localize(feats, xy, region_of, R, q, offs, k, n_reg, agg, reps=reps)
+    st = judge_frames(out["idx"], out["dist"], regs, ora, feats, region_of, R, q, k, reps=reps)
+    same = judge_requests(out["idx"], out["xy"], out["tile"], out["flags"], ora, xy, offs, agg)
+    say(f"[ok] {name}: {st} same_pools={same}/{len(offs) - 1} info={info}")
+    db.close()
+    return st, info, out
+
+
+# ------------------------------------------------------------- workload shapes
+def test_cpu_shape_full_batch(torch_cuda):
+    w = workload.make_workload(0)
+    st, info, _ = check_all(torch_cuda, w.feats, w.xy, w.region_of, w.n_regions_total, w.q, w.k,
+                            w.n_reg, w.req_offsets, w.agg, name="cpu-10k-d256 x1000")
+    assert st["recall"] == 1.0
+
+
+@pytest.fixture(scope="module")
+def fp32_shape(torch_cuda):
+    w = workload.make_workload(1)
+    db = make_db(w.feats, w.xy, w.region_of, w.n_regions_total, w.agg)
+    yield w, db
+    db.close()
+
+
+def test_fp32_shape_full_batch(torch_cuda, fp32_shape):
+    w, db = fp32_shape
+    say("[case] fp32-200k-d256 x256 (the benchmark's batch)")
+    out = run_device(torch_cuda, db, w.q, w.k, w.n_reg, w.req_offsets)
+    regs = db.last_regions()
+    ora = oracle.localize(w.feats, w.xy, w.region_of, w.n_regions_total, w.q, w.req_offsets,
+                          w.k, w.n_reg, w.agg)
+    st = judge_frames(out["idx"], out["dist"], regs, ora, w.feats, w.region_of,
+                      w.n_regions_total, w.q, w.k)
+    same = judge_requests(out["idx"], out["xy"], out["tile"], out["flags"], ora, w.xy,
+                          w.req_offsets, w.agg)
+    say(f"[ok] {st} same_pools={same} info={db.info()}")
+    assert st["recall"] == 1.0
+
+
+def test_batch_invariance(torch_cuda, fp32_shape):
+    # a frame's result must not depend on its batch-mates: bitwise equal alone,
+    # in a subset, in reverse order and in the full batch
+    w, db = fp32_shape
+    say("[case] batch invariance on fp32-200k-d256")
+    full = run_device(torch_cuda, db, w.q, w.k, w.n_reg)
+    rng = np.random.default_rng(5)
+    for sel in (np.arange(17), rng.choice(len(w.q), 40, replace=False), np.arange(len(w.q))[::-1],
+                np.array([100])):
+        part = run_device(torch_cuda, db, w.q[sel], w.k, w.n_reg)
+        np.testing.assert_array_equal(part["idx"], full["idx"][sel])
+        np.testing.assert_array_equal(part["dist"].view(np.uint32), full["dist"][sel].view(np.uint32))
+        np.testing.assert_array_equal(part["xy"].view(np.uint64), full["xy"][sel].view(np.uint64))
+
+
+def test_host_and_device_entry_points_agree(torch_cuda, fp32_shape):
+    w, db = fp32_shape
+    say("[case] sync host-pointer call vs async device call")
+    dev = run_device(torch_cuda, db, w.q[:64], w.k, w.n_reg)
+    host = db.query(w.q[:64], w.k, w.n_reg)
+    for key in ("idx", "dist", "tile", "flags"):
+        np.testing.assert_array_equal(host[key], dev[key])
+    np.testing.assert_array_equal(host["xy"].view(np.uint64), dev["xy"].view(np.uint64))
+
+
+def test_multiframe_paper_aggregation(torch_cuda):
+    w = workload.make_workload(3, nq=48, n=20_000)
+    st, info, _ = check_all(torch_cuda, w.feats, w.xy, w.region_of, w.n_regions_total, w.q, w.k,
+                            w.n_reg, w.req_offsets, w.agg, name="8-frame requests, d512")
+    assert st["recall"] == 1.0
+
+
+def test_serving_shape_mixed_frames(torch_cuda):
+    w = workload.make_workload(4, nq=40, n=30_000)
+    st, info, _ = check_all(torch_cuda, w.feats, w.xy, w.region_of, w.n_regions_total, w.q, 16,
+                            w.n_reg, w.req_offsets, w.agg, name="1-16 frame requests, d256")
+    assert st["recall"] == 1.0
+
+
+# ------------------------------------------------------------- edge cases
+def _random_db(seed, n, d, R, empty=0, dist="normal"):
+    rng = np.random.default_rng(seed)
+    feats = rng.standard_normal((n, d)).astype(np.float32)
+    region_of = rng.integers(0, R - empty, size=n).astype(np.int32)
+    if empty:
+        # move some ids to the top so that ids R-empty..R-1 are empty; shuffle ids
+        perm = rng.permutation(R)
+        region_of = perm[region_of].astype(np.int32)
+    xy = rng.uniform(0, 60, size=(n, 2))
+    return rng, feats, xy, region_of
+
+
+def test_ragged_dims_empty_regions(torch_cuda):
+    rng, feats, xy, region_of = _random_db(1, 1500, 37, 40, empty=6)
+    q = (feats[rng.integers(0, 1500, 45)] + 0.3 * rng.standard_normal((45, 37))).astype(np.float32)
+    for k, n_reg in ((7, 3), (1, 1), (33, 5)):
+        st, _, _ = check_all(torch_cuda, feats, xy, region_of, 40, q, k, n_reg,
+                             name=f"d37 empty regions k{k}")
+        assert st["recall"] == 1.0
+
+
+def test_exhaustive_mode(torch_cuda):
+    rng, feats, xy, region_of = _random_db(2, 2000, 24, 20)
+    q = rng.standard_normal((33, 24)).astype(np.float32)
+    for n_reg in (20, 1000):
+        st, _, out = check_all(torch_cuda, feats, xy, region_of, 20, q, 12, n_reg,
+                               name=f"exhaustive n_regions={n_reg}")
+        assert st["recall"] == 1.0
+
+
+def test_padding_when_candidates_run_out(torch_cuda):
+    rng = np.random.default_rng(3)
+    sizes = rng.integers(1, 4, size=30)
+    region_of = np.repeat(np.arange(30), sizes).astype(np.int32)
+    n = len(region_of)
+    feats = rng.standard_normal((n, 16)).astype(np.float32)
+    xy = rng.uniform(0, 10, size=(n, 2))
+    q = rng.standard_normal((20, 16)).astype(np.float32)
+    st, _, out = check_all(torch_cuda, feats, xy, region_of, 30, q, 8, 1, name="padding")
+    assert (out["idx"] == -1).any() and np.isinf(out["dist"]).any()
+
+
+def test_exact_match_queries(torch_cuda):
+    rng, feats, xy, region_of = _random_db(4, 3000, 64, 30)
+    js = rng.integers(0, 3000, 64)
+    st, _, out = check_all(torch_cuda, feats, xy, region_of, 30, feats[js], 5, 30,
+                           name="exact match")
+    assert (out["idx"][:, 0] == js).all() and (out["dist"][:, 0] == 0).all()
+
+
+def test_duplicate_rows_break_ties_by_index_and_fall_back(torch_cuda):
+    # 200 identical rows: the screen cannot separate them, so the certificate
+    # fails and the exact FP64 pass decides; ties go to the smaller index
+    rng = np.random.default_rng(6)
+    n, d = 1200, 32
+    feats = rng.standard_normal((n, d)).astype(np.float32)
+    dup = rng.choice(n, 200, replace=False)
+    feats[dup] = feats[dup[0]]
+    region_of = (np.arange(n) % 7).astype(np.int32)
+    xy = rng.uniform(0, 20, size=(n, 2))
+    q = np.repeat(feats[dup[:1]], 3, axis=0)
+    st, info, out = check_all(torch_cuda, feats, xy, region_of, 7, q, 10, 7, name="duplicates")
+    assert out["idx"][0].tolist() == sorted(dup.tolist())[:10]
+    assert info["fine_fallbacks"] == 3
+
+
+def test_identical_representatives_fall_back(torch_cuda):
+    # sixteen regions holding the same rows have identical means, more than
+    # the coarse shortlist (n_regions + 8) can hold: the coarse certificate
+    # fails and the exact pass keeps the lowest region ids
+    rng = np.random.default_rng(7)
+    base = rng.standard_normal((50, 16)).astype(np.float32)
+    other = rng.standard_normal((100, 16)).astype(np.float32) + 3.0
+    feats = np.concatenate([np.tile(base, (16, 1)), other])
+    region_of = np.concatenate([np.repeat(np.arange(16), 50),
+                                16 + np.arange(100) % 12]).astype(np.int32)
+    xy = rng.uniform(0, 20, size=(len(feats), 2))
+    q = (base[:5] + 0.01).astype(np.float32)
+    st, info, _ = check_all(torch_cuda, feats, xy, region_of, 28, q, 6, 3, name="equal means")
+    assert info["coarse_fallbacks"] == 5
+
+
+def test_user_representatives_and_relayout(torch_cuda):
+    rng, feats, xy, region_of = _random_db(8, 2500, 48, 25)
+    reps = rng.standard_normal((25, 48)).astype(np.float32)
+    q = rng.standard_normal((30, 48)).astype(np.float32)
+    st, _, _ = check_all(torch_cuda, feats, xy, region_of, 25, q, 9, 4, reps=reps,
+                         name="given representatives")
+    assert st["recall"] == 1.0
+    # set regions twice on one database: the second layout starts from a permuted one
+    say("[case] set_regions twice")
+    db = make_db(feats, xy, region_of, 25)
+    region2 = rng.integers(0, 11, size=2500).astype(np.int32)
+    db.set_regions(region2, 11)
+    out = run_device(torch_cuda, db, q, 9, 3)
+    ora = oracle.retrieve(feats, region2, 11, q, 9, 3)
+    st = judge_frames(out["idx"], out["dist"], db.last_regions(), ora, feats, region2, 11, q, 9)
+    assert st["recall"] == 1.0
+    db.close()
+
+
+def test_max_dim_and_max_k(torch_cuda):
+    rng, feats, xy, region_of = _random_db(9, 1800, 1024, 12)
+    q = rng.standard_normal((20, 1024)).astype(np.float32)
+    st, _, _ = check_all(torch_cuda, feats, xy, region_of, 12, q, 256, 6, name="d1024 k256")
+    assert st["recall"] == 1.0
+
+
+def test_empty_batch_and_bad_offsets(torch_cuda):
+    import torch
+    rng, feats, xy, region_of = _random_db(10, 500, 16, 5)
+    say("[case] empty batch, bad offsets")
+    db = make_db(feats, xy, region_of, 5)
+    out = db.query(np.zeros((0, 16), np.float32), 4, 2)
+    assert out["idx"].shape == (0, 4)
+    q = rng.standard_normal((6, 16)).astype(np.float32)
+    with pytest.raises(hloc.HlocError) as e:
+        db.query(q, 4, 2, req_offsets=[0, 4, 2, 6])
+    assert e.value.code == hloc.EINVAL
+    # the device entry point cannot check offsets on the host: the request is flagged
+    res = run_device(torch, db, q, 4, 2, offs=[0, 4, 2, 6])
+    assert res["flags"].tolist()[1] == hloc.FLAG_BAD_REQUEST
+    assert res["flags"].tolist()[0] in (0, hloc.FLAG_LOW_CONFIDENCE)
+    with pytest.raises(hloc.HlocError) as e:
+        db.query(q, 4, 2, precision="bf16")
+    assert e.value.code == hloc.EUNSUPPORTED
+    with pytest.raises(hloc.HlocError) as e:
+        db.query(q, 0, 2)
+    assert e.value.code == hloc.EINVAL
+    db.close()
+
+
+# ------------------------------------------------------------- aggregation
+def _golden_cases():
+    with open(os.path.join(GOLDEN, "aggregation_cases.json")) as f:
+        return [c for c in json.load(f)["cases"] if -1 not in c.get("rows", [])]
+
+
+@pytest.mark.parametrize("case", _golden_cases(), ids=lambda c: c["name"])
+def test_aggregation_golden_on_device(torch_cuda, case):
+    # one database row per point; each frame is a copy of one row, searched
+    # exhaustively with k = 1, so the pooled candidates are exactly the
+    # case's rows and the device aggregation must give the hand-worked tile
+    cell = case["cell"]
+    if "tiles" in case:
+        pts, rows = [], []
+        for ix, iy, c in case["tiles"]:
+            rows += [len(pts)] * c
+            pts.append([(ix + 0.5) * cell, (iy + 0.5) * cell])
+    else:
+        pts, rows = case["points"], case.get("rows", list(range(len(case["points"]))))
+    pts = np.asarray(pts, np.float64)
+    n = len(pts)
+    rng = np.random.default_rng(11)
+    feats = rng.standard_normal((n, 32)).astype(np.float32)
+    db = make_db(feats, pts, np.zeros(n, np.int32), 1,
+                 (cell, case["top_c"], case["radius"], case["toler_pct"]))
+    q = feats[np.asarray(rows)]
+    out = run_device(torch_cuda, db, q, 1, 1, offs=[0, len(rows)])
+    assert out["idx"][:, 0].tolist() == list(rows)
+    assert out["tile"][0].tolist() == case["expect"]["tile"]
+    assert int(out["flags"][0]) == case["expect"]["flag"]
+    ix, iy = case["expect"]["tile"]
+    assert out["xy"][0].tolist() == [(ix + 0.5) * cell, (iy + 0.5) * cell]
+    db.close()
