@@ -8,9 +8,11 @@ device memory. The default workload is the plain-FP32 shape: N = 200,000 rows
 of D = 256, 1,024 regions of uneven size, 256 single-frame queries per batch,
 8 regions per frame, k = 16.
 
-Prints one JSON line: throughput (frames/s), per-step p50/p99, the roofline of
-the fine screen (algorithmic bytes over its event-timed duration against HBM
-peak), and the FP64 oracle timed on a bounded sample on the host.
+Prints one JSON line: throughput (frames/s) of K back-to-back steps, the
+host-to-host latency p50/p99 of single batches, the roofline of the fine screen
+(algorithmic bytes over its duration from HIP start/stop events in a second
+loop of K steps, against HBM peak), and the FP64 oracle timed on a bounded
+sample on the host.
 """
 from __future__ import annotations
 
@@ -36,24 +38,36 @@ def log(*a):
 
 
 def cpu_baseline(w, gpu_idx, seconds: float):
-    """Time the FP64 oracle on the first frames of the batch (about `seconds`
-    of single-threaded work) and check the GPU's lists on them."""
+    """Time the FP64 oracle on the batch's frames, repeating the batch until
+    about `seconds` of single-threaded work, and check the GPU's lists on the
+    frames it covered."""
     import oracle
-    m = 4
-    while True:
+    done, passes, t_total = 0, 0, 0.0
+    m = min(len(w.q), 8)
+    ora = None
+    while t_total < seconds:
         t0 = time.perf_counter()
-        ora = oracle.retrieve(w.feats, w.region_of, w.n_regions_total, w.q[:m], w.k, w.n_reg)
-        for r in range(m):
-            oracle.aggregate(ora["idx"][r], w.xy, *w.agg)
+        res = oracle.retrieve(w.feats, w.region_of, w.n_regions_total, w.q[:m], w.k, w.n_reg)
+        offs = w.req_offsets
+        for r in range(len(offs) - 1):
+            if offs[r + 1] > m:
+                break
+            oracle.aggregate(res["idx"][offs[r]:offs[r + 1]].ravel(), w.xy, *w.agg)
         dt = time.perf_counter() - t0
-        if dt >= seconds or m >= len(w.q):
-            break
-        m = min(len(w.q), max(m + 1, int(m * seconds / max(dt, 1e-3) * 1.1)))
-    hits = sum(len(set(gpu_idx[i].tolist()) & set(ora["idx"][i].tolist())) for i in range(m))
-    exact = sum(int(np.array_equal(gpu_idx[i], ora["idx"][i])) for i in range(m))
-    return dict(value=m / dt, unit="queries/s", cores=1, kind="oracle",
-                sample=f"first {m} of {len(w.q)} frames of {w.name}, single thread, "
-                       f"{dt:.1f} s"), hits / (m * w.k), exact, m
+        t_total += dt
+        done += m
+        passes += 1
+        if ora is None or m > len(ora["idx"]):
+            ora = res
+        if m < len(w.q):
+            m = min(len(w.q), max(m + 1, int(m * (seconds - t_total) / max(dt, 1e-3))))
+    mm = len(ora["idx"])
+    hits = sum(len(set(gpu_idx[i].tolist()) & set(ora["idx"][i].tolist())) for i in range(mm))
+    exact = sum(int(np.array_equal(gpu_idx[i], ora["idx"][i])) for i in range(mm))
+    return dict(value=done / t_total, unit="queries/s", cores=1, kind="oracle",
+                sample=f"{done} frames of {w.name} ({passes} passes over the first {mm} of "
+                       f"{len(w.q)} frames), single thread, {t_total:.1f} s"), \
+        hits / (mm * w.k), exact, mm
 
 
 def main():
@@ -64,7 +78,11 @@ def main():
     ap.add_argument("--workload", type=int, default=1, help="index of workload.SHAPES")
     ap.add_argument("--nq", type=int, default=None, help="override the batch size")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB ten times (reference for "
+                         "hardware byte counters) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}); this build has no "
@@ -75,6 +93,15 @@ def main():
     from paper_2006_08861_amd import hloc, workload
 
     dev = torch.device("cuda:0")
+    if a.copy_calibration:
+        n = a.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            torch.add(src, 0.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_mib": a.copy_calibration, "launches": 10}))
+        return
     t0 = time.perf_counter()
     w = workload.make_workload(a.workload, nq=a.nq)
     log(f"[bench] workload {w.name}: n={len(w.feats)} d={w.feats.shape[1]} "
@@ -114,20 +141,33 @@ def main():
     d = w.feats.shape[1]
     screen_bytes = unique_rows * (4 * d + 4) + info["candidates"] * 8 + nq * 4 * d
 
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
-    db.profile(True)
+    # throughput: K back-to-back steps, nothing recorded between kernels
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(a.steps):
-        starts[i].record(stream)
+    for _ in range(a.steps):
         step()
-        ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # the same K steps again with every kernel dispatched with HIP start/stop
+    # events on the query stream: per-phase device time for the roofline (the
+    # events add dispatch gaps, so this loop is not used for the throughput)
+    db.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(a.steps):
+        step()
+    torch.cuda.synchronize()
+    wall_prof = time.perf_counter() - t1
     phases = db.profile_read()
     db.profile(False)
-    step_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    # latency: one batch at a time, host to host
+    lat = []
+    for _ in range(a.latency_reps):
+        t1 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+    lat = np.array(lat)
     screen_ms = phases["screen"][0] / max(phases["screen"][1], 1)
     achieved = screen_bytes / (screen_ms * 1e-3) / 1e9
     gpu_idx = idx.cpu().numpy()
@@ -152,8 +192,9 @@ def main():
                    "regions": int(w.n_regions_total), "frames_per_step": int(nq),
                    "requests_per_step": int(nreq), "n_regions": int(w.n_reg), "k": int(k),
                    "screen": "fp32", "aggregation": list(w.agg)},
-        "p50_ms": float(np.percentile(step_ms, 50)),
-        "p99_ms": float(np.percentile(step_ms, 99)),
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "latency": f"host-to-host time of one batch, {len(lat)} batches run one at a time",
         "recall_at_k": recall,
         "exact_lists": None if base is None else f"{exact}/{m}",
         "roofline": {"bound": "hbm", "kernel": "k_screen_f32<false>", "achieved": achieved,
@@ -161,6 +202,7 @@ def main():
                      "traffic": None, "bytes_per_launch": int(screen_bytes),
                      "avg_launch_ms": screen_ms},
         "phases_ms": {p: v[0] / max(v[1], 1) for p, v in phases.items()},
+        "ms_per_step_event_timed": wall_prof * 1e3 / a.steps,
         "fallbacks": {"coarse": info["coarse_fallbacks"], "fine": info["fine_fallbacks"]},
         "cpu_baseline": base,
     }

@@ -167,11 +167,10 @@ int hloc_last_regions(hloc_db *db, int32_t *out, int32_t *nq, int32_t *n_regions
  * Device-time profile of the query path, measured with HIP events recorded on
  * the query's stream around each phase:
  *   HLOC_PHASE_PREP      query norms and padded copy
- *   HLOC_PHASE_COARSE    coarse screen, select, FP64 rerank, exact fallback
+ *   HLOC_PHASE_COARSE    coarse screen, then select + FP64 re-score of regions
  *   HLOC_PHASE_SCHED     region -> frames lists and work items
  *   HLOC_PHASE_SCREEN    fine screen (one kernel launch)
- *   HLOC_PHASE_SELECT    per-frame selection of the survivors
- *   HLOC_PHASE_RERANK    FP64 rerank, certificate, exact fallback
+ *   HLOC_PHASE_SELECT    per-frame select, FP64 rerank, certificate, exact fallback
  *   HLOC_PHASE_AGGREGATE aggregation of each request
  * hloc_profile(db, 1) clears the record and starts recording for later query
  * calls; hloc_profile(db, 0) stops. hloc_profile_read() waits for the device,
@@ -185,9 +184,8 @@ enum {
   HLOC_PHASE_SCHED = 2,
   HLOC_PHASE_SCREEN = 3,
   HLOC_PHASE_SELECT = 4,
-  HLOC_PHASE_RERANK = 5,
-  HLOC_PHASE_AGGREGATE = 6,
-  HLOC_NUM_PHASES = 7
+  HLOC_PHASE_AGGREGATE = 5,
+  HLOC_NUM_PHASES = 6
 };
 int hloc_profile(hloc_db *db, int32_t enable);
 int hloc_profile_read(hloc_db *db, double *ms, int64_t *calls, int32_t n);

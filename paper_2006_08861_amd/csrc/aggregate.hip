@@ -157,8 +157,7 @@ hipError_t launch_aggregate(const AggArgs &a, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr_dev = dev;
   }
-  hipLaunchKernelGGL(k_aggregate, dim3(a.nreq), dim3(256), lds, s, a);
-  return hipGetLastError();
+  return launch_kernel(k_aggregate, dim3(a.nreq), dim3(256), lds, s, a);
 }
 
 }  // namespace hloc

@@ -15,6 +15,10 @@
 
 using namespace hloc;
 
+namespace hloc {
+PhaseEvents *g_phase = nullptr;
+}
+
 namespace {
 
 thread_local std::string g_err;
@@ -61,7 +65,7 @@ struct WsBuf {
 constexpr int kRegionMargin = 8;    // extra regions re-scored in FP64 by the coarse stage
 constexpr int kOversample = 16;     // extra rows re-scored in FP64 by the fine stage
 constexpr int kRowsCoarse = 64;     // rows (representatives) per coarse work item
-constexpr int kRowsFine = 128;      // rows per fine work item
+constexpr int kRowsFine = 64;       // rows per fine work item
 constexpr double kUnit32 = 5.9604644775390625e-08;  // 2^-24
 
 template <class T>
@@ -101,8 +105,8 @@ struct hloc_db {
   double cell = 0.5, radius = 0.0;
   int32_t top_c = 1, rho = 0, pct = 0;
   // workspace
-  WsBuf qp, qn2, cand1, sel1, regions, flag1, flag2, rcount, rfill, rq_off, item_off, cand_off,
-      n_cand, misc, rq, items, cand2, sel2, agg_xy, agg_tile, agg_flags;
+  WsBuf qp, qn2, cand1, regions, rcount, rfill, rq_off, item_off, cand_off, n_cand, misc, rq,
+      items, cand2, agg_xy, agg_tile, agg_flags;
   WsBuf s_q, s_off, s_idx, s_dist, s_xy, s_tile, s_flags;
   // last query
   int32_t last_nq = 0, last_nr = 0, last_kp = 0;
@@ -157,7 +161,7 @@ void dev_free(T *&p) {
 }
 
 struct Plan {
-  int32_t nq, k, nr, L1, want1, kp, want2, nreq;
+  int32_t nq, k, nr, L1, kp, nreq;
   bool exhaustive;
   int64_t cap2, items_bound;
   int32_t grid1, grid2;
@@ -182,10 +186,8 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
                   "n_regions %d is above %d and below the %d non-empty regions; pass "
                   "n_regions >= %d to search every region",
                   n_regions, kMaxSurvivors - kRegionMargin, db->R_nonempty, db->R_nonempty);
-    p.want1 = p.L1 + 1;
   }
   p.kp = std::min(k + kOversample, kMaxSurvivors);
-  p.want2 = p.kp + 1;
   p.cap2 = db->h_desc_prefix[p.nr];
   const int64_t maxch = (db->max_region + kRowsFine - 1) / kRowsFine;
   const int64_t b1 = (int64_t)nq * p.nr * maxch;
@@ -193,11 +195,11 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
   p.items_bound = std::min(b1, b2);
   if (p.items_bound > INT32_MAX || (int64_t)nq * p.cap2 > ((int64_t)1 << 40))
     return fail(HLOC_EINVAL, "batch too large for one call (nq %d)", nq);
-  const int64_t blocks = (int64_t)db->num_cu * 4;
-  p.grid2 = (int32_t)std::max<int64_t>(1, std::min(p.items_bound, blocks));
+  const int32_t max_blocks = db->num_cu * 8;
+  p.grid2 = screen_grid(p.items_bound, db->dp, max_blocks);
   const int64_t dense_items =
       (((int64_t)db->R + kRowsCoarse - 1) / kRowsCoarse) * (((int64_t)nq + kGroup - 1) / kGroup);
-  p.grid1 = (int32_t)std::max<int64_t>(1, std::min(dense_items, blocks));
+  p.grid1 = screen_grid(dense_items, db->dp, max_blocks);
   *pl = p;
   return HLOC_OK;
 }
@@ -208,11 +210,8 @@ int ensure_workspace(hloc_db *db, const Plan &p, bool agg_internal) {
   CHK(ensure(db->qn2, (size_t)nq * sizeof(float)));
   if (!p.exhaustive) {
     CHK(ensure(db->cand1, (size_t)nq * db->R * sizeof(uint64_t)));
-    CHK(ensure(db->sel1, (size_t)nq * p.want1 * sizeof(uint64_t)));
   }
   CHK(ensure(db->regions, (size_t)nq * nr * sizeof(int32_t)));
-  CHK(ensure(db->flag1, (size_t)nq * sizeof(int32_t)));
-  CHK(ensure(db->flag2, (size_t)nq * sizeof(int32_t)));
   CHK(ensure(db->rcount, (size_t)db->R * sizeof(int32_t)));
   CHK(ensure(db->rfill, (size_t)db->R * sizeof(int32_t)));
   CHK(ensure(db->rq_off, (size_t)db->R * sizeof(int32_t)));
@@ -223,7 +222,6 @@ int ensure_workspace(hloc_db *db, const Plan &p, bool agg_internal) {
   CHK(ensure(db->rq, (size_t)nq * nr * sizeof(int2)));
   CHK(ensure(db->items, (size_t)std::max<int64_t>(p.items_bound, 1) * sizeof(Item)));
   CHK(ensure(db->cand2, (size_t)nq * std::max<int64_t>(p.cap2, 1) * sizeof(uint64_t)));
-  CHK(ensure(db->sel2, (size_t)nq * p.want2 * sizeof(uint64_t)));
   if (agg_internal) {
     const int64_t nreq = std::max(p.nreq, 1);
     CHK(ensure(db->agg_xy, (size_t)nreq * 2 * sizeof(double)));
@@ -233,29 +231,38 @@ int ensure_workspace(hloc_db *db, const Plan &p, bool agg_internal) {
   return HLOC_OK;
 }
 
-// Records an event on s when profiling; returns it (or nullptr).
-int prof_mark(hloc_db *db, hipStream_t s, hipEvent_t *ev) {
-  *ev = nullptr;
-  if (!db->prof_on) return HLOC_OK;
+hipEvent_t take_event(hloc_db *db) {
   if (db->ev_used == db->ev_pool.size()) {
     hipEvent_t e;
-    HIPCHK(hipEventCreate(&e));
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
     db->ev_pool.push_back(e);
   }
-  *ev = db->ev_pool[db->ev_used++];
-  HIPCHK(hipEventRecord(*ev, s));
-  return HLOC_OK;
+  return db->ev_pool[db->ev_used++];
 }
 
-// Closes the phase opened by *t (a mark) and opens the next one.
-int prof_phase(hloc_db *db, int phase, hipStream_t s, hipEvent_t *t) {
-  if (!db->prof_on) return HLOC_OK;
-  hipEvent_t e;
-  CHK(prof_mark(db, s, &e));
-  db->prof.push_back({phase, *t, e});
-  *t = e;
-  return HLOC_OK;
-}
+// Times consecutive phases of a query while profiling is on: begin(p) closes
+// the open phase and routes the next kernel launches through event-timed
+// dispatches (see launch_kernel); the destructor closes the last phase.
+struct Phaser {
+  hloc_db *db;
+  int phase = -1;
+  PhaseEvents pe;
+  explicit Phaser(hloc_db *d) : db(d) {}
+  void end() {
+    if (phase >= 0 && pe.launches > 0 && pe.start && pe.stop)
+      db->prof.push_back({phase, pe.start, pe.stop});
+    phase = -1;
+    g_phase = nullptr;
+  }
+  void begin(int p) {
+    end();
+    if (!db->prof_on) return;
+    phase = p;
+    pe = PhaseEvents{take_event(db), take_event(db), 0};
+    g_phase = &pe;
+  }
+  ~Phaser() { end(); }
+};
 
 int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req_offsets,
                   int64_t *idx, float *dist, double *xy, int32_t *tile, int32_t *flags,
@@ -267,14 +274,16 @@ int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req
   db->last_nr = p.nr;
   db->last_kp = p.kp;
   int32_t *misc = as<int32_t>(db->misc);
-  HIPCHK(launch_fill_i32(misc, 16, 0, s));
-  if (p.nq == 0) return HLOC_OK;
+  if (p.nq == 0) {
+    HIPCHK(launch_fill_i32(misc, 16, 0, s));
+    return HLOC_OK;
+  }
   float *qp = as<float>(db->qp), *qn2 = as<float>(db->qn2);
   int32_t *regions = as<int32_t>(db->regions);
-  hipEvent_t t;
-  CHK(prof_mark(db, s, &t));
-  HIPCHK(launch_prep_queries(q, p.nq, db->d, db->dp, qp, qn2, s));
-  CHK(prof_phase(db, HLOC_PHASE_PREP, s, &t));
+  Phaser ph(db);
+  ph.begin(HLOC_PHASE_PREP);
+  HIPCHK(launch_prep_queries(q, p.nq, db->d, db->dp, qp, qn2, misc, s));
+  ph.begin(HLOC_PHASE_COARSE);
   const double coef = (db->dp + 16) * kUnit32 * 1.001;
   if (!p.exhaustive) {
     ScreenF32Args sa{};
@@ -290,13 +299,12 @@ int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req
     sa.nrows = db->R;
     sa.nq = p.nq;
     HIPCHK(launch_screen_f32(sa, p.grid1, s));
-    HIPCHK(launch_select(as<uint64_t>(db->cand1), db->R, nullptr, db->R, p.nq, p.want1,
-                         as<uint64_t>(db->sel1), nullptr, s));
-    RerankArgs ra{};
-    ra.sel = as<uint64_t>(db->sel1);
-    ra.want = p.want1;
+    SelRerankArgs ra{};
+    ra.cand = as<uint64_t>(db->cand1);
+    ra.cap = db->R;
+    ra.n_fixed = db->R;
+    ra.L = p.L1;
     ra.m = p.nr;
-    ra.n_fixed = db->R_nonempty;
     ra.src64 = db->rep64;
     ra.dp = db->dp;
     ra.qp = qp;
@@ -305,30 +313,18 @@ int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req
     ra.max_norm = (double)db->h_rep_max * (1.0 + 1e-6);
     ra.nq = p.nq;
     ra.reg_out = regions;
-    ra.flag = as<int32_t>(db->flag1);
     ra.stat_fallback = misc + 1;
-    HIPCHK(launch_rerank(ra, s));
-    ExactArgs ea{};
-    ea.flag = as<int32_t>(db->flag1);
-    ea.nq = p.nq;
-    ea.m = p.nr;
-    ea.dp = db->dp;
-    ea.qp = qp;
-    ea.src64 = db->rep64;
-    ea.R = db->R;
-    ea.reg_start = db->reg_start;
-    ea.reg_out = regions;
-    HIPCHK(launch_exact(ea, s));
+    HIPCHK(launch_select_rerank(ra, s));
   } else {
     HIPCHK(launch_broadcast_ids(db->nonempty_ids, p.nr, p.nq, regions, s));
   }
-  CHK(prof_phase(db, HLOC_PHASE_COARSE, s, &t));
+  ph.begin(HLOC_PHASE_SCHED);
   int32_t *cand_off = as<int32_t>(db->cand_off), *n_cand = as<int32_t>(db->n_cand);
   HIPCHK(launch_sched(regions, p.nq, p.nr, db->R, db->reg_start, kRowsFine,
                       as<int32_t>(db->rcount), as<int32_t>(db->rfill), as<int32_t>(db->rq_off),
                       as<int32_t>(db->item_off), cand_off, n_cand, misc + 0, as<int2>(db->rq),
                       as<Item>(db->items), s));
-  CHK(prof_phase(db, HLOC_PHASE_SCHED, s, &t));
+  ph.begin(HLOC_PHASE_SCREEN);
   ScreenF32Args sb{};
   sb.rows = db->rows;
   sb.row_n2 = db->row_n2;
@@ -344,15 +340,13 @@ int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req
   sb.rq = as<int2>(db->rq);
   sb.reg_start = db->reg_start;
   HIPCHK(launch_screen_f32(sb, p.grid2, s));
-  CHK(prof_phase(db, HLOC_PHASE_SCREEN, s, &t));
-  HIPCHK(launch_select(as<uint64_t>(db->cand2), p.cap2, n_cand, 0, p.nq, p.want2,
-                       as<uint64_t>(db->sel2), misc + 3, s));
-  CHK(prof_phase(db, HLOC_PHASE_SELECT, s, &t));
-  RerankArgs rb{};
-  rb.sel = as<uint64_t>(db->sel2);
-  rb.want = p.want2;
-  rb.m = p.k;
+  ph.begin(HLOC_PHASE_SELECT);
+  SelRerankArgs rb{};
+  rb.cand = as<uint64_t>(db->cand2);
+  rb.cap = p.cap2;
   rb.n_cand = n_cand;
+  rb.L = p.kp;
+  rb.m = p.k;
   rb.src32 = db->rows;
   rb.dp = db->dp;
   rb.tie_of = db->perm;
@@ -363,26 +357,10 @@ int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req
   rb.nq = p.nq;
   rb.idx_out = idx;
   rb.dist_out = dist;
-  rb.flag = as<int32_t>(db->flag2);
   rb.stat_fallback = misc + 2;
-  HIPCHK(launch_rerank(rb, s));
-  ExactArgs eb{};
-  eb.flag = as<int32_t>(db->flag2);
-  eb.nq = p.nq;
-  eb.m = p.k;
-  eb.dp = db->dp;
-  eb.qp = qp;
-  eb.src32 = db->rows;
-  eb.regions = regions;
-  eb.nr = p.nr;
-  eb.cand_off = cand_off;
-  eb.n_cand = n_cand;
-  eb.reg_start = db->reg_start;
-  eb.tie_of = db->perm;
-  eb.idx_out = idx;
-  eb.dist_out = dist;
-  HIPCHK(launch_exact(eb, s));
-  CHK(prof_phase(db, HLOC_PHASE_RERANK, s, &t));
+  rb.stat_max = misc + 3;
+  HIPCHK(launch_select_rerank(rb, s));
+  ph.end();
   if (want_agg && p.nreq > 0) {
     AggArgs ag{};
     ag.idx = idx;
@@ -398,8 +376,8 @@ int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req
     ag.xy = xy ? xy : as<double>(db->agg_xy);
     ag.tile = tile ? tile : as<int32_t>(db->agg_tile);
     ag.flags = flags ? flags : as<int32_t>(db->agg_flags);
+    ph.begin(HLOC_PHASE_AGGREGATE);
     HIPCHK(launch_aggregate(ag, s));
-    CHK(prof_phase(db, HLOC_PHASE_AGGREGATE, s, &t));
   }
   return HLOC_OK;
 }
@@ -421,10 +399,10 @@ int check_query_args(const hloc_db *db, const float *q, int32_t nq, const int32_
 }
 
 void free_all(hloc_db *db) {
-  WsBuf *bufs[] = {&db->qp,     &db->qn2,      &db->cand1,    &db->sel1,    &db->regions,
-                   &db->flag1,  &db->flag2,    &db->rcount,   &db->rfill,   &db->rq_off,
+  WsBuf *bufs[] = {&db->qp,     &db->qn2,      &db->cand1,    &db->regions,
+                   &db->rcount,   &db->rfill,   &db->rq_off,
                    &db->item_off, &db->cand_off, &db->n_cand, &db->misc,    &db->rq,
-                   &db->items,  &db->cand2,    &db->sel2,     &db->agg_xy,  &db->agg_tile,
+                   &db->items,  &db->cand2,    &db->agg_xy,  &db->agg_tile,
                    &db->agg_flags, &db->s_q,   &db->s_off,    &db->s_idx,   &db->s_dist,
                    &db->s_xy,   &db->s_tile,   &db->s_flags};
   for (WsBuf *b : bufs) free_buf(*b);
@@ -648,8 +626,6 @@ int hloc_reserve(hloc_db *db, int32_t nq_max, int32_t nreq_max, int32_t k_max,
   DeviceGuard g(db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   CHK(ensure_workspace(db, p, true));
-  // a smaller n_regions can need more coarse survivors than the largest one
-  if (!p.exhaustive) CHK(ensure(db->sel1, (size_t)std::max(nq_max, 1) * p.want1 * sizeof(uint64_t)));
   return HLOC_OK;
 }
 

@@ -2,10 +2,37 @@
 // layouts, work-item format and the host-side launch wrappers of each kernel.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace hloc {
+
+// Event pair that times one phase of a query. While g_phase is set, every
+// kernel launched through launch_kernel() is dispatched with
+// hipExtLaunchKernel: the first kernel of the phase records `start` when it
+// begins and each kernel records `stop` when it ends, with no extra packets
+// between kernels. Set only by the query path with profiling enabled (one
+// thread at a time).
+struct PhaseEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+  int launches = 0;
+};
+extern PhaseEvents *g_phase;
+
+template <typename F, typename... Args>
+inline hipError_t launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s,
+                                Args... args) {
+  if (g_phase) {
+    hipEvent_t st = g_phase->launches == 0 ? g_phase->start : nullptr;
+    ++g_phase->launches;
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, s, st, g_phase->stop, 0u, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+  }
+  return hipGetLastError();
+}
 
 constexpr int kGroup = 16;          // frames per MFMA column block of the screen
 constexpr int kBlock = 256;         // threads per block of most kernels
@@ -19,13 +46,14 @@ inline int next_pow2_host(int v) {
   return p;
 }
 
-// One unit of fine-screen work: rows [chunk_row, chunk_row + T) of `region`
-// (clipped to the region) against frames rq[q0 .. q0 + gq).
+// One unit of fine-screen work: rows [row_begin, row_begin + nrows) of one
+// region (absolute row indices; chunk_row = offset of the chunk inside its
+// region) against frames rq[q0 .. q0 + gq).
 struct Item {
-  int32_t region;
-  int32_t chunk_row;  // first row of the chunk, relative to the region start
+  int32_t row_begin;
+  int32_t chunk_row;
   int32_t q0;
-  int32_t gq;
+  int32_t nrows_gq;  // nrows << 16 | gq
 };
 
 // Dense or listed screen of fp32 rows against padded fp32 frames.
@@ -37,7 +65,7 @@ struct ScreenF32Args {
   const float *qn2;       // frames squared norms
   uint64_t *cand;         // per frame: cap keys (dist bits << 32 | row)
   int64_t cap;
-  int32_t rows_per_item;  // T, multiple of 64
+  int32_t rows_per_item;  // T, multiple of 16
   // dense mode: every frame against rows [0, nrows)
   int32_t dense;
   int32_t nrows;
@@ -49,9 +77,12 @@ struct ScreenF32Args {
   const int64_t *reg_start;
 };
 
+// Padded copy and squared norm of each frame; block 0 also clears zero16[0..16).
 hipError_t launch_prep_queries(const float *q, int32_t nq, int32_t d, int32_t dp, float *qp,
-                               float *qn2, hipStream_t s);
+                               float *qn2, int32_t *zero16, hipStream_t s);
 hipError_t launch_screen_f32(const ScreenF32Args &a, int32_t grid, hipStream_t s);
+// Blocks to launch for `items` work items of the screen at padded length dp.
+int32_t screen_grid(int64_t items, int32_t dp, int32_t max_blocks);
 
 // Scheduling of the fine screen.
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
@@ -62,62 +93,33 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
                         int32_t *rq_off, int32_t *item_off, int32_t *cand_off, int32_t *n_cand,
                         int32_t *n_items, int2 *rq, Item *items, hipStream_t s);
 
-// Per-frame selection of the `want` smallest keys of cand[q][0 .. n(q)).
-// n(q) = n_cand ? n_cand[q] : n_fixed. Output sel[q][want], ascending,
-// kKeyNone-padded.
-hipError_t launch_select(const uint64_t *cand, int64_t cap, const int32_t *n_cand,
-                         int32_t n_fixed, int32_t nq, int32_t want, uint64_t *sel,
-                         int32_t *stat_max_cand, hipStream_t s);
-
-// FP64 rerank of the survivors and certificate against the best rejected
-// screen distance.
-struct RerankArgs {
-  const uint64_t *sel;     // nq x want sorted keys; key low word = source row
-  int32_t want;            // survivors + 1
-  int32_t m;               // results per frame
-  const int32_t *n_cand;   // per-frame candidate count (NULL: n_fixed)
+// Per frame: the L + 1 smallest screen keys of cand[f][0 .. n(f)) (n(f) =
+// n_cand ? n_cand[f] : n_fixed; kKeyNone entries are skipped), FP64 rerank of
+// the L smallest, top m by (distance, tie id), certificate against the
+// (L + 1)-th, and the exact FP64 pass over all candidates when it fails.
+struct SelRerankArgs {
+  const uint64_t *cand;
+  int64_t cap;
+  const int32_t *n_cand;
   int32_t n_fixed;
-  const float *src32;      // fp32 source rows (stage 2) or NULL
-  const double *src64;     // fp64 source rows (stage 1) or NULL
+  int32_t L;               // survivors re-scored in FP64 (<= kMaxSurvivors)
+  int32_t m;               // results per frame (<= 256, <= L)
+  const float *src32;      // fp32 source rows (fine stage) or NULL
+  const double *src64;     // fp64 source rows (coarse stage) or NULL
   int32_t dp;
-  const int32_t *tie_of;   // source row -> tie id (original index); NULL: the row itself
+  const int32_t *tie_of;   // source row -> original index; NULL: the row id itself
   const float *qp;         // frames x dp padded fp32
   const float *qn2;
   double err_coef;         // screen error bound: err_coef * (|q| + max_norm)^2
   double max_norm;
   int32_t nq;
-  int64_t *idx_out;        // stage 2: nq x m original indices
-  float *dist_out;         // stage 2: nq x m
-  int32_t *reg_out;        // stage 1: nq x m ids
-  int32_t *flag;           // per frame: 1 = not certified
-  int32_t *stat_fallback;  // counter of uncertified frames
+  int64_t *idx_out;        // fine: nq x m original indices
+  float *dist_out;         // fine: nq x m
+  int32_t *reg_out;        // coarse: nq x m region ids
+  int32_t *stat_fallback;  // frames that needed the exact pass
+  int32_t *stat_max;       // largest candidate count (or NULL)
 };
-hipError_t launch_rerank(const RerankArgs &a, hipStream_t s);
-
-// Exact FP64 recomputation over a frame's whole candidate set, for frames
-// whose rerank was not certified.
-struct ExactArgs {
-  const int32_t *flag;
-  int32_t nq;
-  int32_t m;
-  int32_t dp;
-  const float *qp;
-  // stage 2: candidate rows are the frame's regions, in list order
-  const float *src32;
-  const int32_t *regions;  // nq x nr
-  int32_t nr;
-  const int32_t *cand_off; // nq x nr: first candidate position of each kept region
-  const int32_t *n_cand;   // nq
-  const int64_t *reg_start;
-  const int32_t *tie_of;   // row -> original index
-  int64_t *idx_out;
-  float *dist_out;
-  // stage 1: candidate rows are all regions 0..R-1 of src64 (empty skipped)
-  const double *src64;
-  int32_t R;
-  int32_t *reg_out;
-};
-hipError_t launch_exact(const ExactArgs &a, hipStream_t s);
+hipError_t launch_select_rerank(const SelRerankArgs &a, hipStream_t s);
 
 // Aggregation (Algorithm 2) per request.
 struct AggArgs {

@@ -13,13 +13,17 @@
 #include "hloc_device.h"
 #include "hloc_internal.h"
 
+#include <algorithm>
+
 namespace hloc {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_prep_queries(const float *__restrict__ q, int nq, int d,
                                                       int dp, float *__restrict__ qp,
-                                                      float *__restrict__ qn2) {
+                                                      float *__restrict__ qn2,
+                                                      int32_t *__restrict__ zero16) {
+  if (blockIdx.x == 0 && threadIdx.x < 16 && zero16) zero16[threadIdx.x] = 0;
   const int f = blockIdx.x * 4 + wave_id();
   const int lane = lane_id();
   if (f >= nq) return;
@@ -36,10 +40,10 @@ __global__ __launch_bounds__(256) void k_prep_queries(const float *__restrict__ 
 }
 
 hipError_t launch_prep_queries(const float *q, int32_t nq, int32_t d, int32_t dp, float *qp,
-                               float *qn2, hipStream_t s) {
+                               float *qn2, int32_t *zero16, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prep_queries, dim3((nq + 3) / 4), dim3(256), 0, s, q, nq, d, dp, qp, qn2);
-  return hipGetLastError();
+  return launch_kernel(k_prep_queries, dim3((nq + 3) / 4), dim3(256), 0, s, q, nq, d, dp, qp, qn2,
+                     zero16);
 }
 
 template <bool DENSE>
@@ -75,10 +79,9 @@ __global__ __launch_bounds__(256) void k_screen_f32(ScreenF32Args a) {
       }
     } else {
       const Item itm = a.items[it];
-      const int64_t rs = a.reg_start[itm.region], re = a.reg_start[itm.region + 1];
-      row_begin = rs + itm.chunk_row;
-      nrows = (int)min((int64_t)a.rows_per_item, re - row_begin);
-      gq = itm.gq;
+      row_begin = itm.row_begin;
+      nrows = itm.nrows_gq >> 16;
+      gq = itm.nrows_gq & 0xFFFF;
       if (tid < kGroup) {
         if (tid < gq) {
           const int2 e = a.rq[itm.q0 + tid];
@@ -141,6 +144,96 @@ __global__ __launch_bounds__(256) void k_screen_f32(ScreenF32Args a) {
   }
 }
 
+// Register variant for padded lengths up to 512: one item per block, one
+// 16-row block per wave, no LDS and no barriers. Each wave keeps the frame
+// operand of the MFMA in registers (lane l holds frame l % 16's k-slice); its
+// row loads, frame loads and norms go out together once the item's frame list
+// has been read.
+template <int NS, bool DENSE>
+__global__ __launch_bounds__(256) void k_screen_blk(ScreenF32Args a) {
+  constexpr int DP = NS * 16;
+  const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  int n_items, nchunks = 1;
+  if (DENSE) {
+    nchunks = (a.nrows + a.rows_per_item - 1) / a.rows_per_item;
+    n_items = nchunks * ((a.nq + kGroup - 1) / kGroup);
+  } else {
+    n_items = *a.n_items;
+  }
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    int row_begin, chunk_row, nrows, gq, fr = 0;
+    int64_t off = 0;
+    if (DENSE) {
+      const int c = it % nchunks, grp = it / nchunks;
+      row_begin = c * a.rows_per_item;
+      chunk_row = row_begin;
+      nrows = min(a.rows_per_item, a.nrows - row_begin);
+      gq = min(kGroup, a.nq - grp * kGroup);
+      fr = grp * kGroup + i;
+      off = (int64_t)fr * a.cap + chunk_row;
+    } else {
+      const Item *itm = a.items + it;
+      row_begin = itm->row_begin;
+      chunk_row = itm->chunk_row;
+      const int ng = itm->nrows_gq;
+      nrows = ng >> 16;
+      gq = ng & 0xFFFF;
+      if (i < gq) {
+        const int2 e = a.rq[itm->q0 + i];
+        fr = e.x;
+        off = (int64_t)e.x * a.cap + e.y + chunk_row;
+      }
+    }
+    if (i >= gq) fr = 0;
+    const int nrb = (nrows + 15) >> 4;
+    for (int rb = w; rb < nrb; rb += nw) {
+      const int rl = min(rb * 16 + i, nrows - 1);
+      const float4 *rp =
+          reinterpret_cast<const float4 *>(a.rows + (int64_t)(row_begin + rl) * DP) + g;
+      const float4 *qp = reinterpret_cast<const float4 *>(a.qp + (int64_t)fr * DP) + g;
+      float4 av[NS], bv[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) av[s] = rp[4 * s];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
+      const float qn = a.qn2[fr];
+      v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].x, bv[s].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].y, bv[s].y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].z, bv[s].z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].w, bv[s].w, acc, 0, 0, 0);
+      }
+      // lane l holds dot(row 4*(l/16)+r of the block, frame l%16); columns of
+      // absent frames (i >= gq) hold frame 0's values and are not stored
+      if (i < gq) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rb * 16 + 4 * g + r;
+          if (row < nrows) {
+            const int grow = row_begin + row;
+            const float rn = a.row_n2[grow];
+            uint64_t key = kKeyNone;
+            if (!__builtin_isinf(rn)) {
+              float dd = (qn + rn) - 2.f * acc[r];
+              dd = dd > 0.f ? dd : 0.f;
+              key = dist_key(dd, (uint32_t)grow);
+            }
+            a.cand[off + row] = key;
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int NS, bool DENSE>
+hipError_t launch_blk_t(const ScreenF32Args &a, int32_t grid, hipStream_t s) {
+  return launch_kernel(k_screen_blk<NS, DENSE>, dim3(grid), dim3(256), 0, s, a);
+}
+
 template <bool DENSE>
 hipError_t launch_screen_t(const ScreenF32Args &a, int32_t grid, hipStream_t s) {
   const size_t lds = (size_t)kGroup * (a.dp + 4) * sizeof(float);
@@ -154,13 +247,35 @@ hipError_t launch_screen_t(const ScreenF32Args &a, int32_t grid, hipStream_t s) 
     if (e != hipSuccess) return e;
     attr_dev = dev;
   }
-  hipLaunchKernelGGL(k_screen_f32<DENSE>, dim3(grid), dim3(256), lds, s, a);
-  return hipGetLastError();
+  return launch_kernel(k_screen_f32<DENSE>, dim3(grid), dim3(256), lds, s, a);
 }
 
 hipError_t launch_screen_f32(const ScreenF32Args &a, int32_t grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
+  if (a.rows_per_item % 16 == 0) {
+    switch (a.dp) {
+#define HLOC_WAVE_CASE(DPV)                                     \
+  case DPV:                                                    \
+    return a.dense ? launch_blk_t<DPV / 16, true>(a, grid, s) \
+                   : launch_blk_t<DPV / 16, false>(a, grid, s);
+      HLOC_WAVE_CASE(32)
+      HLOC_WAVE_CASE(64)
+      HLOC_WAVE_CASE(128)
+      HLOC_WAVE_CASE(256)
+      HLOC_WAVE_CASE(512)
+#undef HLOC_WAVE_CASE
+      default:
+        break;
+    }
+  }
   return a.dense ? launch_screen_t<true>(a, grid, s) : launch_screen_t<false>(a, grid, s);
+}
+
+// Number of blocks that covers `items` work items (one per block), up to
+// `max_blocks`; the kernels loop over the rest.
+int32_t screen_grid(int64_t items, int32_t dp, int32_t max_blocks) {
+  (void)dp;
+  return (int32_t)std::max<int64_t>(1, std::min<int64_t>(items, max_blocks));
 }
 
 }  // namespace hloc

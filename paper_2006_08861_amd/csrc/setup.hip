@@ -20,9 +20,8 @@ __global__ void k_gather_rows(const float *__restrict__ src, const int32_t *__re
 hipError_t launch_gather_rows(const float *src, const int32_t *src_row, int64_t n, int32_t d,
                               int32_t src_stride, float *dst, int32_t dp, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, src, src_row,
+  return launch_kernel(k_gather_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, src, src_row,
                      n, d, src_stride, dst, dp);
-  return hipGetLastError();
 }
 
 // Squared norm of each row summed in FP64, stored rounded to fp32; the
@@ -44,9 +43,8 @@ __global__ void k_row_norms(const float *__restrict__ rows, int64_t n, int dp, f
 hipError_t launch_row_norms(const float *rows, int64_t n, int32_t dp, float *n2,
                             float *max_norm, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_row_norms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, rows, n, dp, n2,
+  return launch_kernel(k_row_norms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, rows, n, dp, n2,
                      max_norm);
-  return hipGetLastError();
 }
 
 // Mean of each region's rows: one block per region, threads over columns,
@@ -67,8 +65,7 @@ __global__ void k_region_means(const float *__restrict__ rows,
 hipError_t launch_region_means(const float *rows, const int64_t *reg_start, int32_t R,
                                int32_t dp, double *mean64, hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_region_means, dim3(R), dim3(256), 0, s, rows, reg_start, R, dp, mean64);
-  return hipGetLastError();
+  return launch_kernel(k_region_means, dim3(R), dim3(256), 0, s, rows, reg_start, R, dp, mean64);
 }
 
 // fp32 copy and FP64 squared norm (stored as fp32) of each representative;
@@ -100,9 +97,8 @@ hipError_t launch_rep_finish(const double *rep64, const int64_t *reg_start, int3
                              int32_t dp, float *rep32, float *rep_n2, float *max_norm,
                              hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rep_finish, dim3((R + 3) / 4), dim3(256), 0, s, rep64, reg_start, R, dp,
+  return launch_kernel(k_rep_finish, dim3((R + 3) / 4), dim3(256), 0, s, rep64, reg_start, R, dp,
                      rep32, rep_n2, max_norm);
-  return hipGetLastError();
 }
 
 __global__ void k_tiles(const double *__restrict__ xy, int64_t n, double cell,
@@ -116,9 +112,8 @@ __global__ void k_tiles(const double *__restrict__ xy, int64_t n, double cell,
 
 hipError_t launch_tiles(const double *xy, int64_t n, double cell, int2 *tile, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tiles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xy, n, cell,
+  return launch_kernel(k_tiles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xy, n, cell,
                      tile);
-  return hipGetLastError();
 }
 
 }  // namespace hloc

@@ -211,7 +211,7 @@ class HlocDB:
                 "candidates")
         return dict(zip(keys, list(out)))
 
-    PHASES = ("prep", "coarse", "sched", "screen", "select", "rerank", "aggregate")
+    PHASES = ("prep", "coarse", "sched", "screen", "select", "aggregate")
 
     def profile(self, enable: bool = True):
         """Start (clearing) or stop the per-phase event record."""

@@ -203,6 +203,17 @@ def test_duplicate_rows_break_ties_by_index_and_fall_back(torch_cuda):
     st, info, out = check_all(torch_cuda, feats, xy, region_of, 7, q, 10, 7, name="duplicates")
     assert out["idx"][0].tolist() == sorted(dup.tolist())[:10]
     assert info["fine_fallbacks"] == 3
+    # 1,500 identical rows: the uncertain band exceeds the re-score capacity
+    # and every candidate of the frame is recomputed in FP64
+    feats2 = rng.standard_normal((2400, d)).astype(np.float32)
+    dup2 = rng.choice(2400, 1500, replace=False)
+    feats2[dup2] = feats2[dup2[0]]
+    region2 = (np.arange(2400) % 5).astype(np.int32)
+    xy2 = rng.uniform(0, 20, size=(2400, 2))
+    st, info, out = check_all(torch_cuda, feats2, xy2, region2, 5, feats2[dup2[:2]], 10, 5,
+                              name="duplicates beyond the band capacity")
+    assert out["idx"][0].tolist() == sorted(dup2.tolist())[:10]
+    assert info["fine_fallbacks"] == 2
 
 
 def test_identical_representatives_fall_back(torch_cuda):
