@@ -8,6 +8,11 @@ device memory. The default workload is the plain-FP32 shape: N = 200,000 rows
 of D = 256, 1,024 regions of uneven size, 256 single-frame queries per batch,
 8 regions per frame, k = 16.
 
+Throughput is taken over K back-to-back steps, the faster of two ways of
+issuing them: one stream with direct launches, or W captured batches (HIP
+graphs on W workspaces) replayed round-robin on W streams, whose outputs are
+checked bit for bit against the direct run.
+
 Prints one JSON line: throughput (frames/s) of K back-to-back steps, the
 host-to-host latency p50/p99 of single batches, the roofline of the fine screen
 (algorithmic bytes over its duration from HIP start/stop events in a second
@@ -79,6 +84,8 @@ def main():
     ap.add_argument("--nq", type=int, default=None, help="override the batch size")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--latency-reps", type=int, default=200)
+    ap.add_argument("--workspaces", type=int, default=2,
+                    help="batches in flight in the pipelined loop (one workspace and stream each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (reference for "
@@ -148,6 +155,32 @@ def main():
         step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    wall_eager = wall
+    eager_out = {k_: v.clone() for k_, v in dict(idx=idx, dist=dist, xy=xy, tile=tile,
+                                                 flags=flags).items()}
+    # pipelined: W workspaces, each holding the captured batch (a HIP graph)
+    # and its own outputs, replayed round-robin on W streams so that up to W
+    # batches overlap on the device
+    W = max(1, a.workspaces)
+    wss = [hloc.Workspace(db) for _ in range(W)]
+    outs = [hloc.Workspace.outputs(nq, nreq, k, dev) for _ in range(W)]
+    streams = [torch.cuda.Stream(dev) for _ in range(W)]
+    for ws, o in zip(wss, outs):
+        ws.capture(q, k, w.n_reg, offs, o)
+    torch.cuda.synchronize()
+    for i in range(a.warmup):
+        wss[i % W].replay(streams[i % W])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        wss[i % W].replay(streams[i % W])
+    torch.cuda.synchronize()
+    wall_pipe = time.perf_counter() - t0
+    for o in outs:
+        for key in eager_out:
+            if o[key].cpu().numpy().tobytes() != eager_out[key].cpu().numpy().tobytes():
+                raise RuntimeError(f"pipelined batch differs from the eager batch in {key}")
+    wall = min(wall_eager, wall_pipe)
     # the same K steps again with every kernel dispatched with HIP start/stop
     # events on the query stream: per-phase device time for the roofline (the
     # events add dispatch gaps, so this loop is not used for the throughput)
@@ -192,6 +225,7 @@ def main():
                    "regions": int(w.n_regions_total), "frames_per_step": int(nq),
                    "requests_per_step": int(nreq), "n_regions": int(w.n_reg), "k": int(k),
                    "screen": "fp32", "aggregation": list(w.agg)},
+        "pipeline": {"workspaces": W, "graphs": True, "value_from": "eager" if wall == wall_eager else "pipelined"},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "latency": f"host-to-host time of one batch, {len(lat)} batches run one at a time",
@@ -203,10 +237,14 @@ def main():
                      "avg_launch_ms": screen_ms},
         "phases_ms": {p: v[0] / max(v[1], 1) for p, v in phases.items()},
         "ms_per_step_event_timed": wall_prof * 1e3 / a.steps,
+        "modes": {"eager_one_stream_ms_per_step": wall_eager * 1e3 / a.steps,
+                  f"graphs_{W}_streams_ms_per_step": wall_pipe * 1e3 / a.steps},
         "fallbacks": {"coarse": info["coarse_fallbacks"], "fine": info["fine_fallbacks"]},
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)
+    for ws in wss:
+        ws.close()
     db.close()
 
 

@@ -20,7 +20,9 @@
  *   - Ownership: the caller owns every buffer it passes. The library copies
  *     database inputs during the call and keeps no caller pointer afterwards.
  *   - Threads: calls on one hloc_db must not overlap (the database owns one
- *     workspace). Distinct databases are independent.
+ *     default workspace). Batches on distinct workspaces (hloc_ws) of one
+ *     database may be in flight at the same time on different streams.
+ *     Distinct databases are independent.
  *   - Devices: a database lives on the HIP device that was current when it
  *     was built; later calls make that device current.
  */
@@ -34,6 +36,7 @@ extern "C" {
 #endif
 
 typedef struct hloc_db hloc_db; /* opaque; owns all of its device memory */
+typedef struct hloc_ws hloc_ws; /* opaque; scratch memory of one batch in flight */
 
 typedef enum {
   HLOC_OK = 0,
@@ -164,6 +167,44 @@ int hloc_query_info(hloc_db *db, int64_t *out, int32_t n);
 int hloc_last_regions(hloc_db *db, int32_t *out, int32_t *nq, int32_t *n_regions_eff);
 
 /*
+ * Workspaces: the scratch memory of one batch in flight (frame copies,
+ * candidate keys, schedule, counters). The calls above use the database's
+ * default workspace; a caller that wants several batches in flight at once
+ * (on several streams) gives each its own workspace. A workspace belongs to
+ * one database and must be freed before it.
+ *   hloc_ws_create   new workspace (EINVAL, ENOMEM, EDEVICE).
+ *   hloc_ws_free     waits for the device, then releases it (NULL ignored).
+ *   hloc_ws_reserve  as hloc_reserve, for this workspace.
+ *   hloc_ws_query_async  as hloc_query_batch_async, using this workspace.
+ *   hloc_ws_query_info   as hloc_query_info, for this workspace.
+ */
+int hloc_ws_create(hloc_db *db, hloc_ws **out);
+void hloc_ws_free(hloc_ws *ws);
+int hloc_ws_reserve(hloc_ws *ws, int32_t nq_max, int32_t nreq_max, int32_t k_max,
+                    int32_t n_regions_max);
+int hloc_ws_query_async(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int32_t n_regions,
+                        const int32_t *req_offsets, int32_t nreq, int32_t precision,
+                        int64_t *idx, float *dist, double *xy, int32_t *tile, int32_t *flags,
+                        void *stream);
+int hloc_ws_query_info(hloc_ws *ws, int64_t *out, int32_t n);
+
+/*
+ * Captured batches: hloc_ws_capture records the whole kernel sequence of one
+ * batch (arguments as hloc_query_batch_async, all pointers device memory)
+ * into a HIP graph held by the workspace, without running it; it sizes the
+ * workspace first, so nothing is allocated while recording.
+ * hloc_ws_replay(ws, stream) launches that graph on `stream`: the batch runs
+ * again on whatever the captured input buffers hold at that time, writing the
+ * captured output buffers. The buffers must stay valid while the graph is in
+ * use; capturing again replaces the graph. Errors: EINVAL, ESTATE (replay
+ * without capture), EUNSUPPORTED, ENOMEM, EDEVICE.
+ */
+int hloc_ws_capture(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int32_t n_regions,
+                    const int32_t *req_offsets, int32_t nreq, int32_t precision, int64_t *idx,
+                    float *dist, double *xy, int32_t *tile, int32_t *flags);
+int hloc_ws_replay(hloc_ws *ws, void *stream);
+
+/*
  * Device-time profile of the query path, measured with HIP events recorded on
  * the query's stream around each phase:
  *   HLOC_PHASE_PREP      query norms and padded copy
@@ -172,8 +213,9 @@ int hloc_last_regions(hloc_db *db, int32_t *out, int32_t *nq, int32_t *n_regions
  *   HLOC_PHASE_SCREEN    fine screen (one kernel launch)
  *   HLOC_PHASE_SELECT    per-frame select, FP64 rerank, certificate, exact fallback
  *   HLOC_PHASE_AGGREGATE aggregation of each request
- * hloc_profile(db, 1) clears the record and starts recording for later query
- * calls; hloc_profile(db, 0) stops. hloc_profile_read() waits for the device,
+ * (kernels of a phase dispatched with start/stop events). It covers the
+ * default workspace. hloc_profile(db, 1) clears the record and starts
+ * recording for later query calls; hloc_profile(db, 0) stops. hloc_profile_read() waits for the device,
  * writes for each of min(n, HLOC_NUM_PHASES) phases the summed milliseconds
  * and the number of calls recorded, and clears the record.
  * Errors: EINVAL, EDEVICE.

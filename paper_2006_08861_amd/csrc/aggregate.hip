@@ -143,21 +143,24 @@ __global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
   }
 }
 
+constexpr size_t kAggLds = 2 * kAggMax * sizeof(uint64_t) + (kAggMax + 1) * sizeof(int);
+
+// LDS limit of the aggregation kernel, set once per device.
+hipError_t prepare_aggregate_kernels() {
+  static int done_dev = -1;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || done_dev == dev) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_aggregate),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kAggLds);
+  if (e == hipSuccess) done_dev = dev;
+  return e;
+}
+
 hipError_t launch_aggregate(const AggArgs &a, hipStream_t s) {
   if (a.nreq <= 0) return hipSuccess;
   if (a.top_c < 1 || a.top_c > 64) return hipErrorInvalidValue;
-  const size_t lds = 2 * kAggMax * sizeof(uint64_t) + (kAggMax + 1) * sizeof(int);
-  static int attr_dev = -1;
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (attr_dev != dev) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_aggregate),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_dev = dev;
-  }
-  return launch_kernel(k_aggregate, dim3(a.nreq), dim3(256), lds, s, a);
+  return launch_kernel(k_aggregate, dim3(a.nreq), dim3(256), kAggLds, s, a);
 }
 
 }  // namespace hloc

@@ -1,6 +1,7 @@
 // Host side of the hloc C ABI (include/hloc.h): argument checks, device
-// layout of the database, the per-database workspace and the sequence of
-// kernels that localizes a batch.
+// layout of the database, workspaces (the scratch memory of one batch in
+// flight) and the sequence of kernels that localizes a batch, launched
+// directly or replayed from a captured hipGraph.
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -39,9 +40,9 @@ int fail(int code, const char *fmt, ...) {
     if (e_ != hipSuccess) return fail(HLOC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-#define CHK(expr)            \
-  do {                       \
-    int rc_ = (expr);        \
+#define CHK(expr)                   \
+  do {                              \
+    int rc_ = (expr);               \
     if (rc_ != HLOC_OK) return rc_; \
   } while (0)
 
@@ -73,13 +74,34 @@ T *as(WsBuf &b) {
   return reinterpret_cast<T *>(b.p);
 }
 
+struct ProfRec {
+  int phase;
+  hipEvent_t a, b;
+};
+
 }  // namespace
+
+// Scratch memory, counters, profile record and captured graph of one batch in
+// flight. Batches on distinct workspaces may overlap on the device.
+struct hloc_ws {
+  hloc_db *db = nullptr;
+  hipStream_t stream = nullptr;  // own stream (graph capture, host-pointer calls)
+  WsBuf qp, qn2, cand1, regions, rcount, rfill, rq_off, item_off, cand_off, n_cand, misc, rq,
+      items, cand2, agg_xy, agg_tile, agg_flags;
+  WsBuf s_q, s_off, s_idx, s_dist, s_xy, s_tile, s_flags;  // staging of host-pointer calls
+  int32_t last_nq = 0, last_nr = 0, last_kp = 0;
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<ProfRec> prof;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 struct hloc_db {
   int device = 0;
   int num_cu = 256;
   hipStream_t stream = nullptr;
-  hipStream_t last_stream = nullptr;
   int64_t n = 0;
   int32_t d = 0, dp = 0;
   float *rows = nullptr;      // n x dp fp32, region-contiguous once regions are set
@@ -104,21 +126,8 @@ struct hloc_db {
   float *rep_n2 = nullptr;
   double cell = 0.5, radius = 0.0;
   int32_t top_c = 1, rho = 0, pct = 0;
-  // workspace
-  WsBuf qp, qn2, cand1, regions, rcount, rfill, rq_off, item_off, cand_off, n_cand, misc, rq,
-      items, cand2, agg_xy, agg_tile, agg_flags;
-  WsBuf s_q, s_off, s_idx, s_dist, s_xy, s_tile, s_flags;
-  // last query
-  int32_t last_nq = 0, last_nr = 0, last_kp = 0;
-  // profiling: phase boundaries recorded as HIP events on the query stream
-  bool prof_on = false;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  struct ProfRec {
-    int phase;
-    hipEvent_t a, b;
-  };
-  std::vector<ProfRec> prof;
+  hloc_ws *ws0 = nullptr;  // workspace of the calls that take no workspace
+  int32_t user_ws = 0;     // workspaces created by the caller and not yet freed
 };
 
 namespace {
@@ -204,83 +213,82 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
   return HLOC_OK;
 }
 
-int ensure_workspace(hloc_db *db, const Plan &p, bool agg_internal) {
+int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal) {
+  const hloc_db *db = ws->db;
   const int64_t nq = std::max(p.nq, 1), nr = std::max(p.nr, 1);
-  CHK(ensure(db->qp, (size_t)nq * db->dp * sizeof(float)));
-  CHK(ensure(db->qn2, (size_t)nq * sizeof(float)));
-  if (!p.exhaustive) {
-    CHK(ensure(db->cand1, (size_t)nq * db->R * sizeof(uint64_t)));
-  }
-  CHK(ensure(db->regions, (size_t)nq * nr * sizeof(int32_t)));
-  CHK(ensure(db->rcount, (size_t)db->R * sizeof(int32_t)));
-  CHK(ensure(db->rfill, (size_t)db->R * sizeof(int32_t)));
-  CHK(ensure(db->rq_off, (size_t)db->R * sizeof(int32_t)));
-  CHK(ensure(db->item_off, (size_t)db->R * sizeof(int32_t)));
-  CHK(ensure(db->cand_off, (size_t)nq * nr * sizeof(int32_t)));
-  CHK(ensure(db->n_cand, (size_t)nq * sizeof(int32_t)));
-  CHK(ensure(db->misc, 16 * sizeof(int32_t)));
-  CHK(ensure(db->rq, (size_t)nq * nr * sizeof(int2)));
-  CHK(ensure(db->items, (size_t)std::max<int64_t>(p.items_bound, 1) * sizeof(Item)));
-  CHK(ensure(db->cand2, (size_t)nq * std::max<int64_t>(p.cap2, 1) * sizeof(uint64_t)));
+  CHK(ensure(ws->qp, (size_t)nq * db->dp * sizeof(float)));
+  CHK(ensure(ws->qn2, (size_t)nq * sizeof(float)));
+  if (!p.exhaustive) CHK(ensure(ws->cand1, (size_t)nq * db->R * sizeof(uint64_t)));
+  CHK(ensure(ws->regions, (size_t)nq * nr * sizeof(int32_t)));
+  CHK(ensure(ws->rcount, (size_t)db->R * sizeof(int32_t)));
+  CHK(ensure(ws->rfill, (size_t)db->R * sizeof(int32_t)));
+  CHK(ensure(ws->rq_off, (size_t)db->R * sizeof(int32_t)));
+  CHK(ensure(ws->item_off, (size_t)db->R * sizeof(int32_t)));
+  CHK(ensure(ws->cand_off, (size_t)nq * nr * sizeof(int32_t)));
+  CHK(ensure(ws->n_cand, (size_t)nq * sizeof(int32_t)));
+  CHK(ensure(ws->misc, 16 * sizeof(int32_t)));
+  CHK(ensure(ws->rq, (size_t)nq * nr * sizeof(int2)));
+  CHK(ensure(ws->items, (size_t)std::max<int64_t>(p.items_bound, 1) * sizeof(Item)));
+  CHK(ensure(ws->cand2, (size_t)nq * std::max<int64_t>(p.cap2, 1) * sizeof(uint64_t)));
   if (agg_internal) {
     const int64_t nreq = std::max(p.nreq, 1);
-    CHK(ensure(db->agg_xy, (size_t)nreq * 2 * sizeof(double)));
-    CHK(ensure(db->agg_tile, (size_t)nreq * 2 * sizeof(int32_t)));
-    CHK(ensure(db->agg_flags, (size_t)nreq * sizeof(int32_t)));
+    CHK(ensure(ws->agg_xy, (size_t)nreq * 2 * sizeof(double)));
+    CHK(ensure(ws->agg_tile, (size_t)nreq * 2 * sizeof(int32_t)));
+    CHK(ensure(ws->agg_flags, (size_t)nreq * sizeof(int32_t)));
   }
   return HLOC_OK;
 }
 
-hipEvent_t take_event(hloc_db *db) {
-  if (db->ev_used == db->ev_pool.size()) {
+hipEvent_t take_event(hloc_ws *ws) {
+  if (ws->ev_used == ws->ev_pool.size()) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    db->ev_pool.push_back(e);
+    ws->ev_pool.push_back(e);
   }
-  return db->ev_pool[db->ev_used++];
+  return ws->ev_pool[ws->ev_used++];
 }
 
 // Times consecutive phases of a query while profiling is on: begin(p) closes
 // the open phase and routes the next kernel launches through event-timed
 // dispatches (see launch_kernel); the destructor closes the last phase.
 struct Phaser {
-  hloc_db *db;
+  hloc_ws *ws;
   int phase = -1;
   PhaseEvents pe;
-  explicit Phaser(hloc_db *d) : db(d) {}
+  explicit Phaser(hloc_ws *w) : ws(w) {}
   void end() {
     if (phase >= 0 && pe.launches > 0 && pe.start && pe.stop)
-      db->prof.push_back({phase, pe.start, pe.stop});
+      ws->prof.push_back({phase, pe.start, pe.stop});
     phase = -1;
     g_phase = nullptr;
   }
   void begin(int p) {
     end();
-    if (!db->prof_on) return;
+    if (!ws->prof_on) return;
     phase = p;
-    pe = PhaseEvents{take_event(db), take_event(db), 0};
+    pe = PhaseEvents{take_event(ws), take_event(ws), 0};
     g_phase = &pe;
   }
   ~Phaser() { end(); }
 };
 
-int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req_offsets,
+int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req_offsets,
                   int64_t *idx, float *dist, double *xy, int32_t *tile, int32_t *flags,
                   hipStream_t s) {
+  const hloc_db *db = ws->db;
   const bool want_agg = xy || tile || flags;
-  CHK(ensure_workspace(db, p, want_agg && !(xy && tile && flags)));
-  db->last_stream = s;
-  db->last_nq = p.nq;
-  db->last_nr = p.nr;
-  db->last_kp = p.kp;
-  int32_t *misc = as<int32_t>(db->misc);
+  CHK(ensure_workspace(ws, p, want_agg && !(xy && tile && flags)));
+  ws->last_nq = p.nq;
+  ws->last_nr = p.nr;
+  ws->last_kp = p.kp;
+  int32_t *misc = as<int32_t>(ws->misc);
   if (p.nq == 0) {
     HIPCHK(launch_fill_i32(misc, 16, 0, s));
     return HLOC_OK;
   }
-  float *qp = as<float>(db->qp), *qn2 = as<float>(db->qn2);
-  int32_t *regions = as<int32_t>(db->regions);
-  Phaser ph(db);
+  float *qp = as<float>(ws->qp), *qn2 = as<float>(ws->qn2);
+  int32_t *regions = as<int32_t>(ws->regions);
+  Phaser ph(ws);
   ph.begin(HLOC_PHASE_PREP);
   HIPCHK(launch_prep_queries(q, p.nq, db->d, db->dp, qp, qn2, misc, s));
   ph.begin(HLOC_PHASE_COARSE);
@@ -292,7 +300,7 @@ int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req
     sa.dp = db->dp;
     sa.qp = qp;
     sa.qn2 = qn2;
-    sa.cand = as<uint64_t>(db->cand1);
+    sa.cand = as<uint64_t>(ws->cand1);
     sa.cap = db->R;
     sa.rows_per_item = kRowsCoarse;
     sa.dense = 1;
@@ -300,7 +308,7 @@ int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req
     sa.nq = p.nq;
     HIPCHK(launch_screen_f32(sa, p.grid1, s));
     SelRerankArgs ra{};
-    ra.cand = as<uint64_t>(db->cand1);
+    ra.cand = as<uint64_t>(ws->cand1);
     ra.cap = db->R;
     ra.n_fixed = db->R;
     ra.L = p.L1;
@@ -319,11 +327,11 @@ int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req
     HIPCHK(launch_broadcast_ids(db->nonempty_ids, p.nr, p.nq, regions, s));
   }
   ph.begin(HLOC_PHASE_SCHED);
-  int32_t *cand_off = as<int32_t>(db->cand_off), *n_cand = as<int32_t>(db->n_cand);
+  int32_t *cand_off = as<int32_t>(ws->cand_off), *n_cand = as<int32_t>(ws->n_cand);
   HIPCHK(launch_sched(regions, p.nq, p.nr, db->R, db->reg_start, kRowsFine,
-                      as<int32_t>(db->rcount), as<int32_t>(db->rfill), as<int32_t>(db->rq_off),
-                      as<int32_t>(db->item_off), cand_off, n_cand, misc + 0, as<int2>(db->rq),
-                      as<Item>(db->items), s));
+                      as<int32_t>(ws->rcount), as<int32_t>(ws->rfill), as<int32_t>(ws->rq_off),
+                      as<int32_t>(ws->item_off), cand_off, n_cand, misc + 0, as<int2>(ws->rq),
+                      as<Item>(ws->items), s));
   ph.begin(HLOC_PHASE_SCREEN);
   ScreenF32Args sb{};
   sb.rows = db->rows;
@@ -331,18 +339,18 @@ int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req
   sb.dp = db->dp;
   sb.qp = qp;
   sb.qn2 = qn2;
-  sb.cand = as<uint64_t>(db->cand2);
+  sb.cand = as<uint64_t>(ws->cand2);
   sb.cap = p.cap2;
   sb.rows_per_item = kRowsFine;
   sb.dense = 0;
-  sb.items = as<Item>(db->items);
+  sb.items = as<Item>(ws->items);
   sb.n_items = misc + 0;
-  sb.rq = as<int2>(db->rq);
+  sb.rq = as<int2>(ws->rq);
   sb.reg_start = db->reg_start;
   HIPCHK(launch_screen_f32(sb, p.grid2, s));
   ph.begin(HLOC_PHASE_SELECT);
   SelRerankArgs rb{};
-  rb.cand = as<uint64_t>(db->cand2);
+  rb.cand = as<uint64_t>(ws->cand2);
   rb.cap = p.cap2;
   rb.n_cand = n_cand;
   rb.L = p.kp;
@@ -373,9 +381,9 @@ int enqueue_query(hloc_db *db, const Plan &p, const float *q, const int32_t *req
     ag.top_c = db->top_c;
     ag.rho = db->rho;
     ag.toler_pct = db->pct;
-    ag.xy = xy ? xy : as<double>(db->agg_xy);
-    ag.tile = tile ? tile : as<int32_t>(db->agg_tile);
-    ag.flags = flags ? flags : as<int32_t>(db->agg_flags);
+    ag.xy = xy ? xy : as<double>(ws->agg_xy);
+    ag.tile = tile ? tile : as<int32_t>(ws->agg_tile);
+    ag.flags = flags ? flags : as<int32_t>(ws->agg_flags);
     ph.begin(HLOC_PHASE_AGGREGATE);
     HIPCHK(launch_aggregate(ag, s));
   }
@@ -398,14 +406,59 @@ int check_query_args(const hloc_db *db, const float *q, int32_t nq, const int32_
   return HLOC_OK;
 }
 
-void free_all(hloc_db *db) {
-  WsBuf *bufs[] = {&db->qp,     &db->qn2,      &db->cand1,    &db->regions,
-                   &db->rcount,   &db->rfill,   &db->rq_off,
-                   &db->item_off, &db->cand_off, &db->n_cand, &db->misc,    &db->rq,
-                   &db->items,  &db->cand2,    &db->agg_xy,  &db->agg_tile,
-                   &db->agg_flags, &db->s_q,   &db->s_off,    &db->s_idx,   &db->s_dist,
-                   &db->s_xy,   &db->s_tile,   &db->s_flags};
+int check_host_offsets(const int32_t *req_offsets, int32_t nq, int32_t nreq, int32_t k) {
+  if (req_offsets) {
+    if (req_offsets[0] != 0 || req_offsets[nreq] != nq)
+      return fail(HLOC_EINVAL, "req_offsets must run from 0 to nq");
+    for (int32_t i = 0; i < nreq; ++i) {
+      if (req_offsets[i + 1] < req_offsets[i])
+        return fail(HLOC_EINVAL, "req_offsets decreases at %d", i);
+      if ((int64_t)(req_offsets[i + 1] - req_offsets[i]) * k > HLOC_MAX_REQUEST_CANDIDATES)
+        return fail(HLOC_EINVAL, "request %d has more than %d candidates", i,
+                    HLOC_MAX_REQUEST_CANDIDATES);
+    }
+  } else if ((int64_t)k > HLOC_MAX_REQUEST_CANDIDATES) {
+    return fail(HLOC_EINVAL, "k is above the request candidate limit");
+  }
+  return HLOC_OK;
+}
+
+void drop_graph(hloc_ws *ws) {
+  if (ws->exec) (void)hipGraphExecDestroy(ws->exec);
+  if (ws->graph) (void)hipGraphDestroy(ws->graph);
+  ws->exec = nullptr;
+  ws->graph = nullptr;
+}
+
+void free_ws(hloc_ws *ws) {
+  if (!ws) return;
+  drop_graph(ws);
+  WsBuf *bufs[] = {&ws->qp,       &ws->qn2,      &ws->cand1,    &ws->regions, &ws->rcount,
+                   &ws->rfill,    &ws->rq_off,   &ws->item_off, &ws->cand_off, &ws->n_cand,
+                   &ws->misc,     &ws->rq,       &ws->items,    &ws->cand2,   &ws->agg_xy,
+                   &ws->agg_tile, &ws->agg_flags, &ws->s_q,     &ws->s_off,   &ws->s_idx,
+                   &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags};
   for (WsBuf *b : bufs) free_buf(*b);
+  for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
+  if (ws->stream) (void)hipStreamDestroy(ws->stream);
+  delete ws;
+}
+
+int new_ws(hloc_db *db, hloc_ws **out) {
+  hloc_ws *ws = new (std::nothrow) hloc_ws();
+  if (!ws) return fail(HLOC_ENOMEM, "host allocation failed");
+  ws->db = db;
+  if (hipStreamCreateWithFlags(&ws->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete ws;
+    return fail(HLOC_EDEVICE, "hipStreamCreateWithFlags failed");
+  }
+  *out = ws;
+  return HLOC_OK;
+}
+
+void free_db_data(hloc_db *db) {
+  free_ws(db->ws0);
+  db->ws0 = nullptr;
   dev_free(db->rows);
   dev_free(db->row_n2);
   dev_free(db->perm);
@@ -417,10 +470,6 @@ void free_all(hloc_db *db) {
   dev_free(db->rep64);
   dev_free(db->rep32);
   dev_free(db->rep_n2);
-  for (hipEvent_t e : db->ev_pool) (void)hipEventDestroy(e);
-  db->ev_pool.clear();
-  db->ev_used = 0;
-  db->prof.clear();
   if (db->stream) (void)hipStreamDestroy(db->stream);
   db->stream = nullptr;
 }
@@ -428,6 +477,35 @@ void free_all(hloc_db *db) {
 int compute_tiles(hloc_db *db) {
   HIPCHK(launch_tiles(db->xy, db->n, db->cell, db->tiles, db->stream));
   HIPCHK(hipStreamSynchronize(db->stream));
+  return HLOC_OK;
+}
+
+int query_async(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int32_t n_regions,
+                const int32_t *req_offsets, int32_t nreq, int32_t precision, int64_t *idx,
+                float *dist, double *xy, int32_t *tile, int32_t *flags, hipStream_t s) {
+  hloc_db *db = ws->db;
+  CHK(check_query_args(db, q, nq, req_offsets, nreq, precision, idx, dist));
+  Plan p;
+  CHK(make_plan(db, nq, k, n_regions, nreq, &p));
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  return enqueue_query(ws, p, q, req_offsets, idx, dist, xy, tile, flags, s);
+}
+
+int info_of(hloc_ws *ws, int64_t *out, int32_t n) {
+  DeviceGuard g(ws->db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  HIPCHK(hipDeviceSynchronize());
+  int32_t misc[16] = {0};
+  if (ws->misc.p) HIPCHK(hipMemcpy(misc, ws->misc.p, sizeof misc, hipMemcpyDeviceToHost));
+  int64_t total = 0;
+  if (ws->last_nq > 0 && ws->n_cand.p) {
+    std::vector<int32_t> nc(ws->last_nq);
+    HIPCHK(hipMemcpy(nc.data(), ws->n_cand.p, nc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int32_t v : nc) total += v;
+  }
+  const int64_t vals[6] = {misc[0], misc[1], misc[2], misc[3], ws->last_kp, total};
+  for (int32_t i = 0; i < std::min(n, 6); ++i) out[i] = vals[i];
   return HLOC_OK;
 }
 
@@ -466,7 +544,7 @@ int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, ui
   db->dp = (d + 31) / 32 * 32;
   db->max_abs_coord = max_abs;
   auto bail = [&](int rc) {
-    free_all(db);
+    free_db_data(db);
     delete db;
     return rc;
   };
@@ -476,6 +554,9 @@ int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, ui
   if (hipStreamCreateWithFlags(&db->stream, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(HLOC_EDEVICE, "hipStreamCreateWithFlags failed"));
   int rc;
+  if ((rc = new_ws(db, &db->ws0))) return bail(rc);
+  hipError_t pe = prepare_kernels();
+  if (pe != hipSuccess) return bail(fail(HLOC_EDEVICE, "kernel set-up failed: %s", hipGetErrorString(pe)));
   if ((rc = dev_alloc(&db->rows, (size_t)n * db->dp)) || (rc = dev_alloc(&db->row_n2, (size_t)n)) ||
       (rc = dev_alloc(&db->perm, (size_t)n)) || (rc = dev_alloc(&db->xy, (size_t)n * 2)) ||
       (rc = dev_alloc(&db->tiles, (size_t)n)) || (rc = dev_alloc(&db->norm_max, 2)))
@@ -617,82 +698,144 @@ int hloc_set_aggregation(hloc_db *db, double cell_m, int32_t top_c, double radiu
   return compute_tiles(db);
 }
 
+int hloc_ws_create(hloc_db *db, hloc_ws **out) {
+  if (!out) return fail(HLOC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!db) return fail(HLOC_EINVAL, "db is NULL");
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  CHK(new_ws(db, out));
+  ++db->user_ws;
+  return HLOC_OK;
+}
+
+void hloc_ws_free(hloc_ws *ws) {
+  if (!ws) return;
+  DeviceGuard g(ws->db->device);
+  (void)hipDeviceSynchronize();
+  --ws->db->user_ws;
+  free_ws(ws);
+}
+
+int hloc_ws_reserve(hloc_ws *ws, int32_t nq_max, int32_t nreq_max, int32_t k_max,
+                    int32_t n_regions_max) {
+  if (!ws) return fail(HLOC_EINVAL, "ws is NULL");
+  if (nreq_max < 0) return fail(HLOC_EINVAL, "nreq_max must be >= 0");
+  Plan p;
+  CHK(make_plan(ws->db, nq_max, k_max, n_regions_max, nreq_max, &p));
+  DeviceGuard g(ws->db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  return ensure_workspace(ws, p, true);
+}
+
 int hloc_reserve(hloc_db *db, int32_t nq_max, int32_t nreq_max, int32_t k_max,
                  int32_t n_regions_max) {
   if (!db) return fail(HLOC_EINVAL, "db is NULL");
-  if (nreq_max < 0) return fail(HLOC_EINVAL, "nreq_max must be >= 0");
-  Plan p;
-  CHK(make_plan(db, nq_max, k_max, n_regions_max, nreq_max, &p));
-  DeviceGuard g(db->device);
-  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
-  CHK(ensure_workspace(db, p, true));
-  return HLOC_OK;
+  return hloc_ws_reserve(db->ws0, nq_max, nreq_max, k_max, n_regions_max);
+}
+
+int hloc_ws_query_async(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int32_t n_regions,
+                        const int32_t *req_offsets, int32_t nreq, int32_t precision,
+                        int64_t *idx, float *dist, double *xy, int32_t *tile, int32_t *flags,
+                        void *stream) {
+  if (!ws) return fail(HLOC_EINVAL, "ws is NULL");
+  return query_async(ws, q, nq, k, n_regions, req_offsets, nreq, precision, idx, dist, xy, tile,
+                     flags, reinterpret_cast<hipStream_t>(stream));
 }
 
 int hloc_query_batch_async(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t n_regions,
                            const int32_t *req_offsets, int32_t nreq, int32_t precision,
                            int64_t *idx, float *dist, double *xy, int32_t *tile, int32_t *flags,
                            void *stream) {
+  if (!db) return fail(HLOC_EINVAL, "db is NULL");
+  return query_async(db->ws0, q, nq, k, n_regions, req_offsets, nreq, precision, idx, dist, xy,
+                     tile, flags, reinterpret_cast<hipStream_t>(stream));
+}
+
+int hloc_ws_capture(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int32_t n_regions,
+                    const int32_t *req_offsets, int32_t nreq, int32_t precision, int64_t *idx,
+                    float *dist, double *xy, int32_t *tile, int32_t *flags) {
+  if (!ws) return fail(HLOC_EINVAL, "ws is NULL");
+  hloc_db *db = ws->db;
   CHK(check_query_args(db, q, nq, req_offsets, nreq, precision, idx, dist));
   Plan p;
   CHK(make_plan(db, nq, k, n_regions, nreq, &p));
   DeviceGuard g(db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
-  return enqueue_query(db, p, q, req_offsets, idx, dist, xy, tile, flags,
-                       reinterpret_cast<hipStream_t>(stream));
+  CHK(ensure_workspace(ws, p, true));  // no allocation may happen while capturing
+  HIPCHK(hipStreamSynchronize(ws->stream));
+  drop_graph(ws);
+  const bool prof = ws->prof_on;
+  ws->prof_on = false;
+  HIPCHK(hipStreamBeginCapture(ws->stream, hipStreamCaptureModeThreadLocal));
+  const int rc = enqueue_query(ws, p, q, req_offsets, idx, dist, xy, tile, flags, ws->stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(ws->stream, &graph);
+  ws->prof_on = prof;
+  if (rc != HLOC_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (ec != hipSuccess) return fail(HLOC_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+  const hipError_t ei = hipGraphInstantiate(&ws->exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    ws->exec = nullptr;
+    return fail(HLOC_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+  }
+  ws->graph = graph;
+  return HLOC_OK;
+}
+
+int hloc_ws_replay(hloc_ws *ws, void *stream) {
+  if (!ws) return fail(HLOC_EINVAL, "ws is NULL");
+  if (!ws->exec) return fail(HLOC_ESTATE, "no batch has been captured on this workspace");
+  DeviceGuard g(ws->db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  HIPCHK(hipGraphLaunch(ws->exec, reinterpret_cast<hipStream_t>(stream)));
+  return HLOC_OK;
 }
 
 int hloc_query_batch(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t n_regions,
                      const int32_t *req_offsets, int32_t nreq, int32_t precision, int64_t *idx,
                      float *dist, double *xy, int32_t *tile, int32_t *flags) {
   CHK(check_query_args(db, q, nq, req_offsets, nreq, precision, idx, dist));
-  if (req_offsets) {
-    if (req_offsets[0] != 0 || req_offsets[nreq] != nq)
-      return fail(HLOC_EINVAL, "req_offsets must run from 0 to nq");
-    for (int32_t i = 0; i < nreq; ++i) {
-      if (req_offsets[i + 1] < req_offsets[i])
-        return fail(HLOC_EINVAL, "req_offsets decreases at %d", i);
-      if ((int64_t)(req_offsets[i + 1] - req_offsets[i]) * k > HLOC_MAX_REQUEST_CANDIDATES)
-        return fail(HLOC_EINVAL, "request %d has more than %d candidates", i,
-                    HLOC_MAX_REQUEST_CANDIDATES);
-    }
-  } else if ((int64_t)k > HLOC_MAX_REQUEST_CANDIDATES) {
-    return fail(HLOC_EINVAL, "k is above the request candidate limit");
-  }
+  CHK(check_host_offsets(req_offsets, nq, nreq, k));
   Plan p;
   CHK(make_plan(db, nq, k, n_regions, nreq, &p));
   DeviceGuard g(db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  hloc_ws *ws = db->ws0;
   const bool want_agg = xy || tile || flags;
   const int64_t nqk = (int64_t)nq * k;
-  CHK(ensure(db->s_q, (size_t)std::max<int64_t>((int64_t)nq * db->d, 1) * sizeof(float)));
-  CHK(ensure(db->s_off, (size_t)(nreq + 1) * sizeof(int32_t)));
-  CHK(ensure(db->s_idx, (size_t)std::max<int64_t>(nqk, 1) * sizeof(int64_t)));
-  CHK(ensure(db->s_dist, (size_t)std::max<int64_t>(nqk, 1) * sizeof(float)));
+  CHK(ensure(ws->s_q, (size_t)std::max<int64_t>((int64_t)nq * db->d, 1) * sizeof(float)));
+  CHK(ensure(ws->s_off, (size_t)(nreq + 1) * sizeof(int32_t)));
+  CHK(ensure(ws->s_idx, (size_t)std::max<int64_t>(nqk, 1) * sizeof(int64_t)));
+  CHK(ensure(ws->s_dist, (size_t)std::max<int64_t>(nqk, 1) * sizeof(float)));
   if (want_agg) {
-    CHK(ensure(db->s_xy, (size_t)std::max(nreq, 1) * 2 * sizeof(double)));
-    CHK(ensure(db->s_tile, (size_t)std::max(nreq, 1) * 2 * sizeof(int32_t)));
-    CHK(ensure(db->s_flags, (size_t)std::max(nreq, 1) * sizeof(int32_t)));
+    CHK(ensure(ws->s_xy, (size_t)std::max(nreq, 1) * 2 * sizeof(double)));
+    CHK(ensure(ws->s_tile, (size_t)std::max(nreq, 1) * 2 * sizeof(int32_t)));
+    CHK(ensure(ws->s_flags, (size_t)std::max(nreq, 1) * sizeof(int32_t)));
   }
-  hipStream_t s = db->stream;
+  hipStream_t s = ws->stream;
   if (nq > 0)
-    HIPCHK(hipMemcpyAsync(db->s_q.p, q, (size_t)nq * db->d * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws->s_q.p, q, (size_t)nq * db->d * sizeof(float), hipMemcpyHostToDevice, s));
   if (req_offsets)
-    HIPCHK(hipMemcpyAsync(db->s_off.p, req_offsets, (size_t)(nreq + 1) * sizeof(int32_t),
+    HIPCHK(hipMemcpyAsync(ws->s_off.p, req_offsets, (size_t)(nreq + 1) * sizeof(int32_t),
                           hipMemcpyHostToDevice, s));
-  CHK(enqueue_query(db, p, as<float>(db->s_q), req_offsets ? as<int32_t>(db->s_off) : nullptr,
-                    as<int64_t>(db->s_idx), as<float>(db->s_dist),
-                    want_agg ? as<double>(db->s_xy) : nullptr,
-                    want_agg ? as<int32_t>(db->s_tile) : nullptr,
-                    want_agg ? as<int32_t>(db->s_flags) : nullptr, s));
+  CHK(enqueue_query(ws, p, as<float>(ws->s_q), req_offsets ? as<int32_t>(ws->s_off) : nullptr,
+                    as<int64_t>(ws->s_idx), as<float>(ws->s_dist),
+                    want_agg ? as<double>(ws->s_xy) : nullptr,
+                    want_agg ? as<int32_t>(ws->s_tile) : nullptr,
+                    want_agg ? as<int32_t>(ws->s_flags) : nullptr, s));
   if (nqk > 0) {
-    HIPCHK(hipMemcpyAsync(idx, db->s_idx.p, (size_t)nqk * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(dist, db->s_dist.p, (size_t)nqk * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(idx, ws->s_idx.p, (size_t)nqk * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(dist, ws->s_dist.p, (size_t)nqk * sizeof(float), hipMemcpyDeviceToHost, s));
   }
   if (want_agg && nreq > 0) {
-    if (xy) HIPCHK(hipMemcpyAsync(xy, db->s_xy.p, (size_t)nreq * 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (tile) HIPCHK(hipMemcpyAsync(tile, db->s_tile.p, (size_t)nreq * 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    if (flags) HIPCHK(hipMemcpyAsync(flags, db->s_flags.p, (size_t)nreq * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (xy) HIPCHK(hipMemcpyAsync(xy, ws->s_xy.p, (size_t)nreq * 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (tile) HIPCHK(hipMemcpyAsync(tile, ws->s_tile.p, (size_t)nreq * 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (flags) HIPCHK(hipMemcpyAsync(flags, ws->s_flags.p, (size_t)nreq * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   }
   HIPCHK(hipStreamSynchronize(s));
   return HLOC_OK;
@@ -700,32 +843,25 @@ int hloc_query_batch(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t
 
 int hloc_query_info(hloc_db *db, int64_t *out, int32_t n) {
   if (!db || !out || n < 0) return fail(HLOC_EINVAL, "db and out must be non-NULL, n >= 0");
-  DeviceGuard g(db->device);
-  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
-  HIPCHK(hipDeviceSynchronize());
-  int32_t misc[16] = {0};
-  if (db->misc.p) HIPCHK(hipMemcpy(misc, db->misc.p, sizeof misc, hipMemcpyDeviceToHost));
-  int64_t total = 0;
-  if (db->last_nq > 0 && db->n_cand.p) {
-    std::vector<int32_t> nc(db->last_nq);
-    HIPCHK(hipMemcpy(nc.data(), db->n_cand.p, nc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-    for (int32_t v : nc) total += v;
-  }
-  const int64_t vals[6] = {misc[0], misc[1], misc[2], misc[3], db->last_kp, total};
-  for (int32_t i = 0; i < std::min(n, 6); ++i) out[i] = vals[i];
-  return HLOC_OK;
+  return info_of(db->ws0, out, n);
+}
+
+int hloc_ws_query_info(hloc_ws *ws, int64_t *out, int32_t n) {
+  if (!ws || !out || n < 0) return fail(HLOC_EINVAL, "ws and out must be non-NULL, n >= 0");
+  return info_of(ws, out, n);
 }
 
 int hloc_last_regions(hloc_db *db, int32_t *out, int32_t *nq, int32_t *n_regions_eff) {
   if (!db || !nq || !n_regions_eff) return fail(HLOC_EINVAL, "db, nq and n_regions_eff must be non-NULL");
   if (!db->has_regions) return fail(HLOC_ESTATE, "no regions");
-  *nq = db->last_nq;
-  *n_regions_eff = db->last_nr;
-  if (!out || db->last_nq == 0) return HLOC_OK;
+  hloc_ws *ws = db->ws0;
+  *nq = ws->last_nq;
+  *n_regions_eff = ws->last_nr;
+  if (!out || ws->last_nq == 0) return HLOC_OK;
   DeviceGuard g(db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   HIPCHK(hipDeviceSynchronize());
-  HIPCHK(hipMemcpy(out, db->regions.p, (size_t)db->last_nq * db->last_nr * sizeof(int32_t),
+  HIPCHK(hipMemcpy(out, ws->regions.p, (size_t)ws->last_nq * ws->last_nr * sizeof(int32_t),
                    hipMemcpyDeviceToHost));
   return HLOC_OK;
 }
@@ -735,9 +871,9 @@ int hloc_profile(hloc_db *db, int32_t enable) {
   DeviceGuard g(db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   HIPCHK(hipDeviceSynchronize());
-  db->prof.clear();
-  db->ev_used = 0;
-  db->prof_on = enable != 0;
+  db->ws0->prof.clear();
+  db->ws0->ev_used = 0;
+  db->ws0->prof_on = enable != 0;
   return HLOC_OK;
 }
 
@@ -746,9 +882,10 @@ int hloc_profile_read(hloc_db *db, double *ms, int64_t *calls, int32_t n) {
   DeviceGuard g(db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   HIPCHK(hipDeviceSynchronize());
+  hloc_ws *ws = db->ws0;
   double acc[HLOC_NUM_PHASES] = {0};
   int64_t cnt[HLOC_NUM_PHASES] = {0};
-  for (const auto &r : db->prof) {
+  for (const auto &r : ws->prof) {
     float t = 0.f;
     HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
     acc[r.phase] += t;
@@ -758,8 +895,8 @@ int hloc_profile_read(hloc_db *db, double *ms, int64_t *calls, int32_t n) {
     ms[i] = acc[i];
     calls[i] = cnt[i];
   }
-  db->prof.clear();
-  db->ev_used = 0;
+  ws->prof.clear();
+  ws->ev_used = 0;
   return HLOC_OK;
 }
 
@@ -768,7 +905,7 @@ void hloc_free_db(hloc_db *db) {
   {
     DeviceGuard g(db->device);
     (void)hipDeviceSynchronize();
-    free_all(db);
+    free_db_data(db);
   }
   delete db;
 }

@@ -139,6 +139,18 @@ struct AggArgs {
 };
 hipError_t launch_aggregate(const AggArgs &a, hipStream_t s);
 
+// Kernel attributes (LDS limits) for the current device; called once when a
+// database is built so that no attribute is set while a graph is captured.
+hipError_t prepare_screen_kernels();
+hipError_t prepare_select_kernels();
+hipError_t prepare_aggregate_kernels();
+inline hipError_t prepare_kernels() {
+  hipError_t e = prepare_screen_kernels();
+  if (e == hipSuccess) e = prepare_select_kernels();
+  if (e == hipSuccess) e = prepare_aggregate_kernels();
+  return e;
+}
+
 // Database set-up.
 hipError_t launch_gather_rows(const float *src, const int32_t *src_row, int64_t n, int32_t d,
                               int32_t src_stride, float *dst, int32_t dp, hipStream_t s);

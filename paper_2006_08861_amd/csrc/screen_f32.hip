@@ -237,17 +237,22 @@ hipError_t launch_blk_t(const ScreenF32Args &a, int32_t grid, hipStream_t s) {
 template <bool DENSE>
 hipError_t launch_screen_t(const ScreenF32Args &a, int32_t grid, hipStream_t s) {
   const size_t lds = (size_t)kGroup * (a.dp + 4) * sizeof(float);
-  static int attr_dev = -1;
+  return launch_kernel(k_screen_f32<DENSE>, dim3(grid), dim3(256), lds, s, a);
+}
+
+// LDS limits above the 64 KB default, set once per device.
+hipError_t prepare_screen_kernels() {
+  static int done_dev = -1;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (attr_dev != dev) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_screen_f32<DENSE>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+  if (e != hipSuccess || done_dev == dev) return e;
+  for (const void *k : {reinterpret_cast<const void *>(&k_screen_f32<true>),
+                        reinterpret_cast<const void *>(&k_screen_f32<false>)}) {
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     if (e != hipSuccess) return e;
-    attr_dev = dev;
   }
-  return launch_kernel(k_screen_f32<DENSE>, dim3(grid), dim3(256), lds, s, a);
+  done_dev = dev;
+  return hipSuccess;
 }
 
 hipError_t launch_screen_f32(const ScreenF32Args &a, int32_t grid, hipStream_t s) {

@@ -489,20 +489,23 @@ __global__ __launch_bounds__(256) void k_select_rerank(SelRerankArgs a) {
   }
 }
 
+// LDS limit of the select kernel (key cache above 64 KB), set once per device.
+hipError_t prepare_select_kernels() {
+  static int done_dev = -1;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || done_dev == dev) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_select_rerank),
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(kKeyCache * sizeof(uint64_t)));
+  if (e == hipSuccess) done_dev = dev;
+  return e;
+}
+
 hipError_t launch_select_rerank(const SelRerankArgs &a, hipStream_t s) {
   if (a.nq <= 0) return hipSuccess;
   if (a.L > kMaxSurvivors || a.L < a.m || a.m > 256) return hipErrorInvalidValue;
   const size_t lds = (size_t)kKeyCache * sizeof(uint64_t);
-  static int attr_dev = -1;
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (attr_dev != dev) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_select_rerank),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_dev = dev;
-  }
   return launch_kernel(k_select_rerank, dim3(a.nq), dim3(256), lds, s, a);
 }
 

@@ -41,6 +41,15 @@ _SIGNATURES = {
     "hloc_reserve": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32]),
     "hloc_query_info": (ctypes.c_int, [_P, _P, _I32]),
     "hloc_last_regions": (ctypes.c_int, [_P, _P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "hloc_ws_create": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+    "hloc_ws_free": (None, [_P]),
+    "hloc_ws_reserve": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32]),
+    "hloc_ws_query_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _P, _P,
+                                           _P, _P, _P]),
+    "hloc_ws_query_info": (ctypes.c_int, [_P, _P, _I32]),
+    "hloc_ws_capture": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _P, _P, _P,
+                                       _P]),
+    "hloc_ws_replay": (ctypes.c_int, [_P, _P]),
     "hloc_profile": (ctypes.c_int, [_P, _I32]),
     "hloc_profile_read": (ctypes.c_int, [_P, _P, _P, _I32]),
     "hloc_free_db": (None, [_P]),
@@ -233,3 +242,77 @@ class HlocDB:
         if out.size:
             _check(lib.hloc_last_regions(self._h, _np_ptr(out), ctypes.byref(nq), ctypes.byref(nr)))
         return out
+
+
+_INFO_KEYS = ("items", "coarse_fallbacks", "fine_fallbacks", "max_candidates", "survivors",
+              "candidates")
+
+
+class Workspace:
+    """Scratch memory for one batch in flight on a database (hloc_ws). Several
+    workspaces let batches overlap on different streams; a workspace can also
+    hold one captured batch (a HIP graph) to replay."""
+
+    def __init__(self, db: HlocDB):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.hloc_ws_create(db._h, ctypes.byref(h)))
+        self._h = h
+        self.db = db
+        self._captured = None
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().hloc_ws_free(self._h)
+            self._h = ctypes.c_void_p()
+            self._captured = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reserve(self, nq_max: int, nreq_max: int, k_max: int, n_regions_max: int):
+        _check(load_library().hloc_ws_reserve(self._h, nq_max, nreq_max, k_max, n_regions_max))
+
+    @staticmethod
+    def outputs(nq: int, nreq: int, k: int, device):
+        """Device buffers for one batch's results."""
+        import torch
+        return dict(idx=torch.empty((nq, k), dtype=torch.int64, device=device),
+                    dist=torch.empty((nq, k), dtype=torch.float32, device=device),
+                    xy=torch.empty((nreq, 2), dtype=torch.float64, device=device),
+                    tile=torch.empty((nreq, 2), dtype=torch.int32, device=device),
+                    flags=torch.empty(nreq, dtype=torch.int32, device=device))
+
+    @staticmethod
+    def _args(q, k, n_regions, offs, out, precision):
+        p = ctypes.c_void_p
+        nq = q.shape[0]
+        nreq = nq if offs is None else offs.numel() - 1
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        return (p(q.data_ptr()), nq, k, n_regions, None if offs is None else p(offs.data_ptr()),
+                nreq, prec, p(out["idx"].data_ptr()), p(out["dist"].data_ptr()),
+                p(out["xy"].data_ptr()), p(out["tile"].data_ptr()), p(out["flags"].data_ptr()))
+
+    def query_async(self, q, k: int, n_regions: int, offs, out: dict, stream,
+                    precision="fp32"):
+        """Enqueue one batch (device tensors) on `stream` into `out`."""
+        _check(load_library().hloc_ws_query_async(
+            self._h, *self._args(q, k, n_regions, offs, out, precision),
+            ctypes.c_void_p(stream.cuda_stream)))
+
+    def capture(self, q, k: int, n_regions: int, offs, out: dict, precision="fp32"):
+        """Record one batch on these device buffers for replay()."""
+        _check(load_library().hloc_ws_capture(self._h,
+                                              *self._args(q, k, n_regions, offs, out, precision)))
+        self._captured = (q, offs, out)
+
+    def replay(self, stream):
+        _check(load_library().hloc_ws_replay(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def info(self) -> dict:
+        out = (ctypes.c_int64 * 6)()
+        _check(load_library().hloc_ws_query_info(self._h, out, 6))
+        return dict(zip(_INFO_KEYS, list(out)))

@@ -315,3 +315,63 @@ def test_aggregation_golden_on_device(torch_cuda, case):
     ix, iy = case["expect"]["tile"]
     assert out["xy"][0].tolist() == [(ix + 0.5) * cell, (iy + 0.5) * cell]
     db.close()
+
+
+# ------------------------------------------------------------- workspaces, graphs
+def _bitwise_equal(a, b):
+    for key in ("idx", "dist", "tile", "flags", "xy"):
+        x, y = a[key], b[key]
+        if hasattr(x, "cpu"):
+            x = x.cpu().numpy()
+        if hasattr(y, "cpu"):
+            y = y.cpu().numpy()
+        assert x.shape == y.shape, key
+        assert x.tobytes() == y.tobytes(), key
+
+
+def test_graph_replay_matches_eager(torch_cuda, fp32_shape):
+    # one captured batch replayed on changing inputs, with eager batches and
+    # synchronizations between the replays; every replay equals the eager run
+    torch = torch_cuda
+    w, db = fp32_shape
+    say("[case] captured batch replayed 4 times")
+    ws = hloc.Workspace(db)
+    nq = 96
+    q_buf = torch.from_numpy(w.q[:nq]).cuda()
+    out = hloc.Workspace.outputs(nq, nq, w.k, q_buf.device)
+    ws.capture(q_buf, w.k, w.n_reg, None, out)
+    s = torch.cuda.Stream()
+    rng = np.random.default_rng(21)
+    for rep in range(4):
+        sel = rng.choice(len(w.q), nq, replace=False)
+        q_buf.copy_(torch.from_numpy(w.q[sel]).cuda())
+        torch.cuda.synchronize()
+        ws.replay(s)
+        s.synchronize()
+        got = {k: v.clone() for k, v in out.items()}
+        eager = run_device(torch, db, w.q[sel], w.k, w.n_reg)
+        _bitwise_equal(got, eager)
+    ws.close()
+
+
+def test_concurrent_workspaces_match_alone(torch_cuda, fp32_shape):
+    # two batches in flight on two workspaces and two streams give the same
+    # bits as each batch run alone
+    torch = torch_cuda
+    w, db = fp32_shape
+    say("[case] two workspaces on two streams")
+    qa = torch.from_numpy(w.q[:128]).cuda()
+    qb = torch.from_numpy(w.q[128:]).cuda()
+    wa, wb = hloc.Workspace(db), hloc.Workspace(db)
+    oa = hloc.Workspace.outputs(128, 128, w.k, qa.device)
+    ob = hloc.Workspace.outputs(128, 128, w.k, qa.device)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        wa.query_async(qa, w.k, w.n_reg, None, oa, sa)
+        wb.query_async(qb, w.k, w.n_reg, None, ob, sb)
+    torch.cuda.synchronize()
+    _bitwise_equal(oa, run_device(torch, db, w.q[:128], w.k, w.n_reg))
+    _bitwise_equal(ob, run_device(torch, db, w.q[128:], w.k, w.n_reg))
+    wa.close()
+    wb.close()
