@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", type=int, default=1, help="index of workload.SHAPES")
     ap.add_argument("--nq", type=int, default=None, help="override the batch size")
+    ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32",
+                    help="fine-screen precision (the rerank is FP64 either way)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--workspaces", type=int, default=2,
@@ -114,7 +116,7 @@ def main():
     log(f"[bench] workload {w.name}: n={len(w.feats)} d={w.feats.shape[1]} "
         f"regions={w.n_regions_total} frames={len(w.q)} requests={len(w.req_offsets) - 1} "
         f"({time.perf_counter() - t0:.1f} s)")
-    db = hloc.HlocDB(w.feats, w.xy)
+    db = hloc.HlocDB(w.feats, w.xy, mirrors=hloc.MIRROR_BF16 if a.precision == "bf16" else 0)
     db.set_regions(w.region_of, w.n_regions_total)
     db.set_aggregation(*w.agg)
     nq, k, nreq = len(w.q), w.k, len(w.req_offsets) - 1
@@ -129,7 +131,8 @@ def main():
     stream = torch.cuda.current_stream(dev)
     lib = hloc.load_library()
     P = ctypes.c_void_p
-    args = (db._h, P(q.data_ptr()), nq, k, w.n_reg, P(offs.data_ptr()), nreq, hloc.FP32,
+    args = (db._h, P(q.data_ptr()), nq, k, w.n_reg, P(offs.data_ptr()), nreq,
+            hloc.PRECISIONS[a.precision],
             P(idx.data_ptr()), P(dist.data_ptr()), P(xy.data_ptr()), P(tile.data_ptr()),
             P(flags.data_ptr()), P(stream.cuda_stream))
 
@@ -146,7 +149,8 @@ def main():
     sizes = np.bincount(w.region_of, minlength=w.n_regions_total)
     unique_rows = int(sizes[np.unique(regions)].sum())
     d = w.feats.shape[1]
-    screen_bytes = unique_rows * (4 * d + 4) + info["candidates"] * 8 + nq * 4 * d
+    row_bytes = 2 * d if a.precision == "bf16" else 4 * d
+    screen_bytes = unique_rows * (row_bytes + 4) + info["candidates"] * 8 + nq * row_bytes
 
     # throughput: K back-to-back steps, nothing recorded between kernels
     torch.cuda.synchronize()
@@ -166,7 +170,7 @@ def main():
     outs = [hloc.Workspace.outputs(nq, nreq, k, dev) for _ in range(W)]
     streams = [torch.cuda.Stream(dev) for _ in range(W)]
     for ws, o in zip(wss, outs):
-        ws.capture(q, k, w.n_reg, offs, o)
+        ws.capture(q, k, w.n_reg, offs, o, precision=a.precision)
     torch.cuda.synchronize()
     for i in range(a.warmup):
         wss[i % W].replay(streams[i % W])
@@ -219,19 +223,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if a.precision == "fp32" else "bf16",
         "data": "synthetic",
         "config": {"workload": w.name, "n": int(len(w.feats)), "d": int(d),
                    "regions": int(w.n_regions_total), "frames_per_step": int(nq),
                    "requests_per_step": int(nreq), "n_regions": int(w.n_reg), "k": int(k),
-                   "screen": "fp32", "aggregation": list(w.agg)},
+                   "screen": a.precision, "rerank": "f64", "aggregation": list(w.agg)},
         "pipeline": {"workspaces": W, "graphs": True, "value_from": "eager" if wall == wall_eager else "pipelined"},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "latency": f"host-to-host time of one batch, {len(lat)} batches run one at a time",
         "recall_at_k": recall,
         "exact_lists": None if base is None else f"{exact}/{m}",
-        "roofline": {"bound": "hbm", "kernel": "k_screen_f32<false>", "achieved": achieved,
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_screen_bf16<NS,false>" if a.precision == "bf16" else "k_screen_blk<NS,false>",
+                     "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "bytes_per_launch": int(screen_bytes),
                      "avg_launch_ms": screen_ms},

@@ -47,8 +47,12 @@ typedef enum {
   HLOC_EUNSUPPORTED = -5 /* the requested screen precision is not available */
 } hloc_status;
 
-/* Screen precision of the fine (and coarse) screen. Whatever the screen, the
- * returned top-k is decided by an FP64 rerank of the survivors. */
+/* Precision of the fine screen (the coarse screen is fp32). Whatever the
+ * screen, the returned top-k is decided by an FP64 rerank of the survivors
+ * (k + 16 of them behind fp32, 4k behind bf16) with a certificate: rows the
+ * screen's error bound cannot exclude are re-scored too, so the result is the
+ * same for every precision. HLOC_BF16 needs a database built with
+ * HLOC_MIRROR_BF16; HLOC_FP8 is not available yet. */
 typedef enum { HLOC_FP32 = 0, HLOC_BF16 = 1, HLOC_FP8 = 2 } hloc_precision;
 
 /* Per-request flags written by the aggregation (bit set). */
@@ -57,6 +61,9 @@ enum {
   HLOC_FLAG_EMPTY = 2,          /* request had no candidate; position is NaN */
   HLOC_FLAG_BAD_REQUEST = 4     /* offsets not monotone / out of range, or too many candidates */
 };
+
+/* Low-precision copies of the rows kept beside the fp32 rows (build flags). */
+enum { HLOC_MIRROR_BF16 = 1 };
 
 /* Limits. */
 #define HLOC_MAX_DIM 1024            /* d */
@@ -71,9 +78,11 @@ enum {
  *   feats : host, n x d float32, row-major, every value finite.
  *   xy    : host, n x 2 float64 metres (x west->east, y south->north), finite.
  *   n     : 1 .. 2^31-1 rows;  d : 1 .. HLOC_MAX_DIM.
- *   mirrors: reserved for low-precision copies; pass 0.
+ *   mirrors: HLOC_MIRROR_* bits: HLOC_MIRROR_BF16 keeps a bf16 copy of the rows
+ *            (half the bytes) for the HLOC_BF16 screen; 0 for fp32 only.
  *   out   : receives the new handle (set to NULL on error).
- * Errors: EINVAL (sizes, NULL pointers, non-finite values), ENOMEM, EDEVICE.
+ * Errors: EINVAL (sizes, NULL pointers, non-finite values), EUNSUPPORTED
+ * (unknown mirror flag), ENOMEM, EDEVICE.
  * The database is not queryable until hloc_set_regions() succeeds.
  */
 int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, uint32_t mirrors,

@@ -87,7 +87,7 @@ struct hloc_ws {
   hloc_db *db = nullptr;
   hipStream_t stream = nullptr;  // own stream (graph capture, host-pointer calls)
   WsBuf qp, qn2, cand1, regions, rcount, rfill, rq_off, item_off, cand_off, n_cand, misc, rq,
-      items, cand2, agg_xy, agg_tile, agg_flags;
+      items, cand2, agg_xy, agg_tile, agg_flags, qp16, q_err, q_lon;
   WsBuf s_q, s_off, s_idx, s_dist, s_xy, s_tile, s_flags;  // staging of host-pointer calls
   int32_t last_nq = 0, last_nr = 0, last_kp = 0;
   bool prof_on = false;
@@ -109,8 +109,11 @@ struct hloc_db {
   int32_t *perm = nullptr;    // device row -> original index
   double *xy = nullptr;       // n x 2 by original index
   int2 *tiles = nullptr;      // n by original index
-  float *norm_max = nullptr;  // [0] rows, [1] representatives
+  float *norm_max = nullptr;  // [0] rows, [1] representatives, [2] bf16 error, [3] bf16 rows
   float h_row_max = 0.f, h_rep_max = 0.f;
+  uint32_t mirrors = 0;        // HLOC_MIRROR_* copies kept beside the fp32 rows
+  uint16_t *rows16 = nullptr;  // bf16 copy of rows
+  float h_bf16_err = 0.f, h_bf16_norm = 0.f;
   std::vector<int32_t> h_perm;
   double max_abs_coord = 0.0;
   bool has_regions = false;
@@ -170,15 +173,23 @@ void dev_free(T *&p) {
 }
 
 struct Plan {
-  int32_t nq, k, nr, L1, kp, nreq;
+  int32_t nq, k, nr, L1, kp, nreq, precision;
   bool exhaustive;
   int64_t cap2, items_bound;
   int32_t grid1, grid2;
 };
 
 int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32_t nreq,
-              Plan *pl) {
+              int32_t precision, Plan *pl) {
   if (!db->has_regions) return fail(HLOC_ESTATE, "hloc_set_regions has not been called");
+  if (precision == HLOC_BF16) {
+    if (!db->rows16)
+      return fail(HLOC_EUNSUPPORTED, "the bf16 screen needs a database built with HLOC_MIRROR_BF16");
+    if (!bf16_screen_supports(db->dp))
+      return fail(HLOC_EUNSUPPORTED, "the bf16 screen does not support padded length %d", db->dp);
+  } else if (precision != HLOC_FP32) {
+    return fail(HLOC_EUNSUPPORTED, "screen precision %d is not available in this build", precision);
+  }
   if (nq < 0) return fail(HLOC_EINVAL, "nq must be >= 0 (got %d)", nq);
   if (k < 1 || k > HLOC_MAX_K) return fail(HLOC_EINVAL, "k must be in 1..%d (got %d)", HLOC_MAX_K, k);
   if (n_regions < 1) return fail(HLOC_EINVAL, "n_regions must be >= 1 (got %d)", n_regions);
@@ -186,6 +197,7 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
   p.nq = nq;
   p.k = k;
   p.nreq = nreq;
+  p.precision = precision;
   p.nr = std::min(n_regions, db->R_nonempty);
   p.exhaustive = p.nr == db->R_nonempty;
   if (!p.exhaustive) {
@@ -196,7 +208,9 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
                   "n_regions >= %d to search every region",
                   n_regions, kMaxSurvivors - kRegionMargin, db->R_nonempty, db->R_nonempty);
   }
-  p.kp = std::min(k + kOversample, kMaxSurvivors);
+  // survivors re-scored in FP64: k + 16 behind the fp32 screen, 4k behind bf16
+  p.kp = std::min(precision == HLOC_FP32 ? k + kOversample : std::max(4 * k, k + kOversample),
+                  kMaxSurvivors);
   p.cap2 = db->h_desc_prefix[p.nr];
   const int64_t maxch = (db->max_region + kRowsFine - 1) / kRowsFine;
   const int64_t b1 = (int64_t)nq * p.nr * maxch;
@@ -230,6 +244,11 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal) {
   CHK(ensure(ws->rq, (size_t)nq * nr * sizeof(int2)));
   CHK(ensure(ws->items, (size_t)std::max<int64_t>(p.items_bound, 1) * sizeof(Item)));
   CHK(ensure(ws->cand2, (size_t)nq * std::max<int64_t>(p.cap2, 1) * sizeof(uint64_t)));
+  if (db->rows16) {
+    CHK(ensure(ws->qp16, (size_t)nq * db->dp * sizeof(uint16_t)));
+    CHK(ensure(ws->q_err, (size_t)nq * sizeof(float)));
+    CHK(ensure(ws->q_lon, (size_t)nq * sizeof(float)));
+  }
   if (agg_internal) {
     const int64_t nreq = std::max(p.nreq, 1);
     CHK(ensure(ws->agg_xy, (size_t)nreq * 2 * sizeof(double)));
@@ -290,11 +309,15 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   int32_t *regions = as<int32_t>(ws->regions);
   Phaser ph(ws);
   ph.begin(HLOC_PHASE_PREP);
-  HIPCHK(launch_prep_queries(q, p.nq, db->d, db->dp, qp, qn2, misc, s));
+  const bool bf16 = p.precision == HLOC_BF16;
+  uint16_t *qp16 = bf16 ? as<uint16_t>(ws->qp16) : nullptr;
+  HIPCHK(launch_prep_queries(q, p.nq, db->d, db->dp, qp, qn2, misc, qp16,
+                             bf16 ? as<float>(ws->q_err) : nullptr,
+                             bf16 ? as<float>(ws->q_lon) : nullptr, s));
   ph.begin(HLOC_PHASE_COARSE);
   const double coef = (db->dp + 16) * kUnit32 * 1.001;
   if (!p.exhaustive) {
-    ScreenF32Args sa{};
+    ScreenArgs sa{};
     sa.rows = db->rep32;
     sa.row_n2 = db->rep_n2;
     sa.dp = db->dp;
@@ -333,7 +356,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
                       as<int32_t>(ws->item_off), cand_off, n_cand, misc + 0, as<int2>(ws->rq),
                       as<Item>(ws->items), s));
   ph.begin(HLOC_PHASE_SCREEN);
-  ScreenF32Args sb{};
+  ScreenArgs sb{};
   sb.rows = db->rows;
   sb.row_n2 = db->row_n2;
   sb.dp = db->dp;
@@ -347,7 +370,13 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   sb.n_items = misc + 0;
   sb.rq = as<int2>(ws->rq);
   sb.reg_start = db->reg_start;
-  HIPCHK(launch_screen_f32(sb, p.grid2, s));
+  if (bf16) {
+    sb.rows16 = db->rows16;
+    sb.qp16 = qp16;
+    HIPCHK(launch_screen_bf16(sb, p.grid2, s));
+  } else {
+    HIPCHK(launch_screen_f32(sb, p.grid2, s));
+  }
   ph.begin(HLOC_PHASE_SELECT);
   SelRerankArgs rb{};
   rb.cand = as<uint64_t>(ws->cand2);
@@ -362,6 +391,16 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   rb.qn2 = qn2;
   rb.err_coef = coef;
   rb.max_norm = (double)db->h_row_max * (1.0 + 1e-6);
+  if (bf16) {
+    // the bf16 roundings enter the screen through q~.d~ - q.d =
+    // q~.(d~-d) + (q~-q).d~ - (q~-q).(d~-d), doubled by the -2 q.d term
+    rb.q_err = as<float>(ws->q_err);
+    rb.q_lon = as<float>(ws->q_lon);
+    rb.lo_dmax = (double)db->h_bf16_err * (1.0 + 1e-6);
+    rb.lo_nmax = (double)db->h_bf16_norm * (1.0 + 1e-6);
+    rb.lo_coef = 2.0 * (1.0 + 1e-6);
+    rb.err_coef = coef * 1.01;  // fp32 accumulation of bf16 products (|q~||d~| <= 1.004 |q||d|)
+  }
   rb.nq = p.nq;
   rb.idx_out = idx;
   rb.dist_out = dist;
@@ -393,12 +432,8 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
 int check_query_args(const hloc_db *db, const float *q, int32_t nq, const int32_t *req_offsets,
                      int32_t nreq, int32_t precision, const int64_t *idx, const float *dist) {
   if (!db) return fail(HLOC_EINVAL, "db is NULL");
-  if (precision != HLOC_FP32) {
-    if (precision == HLOC_BF16 || precision == HLOC_FP8)
-      return fail(HLOC_EUNSUPPORTED, "screen precision %d is not available in this build",
-                  precision);
+  if (precision != HLOC_FP32 && precision != HLOC_BF16 && precision != HLOC_FP8)
     return fail(HLOC_EINVAL, "unknown precision %d", precision);
-  }
   if (nq > 0 && (!q || !idx || !dist)) return fail(HLOC_EINVAL, "q, idx and dist must be non-NULL");
   if (nreq < 0) return fail(HLOC_EINVAL, "nreq must be >= 0");
   if (!req_offsets && nreq != nq)
@@ -437,7 +472,8 @@ void free_ws(hloc_ws *ws) {
                    &ws->rfill,    &ws->rq_off,   &ws->item_off, &ws->cand_off, &ws->n_cand,
                    &ws->misc,     &ws->rq,       &ws->items,    &ws->cand2,   &ws->agg_xy,
                    &ws->agg_tile, &ws->agg_flags, &ws->s_q,     &ws->s_off,   &ws->s_idx,
-                   &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags};
+                   &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags, &ws->qp16,
+                   &ws->q_err,    &ws->q_lon};
   for (WsBuf *b : bufs) free_buf(*b);
   for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
   if (ws->stream) (void)hipStreamDestroy(ws->stream);
@@ -460,6 +496,7 @@ void free_db_data(hloc_db *db) {
   free_ws(db->ws0);
   db->ws0 = nullptr;
   dev_free(db->rows);
+  dev_free(db->rows16);
   dev_free(db->row_n2);
   dev_free(db->perm);
   dev_free(db->xy);
@@ -486,7 +523,7 @@ int query_async(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int32_t n_re
   hloc_db *db = ws->db;
   CHK(check_query_args(db, q, nq, req_offsets, nreq, precision, idx, dist));
   Plan p;
-  CHK(make_plan(db, nq, k, n_regions, nreq, &p));
+  CHK(make_plan(db, nq, k, n_regions, nreq, precision, &p));
   DeviceGuard g(db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   return enqueue_query(ws, p, q, req_offsets, idx, dist, xy, tile, flags, s);
@@ -522,7 +559,8 @@ int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, ui
   if (!feats || !xy) return fail(HLOC_EINVAL, "feats and xy must be non-NULL");
   if (n < 1 || n > INT32_MAX) return fail(HLOC_EINVAL, "n must be in 1..2^31-1 (got %lld)", (long long)n);
   if (d < 1 || d > HLOC_MAX_DIM) return fail(HLOC_EINVAL, "d must be in 1..%d (got %d)", HLOC_MAX_DIM, d);
-  if (mirrors != 0) return fail(HLOC_EUNSUPPORTED, "low-precision mirrors are not available in this build");
+  if (mirrors & ~(uint32_t)HLOC_MIRROR_BF16)
+    return fail(HLOC_EUNSUPPORTED, "mirror flags 0x%x are not available in this build", mirrors);
   const int64_t nd = n * (int64_t)d;
   for (int64_t i = 0; i < nd; ++i)
     if (!std::isfinite(feats[i]))
@@ -543,6 +581,7 @@ int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, ui
   db->d = d;
   db->dp = (d + 31) / 32 * 32;
   db->max_abs_coord = max_abs;
+  db->mirrors = mirrors;
   auto bail = [&](int rc) {
     free_db_data(db);
     delete db;
@@ -559,7 +598,7 @@ int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, ui
   if (pe != hipSuccess) return bail(fail(HLOC_EDEVICE, "kernel set-up failed: %s", hipGetErrorString(pe)));
   if ((rc = dev_alloc(&db->rows, (size_t)n * db->dp)) || (rc = dev_alloc(&db->row_n2, (size_t)n)) ||
       (rc = dev_alloc(&db->perm, (size_t)n)) || (rc = dev_alloc(&db->xy, (size_t)n * 2)) ||
-      (rc = dev_alloc(&db->tiles, (size_t)n)) || (rc = dev_alloc(&db->norm_max, 2)))
+      (rc = dev_alloc(&db->tiles, (size_t)n)) || (rc = dev_alloc(&db->norm_max, 4)))
     return bail(rc);
   float *tmp = nullptr;
   if ((rc = dev_alloc(&tmp, (size_t)nd))) return bail(rc);
@@ -568,7 +607,7 @@ int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, ui
   hipError_t e = hipMemcpy(tmp, feats, (size_t)nd * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(db->perm, db->h_perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(db->xy, xy, (size_t)n * 2 * sizeof(double), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemsetAsync(db->norm_max, 0, 2 * sizeof(float), db->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(db->norm_max, 0, 4 * sizeof(float), db->stream);
   if (e == hipSuccess) e = launch_gather_rows(tmp, db->perm, n, d, d, db->rows, db->dp, db->stream);
   if (e == hipSuccess) e = launch_row_norms(db->rows, n, db->dp, db->row_n2, db->norm_max, db->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(db->stream);
@@ -645,8 +684,14 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   HIPCHK(hipMemcpy(db->perm, new_perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(db->reg_start, start.data(), (size_t)(R + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(db->nonempty_ids, ids.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  HIPCHK(hipMemsetAsync(db->norm_max, 0, 2 * sizeof(float), db->stream));
+  HIPCHK(hipMemsetAsync(db->norm_max, 0, 4 * sizeof(float), db->stream));
   HIPCHK(launch_row_norms(db->rows, n, db->dp, db->row_n2, db->norm_max, db->stream));
+  dev_free(db->rows16);
+  if (db->mirrors & HLOC_MIRROR_BF16) {
+    if ((rc = dev_alloc(&db->rows16, (size_t)n * db->dp))) return rc;
+    HIPCHK(launch_rows_to_bf16(db->rows, n, db->dp, db->rows16, db->norm_max + 2,
+                               db->norm_max + 3, db->stream));
+  }
   if (reps) {
     std::vector<double> r64((size_t)R * db->dp, 0.0);
     for (int32_t r = 0; r < R; ++r)
@@ -657,11 +702,13 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   }
   HIPCHK(launch_rep_finish(db->rep64, db->reg_start, R, db->dp, db->rep32, db->rep_n2,
                            db->norm_max + 1, db->stream));
-  float mx[2];
+  float mx[4];
   HIPCHK(hipMemcpyAsync(mx, db->norm_max, sizeof mx, hipMemcpyDeviceToHost, db->stream));
   HIPCHK(hipStreamSynchronize(db->stream));
   db->h_row_max = mx[0];
   db->h_rep_max = mx[1];
+  db->h_bf16_err = mx[2];
+  db->h_bf16_norm = mx[3];
   db->R = R;
   db->R_nonempty = (int32_t)ids.size();
   db->h_reg_start = start;
@@ -722,7 +769,7 @@ int hloc_ws_reserve(hloc_ws *ws, int32_t nq_max, int32_t nreq_max, int32_t k_max
   if (!ws) return fail(HLOC_EINVAL, "ws is NULL");
   if (nreq_max < 0) return fail(HLOC_EINVAL, "nreq_max must be >= 0");
   Plan p;
-  CHK(make_plan(ws->db, nq_max, k_max, n_regions_max, nreq_max, &p));
+  CHK(make_plan(ws->db, nq_max, k_max, n_regions_max, nreq_max, HLOC_FP32, &p));
   DeviceGuard g(ws->db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   return ensure_workspace(ws, p, true);
@@ -759,7 +806,7 @@ int hloc_ws_capture(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int32_t 
   hloc_db *db = ws->db;
   CHK(check_query_args(db, q, nq, req_offsets, nreq, precision, idx, dist));
   Plan p;
-  CHK(make_plan(db, nq, k, n_regions, nreq, &p));
+  CHK(make_plan(db, nq, k, n_regions, nreq, precision, &p));
   DeviceGuard g(db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   CHK(ensure_workspace(ws, p, true));  // no allocation may happen while capturing
@@ -802,7 +849,7 @@ int hloc_query_batch(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t
   CHK(check_query_args(db, q, nq, req_offsets, nreq, precision, idx, dist));
   CHK(check_host_offsets(req_offsets, nq, nreq, k));
   Plan p;
-  CHK(make_plan(db, nq, k, n_regions, nreq, &p));
+  CHK(make_plan(db, nq, k, n_regions, nreq, precision, &p));
   DeviceGuard g(db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   hloc_ws *ws = db->ws0;

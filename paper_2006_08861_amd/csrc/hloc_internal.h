@@ -56,9 +56,11 @@ struct Item {
   int32_t nrows_gq;  // nrows << 16 | gq
 };
 
-// Dense or listed screen of fp32 rows against padded fp32 frames.
-struct ScreenF32Args {
+// Dense or listed screen of rows against padded frames (fp32 or bf16 copies).
+struct ScreenArgs {
   const float *rows;      // nrows x dp, row-major
+  const uint16_t *rows16; // bf16 copy of rows (bf16 screen)
+  const uint16_t *qp16;   // bf16 copy of qp (bf16 screen)
   const float *row_n2;    // nrows squared norms (+inf marks a row never to select)
   int32_t dp;             // padded row length (multiple of 32)
   const float *qp;        // frames x dp
@@ -78,9 +80,18 @@ struct ScreenF32Args {
 };
 
 // Padded copy and squared norm of each frame; block 0 also clears zero16[0..16).
+// With qp16 set, also the bf16 rounding of each frame, the norm of its rounding
+// error (q_err) and of the rounded frame (q_lon).
 hipError_t launch_prep_queries(const float *q, int32_t nq, int32_t d, int32_t dp, float *qp,
-                               float *qn2, int32_t *zero16, hipStream_t s);
-hipError_t launch_screen_f32(const ScreenF32Args &a, int32_t grid, hipStream_t s);
+                               float *qn2, int32_t *zero16, uint16_t *qp16, float *q_err,
+                               float *q_lon, hipStream_t s);
+hipError_t launch_screen_f32(const ScreenArgs &a, int32_t grid, hipStream_t s);
+hipError_t launch_screen_bf16(const ScreenArgs &a, int32_t grid, hipStream_t s);
+bool bf16_screen_supports(int32_t dp);
+// bf16 copy of n rows; maxima of the per-row norms of the rounding error and
+// of the rounded row.
+hipError_t launch_rows_to_bf16(const float *src, int64_t n, int32_t dp, uint16_t *dst,
+                               float *max_err, float *max_norm, hipStream_t s);
 // Blocks to launch for `items` work items of the screen at padded length dp.
 int32_t screen_grid(int64_t items, int32_t dp, int32_t max_blocks);
 
@@ -112,6 +123,12 @@ struct SelRerankArgs {
   const float *qn2;
   double err_coef;         // screen error bound: err_coef * (|q| + max_norm)^2
   double max_norm;
+  // low-precision screen: + lo_coef * (|q~| lo_dmax + |q~ - q| lo_nmax + |q~ - q| lo_dmax)
+  const float *q_err;      // per frame |q~ - q| (NULL: fp32 screen)
+  const float *q_lon;      // per frame |q~|
+  double lo_dmax;          // largest |d~ - d| over the rows
+  double lo_nmax;          // largest |d~|
+  double lo_coef;
   int32_t nq;
   int64_t *idx_out;        // fine: nq x m original indices
   float *dist_out;         // fine: nq x m

@@ -22,7 +22,10 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_prep_queries(const float *__restrict__ q, int nq, int d,
                                                       int dp, float *__restrict__ qp,
                                                       float *__restrict__ qn2,
-                                                      int32_t *__restrict__ zero16) {
+                                                      int32_t *__restrict__ zero16,
+                                                      uint16_t *__restrict__ qp16,
+                                                      float *__restrict__ q_err,
+                                                      float *__restrict__ q_lon) {
   if (blockIdx.x == 0 && threadIdx.x < 16 && zero16) zero16[threadIdx.x] = 0;
   const int f = blockIdx.x * 4 + wave_id();
   const int lane = lane_id();
@@ -30,24 +33,44 @@ __global__ __launch_bounds__(256) void k_prep_queries(const float *__restrict__ 
   const float *src = q + (int64_t)f * d;
   float *dst = qp + (int64_t)f * dp;
   float acc = 0.f;
+  double e2 = 0.0, l2 = 0.0;
   for (int c = lane; c < dp; c += 64) {
     const float v = c < d ? src[c] : 0.f;
     dst[c] = v;
     acc = fmaf(v, v, acc);
+    if (qp16) {
+      const uint32_t u = __float_as_uint(v);
+      const uint16_t h = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+      qp16[(int64_t)f * dp + c] = h;
+      const double t = (double)__uint_as_float((uint32_t)h << 16);
+      e2 = fma(t - (double)v, t - (double)v, e2);
+      l2 = fma(t, t, l2);
+    }
   }
   acc = wave_sum_f32(acc);
-  if (lane == 0) qn2[f] = acc;
+  if (qp16) {
+    e2 = wave_sum_f64(e2);
+    l2 = wave_sum_f64(l2);
+  }
+  if (lane == 0) {
+    qn2[f] = acc;
+    if (qp16) {
+      q_err[f] = (float)sqrt(e2) * (1.0f + 1e-6f);
+      q_lon[f] = (float)sqrt(l2) * (1.0f + 1e-6f);
+    }
+  }
 }
 
 hipError_t launch_prep_queries(const float *q, int32_t nq, int32_t d, int32_t dp, float *qp,
-                               float *qn2, int32_t *zero16, hipStream_t s) {
+                               float *qn2, int32_t *zero16, uint16_t *qp16, float *q_err,
+                               float *q_lon, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
   return launch_kernel(k_prep_queries, dim3((nq + 3) / 4), dim3(256), 0, s, q, nq, d, dp, qp, qn2,
-                     zero16);
+                       zero16, qp16, q_err, q_lon);
 }
 
 template <bool DENSE>
-__global__ __launch_bounds__(256) void k_screen_f32(ScreenF32Args a) {
+__global__ __launch_bounds__(256) void k_screen_f32(ScreenArgs a) {
   extern __shared__ float4 qs4[];  // kGroup x (dp + 4) floats, 16-byte aligned
   float *qs = reinterpret_cast<float *>(qs4);
   __shared__ int s_q[kGroup];
@@ -150,7 +173,7 @@ __global__ __launch_bounds__(256) void k_screen_f32(ScreenF32Args a) {
 // row loads, frame loads and norms go out together once the item's frame list
 // has been read.
 template <int NS, bool DENSE>
-__global__ __launch_bounds__(256) void k_screen_blk(ScreenF32Args a) {
+__global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
   constexpr int DP = NS * 16;
   const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
   const int i = lane & 15, g = lane >> 4;
@@ -230,12 +253,12 @@ __global__ __launch_bounds__(256) void k_screen_blk(ScreenF32Args a) {
 }
 
 template <int NS, bool DENSE>
-hipError_t launch_blk_t(const ScreenF32Args &a, int32_t grid, hipStream_t s) {
+hipError_t launch_blk_t(const ScreenArgs &a, int32_t grid, hipStream_t s) {
   return launch_kernel(k_screen_blk<NS, DENSE>, dim3(grid), dim3(256), 0, s, a);
 }
 
 template <bool DENSE>
-hipError_t launch_screen_t(const ScreenF32Args &a, int32_t grid, hipStream_t s) {
+hipError_t launch_screen_t(const ScreenArgs &a, int32_t grid, hipStream_t s) {
   const size_t lds = (size_t)kGroup * (a.dp + 4) * sizeof(float);
   return launch_kernel(k_screen_f32<DENSE>, dim3(grid), dim3(256), lds, s, a);
 }
@@ -255,7 +278,7 @@ hipError_t prepare_screen_kernels() {
   return hipSuccess;
 }
 
-hipError_t launch_screen_f32(const ScreenF32Args &a, int32_t grid, hipStream_t s) {
+hipError_t launch_screen_f32(const ScreenArgs &a, int32_t grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   if (a.rows_per_item % 16 == 0) {
     switch (a.dp) {

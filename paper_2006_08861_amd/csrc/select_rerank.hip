@@ -404,7 +404,11 @@ __global__ __launch_bounds__(256) void k_select_rerank(SelRerankArgs a) {
     if (rejected && a.m > 0) {
       const double rejd = (double)__uint_as_float((uint32_t)(thresh >> 32));
       const double qn = sqrt((double)qn2) * (1.0 + 1e-6);
-      const double e = a.err_coef * (qn + a.max_norm) * (qn + a.max_norm);
+      double e = a.err_coef * (qn + a.max_norm) * (qn + a.max_norm);
+      if (a.q_err) {
+        const double qe = a.q_err[f], ql = a.q_lon[f];
+        e += a.lo_coef * (ql * a.lo_dmax + qe * a.lo_nmax + qe * a.lo_dmax);
+      }
       const double dm = __longlong_as_double((long long)sh.sort_hi[a.m - 1]);
       const double tau = dm * (1.0 + 1e-12) + e;
       if (!(rejd > tau)) {

@@ -65,7 +65,7 @@ def test_build_db_rejects_bad_arguments():
     badxy[1, 0] = np.inf
     rc, h, msg = _build(feats, badxy)
     assert rc == hloc.EINVAL and "position" in msg
-    rc, h, msg = _build(feats, xy, mirrors=1)
+    rc, h, msg = _build(feats, xy, mirrors=0x80)
     assert rc == hloc.EUNSUPPORTED
 
 
@@ -105,5 +105,5 @@ def test_header_limits_match_binding_constants():
     with open(hloc.HEADER) as f:
         text = f.read()
     for name, val in (("HLOC_EINVAL", hloc.EINVAL), ("HLOC_EUNSUPPORTED", hloc.EUNSUPPORTED),
-                      ("HLOC_FLAG_EMPTY", hloc.FLAG_EMPTY)):
+                      ("HLOC_FLAG_EMPTY", hloc.FLAG_EMPTY), ("HLOC_MIRROR_BF16", hloc.MIRROR_BF16)):
         assert f"{name} = {val}" in text

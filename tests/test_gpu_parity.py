@@ -36,28 +36,30 @@ def torch_cuda():
     return torch
 
 
-def make_db(feats, xy, region_of, R, agg=None, reps=None):
-    db = hloc.HlocDB(feats, xy)
+def make_db(feats, xy, region_of, R, agg=None, reps=None, mirrors=0):
+    db = hloc.HlocDB(feats, xy, mirrors=mirrors)
     db.set_regions(region_of, R, reps)
     if agg is not None:
         db.set_aggregation(*agg)
     return db
 
 
-def run_device(torch, db, q, k, n_reg, offs=None):
+def run_device(torch, db, q, k, n_reg, offs=None, precision="fp32"):
     qd = torch.from_numpy(np.ascontiguousarray(q, np.float32)).to("cuda:0")
     od = None if offs is None else torch.from_numpy(np.asarray(offs, np.int32)).to("cuda:0")
-    out = db.query(qd, k, n_reg, od)
+    out = db.query(qd, k, n_reg, od, precision=precision)
     torch.cuda.synchronize()
     return {key: v.cpu().numpy() for key, v in out.items()}
 
 
 def check_all(torch, feats, xy, region_of, R, q, k, n_reg, offs=None, agg=(0.5, 1, 0.0, 0),
-              reps=None, name=""):
-    say(f"[case] {name}: n={len(feats)} d={feats.shape[1]} R={R} nq={len(q)} k={k} n_reg={n_reg}")
-    db = make_db(feats, xy, region_of, R, agg, reps)
+              reps=None, name="", precision="fp32"):
+    say(f"[case] {name}: n={len(feats)} d={feats.shape[1]} R={R} nq={len(q)} k={k} "
+        f"n_reg={n_reg} screen={precision}")
+    db = make_db(feats, xy, region_of, R, agg, reps,
+                 mirrors=hloc.MIRROR_BF16 if precision == "bf16" else 0)
     offs = np.arange(len(q) + 1) if offs is None else np.asarray(offs)
-    out = run_device(torch, db, q, k, n_reg, offs)
+    out = run_device(torch, db, q, k, n_reg, offs, precision=precision)
     regs = db.last_regions()
     info = db.info()
     ora = oracle.localize(feats, xy, region_of, R, q, offs, k, n_reg, agg, reps=reps)
@@ -375,3 +377,44 @@ def test_concurrent_workspaces_match_alone(torch_cuda, fp32_shape):
     _bitwise_equal(ob, run_device(torch, db, w.q[128:], w.k, w.n_reg))
     wa.close()
     wb.close()
+
+
+# ------------------------------------------------------------- bf16 screen
+def test_bf16_screen_fp32_shape(torch_cuda):
+    w = workload.make_workload(1)
+    st, info, _ = check_all(torch_cuda, w.feats, w.xy, w.region_of, w.n_regions_total, w.q, w.k,
+                            w.n_reg, w.req_offsets, w.agg, name="fp32-200k-d256", precision="bf16")
+    assert st["recall"] == 1.0
+
+
+def test_bf16_screen_multiframe_d512(torch_cuda):
+    w = workload.make_workload(3, nq=48, n=20_000)
+    st, info, _ = check_all(torch_cuda, w.feats, w.xy, w.region_of, w.n_regions_total, w.q, w.k,
+                            w.n_reg, w.req_offsets, w.agg, name="8-frame d512", precision="bf16")
+    assert st["recall"] == 1.0
+
+
+def test_bf16_screen_ragged_and_duplicates(torch_cuda):
+    rng, feats, xy, region_of = _random_db(31, 1500, 37, 40, empty=6)
+    q = (feats[rng.integers(0, 1500, 45)] + 0.3 * rng.standard_normal((45, 37))).astype(np.float32)
+    st, _, _ = check_all(torch_cuda, feats, xy, region_of, 40, q, 7, 3, name="d37", precision="bf16")
+    assert st["recall"] == 1.0
+    dup = rng.choice(1500, 300, replace=False)
+    feats[dup] = feats[dup[0]]
+    st, info, out = check_all(torch_cuda, feats, xy, region_of, 40, feats[dup[:2]], 10, 40,
+                              name="duplicates", precision="bf16")
+    assert out["idx"][0].tolist() == sorted(dup.tolist())[:10]
+
+
+def test_bf16_and_fp32_screens_agree_bitwise(torch_cuda):
+    # both screens end in the same certified FP64 rerank: identical results
+    torch = torch_cuda
+    w = workload.make_workload(1, nq=128)
+    say("[case] bf16 vs fp32 screen on one database")
+    db = make_db(w.feats, w.xy, w.region_of, w.n_regions_total, w.agg, mirrors=hloc.MIRROR_BF16)
+    a = run_device(torch, db, w.q, w.k, w.n_reg, precision="fp32")
+    b = run_device(torch, db, w.q, w.k, w.n_reg, precision="bf16")
+    say(f"[ok] bf16 info {db.info()}")
+    for key in ("idx", "dist", "tile", "flags", "xy"):
+        assert a[key].tobytes() == b[key].tobytes(), key
+    db.close()
