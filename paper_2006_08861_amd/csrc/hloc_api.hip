@@ -236,8 +236,8 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal) {
   CHK(ensure(ws->regions, (size_t)nq * nr * sizeof(int32_t)));
   CHK(ensure(ws->rcount, (size_t)db->R * sizeof(int32_t)));
   CHK(ensure(ws->rfill, (size_t)db->R * sizeof(int32_t)));
-  CHK(ensure(ws->rq_off, (size_t)db->R * sizeof(int32_t)));
-  CHK(ensure(ws->item_off, (size_t)db->R * sizeof(int32_t)));
+  CHK(ensure(ws->rq_off, (size_t)(db->R + 1) * sizeof(int32_t)));
+  CHK(ensure(ws->item_off, (size_t)(db->R + 1) * sizeof(int32_t)));
   CHK(ensure(ws->cand_off, (size_t)nq * nr * sizeof(int32_t)));
   CHK(ensure(ws->n_cand, (size_t)nq * sizeof(int32_t)));
   CHK(ensure(ws->misc, 16 * sizeof(int32_t)));

@@ -161,9 +161,11 @@ hipError_t launch_aggregate(const AggArgs &a, hipStream_t s);
 hipError_t prepare_screen_kernels();
 hipError_t prepare_select_kernels();
 hipError_t prepare_aggregate_kernels();
+hipError_t prepare_sched_kernels();
 inline hipError_t prepare_kernels() {
   hipError_t e = prepare_screen_kernels();
   if (e == hipSuccess) e = prepare_select_kernels();
+  if (e == hipSuccess) e = prepare_sched_kernels();
   if (e == hipSuccess) e = prepare_aggregate_kernels();
   return e;
 }

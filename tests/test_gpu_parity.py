@@ -418,3 +418,36 @@ def test_bf16_and_fp32_screens_agree_bitwise(torch_cuda):
     for key in ("idx", "dist", "tile", "flags", "xy"):
         assert a[key].tobytes() == b[key].tobytes(), key
     db.close()
+
+
+# ------------------------------------------------------------- scheduling shapes
+def test_many_regions_multi_kernel_schedule(torch_cuda):
+    # more regions than the single-block scheduler holds in LDS (16384): the
+    # count / scan / scatter / expand kernels build the schedule
+    rng = np.random.default_rng(21)
+    R, n, d = 20_000, 40_000, 16
+    region_of = np.sort(rng.integers(0, R, size=n)).astype(np.int32)
+    feats = rng.standard_normal((n, d)).astype(np.float32)
+    xy = rng.uniform(0, 80, size=(n, 2))
+    q = (feats[rng.integers(0, n, 300)] + 0.2 * rng.standard_normal((300, d))).astype(np.float32)
+    st, info, _ = check_all(torch_cuda, feats, xy, region_of, R, q, 5, 8,
+                            name="20000 regions (multi-kernel schedule)")
+    assert st["recall"] == 1.0 and info["items"] > 0
+
+
+def test_region_kept_by_every_frame(torch_cuda):
+    # one large region kept by all 700 frames: 44 frame groups x 47 row chunks
+    # of work items expanded from a single region
+    rng = np.random.default_rng(22)
+    sizes = np.array([3000] + [250] * 12)
+    region_of = np.repeat(np.arange(len(sizes)), sizes).astype(np.int32)
+    n, d = len(region_of), 32
+    feats = rng.standard_normal((n, d)).astype(np.float32)
+    feats[:3000] *= 0.2  # the big region sits near the origin, close to every query,
+    feats[3000:] += 0.6  # the others are shifted away from it
+    xy = rng.uniform(0, 40, size=(n, 2))
+    q = (feats[rng.integers(0, 3000, 700)] + 0.05 * rng.standard_normal((700, d))).astype(np.float32)
+    st, info, _ = check_all(torch_cuda, feats, xy, region_of, len(sizes), q, 9, 3,
+                            name="one region kept by 700 frames")
+    assert st["recall"] == 1.0
+    assert info["items"] >= 44 * 47
