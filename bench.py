@@ -23,6 +23,8 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -40,6 +42,100 @@ HBM_PEAK_GBS = 8000.0
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+# the fine screen's sources: hardware counters taken on it stay valid while
+# these files are unchanged
+SCREEN_SOURCES = ("paper_2006_08861_amd/csrc/screen_f32.hip",
+                  "paper_2006_08861_amd/csrc/screen_bf16.hip",
+                  "paper_2006_08861_amd/csrc/hloc_device.h",
+                  "paper_2006_08861_amd/csrc/hloc_internal.h")
+SCREEN_KERNELS = {"fp32": "k_screen_blk<", "bf16": "k_screen_bf16<"}
+
+
+def screen_digest() -> str:
+    h = hashlib.sha256()
+    for rel in SCREEN_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counters_path(workload: str, precision: str) -> str:
+    return os.path.join(ROOT, "profiles", f"counters_screen_{precision}_{workload}.md")
+
+
+def load_traffic(workload: str, precision: str):
+    """HBM bytes per launch of the fine screen from the committed counter
+    summary: FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
+    same counter reads for a plain device copy. None when there is no summary
+    for this workload or the screen's sources changed since it was taken."""
+    path = counters_path(workload, precision)
+    if not os.path.exists(path):
+        return None, "no counter summary for this workload"
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("record: "):
+                rec = json.loads(line[len("record: "):])
+    if rec is None:
+        return None, f"{os.path.relpath(path, ROOT)} holds no record line"
+    if rec["sources"] != screen_digest():
+        return None, "screen sources changed since the counters were taken"
+    b = 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+    return b, os.path.relpath(path, ROOT)
+
+
+def per_dispatch_kib(path: str, name_prefix: str, counter: str,
+                     suffix: str = "") -> tuple[float, int]:
+    """Mean counter value (KiB) per dispatch of the kernels whose name starts
+    with name_prefix (after an optional namespace) and ends with suffix in a
+    rocprofv3 counter CSV."""
+    vals = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("hloc::", "")
+            if name.startswith(name_prefix) and name.endswith(suffix) and \
+                    r["Counter_Name"] == counter:
+                vals.append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no {counter} rows for {name_prefix} in {path}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def counters_summary(a) -> None:
+    """Prints the markdown counter summary of the fine screen (with the record
+    line load_traffic reads) from four rocprofv3 --pmc CSVs: the benchmark's
+    FETCH_SIZE and WRITE_SIZE runs and the copy calibration's."""
+    fetch_csv, write_csv, cf_csv, cw_csv = a.counters_summary
+    prefix = SCREEN_KERNELS[a.precision]
+    fk, nf = per_dispatch_kib(fetch_csv, prefix, "FETCH_SIZE", ", false>")
+    wk, nw = per_dispatch_kib(write_csv, prefix, "WRITE_SIZE", ", false>")
+    copy_bytes = a.copy_mib * (1 << 20)
+    copy_kernel = "at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add"
+    cfk, _ = per_dispatch_kib(cf_csv, copy_kernel, "FETCH_SIZE")
+    cwk, _ = per_dispatch_kib(cw_csv, copy_kernel, "WRITE_SIZE")
+    fetch_scale = copy_bytes / 1024.0 / cfk
+    write_scale = copy_bytes / 1024.0 / cwk
+    fetch_scale, write_scale = round(fetch_scale, 3), round(write_scale, 3)
+    traffic = 1024.0 * (fk * fetch_scale + wk * write_scale)
+    rec = dict(kernel=prefix + "NS, false>", workload=a.workload_name, fetch_kib=round(fk, 1),
+               write_kib=round(wk, 1), fetch_scale=fetch_scale, write_scale=write_scale,
+               sources=screen_digest())
+    print(f"# Fine-screen HBM traffic, {a.precision} screen, {a.workload_name}\n")
+    print("Commands (from the repository root, one counter per run):\n")
+    print("```")
+    for c in a.commands:
+        print(c)
+    print("```\n")
+    print("| Counter | Kernel | Dispatches | KiB per dispatch | Copy calibration | Bytes per dispatch |")
+    print("|---|---|---|---|---|---|")
+    print(f"| FETCH_SIZE | `{prefix}NS, false>` | {nf} | {fk:.1f} | {a.copy_mib} MiB copy reads "
+          f"{cfk:.0f} KiB: x{fetch_scale} | {fk * fetch_scale * 1024 / 1e6:.2f} MB |")
+    print(f"| WRITE_SIZE | `{prefix}NS, false>` | {nw} | {wk:.1f} | {a.copy_mib} MiB copy writes "
+          f"{cwk:.0f} KiB: x{write_scale} | {wk * write_scale * 1024 / 1e6:.2f} MB |")
+    print(f"\nHBM traffic per launch: {traffic / 1e6:.2f} MB.\n")
+    print("record: " + json.dumps(rec))
 
 
 def cpu_baseline(w, gpu_idx, seconds: float):
@@ -75,6 +171,94 @@ def cpu_baseline(w, gpu_idx, seconds: float):
         hits / (mm * w.k), exact, mm
 
 
+def serve_bench(a) -> None:
+    """Poisson arrivals of 1-16 frame requests (k in {8, 16, 32}) at a.serve
+    requests/s into the request server for a.serve_seconds; prints one JSON
+    line with the completed rate and the submit-to-completion latency."""
+    import queue
+    import threading
+
+    import torch  # noqa: F401
+    from paper_2006_08861_amd import hloc, workload
+
+    t0 = time.perf_counter()
+    w = workload.make_workload(4, n=a.serve_n)
+    log(f"[serve] workload {w.name}: n={len(w.feats)} d={w.feats.shape[1]} "
+        f"regions={w.n_regions_total} request pool={len(w.req_offsets) - 1} "
+        f"({time.perf_counter() - t0:.1f} s)")
+    db = hloc.HlocDB(w.feats, w.xy, mirrors=hloc.MIRROR_BF16 if a.precision == "bf16" else 0)
+    db.set_regions(w.region_of, w.n_regions_total)
+    db.set_aggregation(*w.agg)
+    srv = hloc.Server(db, k=32, n_regions=w.n_reg, precision=a.precision,
+                      max_batch_frames=a.serve_batch, max_slots=a.workspaces,
+                      max_queue_frames=a.serve_queue, hbm_budget_bytes=a.serve_budget)
+    rng = np.random.default_rng(77)
+    offs = w.req_offsets
+    npool = len(offs) - 1
+    n_req = int(a.serve * a.serve_seconds)
+    arrivals = np.cumsum(rng.exponential(1.0 / a.serve, n_req))
+    pick = rng.integers(0, npool, n_req)
+    ks = rng.choice([8, 16, 32], n_req)
+    pool = [np.ascontiguousarray(w.q[offs[r]:offs[r + 1]]) for r in range(npool)]
+    # warm-up: one request of every size through every slot
+    for f in range(1, 17):
+        r = next(i for i in range(npool) if offs[i + 1] - offs[i] >= f)
+        t = srv.submit(pool[r][:f], 32)
+        srv.wait(t, f, 32)
+    tickets = queue.Queue()
+    lat, refused = [], [0]
+    done_frames = [0]
+
+    def waiter():
+        while True:
+            item = tickets.get()
+            if item is None:
+                return
+            t, nf, k = item
+            out = srv.wait(t, nf, k)
+            lat.append(out["latency_ms"])
+            done_frames[0] += nf
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    start = time.perf_counter()
+    for i in range(n_req):
+        due = start + arrivals[i]
+        while True:
+            now = time.perf_counter()
+            if now >= due:
+                break
+            if due - now > 3e-4:
+                time.sleep(due - now - 2e-4)
+        frames = pool[pick[i]]
+        try:
+            t = srv.submit(frames, int(ks[i]))
+        except hloc.HlocError as e:
+            if e.code != hloc.EBUSY:
+                raise
+            refused[0] += 1
+            continue
+        tickets.put((t, len(frames), int(ks[i])))
+    tickets.put(None)
+    th.join()
+    wall = time.perf_counter() - start
+    st = srv.stats()
+    srv.close()
+    db.close()
+    lat = np.array(lat)
+    print(json.dumps({
+        "metric": "served localization requests/s (Poisson arrivals, 1-16 frames, k 8/16/32)",
+        "offered_req_per_s": a.serve, "value": len(lat) / wall, "unit": "requests/s",
+        "frames_per_s": done_frames[0] / wall, "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)), "refused": refused[0], "seconds": wall,
+        "dtype": "f32" if a.precision == "fp32" else "bf16", "data": "synthetic",
+        "config": {"workload": w.name, "n": int(len(w.feats)), "d": int(w.feats.shape[1]),
+                   "regions": int(w.n_regions_total), "n_regions": int(w.n_reg),
+                   "max_batch_frames": a.serve_batch, "slots": st["slots"],
+                   "hbm_budget_bytes": a.serve_budget},
+        "server": st}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,13 +270,35 @@ def main():
                     help="fine-screen precision (the rerank is FP64 either way)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--latency-reps", type=int, default=200)
-    ap.add_argument("--workspaces", type=int, default=2,
+    ap.add_argument("--workspaces", type=int, default=4,
                     help="batches in flight in the pipelined loop (one workspace and stream each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (reference for "
                          "hardware byte counters) and exit")
+    ap.add_argument("--counters-summary", nargs=4, metavar="CSV",
+                    help="only print the fine screen's counter summary from rocprofv3 --pmc "
+                         "CSVs: FETCH_SIZE, WRITE_SIZE, copy FETCH_SIZE, copy WRITE_SIZE")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="copy size of the calibration CSVs")
+    ap.add_argument("--workload-name", default="fp32-200k-d256")
+    ap.add_argument("--commands", nargs="*", default=[], help="commands quoted in the summary")
+    ap.add_argument("--serve", type=float, default=0.0, metavar="REQ_PER_S",
+                    help="only run the request server under Poisson arrivals at this rate")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-n", type=int, default=None, help="database rows (default: 4M)")
+    ap.add_argument("--serve-batch", type=int, default=512, help="frames per batch")
+    ap.add_argument("--serve-queue", type=int, default=1 << 16, help="frames waiting at most")
+    ap.add_argument("--serve-budget", type=int, default=0, help="HBM bytes for the slots")
     a = ap.parse_args()
+    if a.serve:
+        if a.gpus != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        serve_bench(a)
+        return
+    if a.counters_summary:
+        counters_summary(a)
+        return
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
@@ -150,7 +356,7 @@ def main():
     unique_rows = int(sizes[np.unique(regions)].sum())
     d = w.feats.shape[1]
     row_bytes = 2 * d if a.precision == "bf16" else 4 * d
-    screen_bytes = unique_rows * (row_bytes + 4) + info["candidates"] * 8 + nq * row_bytes
+    screen_bytes = unique_rows * (row_bytes + 4) + info["candidates"] * 4 + nq * row_bytes
 
     # throughput: K back-to-back steps, nothing recorded between kernels
     torch.cuda.synchronize()
@@ -207,6 +413,7 @@ def main():
     lat = np.array(lat)
     screen_ms = phases["screen"][0] / max(phases["screen"][1], 1)
     achieved = screen_bytes / (screen_ms * 1e-3) / 1e9
+    traffic, traffic_src = load_traffic(w.name, a.precision)
     gpu_idx = idx.cpu().numpy()
 
     base, recall, exact, m = (None, None, None, 0)
@@ -239,7 +446,8 @@ def main():
                      "kernel": "k_screen_bf16<NS,false>" if a.precision == "bf16" else "k_screen_blk<NS,false>",
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": int(screen_bytes),
+                     "traffic": None if traffic is None else int(traffic),
+                     "traffic_source": traffic_src, "bytes_per_launch": int(screen_bytes),
                      "avg_launch_ms": screen_ms},
         "phases_ms": {p: v[0] / max(v[1], 1) for p, v in phases.items()},
         "ms_per_step_event_timed": wall_prof * 1e3 / a.steps,

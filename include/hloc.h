@@ -37,6 +37,7 @@ extern "C" {
 
 typedef struct hloc_db hloc_db; /* opaque; owns all of its device memory */
 typedef struct hloc_ws hloc_ws; /* opaque; scratch memory of one batch in flight */
+typedef struct hloc_server hloc_server; /* opaque; request loop over one database */
 
 typedef enum {
   HLOC_OK = 0,
@@ -44,7 +45,9 @@ typedef enum {
   HLOC_ENOMEM = -2,      /* device or host allocation failed */
   HLOC_ESTATE = -3,      /* call order violated (e.g. query before set_regions) */
   HLOC_EDEVICE = -4,     /* a HIP call failed; the message names it */
-  HLOC_EUNSUPPORTED = -5 /* the requested screen precision is not available */
+  HLOC_EUNSUPPORTED = -5, /* the requested screen precision is not available */
+  HLOC_EBUSY = -6,       /* the request server's queue is full; submit again later */
+  HLOC_ETIMEDOUT = -7    /* the wait ended before the request completed */
 } hloc_status;
 
 /* Precision of the fine screen (the coarse screen is fp32). Whatever the
@@ -177,7 +180,7 @@ int hloc_last_regions(hloc_db *db, int32_t *out, int32_t *nq, int32_t *n_regions
 
 /*
  * Workspaces: the scratch memory of one batch in flight (frame copies,
- * candidate keys, schedule, counters). The calls above use the database's
+ * candidate screen distances, schedule, counters). The calls above use the database's
  * default workspace; a caller that wants several batches in flight at once
  * (on several streams) gives each its own workspace. A workspace belongs to
  * one database and must be freed before it.
@@ -240,6 +243,79 @@ enum {
 };
 int hloc_profile(hloc_db *db, int32_t enable);
 int hloc_profile_read(hloc_db *db, double *ms, int64_t *calls, int32_t n);
+
+/*
+ * Request server: continuous batching of localization requests (the
+ * client/server request model of Section 3.1: a request brings the frames
+ * around one position, the server returns each frame's top-N candidates and
+ * one floor-plan position). Requests of 1 .. max_batch_frames frames are
+ * queued as they arrive; whenever one of the server's slots is free, a
+ * launcher thread packs the waiting requests, oldest first and never split,
+ * into one batch of at most max_batch_frames frames and runs it on that
+ * slot's workspace and stream, so up to `slots` batches overlap on the
+ * device while new requests keep arriving. A completion thread returns each
+ * request's results. A request's results are the same whatever it shares a
+ * batch with (every step is per frame or per request).
+ *
+ * Admission by device memory: each slot holds the workspace and input/output
+ * buffers of one full batch, sized once at creation; the server takes
+ * min(max_slots, hbm_budget_bytes / bytes per slot) slots (ENOMEM if not even
+ * one fits; hbm_budget_bytes = 0 means no limit). Admission of requests: at
+ * most max_queue_frames frames wait at once; beyond that submit returns
+ * HLOC_EBUSY.
+ *
+ * While a server exists the database is read-only: hloc_set_regions and
+ * hloc_set_aggregation return ESTATE. Frames are copied at submit; results
+ * are copied out at wait. Server calls may come from any threads.
+ */
+typedef struct {
+  int32_t k;                /* candidates per frame computed (1 .. HLOC_MAX_K) */
+  int32_t n_regions;        /* regions searched per frame (>= 1) */
+  int32_t precision;        /* hloc_precision of the screen */
+  int32_t max_batch_frames; /* frames per batch (>= 1); also the largest request */
+  int32_t max_slots;        /* batches in flight at most (>= 1) */
+  int32_t max_queue_frames; /* frames waiting at most (>= max_batch_frames) */
+  int64_t hbm_budget_bytes; /* device memory for all slots; 0 = no limit */
+} hloc_server_config;
+
+/* Errors: EINVAL (config out of range), ESTATE (no regions), EUNSUPPORTED,
+ * ENOMEM (budget below one slot, or allocation failed), EDEVICE. */
+int hloc_server_create(hloc_db *db, const hloc_server_config *cfg, hloc_server **out);
+
+/*
+ * Queue one request: frames is host nframes x d float32 (copied), nframes in
+ * 1 .. cfg.max_batch_frames; k_req in 1 .. cfg.k candidates per frame
+ * returned and pooled by the aggregation (nframes x k_req at most
+ * HLOC_MAX_REQUEST_CANDIDATES). *ticket identifies it for hloc_server_wait.
+ * Errors: EINVAL, EBUSY (queue full), EDEVICE (the server stopped after a
+ * device error).
+ */
+int hloc_server_submit(hloc_server *srv, const float *frames, int32_t nframes, int32_t k_req,
+                       uint64_t *ticket);
+
+/*
+ * Wait up to timeout_ms (< 0: no limit) for a request and copy its results:
+ * idx / dist nframes x k_req (as hloc_query_batch), xy[2], tile[2], flags[1]
+ * (any output may be NULL) and latency_ms (submit to completion, may be
+ * NULL). A successful wait releases the ticket. Errors: EINVAL (unknown
+ * ticket), ETIMEDOUT (the request stays queued or running; wait again),
+ * EDEVICE.
+ */
+int hloc_server_wait(hloc_server *srv, uint64_t ticket, int32_t timeout_ms, int64_t *idx,
+                     float *dist, double *xy, int32_t *tile, int32_t *flags, double *latency_ms);
+
+/*
+ * Counters: out[0] slots, out[1] bytes of device memory per slot, out[2]
+ * batches run, out[3] requests completed, out[4] frames completed, out[5]
+ * largest batch (frames), out[6] frames waiting now, out[7] most frames
+ * waiting at once, out[8] most batches in flight at once, out[9] submits
+ * refused with EBUSY. Writes min(n, 10) values. Errors: EINVAL.
+ */
+int hloc_server_stats(hloc_server *srv, int64_t *out, int32_t n);
+
+/* Finish the batches in flight, drop queued requests and release the server
+ * (NULL is ignored). Must be called before hloc_free_db of its database. */
+void hloc_server_free(hloc_server *srv);
 
 /* Release every resource of the database (NULL is ignored). */
 void hloc_free_db(hloc_db *db);

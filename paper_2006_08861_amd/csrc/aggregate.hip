@@ -1,7 +1,7 @@
 // Multi-frame candidate aggregation (Section 3.2, Algorithm 2), one block per
 // request, integer arithmetic throughout:
-//   1. the request's frames pool their k candidates each (duplicates count,
-//      padding -1 is dropped) and every candidate becomes its tile key
+//   1. the request's frames pool their k candidates each (or the first
+//      req_k[r] of them; duplicates count, padding -1 is dropped) and every candidate becomes its tile key
 //      (iy, ix) from the precomputed floor(coord / cell) table;
 //   2. the keys are sorted; runs give each distinct tile and its count
 //      (the 2-D binning of the location distribution array);
@@ -44,8 +44,9 @@ __global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
     f0 = req;
     f1 = req + 1;
   }
-  const bool bad = f0 < 0 || f1 < f0 || f1 > a.nq ||
-                   (int64_t)(f1 - f0) * a.k > (int64_t)kAggMax;
+  const int kr = a.req_k ? a.req_k[req] : a.k;  // candidates pooled per frame
+  const bool bad = f0 < 0 || f1 < f0 || f1 > a.nq || kr < 1 || kr > a.k ||
+                   (int64_t)(f1 - f0) * kr > (int64_t)kAggMax;
   if (bad) {
     if (tid == 0) {
       a.tile[2 * req] = 0;
@@ -56,14 +57,15 @@ __global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
     }
     return;
   }
-  const int P = (f1 - f0) * a.k;
+  const int P = (f1 - f0) * kr;
   const int Pp = next_pow2(P > 0 ? P : 1);
   const int64_t *idx = a.idx + (int64_t)f0 * a.k;
   int valid_local = 0;
   for (int p = tid; p < Pp; p += blockDim.x) {
     uint64_t key = kKeyNone;
     if (p < P) {
-      const int64_t j = idx[p];
+      const int fr = p / kr;
+      const int64_t j = idx[(int64_t)fr * a.k + (p - fr * kr)];
       if (j >= 0) {
         const int2 t = a.tile_of[j];
         key = ((uint64_t)flip(t.y) << 32) | flip(t.x);

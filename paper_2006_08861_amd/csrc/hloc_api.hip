@@ -11,20 +11,21 @@
 #include <string>
 #include <vector>
 
-#include "hloc.h"
-#include "hloc_internal.h"
+#include "hloc_host.h"
 
 using namespace hloc;
 
 namespace hloc {
-PhaseEvents *g_phase = nullptr;
+thread_local PhaseEvents *g_phase = nullptr;
 }
 
 namespace {
 
 thread_local std::string g_err;
 
-int fail(int code, const char *fmt, ...) {
+}  // namespace
+
+int hloc::fail(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -34,106 +35,7 @@ int fail(int code, const char *fmt, ...) {
   return code;
 }
 
-#define HIPCHK(expr)                                                                        \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess) return fail(HLOC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
-
-#define CHK(expr)                   \
-  do {                              \
-    int rc_ = (expr);               \
-    if (rc_ != HLOC_OK) return rc_; \
-  } while (0)
-
-struct DeviceGuard {
-  int old = -1;
-  hipError_t err;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&old) != hipSuccess) old = -1;
-    err = hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    if (old >= 0) (void)hipSetDevice(old);
-  }
-};
-
-struct WsBuf {
-  void *p = nullptr;
-  size_t cap = 0;
-};
-
-constexpr int kRegionMargin = 8;    // extra regions re-scored in FP64 by the coarse stage
-constexpr int kOversample = 16;     // extra rows re-scored in FP64 by the fine stage
-constexpr int kRowsCoarse = 64;     // rows (representatives) per coarse work item
-constexpr int kRowsFine = 64;       // rows per fine work item
-constexpr double kUnit32 = 5.9604644775390625e-08;  // 2^-24
-
-template <class T>
-T *as(WsBuf &b) {
-  return reinterpret_cast<T *>(b.p);
-}
-
-struct ProfRec {
-  int phase;
-  hipEvent_t a, b;
-};
-
-}  // namespace
-
-// Scratch memory, counters, profile record and captured graph of one batch in
-// flight. Batches on distinct workspaces may overlap on the device.
-struct hloc_ws {
-  hloc_db *db = nullptr;
-  hipStream_t stream = nullptr;  // own stream (graph capture, host-pointer calls)
-  WsBuf qp, qn2, cand1, regions, rcount, rfill, rq_off, item_off, cand_off, n_cand, misc, rq,
-      items, cand2, agg_xy, agg_tile, agg_flags, qp16, q_err, q_lon;
-  WsBuf s_q, s_off, s_idx, s_dist, s_xy, s_tile, s_flags;  // staging of host-pointer calls
-  int32_t last_nq = 0, last_nr = 0, last_kp = 0;
-  bool prof_on = false;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  std::vector<ProfRec> prof;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-};
-
-struct hloc_db {
-  int device = 0;
-  int num_cu = 256;
-  hipStream_t stream = nullptr;
-  int64_t n = 0;
-  int32_t d = 0, dp = 0;
-  float *rows = nullptr;      // n x dp fp32, region-contiguous once regions are set
-  float *row_n2 = nullptr;    // n squared norms
-  int32_t *perm = nullptr;    // device row -> original index
-  double *xy = nullptr;       // n x 2 by original index
-  int2 *tiles = nullptr;      // n by original index
-  float *norm_max = nullptr;  // [0] rows, [1] representatives, [2] bf16 error, [3] bf16 rows
-  float h_row_max = 0.f, h_rep_max = 0.f;
-  uint32_t mirrors = 0;        // HLOC_MIRROR_* copies kept beside the fp32 rows
-  uint16_t *rows16 = nullptr;  // bf16 copy of rows
-  float h_bf16_err = 0.f, h_bf16_norm = 0.f;
-  std::vector<int32_t> h_perm;
-  double max_abs_coord = 0.0;
-  bool has_regions = false;
-  int32_t R = 0, R_nonempty = 0;
-  int64_t max_region = 0;
-  int64_t *reg_start = nullptr;
-  std::vector<int64_t> h_reg_start;
-  std::vector<int64_t> h_desc_prefix;  // sum of the j largest region sizes, j = 0..R
-  int64_t chunks_fine = 0;             // sum over regions of ceil(size / kRowsFine)
-  int32_t *nonempty_ids = nullptr;
-  double *rep64 = nullptr;
-  float *rep32 = nullptr;
-  float *rep_n2 = nullptr;
-  double cell = 0.5, radius = 0.0;
-  int32_t top_c = 1, rho = 0, pct = 0;
-  hloc_ws *ws0 = nullptr;  // workspace of the calls that take no workspace
-  int32_t user_ws = 0;     // workspaces created by the caller and not yet freed
-};
-
-namespace {
+namespace hloc {
 
 void free_buf(WsBuf &b) {
   if (b.p) (void)hipFree(b.p);
@@ -141,11 +43,13 @@ void free_buf(WsBuf &b) {
   b.cap = 0;
 }
 
+size_t alloc_size(size_t bytes) { return std::max<size_t>(bytes + bytes / 4, 256); }
+
 int ensure(WsBuf &b, size_t bytes) {
   if (bytes <= b.cap && b.p) return HLOC_OK;
   HIPCHK(hipDeviceSynchronize());  // the old buffer may still be in use
   free_buf(b);
-  size_t want = std::max<size_t>(bytes + bytes / 4, 256);
+  const size_t want = alloc_size(bytes);
   if (hipMalloc(&b.p, want) != hipSuccess) {
     (void)hipGetLastError();
     b.p = nullptr;
@@ -172,12 +76,6 @@ void dev_free(T *&p) {
   p = nullptr;
 }
 
-struct Plan {
-  int32_t nq, k, nr, L1, kp, nreq, precision;
-  bool exhaustive;
-  int64_t cap2, items_bound;
-  int32_t grid1, grid2;
-};
 
 int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32_t nreq,
               int32_t precision, Plan *pl) {
@@ -227,33 +125,41 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
   return HLOC_OK;
 }
 
-int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal) {
+int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *bytes) {
   const hloc_db *db = ws->db;
+  // with `bytes`: only add up what the buffers would take
+  auto fit = [&](WsBuf &b, size_t need) -> int {
+    if (bytes) {
+      *bytes += alloc_size(need);
+      return HLOC_OK;
+    }
+    return ensure(b, need);
+  };
   const int64_t nq = std::max(p.nq, 1), nr = std::max(p.nr, 1);
-  CHK(ensure(ws->qp, (size_t)nq * db->dp * sizeof(float)));
-  CHK(ensure(ws->qn2, (size_t)nq * sizeof(float)));
-  if (!p.exhaustive) CHK(ensure(ws->cand1, (size_t)nq * db->R * sizeof(uint64_t)));
-  CHK(ensure(ws->regions, (size_t)nq * nr * sizeof(int32_t)));
-  CHK(ensure(ws->rcount, (size_t)db->R * sizeof(int32_t)));
-  CHK(ensure(ws->rfill, (size_t)db->R * sizeof(int32_t)));
-  CHK(ensure(ws->rq_off, (size_t)(db->R + 1) * sizeof(int32_t)));
-  CHK(ensure(ws->item_off, (size_t)(db->R + 1) * sizeof(int32_t)));
-  CHK(ensure(ws->cand_off, (size_t)nq * nr * sizeof(int32_t)));
-  CHK(ensure(ws->n_cand, (size_t)nq * sizeof(int32_t)));
-  CHK(ensure(ws->misc, 16 * sizeof(int32_t)));
-  CHK(ensure(ws->rq, (size_t)nq * nr * sizeof(int2)));
-  CHK(ensure(ws->items, (size_t)std::max<int64_t>(p.items_bound, 1) * sizeof(Item)));
-  CHK(ensure(ws->cand2, (size_t)nq * std::max<int64_t>(p.cap2, 1) * sizeof(uint64_t)));
+  CHK(fit(ws->qp, (size_t)nq * db->dp * sizeof(float)));
+  CHK(fit(ws->qn2, (size_t)nq * sizeof(float)));
+  if (!p.exhaustive) CHK(fit(ws->cand1, (size_t)nq * db->R * sizeof(uint32_t)));
+  CHK(fit(ws->regions, (size_t)nq * nr * sizeof(int32_t)));
+  CHK(fit(ws->rcount, (size_t)db->R * sizeof(int32_t)));
+  CHK(fit(ws->rfill, (size_t)db->R * sizeof(int32_t)));
+  CHK(fit(ws->rq_off, (size_t)(db->R + 1) * sizeof(int32_t)));
+  CHK(fit(ws->item_off, (size_t)(db->R + 1) * sizeof(int32_t)));
+  CHK(fit(ws->cand_off, (size_t)nq * nr * sizeof(int32_t)));
+  CHK(fit(ws->n_cand, (size_t)nq * sizeof(int32_t)));
+  CHK(fit(ws->misc, 16 * sizeof(int32_t)));
+  CHK(fit(ws->rq, (size_t)nq * nr * sizeof(int2)));
+  CHK(fit(ws->items, (size_t)std::max<int64_t>(p.items_bound, 1) * sizeof(Item)));
+  CHK(fit(ws->cand2, (size_t)nq * std::max<int64_t>(p.cap2, 1) * sizeof(uint32_t)));
   if (db->rows16) {
-    CHK(ensure(ws->qp16, (size_t)nq * db->dp * sizeof(uint16_t)));
-    CHK(ensure(ws->q_err, (size_t)nq * sizeof(float)));
-    CHK(ensure(ws->q_lon, (size_t)nq * sizeof(float)));
+    CHK(fit(ws->qp16, (size_t)nq * db->dp * sizeof(uint16_t)));
+    CHK(fit(ws->q_err, (size_t)nq * sizeof(float)));
+    CHK(fit(ws->q_lon, (size_t)nq * sizeof(float)));
   }
   if (agg_internal) {
     const int64_t nreq = std::max(p.nreq, 1);
-    CHK(ensure(ws->agg_xy, (size_t)nreq * 2 * sizeof(double)));
-    CHK(ensure(ws->agg_tile, (size_t)nreq * 2 * sizeof(int32_t)));
-    CHK(ensure(ws->agg_flags, (size_t)nreq * sizeof(int32_t)));
+    CHK(fit(ws->agg_xy, (size_t)nreq * 2 * sizeof(double)));
+    CHK(fit(ws->agg_tile, (size_t)nreq * 2 * sizeof(int32_t)));
+    CHK(fit(ws->agg_flags, (size_t)nreq * sizeof(int32_t)));
   }
   return HLOC_OK;
 }
@@ -292,8 +198,8 @@ struct Phaser {
 };
 
 int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req_offsets,
-                  int64_t *idx, float *dist, double *xy, int32_t *tile, int32_t *flags,
-                  hipStream_t s) {
+                  const int32_t *req_k, int64_t *idx, float *dist, double *xy, int32_t *tile,
+                  int32_t *flags, hipStream_t s) {
   const hloc_db *db = ws->db;
   const bool want_agg = xy || tile || flags;
   CHK(ensure_workspace(ws, p, want_agg && !(xy && tile && flags)));
@@ -323,7 +229,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     sa.dp = db->dp;
     sa.qp = qp;
     sa.qn2 = qn2;
-    sa.cand = as<uint64_t>(ws->cand1);
+    sa.cand = as<uint32_t>(ws->cand1);
     sa.cap = db->R;
     sa.rows_per_item = kRowsCoarse;
     sa.dense = 1;
@@ -331,7 +237,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     sa.nq = p.nq;
     HIPCHK(launch_screen_f32(sa, p.grid1, s));
     SelRerankArgs ra{};
-    ra.cand = as<uint64_t>(ws->cand1);
+    ra.cand = as<uint32_t>(ws->cand1);
     ra.cap = db->R;
     ra.n_fixed = db->R;
     ra.L = p.L1;
@@ -362,7 +268,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   sb.dp = db->dp;
   sb.qp = qp;
   sb.qn2 = qn2;
-  sb.cand = as<uint64_t>(ws->cand2);
+  sb.cand = as<uint32_t>(ws->cand2);
   sb.cap = p.cap2;
   sb.rows_per_item = kRowsFine;
   sb.dense = 0;
@@ -379,8 +285,15 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   }
   ph.begin(HLOC_PHASE_SELECT);
   SelRerankArgs rb{};
-  rb.cand = as<uint64_t>(ws->cand2);
+  rb.cand = as<uint32_t>(ws->cand2);
   rb.cap = p.cap2;
+  // positions -> rows through the frame's region slots; in the exhaustive
+  // search the slots are every non-empty region in id order, so the position
+  // is the row itself
+  rb.nslots = p.exhaustive ? 0 : p.nr;
+  rb.slot_off = cand_off;
+  rb.slot_reg = regions;
+  rb.reg_start = db->reg_start;
   rb.n_cand = n_cand;
   rb.L = p.kp;
   rb.m = p.k;
@@ -414,6 +327,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     ag.k = p.k;
     ag.nq = p.nq;
     ag.req_offsets = req_offsets;
+    ag.req_k = req_k;
     ag.nreq = p.nreq;
     ag.tile_of = db->tiles;
     ag.cell = db->cell;
@@ -526,7 +440,7 @@ int query_async(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int32_t n_re
   CHK(make_plan(db, nq, k, n_regions, nreq, precision, &p));
   DeviceGuard g(db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
-  return enqueue_query(ws, p, q, req_offsets, idx, dist, xy, tile, flags, s);
+  return enqueue_query(ws, p, q, req_offsets, nullptr, idx, dist, xy, tile, flags, s);
 }
 
 int info_of(hloc_ws *ws, int64_t *out, int32_t n) {
@@ -546,7 +460,7 @@ int info_of(hloc_ws *ws, int64_t *out, int32_t n) {
   return HLOC_OK;
 }
 
-}  // namespace
+}  // namespace hloc
 
 extern "C" {
 
@@ -621,6 +535,7 @@ int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, ui
 int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_total,
                      const float *reps) {
   if (!db || !region_of) return fail(HLOC_EINVAL, "db and region_of must be non-NULL");
+  if (db->servers > 0) return fail(HLOC_ESTATE, "a request server is using the database");
   if (n_regions_total < 1) return fail(HLOC_EINVAL, "n_regions_total must be >= 1");
   const int64_t n = db->n;
   const int32_t R = n_regions_total;
@@ -726,6 +641,7 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
 int hloc_set_aggregation(hloc_db *db, double cell_m, int32_t top_c, double radius_m,
                          int32_t toler_pct) {
   if (!db) return fail(HLOC_EINVAL, "db is NULL");
+  if (db->servers > 0) return fail(HLOC_ESTATE, "a request server is using the database");
   if (!(cell_m > 0.0) || !std::isfinite(cell_m)) return fail(HLOC_EINVAL, "cell_m must be > 0");
   if (top_c < 1 || top_c > HLOC_MAX_TOP_C) return fail(HLOC_EINVAL, "top_c must be in 1..%d", HLOC_MAX_TOP_C);
   if (!(radius_m >= 0.0) || !std::isfinite(radius_m)) return fail(HLOC_EINVAL, "radius_m must be >= 0");
@@ -815,7 +731,8 @@ int hloc_ws_capture(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int32_t 
   const bool prof = ws->prof_on;
   ws->prof_on = false;
   HIPCHK(hipStreamBeginCapture(ws->stream, hipStreamCaptureModeThreadLocal));
-  const int rc = enqueue_query(ws, p, q, req_offsets, idx, dist, xy, tile, flags, ws->stream);
+  const int rc = enqueue_query(ws, p, q, req_offsets, nullptr, idx, dist, xy, tile, flags,
+                               ws->stream);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(ws->stream, &graph);
   ws->prof_on = prof;
@@ -871,7 +788,7 @@ int hloc_query_batch(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t
     HIPCHK(hipMemcpyAsync(ws->s_off.p, req_offsets, (size_t)(nreq + 1) * sizeof(int32_t),
                           hipMemcpyHostToDevice, s));
   CHK(enqueue_query(ws, p, as<float>(ws->s_q), req_offsets ? as<int32_t>(ws->s_off) : nullptr,
-                    as<int64_t>(ws->s_idx), as<float>(ws->s_dist),
+                    nullptr, as<int64_t>(ws->s_idx), as<float>(ws->s_dist),
                     want_agg ? as<double>(ws->s_xy) : nullptr,
                     want_agg ? as<int32_t>(ws->s_tile) : nullptr,
                     want_agg ? as<int32_t>(ws->s_flags) : nullptr, s));

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace hloc {
 
 // Event pair that times one phase of a query. While g_phase is set, every
@@ -19,7 +21,7 @@ struct PhaseEvents {
   hipEvent_t stop = nullptr;
   int launches = 0;
 };
-extern PhaseEvents *g_phase;
+extern thread_local PhaseEvents *g_phase;
 
 template <typename F, typename... Args>
 inline hipError_t launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s,
@@ -65,7 +67,7 @@ struct ScreenArgs {
   int32_t dp;             // padded row length (multiple of 32)
   const float *qp;        // frames x dp
   const float *qn2;       // frames squared norms
-  uint64_t *cand;         // per frame: cap keys (dist bits << 32 | row)
+  uint32_t *cand;         // per frame: cap screen words (float bits of the screen distance)
   int64_t cap;
   int32_t rows_per_item;  // T, multiple of 16
   // dense mode: every frame against rows [0, nrows)
@@ -104,13 +106,21 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
                         int32_t *rq_off, int32_t *item_off, int32_t *cand_off, int32_t *n_cand,
                         int32_t *n_items, int2 *rq, Item *items, hipStream_t s);
 
-// Per frame: the L + 1 smallest screen keys of cand[f][0 .. n(f)) (n(f) =
-// n_cand ? n_cand[f] : n_fixed; kKeyNone entries are skipped), FP64 rerank of
-// the L smallest, top m by (distance, tie id), certificate against the
-// (L + 1)-th, and the exact FP64 pass over all candidates when it fails.
+// Per frame: the L + 1 smallest screen words of cand[f][0 .. n(f)) (n(f) =
+// n_cand ? n_cand[f] : n_fixed; 0xFFFFFFFF entries are skipped; equal words
+// ordered by position), FP64 rerank of the L smallest, top m by (distance,
+// tie id), certificate against the (L + 1)-th, and the exact FP64 pass over
+// all candidates when it fails. Candidate positions map to source rows through
+// the frame's region slots (slot j: region slot_reg[f][j] from position
+// slot_off[f][j]), or are the rows themselves when nslots is 0.
 struct SelRerankArgs {
-  const uint64_t *cand;
+  const uint32_t *cand;
   int64_t cap;
+  const int32_t *slot_off;   // nq x nslots
+  const int32_t *slot_reg;   // nq x nslots
+  int32_t nslots;            // <= 1024
+  const int64_t *reg_start;  // first row of each region
+  int32_t cache;             // words kept in LDS (set by the launcher)
   const int32_t *n_cand;
   int32_t n_fixed;
   int32_t L;               // survivors re-scored in FP64 (<= kMaxSurvivors)
@@ -136,7 +146,7 @@ struct SelRerankArgs {
   int32_t *stat_fallback;  // frames that needed the exact pass
   int32_t *stat_max;       // largest candidate count (or NULL)
 };
-hipError_t launch_select_rerank(const SelRerankArgs &a, hipStream_t s);
+hipError_t launch_select_rerank(SelRerankArgs a, hipStream_t s);
 
 // Aggregation (Algorithm 2) per request.
 struct AggArgs {
@@ -144,6 +154,7 @@ struct AggArgs {
   int32_t k;
   int32_t nq;
   const int32_t *req_offsets;  // nreq + 1 or NULL (one frame per request)
+  const int32_t *req_k;      // per request: candidates per frame pooled (<= k), or NULL (k)
   int32_t nreq;
   const int2 *tile_of;       // original index -> (ix, iy)
   double cell;

@@ -68,23 +68,33 @@ hipError_t launch_rows_to_bf16(const float *src, int64_t n, int32_t dp, uint16_t
                        dp, dst, max_err, max_norm);
 }
 
+// 64-row items, the 16-row block w of the item on wave w; item order, the
+// prefetch of the next list item and the epilogue as in the fp32 register
+// screen.
 template <int NS, bool DENSE>  // NS = dp / 32
 __global__ __launch_bounds__(256) void k_screen_bf16(ScreenArgs a) {
   constexpr int DP = NS * 32;
-  const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
+  const int lane = lane_id(), w = wave_id();
   const int i = lane & 15, g = lane >> 4;
-  int n_items, nchunks = 1;
+  int n_items, ngroups = 1;
   if (DENSE) {
-    nchunks = (a.nrows + a.rows_per_item - 1) / a.rows_per_item;
-    n_items = nchunks * ((a.nq + kGroup - 1) / kGroup);
+    ngroups = (a.nq + kGroup - 1) / kGroup;
+    n_items = ((a.nrows + a.rows_per_item - 1) / a.rows_per_item) * ngroups;
   } else {
     n_items = *a.n_items;
   }
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  const ItemWalk wk = item_walk(n_items);
+  Item nit{};
+  int2 ne = make_int2(0, 0);
+  if (!DENSE && wk.it < wk.end) {
+    nit = a.items[wk.it];
+    if (i < (nit.nrows_gq & 0xFFFF)) ne = a.rq[nit.q0 + i];
+  }
+  for (int it = wk.it; it < wk.end; it += wk.step) {
     int row_begin, chunk_row, nrows, gq, fr = 0;
     int64_t off = 0;
     if (DENSE) {
-      const int c = it % nchunks, grp = it / nchunks;
+      const int c = it / ngroups, grp = it - c * ngroups;
       row_begin = c * a.rows_per_item;
       chunk_row = row_begin;
       nrows = min(a.rows_per_item, a.nrows - row_begin);
@@ -92,52 +102,59 @@ __global__ __launch_bounds__(256) void k_screen_bf16(ScreenArgs a) {
       fr = grp * kGroup + i;
       off = (int64_t)fr * a.cap + chunk_row;
     } else {
-      const Item itm = a.items[it];
-      row_begin = itm.row_begin;
-      chunk_row = itm.chunk_row;
-      nrows = itm.nrows_gq >> 16;
-      gq = itm.nrows_gq & 0xFFFF;
+      row_begin = nit.row_begin;
+      chunk_row = nit.chunk_row;
+      nrows = nit.nrows_gq >> 16;
+      gq = nit.nrows_gq & 0xFFFF;
       if (i < gq) {
-        const int2 e = a.rq[itm.q0 + i];
-        fr = e.x;
-        off = (int64_t)e.x * a.cap + e.y + chunk_row;
+        fr = ne.x;
+        off = (int64_t)ne.x * a.cap + ne.y + chunk_row;
       }
     }
     if (i >= gq) fr = 0;
-    const int nrb = (nrows + 15) >> 4;
-    for (int rb = w; rb < nrb; rb += nw) {
-      const int rl = min(rb * 16 + i, nrows - 1);
-      const uint4 *rp = reinterpret_cast<const uint4 *>(a.rows16 + (int64_t)(row_begin + rl) * DP) + g;
+    const bool active = w * 16 < nrows;
+    uint4 av[NS], bv[NS];
+    float rn[4], qn = 0.f;
+    if (active) {
+      const int rl = min(w * 16 + i, nrows - 1);
+      const uint4 *rp =
+          reinterpret_cast<const uint4 *>(a.rows16 + (int64_t)(row_begin + rl) * DP) + g;
       const uint4 *qp = reinterpret_cast<const uint4 *>(a.qp16 + (int64_t)fr * DP) + g;
-      uint4 av[NS], bv[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) av[s] = rp[4 * s];
 #pragma unroll
       for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
-      const float qn = a.qn2[fr];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rn[r] = a.row_n2[row_begin + min(w * 16 + 4 * g + r, nrows - 1)];
+      qn = a.qn2[fr];
+    }
+    const int nx = it + wk.step;
+    if (!DENSE && nx < wk.end) nit = a.items[nx];
+    if (active) {
       v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < NS; ++s)
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av[s]),
                                                       __builtin_bit_cast(v8bf, bv[s]), acc, 0,
                                                       0, 0);
+      if (!DENSE && nx < wk.end && i < (nit.nrows_gq & 0xFFFF)) ne = a.rq[nit.q0 + i];
       if (i < gq) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = rb * 16 + 4 * g + r;
+          const int row = w * 16 + 4 * g + r;
           if (row < nrows) {
-            const int grow = row_begin + row;
-            const float rn = a.row_n2[grow];
-            uint64_t key = kKeyNone;
-            if (!__builtin_isinf(rn)) {
-              float dd = (qn + rn) - 2.f * acc[r];
+            uint32_t word = 0xFFFFFFFFu;
+            if (!__builtin_isinf(rn[r])) {
+              float dd = (qn + rn[r]) - 2.f * acc[r];
               dd = dd > 0.f ? dd : 0.f;
-              key = dist_key(dd, (uint32_t)grow);
+              word = __float_as_uint(dd);
             }
-            a.cand[off + row] = key;
+            a.cand[off + row] = word;
           }
         }
       }
+    } else if (!DENSE && nx < wk.end && i < (nit.nrows_gq & 0xFFFF)) {
+      ne = a.rq[nit.q0 + i];
     }
   }
 }
@@ -149,7 +166,7 @@ hipError_t launch_bf16_t(const ScreenArgs &a, int32_t grid, hipStream_t s) {
 
 hipError_t launch_screen_bf16(const ScreenArgs &a, int32_t grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  if (a.rows_per_item % 16 != 0) return hipErrorInvalidValue;
+  if (a.rows_per_item != 64 || grid % kXcds != 0) return hipErrorInvalidValue;
   switch (a.dp) {
 #define HLOC_BF16_CASE(DPV)                                     \
   case DPV:                                                    \

@@ -1,27 +1,29 @@
 // Top candidates per frame ("select top candidates", Algorithm 1), one block
 // per frame, in one kernel:
-//   1. select: the L + 1 smallest screen keys (dist_bits << 32 | row; one
-//      integer compare orders by screen distance, then row). The keys are
-//      cached in LDS; a radix select finds the distance word of the (L+1)-th
-//      key (leading bits shared by the smallest and largest word skipped, the
-//      rest resolved 8 bits per pass with an LDS histogram), a second one its
-//      row among the keys with that word. Keys are unique, so exactly L + 1
-//      keys are <= the threshold;
-//   2. rerank: FP64 direct sum of (q_i - d_i)^2 for the L smallest (the
-//      survivors), ordered by (distance, tie id) with tie id = original row
+//   1. select: the L + 1 smallest screen words (float bits of the screen
+//      distance, one per candidate position; the bits of a non-negative float
+//      order like its value), ties between equal words going to the smaller
+//      position. The words are cached in LDS; a radix select finds the word of
+//      the (L+1)-th (leading bits shared by the smallest and largest word
+//      skipped, the rest resolved kDigitBits per pass with an LDS histogram);
+//   2. rerank: the positions of the L smallest (the survivors) are mapped to
+//      source rows through the frame's region slots, then FP64 direct sum of
+//      (q_i - d_i)^2, ordered by (distance, tie id) with tie id = original row
 //      index (fine stage) or region id (coarse stage);
-//   3. certificate: the largest selected key is the best rejected screen
-//      distance; if it minus the screen's error bound does not exceed the
-//      m-th reranked distance, the block also re-scores every rejected
-//      candidate within that bound (or, if there are too many, all of them)
-//      and counts the frame.
+//   3. certificate: the (L+1)-th word is the best rejected screen distance; if
+//      it minus the screen's error bound does not exceed the m-th reranked
+//      distance, the block also re-scores every rejected candidate within that
+//      bound (or, if there are too many, all of them) and counts the frame.
 // Distances are squared L2 (same order as the Euclidean distance of Section 4).
 #include "hloc_device.h"
 #include "hloc_internal.h"
 
 namespace hloc {
 
-constexpr int kKeyCache = 8192;  // candidate keys kept in (dynamic) LDS
+constexpr int kWordCache = 16384;  // screen words of a frame kept in (dynamic) LDS
+constexpr int kMaxSlots = 1024;    // region slots of a frame kept in (dynamic) LDS
+constexpr uint32_t kWordNone = 0xFFFFFFFFu;  // no candidate at this position
+constexpr int kDigitBits = 11;     // radix digit of the select (three passes cover 32 bits)
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
@@ -73,12 +75,13 @@ __device__ __forceinline__ double thread_dist(const SelRerankArgs &a, const floa
 }
 
 struct SelShared {
-  uint64_t sel[kMaxSurvivors + 1];
+  uint32_t sel[kMaxSurvivors + 1];  // candidate positions of the survivors (+ band)
+  uint32_t srow[kMaxSurvivors];     // their source rows
   uint64_t sort_hi[kMaxSurvivors];
   uint32_t sort_lo[kMaxSurvivors];
-  int hist[4096];
-  int part[256];
+  int hist[1 << kDigitBits];
   int red_i[16];
+  int red_j[16];
   uint32_t red_u[16];
   uint32_t red_v[16];
   uint32_t word;
@@ -102,11 +105,32 @@ __device__ __forceinline__ int block_incl_scan(int v, int *wave_tot) {
   return v;
 }
 
+// The same for two ints per thread at once.
+__device__ __forceinline__ void block_incl_scan2(int &v, int &u, int *tot_v, int *tot_u) {
+  const int lane = lane_id(), w = wave_id();
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(v, o), z = __shfl_up(u, o);
+    if (lane >= o) {
+      v += y;
+      u += z;
+    }
+  }
+  if (lane == 63) {
+    tot_v[w] = v;
+    tot_u[w] = u;
+  }
+  __syncthreads();
+  for (int i = 0; i < w; ++i) {
+    v += tot_v[i];
+    u += tot_u[i];
+  }
+}
+
 // Block-wide radix select over 32-bit words: returns the target-th smallest
 // (1-based) of get(i), i < n, ignoring 0xFFFFFFFF (no candidate); every other
 // word lies in [lo, hi]. *krem_out receives its rank among equal words and
 // *eq_out how many words equal it. Leading bits shared by lo and hi are
-// skipped; the rest are resolved 12 bits per pass with an LDS histogram.
+// skipped; the rest are resolved kDigitBits per pass with an LDS histogram.
 template <class Get>
 __device__ uint32_t block_select_u32(Get get, int n, uint32_t lo, uint32_t hi, int target,
                                      SelShared &sh, int *krem_out, int *eq_out) {
@@ -127,7 +151,7 @@ __device__ uint32_t block_select_u32(Get get, int n, uint32_t lo, uint32_t hi, i
     __syncthreads();
   }
   while (remaining > 0) {
-    const int bits = remaining >= 12 ? 12 : remaining;
+    const int bits = remaining >= kDigitBits ? kDigitBits : remaining;
     const int nb = 1 << bits;
     const int shift = remaining - bits;
     const int top = shift + bits;
@@ -193,7 +217,7 @@ __device__ __forceinline__ void wave_sort64_pairs(uint64_t &hi, uint32_t &lo) {
 constexpr int kRowBatch = 8;    // survivor rows fetched together by one wave
 constexpr int kEarlyKeys = 1024;  // keys requested before the count is known
 
-// FP64 distances of the frame to source rows sh.sel[s0 .. s1) into
+// FP64 distances of the frame to source rows sh.srow[s0 .. s1) into
 // sort_hi / sort_lo[s] (distance bits, tie id). For fp32 sources each wave
 // fetches kRowBatch rows at once with the frame slice reused across them.
 __device__ void rerank_range(const SelRerankArgs &a, SelShared &sh, const float *qrow, int s0,
@@ -209,7 +233,7 @@ __device__ void rerank_range(const SelRerankArgs &a, SelShared &sh, const float 
 #pragma unroll
       for (int r = 0; r < kRowBatch; ++r) {
         acc[r] = 0.0;
-        const uint32_t row = (uint32_t)sh.sel[min(b + r, s1 - 1)];
+        const uint32_t row = sh.srow[min(b + r, s1 - 1)];
         rp[r] = a.src32 + (int64_t)row * a.dp;
         tie[r] = (lane == r && a.tie_of) ? (uint32_t)a.tie_of[row] : row;
       }
@@ -242,7 +266,7 @@ __device__ void rerank_range(const SelRerankArgs &a, SelShared &sh, const float 
     }
   } else {
     for (int sidx = s0 + w; sidx < s1; sidx += nw) {
-      const uint32_t row = (uint32_t)sh.sel[sidx];
+      const uint32_t row = sh.srow[sidx];
       const double d = wave_dist_f64(a.src64 + (int64_t)row * a.dp, qrow, a.dp);
       if (lane == 0) {
         sh.sort_hi[sidx] = (uint64_t)__double_as_longlong(d);
@@ -278,51 +302,74 @@ __device__ void sort_pairs(SelShared &sh, int cnt) {
   }
 }
 
+// Source row of candidate position p of a frame: with region slots, slot j
+// holds the rows of region s_reg[j] at positions s_off[j] .. (s_off[0] = 0,
+// non-decreasing; the slot holding p is the last with s_off[j] <= p, and it
+// is never empty); without slots the position is the row.
+__device__ __forceinline__ uint32_t row_of(const int32_t *s_off, const int32_t *s_reg, int nslots,
+                                           const int64_t *__restrict__ reg_start, uint32_t p) {
+  if (nslots == 0) return p;
+  int lo = 0, hi = nslots;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (s_off[mid] <= (int32_t)p) lo = mid;
+    else hi = mid;
+  }
+  return (uint32_t)(reg_start[s_reg[lo]] + ((int32_t)p - s_off[lo]));
+}
+
 __global__ __launch_bounds__(256) void k_select_rerank(SelRerankArgs a) {
   __shared__ SelShared sh;
-  extern __shared__ uint64_t kc[];  // up to kKeyCache keys of the frame
+  extern __shared__ uint32_t dyn[];  // [slot offsets | slot regions | word cache]
   const int f = blockIdx.x;
   if (f >= a.nq) return;
   const int tid = threadIdx.x, w = wave_id(), lane = lane_id();
   const int nw = blockDim.x >> 6;
-  const uint64_t *keys = a.cand + (int64_t)f * a.cap;
-  // the first keys are requested together with the count (one round trip)
+  const int nslots = a.nslots;
+  int32_t *s_off = reinterpret_cast<int32_t *>(dyn);
+  int32_t *s_reg = s_off + nslots;
+  uint32_t *wc = dyn + 2 * nslots;
+  const uint32_t *words = a.cand + (int64_t)f * a.cap;
+  // the first words are requested together with the count (one round trip)
   const int early = (int)min<int64_t>(a.cap, kEarlyKeys);
-  uint64_t ek[kEarlyKeys / 256];
+  uint32_t ew[kEarlyKeys / 256];
 #pragma unroll
   for (int u = 0; u < kEarlyKeys / 256; ++u) {
     const int i = u * 256 + tid;
-    ek[u] = (i < early && tid < 256) ? keys[i] : kKeyNone;
+    ew[u] = (i < early && tid < 256) ? words[i] : kWordNone;
+  }
+  for (int j = tid; j < nslots; j += blockDim.x) {
+    s_off[j] = a.slot_off[(int64_t)f * nslots + j];
+    s_reg[j] = a.slot_reg[(int64_t)f * nslots + j];
   }
   const int n = a.n_cand ? a.n_cand[f] : a.n_fixed;
+  const int C = min(n, a.cache);  // positions [0, C) cached, the rest read from memory
   const float qn2 = a.qn2[f];
-  const bool cached = n <= kKeyCache;
   if (tid == 0 && a.stat_max) atomicMax(a.stat_max, n);
-  auto key_at = [&](int i) -> uint64_t { return cached ? kc[i] : keys[i]; };
+  auto word_at = [&](int i) -> uint32_t { return i < C ? wc[i] : words[i]; };
 
   int nv_local = 0;
   uint32_t vmin = 0xFFFFFFFFu, vmax = 0u;
-  auto account = [&](int i, uint64_t k) {
+  auto account = [&](int i, uint32_t v) {
     if (i >= n) return;
-    if (cached) kc[i] = k;
-    if (k != kKeyNone) {
-      const uint32_t h = (uint32_t)(k >> 32);
+    if (i < C) wc[i] = v;
+    if (v != kWordNone) {
       ++nv_local;
-      vmin = min(vmin, h);
-      vmax = max(vmax, h);
+      vmin = min(vmin, v);
+      vmax = max(vmax, v);
     }
   };
 #pragma unroll
-  for (int u = 0; u < kEarlyKeys / 256; ++u) account(u * 256 + tid, ek[u]);
-  for (int base = kEarlyKeys; base < n; base += 4 * blockDim.x) {
-    uint64_t k[4];
+  for (int u = 0; u < kEarlyKeys / 256; ++u) account(u * 256 + tid, ew[u]);
+  for (int base = kEarlyKeys; base < n; base += 8 * blockDim.x) {
+    uint32_t v[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       const int i = base + u * blockDim.x + tid;
-      k[u] = i < n ? keys[i] : kKeyNone;
+      v[u] = i < n ? words[i] : kWordNone;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) account(base + u * blockDim.x + tid, k[u]);
+    for (int u = 0; u < 8; ++u) account(base + u * blockDim.x + tid, v[u]);
   }
   nv_local = wave_sum_i32(nv_local);
   vmin = wave_min_u32(vmin);
@@ -345,64 +392,61 @@ __global__ __launch_bounds__(256) void k_select_rerank(SelRerankArgs a) {
   const int L = a.L;
   const int nsurv = min(L, nvalid);
   const bool rejected = nvalid > L;
-  // the (L+1)-th smallest key: its distance word by radix select, then, if
-  // several keys share that word, its row among them
-  uint64_t thresh = kKeyNone;
+  // the (L+1)-th smallest (word, position): its word tw by radix select; the
+  // survivors are every word below tw and the first take_eq positions whose
+  // word equals tw
+  uint32_t tw = kWordNone;
+  int take_eq = 0;
   if (rejected) {
     int krem, eq;
-    const uint32_t tw = block_select_u32([&](int i) { return (uint32_t)(key_at(i) >> 32); }, n,
-                                         vmin, vmax, L + 1, sh, &krem, &eq);
-    uint32_t rw;
-    if (eq == 1) {
-      // the one key with word tw: found by whichever thread holds it
-      for (int i = tid; i < n; i += blockDim.x) {
-        const uint64_t k = key_at(i);
-        if ((uint32_t)(k >> 32) == tw) sh.word = (uint32_t)k;
-      }
-      __syncthreads();
-      rw = sh.word;
-      __syncthreads();
-    } else {
-      int e2;
-      rw = block_select_u32(
-          [&](int i) {
-            const uint64_t k = key_at(i);
-            return (uint32_t)(k >> 32) == tw ? (uint32_t)k : 0xFFFFFFFFu;
-          },
-          n, 0u, 0x7FFFFFFFu, krem, sh, &krem, &e2);
-    }
-    thresh = ((uint64_t)tw << 32) | rw;
+    tw = block_select_u32(word_at, n, vmin, vmax, L + 1, sh, &krem, &eq);
+    take_eq = krem - 1;
   }
-  // survivors: every valid key below the threshold (all valid keys if none is
-  // rejected); each thread takes a contiguous run, one block scan places them
+  const int n_lt = nsurv - take_eq;
+  // each thread takes a contiguous run of positions, so that one block scan
+  // orders both the survivors below tw and the positions equal to tw
+  const int per = (n + blockDim.x - 1) / blockDim.x;
+  const int i0 = min(n, tid * per), i1 = min(n, i0 + per);
+  int eq_base;
   {
-    const int per = (n + blockDim.x - 1) / blockDim.x;
-    const int i0 = tid * per, i1 = min(n, i0 + per);
-    int mine = 0;
+    int mlt = 0, meq = 0;
     for (int i = i0; i < i1; ++i) {
-      const uint64_t k = key_at(i);
-      mine += k != kKeyNone && k < thresh;
+      const uint32_t v = word_at(i);
+      mlt += v < tw;
+      meq += rejected && v == tw;
     }
-    int pos = block_incl_scan(mine, sh.red_i) - mine;
+    int ilt = mlt, ieq = meq;
+    block_incl_scan2(ilt, ieq, sh.red_i, sh.red_j);
+    int plt = ilt - mlt, peq = ieq - meq;
+    eq_base = peq;
     for (int i = i0; i < i1; ++i) {
-      const uint64_t k = key_at(i);
-      if (k != kKeyNone && k < thresh) sh.sel[pos++] = k;
+      const uint32_t v = word_at(i);
+      if (v < tw) {
+        sh.sel[plt++] = (uint32_t)i;
+      } else if (rejected && v == tw) {
+        if (peq < take_eq) sh.sel[n_lt + peq] = (uint32_t)i;
+        ++peq;
+      }
     }
     __syncthreads();
   }
+  for (int s = tid; s < nsurv; s += blockDim.x)
+    sh.srow[s] = row_of(s_off, s_reg, nslots, a.reg_start, sh.sel[s]);
+  __syncthreads();
   // FP64 rerank of the survivors, sorted by (distance, tie id)
   const float *qrow = a.qp + (int64_t)f * a.dp;
   rerank_range(a, sh, qrow, 0, nsurv);
   __syncthreads();
   sort_pairs(sh, nsurv);
-  // certificate: a rejected key can only beat the m-th reranked distance dm if
-  // its screen distance is within the screen's error bound e of dm. If the
-  // best rejected one is not beyond dm + e, every rejected key up to dm + e
-  // (the band) is re-scored too; if the band does not fit, every candidate is.
+  // certificate: a rejected candidate can only beat the m-th reranked
+  // distance dm if its screen distance is within the screen's error bound e
+  // of dm. If the best rejected one is not beyond dm + e, every rejected
+  // candidate up to dm + e (the band) is re-scored too; if the band does not
+  // fit, every candidate is.
   if (tid == 0) {
     sh.flag = 0;
     if (rejected && a.m > 0) {
-      const double rejd = (double)__uint_as_float((uint32_t)(thresh >> 32));
+      const double rejd = (double)__uint_as_float(tw);
       const double qn = sqrt((double)qn2) * (1.0 + 1e-6);
       double e = a.err_coef * (qn + a.max_norm) * (qn + a.max_norm);
       if (a.q_err) {
@@ -421,13 +465,17 @@ __global__ __launch_bounds__(256) void k_select_rerank(SelRerankArgs a) {
   __syncthreads();
   int have = min(nsurv, a.m);
   if (sh.flag) {
+    // the band: rejected positions (above tw, or equal to tw past the first
+    // take_eq) with a word up to tau_w (>= tw)
     const uint32_t tau_w = sh.word;
-    const int per = (n + blockDim.x - 1) / blockDim.x;
-    const int i0 = tid * per, i1 = min(n, i0 + per);
+    auto in_band = [&](uint32_t v, int &peq) {
+      if (v == tw) return peq++ >= take_eq;
+      return v > tw && v <= tau_w;
+    };
     int mine = 0;
-    for (int i = i0; i < i1; ++i) {
-      const uint64_t k = key_at(i);
-      mine += k != kKeyNone && k >= thresh && (uint32_t)(k >> 32) <= tau_w;
+    {
+      int peq = eq_base;
+      for (int i = i0; i < i1; ++i) mine += in_band(word_at(i), peq);
     }
     const int incl = block_incl_scan(mine, sh.red_i);
     __syncthreads();
@@ -435,11 +483,12 @@ __global__ __launch_bounds__(256) void k_select_rerank(SelRerankArgs a) {
     __syncthreads();
     const int total_band = sh.krem;
     if (nsurv + total_band <= kMaxSurvivors) {
-      int pos = nsurv + incl - mine;
-      for (int i = i0; i < i1; ++i) {
-        const uint64_t k = key_at(i);
-        if (k != kKeyNone && k >= thresh && (uint32_t)(k >> 32) <= tau_w) sh.sel[pos++] = k;
-      }
+      int pos = nsurv + incl - mine, peq = eq_base;
+      for (int i = i0; i < i1; ++i)
+        if (in_band(word_at(i), peq)) sh.sel[pos++] = (uint32_t)i;
+      __syncthreads();
+      for (int s = nsurv + tid; s < nsurv + total_band; s += blockDim.x)
+        sh.srow[s] = row_of(s_off, s_reg, nslots, a.reg_start, sh.sel[s]);
       __syncthreads();
       rerank_range(a, sh, qrow, nsurv, nsurv + total_band);
       __syncthreads();
@@ -458,10 +507,9 @@ __global__ __launch_bounds__(256) void k_select_rerank(SelRerankArgs a) {
         const int i = base + tid;
         uint64_t hi = kKeyNone;
         uint32_t lo = 0xFFFFFFFFu;
-        if (i < n) {
-          const uint64_t k = key_at(i);
-          if (k != kKeyNone) {
-            const uint32_t row = (uint32_t)k;
+        if (i < n && tid < 256) {
+          if (word_at(i) != kWordNone) {
+            const uint32_t row = row_of(s_off, s_reg, nslots, a.reg_start, (uint32_t)i);
             hi = (uint64_t)__double_as_longlong(thread_dist(a, qrow, row));
             lo = a.tie_of ? (uint32_t)a.tie_of[row] : row;
           }
@@ -493,7 +541,12 @@ __global__ __launch_bounds__(256) void k_select_rerank(SelRerankArgs a) {
   }
 }
 
-// LDS limit of the select kernel (key cache above 64 KB), set once per device.
+size_t select_lds_bytes(int nslots, int cache) {
+  return (size_t)(2 * nslots + cache) * sizeof(uint32_t);
+}
+
+// LDS limit of the select kernel (word cache and slot table above 64 KB),
+// set once per device.
 hipError_t prepare_select_kernels() {
   static int done_dev = -1;
   int dev = 0;
@@ -501,16 +554,19 @@ hipError_t prepare_select_kernels() {
   if (e != hipSuccess || done_dev == dev) return e;
   e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_select_rerank),
                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)(kKeyCache * sizeof(uint64_t)));
+                          (int)select_lds_bytes(kMaxSlots, kWordCache));
   if (e == hipSuccess) done_dev = dev;
   return e;
 }
 
-hipError_t launch_select_rerank(const SelRerankArgs &a, hipStream_t s) {
+hipError_t launch_select_rerank(SelRerankArgs a, hipStream_t s) {
   if (a.nq <= 0) return hipSuccess;
   if (a.L > kMaxSurvivors || a.L < a.m || a.m > 256) return hipErrorInvalidValue;
-  const size_t lds = (size_t)kKeyCache * sizeof(uint64_t);
-  return launch_kernel(k_select_rerank, dim3(a.nq), dim3(256), lds, s, a);
+  if (a.nslots < 0 || a.nslots > kMaxSlots || (a.nslots > 0 && (!a.slot_off || !a.slot_reg)))
+    return hipErrorInvalidValue;
+  a.cache = (int32_t)std::min<int64_t>(a.cap, kWordCache);
+  return launch_kernel(k_select_rerank, dim3(a.nq), dim3(256),
+                       (uint32_t)select_lds_bytes(a.nslots, a.cache), s, a);
 }
 
 }  // namespace hloc

@@ -15,13 +15,16 @@ import re
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhloc.so")
+# the in-tree build; HLOC_LIBRARY names another build of the same sources
+LIB_PATH = os.environ.get("HLOC_LIBRARY") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libhloc.so")
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
                       "hloc.h")
 
-OK, EINVAL, ENOMEM, ESTATE, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, ESTATE, EDEVICE, EUNSUPPORTED, EBUSY, ETIMEDOUT = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", ESTATE: "ESTATE",
-                EDEVICE: "EDEVICE", EUNSUPPORTED: "EUNSUPPORTED"}
+                EDEVICE: "EDEVICE", EUNSUPPORTED: "EUNSUPPORTED", EBUSY: "EBUSY",
+                ETIMEDOUT: "ETIMEDOUT"}
 FP32, BF16, FP8 = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8}
 FLAG_LOW_CONFIDENCE, FLAG_EMPTY, FLAG_BAD_REQUEST = 1, 2, 4
@@ -31,6 +34,14 @@ _lib = None
 
 _P = ctypes.c_void_p
 _I32, _I64, _U32, _F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
+_U64 = ctypes.c_uint64
+
+
+class ServerConfig(ctypes.Structure):
+    """hloc_server_config."""
+    _fields_ = [("k", _I32), ("n_regions", _I32), ("precision", _I32),
+                ("max_batch_frames", _I32), ("max_slots", _I32), ("max_queue_frames", _I32),
+                ("hbm_budget_bytes", _I64)]
 _SIGNATURES = {
     "hloc_build_db": (ctypes.c_int, [_P, _I64, _I32, _P, _U32, ctypes.POINTER(_P)]),
     "hloc_set_regions": (ctypes.c_int, [_P, _P, _I32, _P]),
@@ -53,6 +64,12 @@ _SIGNATURES = {
     "hloc_ws_replay": (ctypes.c_int, [_P, _P]),
     "hloc_profile": (ctypes.c_int, [_P, _I32]),
     "hloc_profile_read": (ctypes.c_int, [_P, _P, _P, _I32]),
+    "hloc_server_create": (ctypes.c_int, [_P, ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
+    "hloc_server_submit": (ctypes.c_int, [_P, _P, _I32, _I32, ctypes.POINTER(_U64)]),
+    "hloc_server_wait": (ctypes.c_int, [_P, _U64, _I32, _P, _P, _P, _P, _P,
+                                        ctypes.POINTER(_F64)]),
+    "hloc_server_stats": (ctypes.c_int, [_P, _P, _I32]),
+    "hloc_server_free": (None, [_P]),
     "hloc_free_db": (None, [_P]),
     "hloc_last_error": (ctypes.c_char_p, []),
 }
@@ -317,3 +334,65 @@ class Workspace:
         out = (ctypes.c_int64 * 6)()
         _check(load_library().hloc_ws_query_info(self._h, out, 6))
         return dict(zip(_INFO_KEYS, list(out)))
+
+
+_SERVER_STATS = ("slots", "slot_bytes", "batches", "requests", "frames", "max_batch_frames",
+                 "queued_frames", "peak_queued_frames", "max_in_flight", "refused")
+
+
+class Server:
+    """Request server over a database (hloc_server): requests of 1 ..
+    max_batch_frames frames are batched continuously on up to max_slots
+    batches in flight, within an HBM budget (0 = none)."""
+
+    def __init__(self, db: HlocDB, k: int, n_regions: int, precision="fp32",
+                 max_batch_frames: int = 256, max_slots: int = 4, max_queue_frames: int = 4096,
+                 hbm_budget_bytes: int = 0):
+        lib = load_library()
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.cfg = ServerConfig(k, n_regions, prec, max_batch_frames, max_slots,
+                                max_queue_frames, hbm_budget_bytes)
+        h = ctypes.c_void_p()
+        _check(lib.hloc_server_create(db._h, ctypes.byref(self.cfg), ctypes.byref(h)))
+        self._h = h
+        self.db = db
+
+    def submit(self, frames, k: int | None = None) -> int:
+        """Queue one request (frames: F x d); returns its ticket."""
+        frames = np.ascontiguousarray(frames, dtype=np.float32)
+        t = _U64()
+        _check(load_library().hloc_server_submit(self._h, _np_ptr(frames), frames.shape[0],
+                                                 self.cfg.k if k is None else k, ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, nframes: int, k: int | None = None, timeout_ms: int = -1) -> dict:
+        """Results of one request: idx / dist (nframes x k), xy, tile, flags,
+        latency_ms (submit to completion)."""
+        k = self.cfg.k if k is None else k
+        idx = np.empty((nframes, k), np.int64)
+        dist = np.empty((nframes, k), np.float32)
+        xy = np.empty(2, np.float64)
+        tile = np.empty(2, np.int32)
+        flags = np.empty(1, np.int32)
+        lat = _F64()
+        _check(load_library().hloc_server_wait(self._h, ticket, timeout_ms, _np_ptr(idx),
+                                               _np_ptr(dist), _np_ptr(xy), _np_ptr(tile),
+                                               _np_ptr(flags), ctypes.byref(lat)))
+        return dict(idx=idx, dist=dist, xy=xy, tile=tile, flags=int(flags[0]),
+                    latency_ms=lat.value)
+
+    def stats(self) -> dict:
+        out = (ctypes.c_int64 * len(_SERVER_STATS))()
+        _check(load_library().hloc_server_stats(self._h, out, len(_SERVER_STATS)))
+        return dict(zip(_SERVER_STATS, list(out)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().hloc_server_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -94,6 +94,22 @@ def test_calls_on_null_database():
     assert "NULL" in lib.hloc_last_error().decode()
 
 
+def test_server_calls_on_null_handles():
+    lib = _lib()
+    cfg = hloc.ServerConfig(16, 8, 0, 64, 2, 4096, 0)
+    h = ctypes.c_void_p()
+    assert lib.hloc_server_create(None, ctypes.byref(cfg), ctypes.byref(h)) == hloc.EINVAL
+    assert h.value is None
+    t = ctypes.c_uint64()
+    frames = np.zeros((2, 8), np.float32)
+    assert lib.hloc_server_submit(None, frames.ctypes.data_as(ctypes.c_void_p), 2, 4,
+                                  ctypes.byref(t)) == hloc.EINVAL
+    assert lib.hloc_server_wait(None, 1, 0, None, None, None, None, None, None) == hloc.EINVAL
+    out = (ctypes.c_int64 * 10)()
+    assert lib.hloc_server_stats(None, out, 10) == hloc.EINVAL
+    lib.hloc_server_free(None)  # ignored
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(hloc, "LIB_PATH", str(tmp_path / "absent.so"))
     monkeypatch.setattr(hloc, "_lib", None)
@@ -105,5 +121,6 @@ def test_header_limits_match_binding_constants():
     with open(hloc.HEADER) as f:
         text = f.read()
     for name, val in (("HLOC_EINVAL", hloc.EINVAL), ("HLOC_EUNSUPPORTED", hloc.EUNSUPPORTED),
+                      ("HLOC_EBUSY", hloc.EBUSY), ("HLOC_ETIMEDOUT", hloc.ETIMEDOUT),
                       ("HLOC_FLAG_EMPTY", hloc.FLAG_EMPTY), ("HLOC_MIRROR_BF16", hloc.MIRROR_BF16)):
         assert f"{name} = {val}" in text
