@@ -50,12 +50,14 @@ typedef enum {
   HLOC_ETIMEDOUT = -7    /* the wait ended before the request completed */
 } hloc_status;
 
-/* Precision of the fine screen (the coarse screen is fp32). Whatever the
- * screen, the returned top-k is decided by an FP64 rerank of the survivors
- * (k + 16 of them behind fp32, 4k behind bf16) with a certificate: rows the
- * screen's error bound cannot exclude are re-scored too, so the result is the
- * same for every precision. HLOC_BF16 needs a database built with
- * HLOC_MIRROR_BF16; HLOC_FP8 is not available yet. */
+/* Precision of the screens. HLOC_BF16 screens rows and region
+ * representatives from bf16 copies (the database must be built with
+ * HLOC_MIRROR_BF16). Whatever the screen, the returned top-k is decided by an
+ * FP64 rerank of the survivors (k + 16 of them behind fp32, 4k behind bf16)
+ * and the regions by an FP64 re-score of the best n_regions + 8, each with a
+ * certificate: candidates the screen's error bound cannot exclude are
+ * re-scored too, so the result is the same for every precision. HLOC_FP8 is
+ * not available yet. */
 typedef enum { HLOC_FP32 = 0, HLOC_BF16 = 1, HLOC_FP8 = 2 } hloc_precision;
 
 /* Per-request flags written by the aggregation (bit set). */

@@ -235,7 +235,14 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     sa.dense = 1;
     sa.nrows = db->R;
     sa.nq = p.nq;
-    HIPCHK(launch_screen_f32(sa, p.grid1, s));
+    const bool coarse16 = bf16 && db->rep16;
+    if (coarse16) {
+      sa.rows16 = db->rep16;
+      sa.qp16 = qp16;
+      HIPCHK(launch_screen_bf16(sa, p.grid1, s));
+    } else {
+      HIPCHK(launch_screen_f32(sa, p.grid1, s));
+    }
     SelRerankArgs ra{};
     ra.cand = as<uint32_t>(ws->cand1);
     ra.cap = db->R;
@@ -248,6 +255,14 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     ra.qn2 = qn2;
     ra.err_coef = coef;
     ra.max_norm = (double)db->h_rep_max * (1.0 + 1e-6);
+    if (coarse16) {
+      ra.q_err = as<float>(ws->q_err);
+      ra.q_lon = as<float>(ws->q_lon);
+      ra.lo_dmax = (double)db->h_rep16_err * (1.0 + 1e-6);
+      ra.lo_nmax = (double)db->h_rep16_norm * (1.0 + 1e-6);
+      ra.lo_coef = 2.0 * (1.0 + 1e-6);
+      ra.err_coef = coef * 1.01;
+    }
     ra.nq = p.nq;
     ra.reg_out = regions;
     ra.stat_fallback = misc + 1;
@@ -421,6 +436,7 @@ void free_db_data(hloc_db *db) {
   dev_free(db->rep64);
   dev_free(db->rep32);
   dev_free(db->rep_n2);
+  dev_free(db->rep16);
   if (db->stream) (void)hipStreamDestroy(db->stream);
   db->stream = nullptr;
 }
@@ -512,7 +528,7 @@ int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, ui
   if (pe != hipSuccess) return bail(fail(HLOC_EDEVICE, "kernel set-up failed: %s", hipGetErrorString(pe)));
   if ((rc = dev_alloc(&db->rows, (size_t)n * db->dp)) || (rc = dev_alloc(&db->row_n2, (size_t)n)) ||
       (rc = dev_alloc(&db->perm, (size_t)n)) || (rc = dev_alloc(&db->xy, (size_t)n * 2)) ||
-      (rc = dev_alloc(&db->tiles, (size_t)n)) || (rc = dev_alloc(&db->norm_max, 4)))
+      (rc = dev_alloc(&db->tiles, (size_t)n)) || (rc = dev_alloc(&db->norm_max, 8)))
     return bail(rc);
   float *tmp = nullptr;
   if ((rc = dev_alloc(&tmp, (size_t)nd))) return bail(rc);
@@ -521,7 +537,7 @@ int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, ui
   hipError_t e = hipMemcpy(tmp, feats, (size_t)nd * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(db->perm, db->h_perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(db->xy, xy, (size_t)n * 2 * sizeof(double), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemsetAsync(db->norm_max, 0, 4 * sizeof(float), db->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(db->norm_max, 0, 8 * sizeof(float), db->stream);
   if (e == hipSuccess) e = launch_gather_rows(tmp, db->perm, n, d, d, db->rows, db->dp, db->stream);
   if (e == hipSuccess) e = launch_row_norms(db->rows, n, db->dp, db->row_n2, db->norm_max, db->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(db->stream);
@@ -569,6 +585,7 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   dev_free(db->rep64);
   dev_free(db->rep32);
   dev_free(db->rep_n2);
+  dev_free(db->rep16);
   db->has_regions = false;
   int rc;
   float *new_rows = nullptr;
@@ -599,7 +616,7 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   HIPCHK(hipMemcpy(db->perm, new_perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(db->reg_start, start.data(), (size_t)(R + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(db->nonempty_ids, ids.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  HIPCHK(hipMemsetAsync(db->norm_max, 0, 4 * sizeof(float), db->stream));
+  HIPCHK(hipMemsetAsync(db->norm_max, 0, 8 * sizeof(float), db->stream));
   HIPCHK(launch_row_norms(db->rows, n, db->dp, db->row_n2, db->norm_max, db->stream));
   dev_free(db->rows16);
   if (db->mirrors & HLOC_MIRROR_BF16) {
@@ -617,13 +634,20 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   }
   HIPCHK(launch_rep_finish(db->rep64, db->reg_start, R, db->dp, db->rep32, db->rep_n2,
                            db->norm_max + 1, db->stream));
-  float mx[4];
+  if (db->mirrors & HLOC_MIRROR_BF16) {
+    if ((rc = dev_alloc(&db->rep16, (size_t)R * db->dp))) return rc;
+    HIPCHK(launch_rows_to_bf16(db->rep32, R, db->dp, db->rep16, db->norm_max + 4,
+                               db->norm_max + 5, db->stream));
+  }
+  float mx[6];
   HIPCHK(hipMemcpyAsync(mx, db->norm_max, sizeof mx, hipMemcpyDeviceToHost, db->stream));
   HIPCHK(hipStreamSynchronize(db->stream));
   db->h_row_max = mx[0];
   db->h_rep_max = mx[1];
   db->h_bf16_err = mx[2];
   db->h_bf16_norm = mx[3];
+  db->h_rep16_err = mx[4];
+  db->h_rep16_norm = mx[5];
   db->R = R;
   db->R_nonempty = (int32_t)ids.size();
   db->h_reg_start = start;

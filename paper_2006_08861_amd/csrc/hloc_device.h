@@ -10,21 +10,6 @@ namespace hloc {
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
-// Work items of this block in a persistent launch whose grid is a multiple
-// of kXcds. Blocks are dispatched to the eight XCDs of the chip round-robin,
-// so the blocks of one XCD (blockIdx.x % kXcds) take one contiguous range of
-// the items: neighbouring items, which read the same rows, share that XCD's
-// L2 instead of being fetched into every L2.
-constexpr int kXcds = 8;
-struct ItemWalk {
-  int it, end, step;
-};
-__device__ __forceinline__ ItemWalk item_walk(int n_items) {
-  const int x = blockIdx.x % kXcds, per = (n_items + kXcds - 1) / kXcds;
-  const int b = min(n_items, x * per);
-  return {b + (int)(blockIdx.x / kXcds), min(n_items, b + per), (int)(gridDim.x / kXcds)};
-}
-
 // Ascending bitonic sort of n (power of two) keys in LDS by the whole block.
 __device__ inline void block_sort_u64(uint64_t *a, int n) {
   for (int size = 2; size <= n; size <<= 1) {

@@ -92,7 +92,10 @@ struct hloc_db {
   int32_t *perm = nullptr;    // device row -> original index
   double *xy = nullptr;       // n x 2 by original index
   int2 *tiles = nullptr;      // n by original index
-  float *norm_max = nullptr;  // [0] rows, [1] representatives, [2] bf16 error, [3] bf16 rows
+  // largest norms: [0] rows, [1] representatives, [2] bf16 rounding error of
+  // the rows, [3] bf16 rows, [4] bf16 rounding error of the representatives,
+  // [5] bf16 representatives
+  float *norm_max = nullptr;
   float h_row_max = 0.f, h_rep_max = 0.f;
   uint32_t mirrors = 0;        // HLOC_MIRROR_* copies kept beside the fp32 rows
   uint16_t *rows16 = nullptr;  // bf16 copy of rows
@@ -110,6 +113,8 @@ struct hloc_db {
   double *rep64 = nullptr;
   float *rep32 = nullptr;
   float *rep_n2 = nullptr;
+  uint16_t *rep16 = nullptr;  // bf16 copy of rep32 (with the bf16 mirror)
+  float h_rep16_err = 0.f, h_rep16_norm = 0.f;
   double cell = 0.5, radius = 0.0;
   int32_t top_c = 1, rho = 0, pct = 0;
   hloc_ws *ws0 = nullptr;  // workspace of the calls that take no workspace

@@ -25,16 +25,20 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// bf16 copy of n rows of dp floats; per-row FP64 norms of the rounding error
-// and of the rounded row, maxima into max_err / max_norm (float bits).
+constexpr int kBf16RowsPerWave = 16;
+
+// bf16 copy of n rows, kBf16RowsPerWave rows per wave; per-row FP64 norms of
+// the rounding error and of the rounded row, maxima into max_err / max_norm
+// (float bits, one atomic per block).
 __global__ void k_rows_to_bf16(const float *__restrict__ src, int64_t n, int dp,
                                uint16_t *__restrict__ dst, float *max_err, float *max_norm) {
   __shared__ float s_e[4], s_n[4];
-  const int64_t i = blockIdx.x * 4 + wave_id();
-  double e2 = 0.0, n2 = 0.0;
-  if (i < n) {
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + wave_id()) * kBf16RowsPerWave;
+  float me = 0.f, mn = 0.f;
+  for (int64_t i = i0; i < min(n, i0 + kBf16RowsPerWave); ++i) {
     const float *r = src + i * dp;
     uint16_t *o = dst + i * dp;
+    double e2 = 0.0, n2 = 0.0;
     for (int c = lane_id(); c < dp; c += 64) {
       const uint16_t h = bf16_rne(r[c]);
       o[c] = h;
@@ -42,59 +46,52 @@ __global__ void k_rows_to_bf16(const float *__restrict__ src, int64_t n, int dp,
       e2 = fma(t - (double)r[c], t - (double)r[c], e2);
       n2 = fma(t, t, n2);
     }
+    e2 = wave_sum_f64(e2);
+    n2 = wave_sum_f64(n2);
+    me = fmaxf(me, (float)sqrt(e2));
+    mn = fmaxf(mn, (float)sqrt(n2));
   }
-  e2 = wave_sum_f64(e2);
-  n2 = wave_sum_f64(n2);
   if (lane_id() == 0) {
-    s_e[wave_id()] = (float)sqrt(e2);
-    s_n[wave_id()] = (float)sqrt(n2);
+    s_e[wave_id()] = me;
+    s_n[wave_id()] = mn;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    float me = 0.f, mn = 0.f;
-    for (int w = 0; w < 4; ++w) {
-      me = fmaxf(me, s_e[w]);
-      mn = fmaxf(mn, s_n[w]);
+    for (int w = 1; w < 4; ++w) {
+      s_e[0] = fmaxf(s_e[0], s_e[w]);
+      s_n[0] = fmaxf(s_n[0], s_n[w]);
     }
-    atomicMax(reinterpret_cast<unsigned int *>(max_err), __float_as_uint(me));
-    atomicMax(reinterpret_cast<unsigned int *>(max_norm), __float_as_uint(mn));
+    atomicMax(reinterpret_cast<unsigned int *>(max_err), __float_as_uint(s_e[0]));
+    atomicMax(reinterpret_cast<unsigned int *>(max_norm), __float_as_uint(s_n[0]));
   }
 }
 
 hipError_t launch_rows_to_bf16(const float *src, int64_t n, int32_t dp, uint16_t *dst,
                                float *max_err, float *max_norm, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  return launch_kernel(k_rows_to_bf16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, src, n,
-                       dp, dst, max_err, max_norm);
+  const int64_t per_block = 4 * kBf16RowsPerWave;
+  return launch_kernel(k_rows_to_bf16, dim3((unsigned)((n + per_block - 1) / per_block)),
+                       dim3(256), 0, s, src, n, dp, dst, max_err, max_norm);
 }
 
-// 64-row items, the 16-row block w of the item on wave w; item order, the
-// prefetch of the next list item and the epilogue as in the fp32 register
-// screen.
+// One item per block, one 16-row block per wave, as the fp32 register screen.
 template <int NS, bool DENSE>  // NS = dp / 32
 __global__ __launch_bounds__(256) void k_screen_bf16(ScreenArgs a) {
   constexpr int DP = NS * 32;
-  const int lane = lane_id(), w = wave_id();
+  const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
   const int i = lane & 15, g = lane >> 4;
-  int n_items, ngroups = 1;
+  int n_items, nchunks = 1;
   if (DENSE) {
-    ngroups = (a.nq + kGroup - 1) / kGroup;
-    n_items = ((a.nrows + a.rows_per_item - 1) / a.rows_per_item) * ngroups;
+    nchunks = (a.nrows + a.rows_per_item - 1) / a.rows_per_item;
+    n_items = nchunks * ((a.nq + kGroup - 1) / kGroup);
   } else {
     n_items = *a.n_items;
   }
-  const ItemWalk wk = item_walk(n_items);
-  Item nit{};
-  int2 ne = make_int2(0, 0);
-  if (!DENSE && wk.it < wk.end) {
-    nit = a.items[wk.it];
-    if (i < (nit.nrows_gq & 0xFFFF)) ne = a.rq[nit.q0 + i];
-  }
-  for (int it = wk.it; it < wk.end; it += wk.step) {
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     int row_begin, chunk_row, nrows, gq, fr = 0;
     int64_t off = 0;
     if (DENSE) {
-      const int c = it / ngroups, grp = it - c * ngroups;
+      const int c = it % nchunks, grp = it / nchunks;
       row_begin = c * a.rows_per_item;
       chunk_row = row_begin;
       nrows = min(a.rows_per_item, a.nrows - row_begin);
@@ -102,50 +99,45 @@ __global__ __launch_bounds__(256) void k_screen_bf16(ScreenArgs a) {
       fr = grp * kGroup + i;
       off = (int64_t)fr * a.cap + chunk_row;
     } else {
-      row_begin = nit.row_begin;
-      chunk_row = nit.chunk_row;
-      nrows = nit.nrows_gq >> 16;
-      gq = nit.nrows_gq & 0xFFFF;
+      const Item itm = a.items[it];
+      row_begin = itm.row_begin;
+      chunk_row = itm.chunk_row;
+      nrows = itm.nrows_gq >> 16;
+      gq = itm.nrows_gq & 0xFFFF;
       if (i < gq) {
-        fr = ne.x;
-        off = (int64_t)ne.x * a.cap + ne.y + chunk_row;
+        const int2 e = a.rq[itm.q0 + i];
+        fr = e.x;
+        off = (int64_t)e.x * a.cap + e.y + chunk_row;
       }
     }
     if (i >= gq) fr = 0;
-    const bool active = w * 16 < nrows;
-    uint4 av[NS], bv[NS];
-    float rn[4], qn = 0.f;
-    if (active) {
-      const int rl = min(w * 16 + i, nrows - 1);
-      const uint4 *rp =
-          reinterpret_cast<const uint4 *>(a.rows16 + (int64_t)(row_begin + rl) * DP) + g;
+    const int nrb = (nrows + 15) >> 4;
+    for (int rb = w; rb < nrb; rb += nw) {
+      const int rl = min(rb * 16 + i, nrows - 1);
+      const uint4 *rp = reinterpret_cast<const uint4 *>(a.rows16 + (int64_t)(row_begin + rl) * DP) + g;
       const uint4 *qp = reinterpret_cast<const uint4 *>(a.qp16 + (int64_t)fr * DP) + g;
+      uint4 av[NS], bv[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) av[s] = rp[4 * s];
 #pragma unroll
       for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) rn[r] = a.row_n2[row_begin + min(w * 16 + 4 * g + r, nrows - 1)];
-      qn = a.qn2[fr];
-    }
-    const int nx = it + wk.step;
-    if (!DENSE && nx < wk.end) nit = a.items[nx];
-    if (active) {
+      const float qn = a.qn2[fr];
       v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < NS; ++s)
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av[s]),
                                                       __builtin_bit_cast(v8bf, bv[s]), acc, 0,
                                                       0, 0);
-      if (!DENSE && nx < wk.end && i < (nit.nrows_gq & 0xFFFF)) ne = a.rq[nit.q0 + i];
       if (i < gq) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = w * 16 + 4 * g + r;
+          const int row = rb * 16 + 4 * g + r;
           if (row < nrows) {
+            const int grow = row_begin + row;
+            const float rn = a.row_n2[grow];
             uint32_t word = 0xFFFFFFFFu;
-            if (!__builtin_isinf(rn[r])) {
-              float dd = (qn + rn[r]) - 2.f * acc[r];
+            if (!__builtin_isinf(rn)) {
+              float dd = (qn + rn) - 2.f * acc[r];
               dd = dd > 0.f ? dd : 0.f;
               word = __float_as_uint(dd);
             }
@@ -153,8 +145,6 @@ __global__ __launch_bounds__(256) void k_screen_bf16(ScreenArgs a) {
           }
         }
       }
-    } else if (!DENSE && nx < wk.end && i < (nit.nrows_gq & 0xFFFF)) {
-      ne = a.rq[nit.q0 + i];
     }
   }
 }
@@ -166,7 +156,7 @@ hipError_t launch_bf16_t(const ScreenArgs &a, int32_t grid, hipStream_t s) {
 
 hipError_t launch_screen_bf16(const ScreenArgs &a, int32_t grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  if (a.rows_per_item != 64 || grid % kXcds != 0) return hipErrorInvalidValue;
+  if (a.rows_per_item % 16 != 0) return hipErrorInvalidValue;
   switch (a.dp) {
 #define HLOC_BF16_CASE(DPV)                                     \
   case DPV:                                                    \

@@ -167,37 +167,28 @@ __global__ __launch_bounds__(256) void k_screen_f32(ScreenArgs a) {
   }
 }
 
-// Register variant for padded lengths up to 512 and 64-row items: one item
-// per block at a time, the 16-row block w of the item on wave w, no LDS and no
-// barriers. The frame operand of the MFMA sits in registers next to the row
-// operand (lane l holds frame l % 16's k-slice); row loads, frame loads and
-// norms go out together, and in list mode the next item's descriptor and
-// frame entries are fetched while the current item is computed. Dense items
-// are chunk-major (the frame groups of one row chunk are neighbours).
+// Register variant for padded lengths up to 512: one item per block, one
+// 16-row block per wave, no LDS and no barriers. Each wave keeps the frame
+// operand of the MFMA in registers (lane l holds frame l % 16's k-slice); its
+// row loads, frame loads and norms go out together once the item's frame list
+// has been read.
 template <int NS, bool DENSE>
 __global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
   constexpr int DP = NS * 16;
-  const int lane = lane_id(), w = wave_id();
+  const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
   const int i = lane & 15, g = lane >> 4;
-  int n_items, ngroups = 1;
+  int n_items, nchunks = 1;
   if (DENSE) {
-    ngroups = (a.nq + kGroup - 1) / kGroup;
-    n_items = ((a.nrows + a.rows_per_item - 1) / a.rows_per_item) * ngroups;
+    nchunks = (a.nrows + a.rows_per_item - 1) / a.rows_per_item;
+    n_items = nchunks * ((a.nq + kGroup - 1) / kGroup);
   } else {
     n_items = *a.n_items;
   }
-  const ItemWalk wk = item_walk(n_items);
-  Item nit{};
-  int2 ne = make_int2(0, 0);
-  if (!DENSE && wk.it < wk.end) {
-    nit = a.items[wk.it];
-    if (i < (nit.nrows_gq & 0xFFFF)) ne = a.rq[nit.q0 + i];
-  }
-  for (int it = wk.it; it < wk.end; it += wk.step) {
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     int row_begin, chunk_row, nrows, gq, fr = 0;
     int64_t off = 0;
     if (DENSE) {
-      const int c = it / ngroups, grp = it - c * ngroups;
+      const int c = it % nchunks, grp = it / nchunks;
       row_begin = c * a.rows_per_item;
       chunk_row = row_begin;
       nrows = min(a.rows_per_item, a.nrows - row_begin);
@@ -205,35 +196,31 @@ __global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
       fr = grp * kGroup + i;
       off = (int64_t)fr * a.cap + chunk_row;
     } else {
-      row_begin = nit.row_begin;
-      chunk_row = nit.chunk_row;
-      nrows = nit.nrows_gq >> 16;
-      gq = nit.nrows_gq & 0xFFFF;
+      const Item *itm = a.items + it;
+      row_begin = itm->row_begin;
+      chunk_row = itm->chunk_row;
+      const int ng = itm->nrows_gq;
+      nrows = ng >> 16;
+      gq = ng & 0xFFFF;
       if (i < gq) {
-        fr = ne.x;
-        off = (int64_t)ne.x * a.cap + ne.y + chunk_row;
+        const int2 e = a.rq[itm->q0 + i];
+        fr = e.x;
+        off = (int64_t)e.x * a.cap + e.y + chunk_row;
       }
     }
     if (i >= gq) fr = 0;
-    const bool active = w * 16 < nrows;
-    float4 av[NS], bv[NS];
-    float rn[4], qn = 0.f;
-    if (active) {
-      const int rl = min(w * 16 + i, nrows - 1);
+    const int nrb = (nrows + 15) >> 4;
+    for (int rb = w; rb < nrb; rb += nw) {
+      const int rl = min(rb * 16 + i, nrows - 1);
       const float4 *rp =
           reinterpret_cast<const float4 *>(a.rows + (int64_t)(row_begin + rl) * DP) + g;
       const float4 *qp = reinterpret_cast<const float4 *>(a.qp + (int64_t)fr * DP) + g;
+      float4 av[NS], bv[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) av[s] = rp[4 * s];
 #pragma unroll
       for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) rn[r] = a.row_n2[row_begin + min(w * 16 + 4 * g + r, nrows - 1)];
-      qn = a.qn2[fr];
-    }
-    const int nx = it + wk.step;
-    if (!DENSE && nx < wk.end) nit = a.items[nx];
-    if (active) {
+      const float qn = a.qn2[fr];
       v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
@@ -242,17 +229,16 @@ __global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].z, bv[s].z, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].w, bv[s].w, acc, 0, 0, 0);
       }
-      if (!DENSE && nx < wk.end && i < (nit.nrows_gq & 0xFFFF)) ne = a.rq[nit.q0 + i];
-      // lane l holds dot(row 4*(l/16)+r of the block, frame l%16); columns of
-      // absent frames (i >= gq) hold frame 0's values and are not stored
       if (i < gq) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = w * 16 + 4 * g + r;
+          const int row = rb * 16 + 4 * g + r;
           if (row < nrows) {
+            const int grow = row_begin + row;
+            const float rn = a.row_n2[grow];
             uint32_t word = 0xFFFFFFFFu;
-            if (!__builtin_isinf(rn[r])) {
-              float dd = (qn + rn[r]) - 2.f * acc[r];
+            if (!__builtin_isinf(rn)) {
+              float dd = (qn + rn) - 2.f * acc[r];
               dd = dd > 0.f ? dd : 0.f;
               word = __float_as_uint(dd);
             }
@@ -260,8 +246,6 @@ __global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
           }
         }
       }
-    } else if (!DENSE && nx < wk.end && i < (nit.nrows_gq & 0xFFFF)) {
-      ne = a.rq[nit.q0 + i];
     }
   }
 }
@@ -294,8 +278,7 @@ hipError_t prepare_screen_kernels() {
 
 hipError_t launch_screen_f32(const ScreenArgs &a, int32_t grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  if (grid % kXcds != 0) return hipErrorInvalidValue;
-  if (a.rows_per_item == 64) {
+  if (a.rows_per_item % 16 == 0) {
     switch (a.dp) {
 #define HLOC_WAVE_CASE(DPV)                                     \
   case DPV:                                                    \
@@ -315,12 +298,10 @@ hipError_t launch_screen_f32(const ScreenArgs &a, int32_t grid, hipStream_t s) {
 }
 
 // Number of blocks that covers `items` work items (one per block), up to
-// `max_blocks`, rounded up to a multiple of the XCD count; the kernels loop
-// over the rest.
+// `max_blocks`; the kernels loop over the rest.
 int32_t screen_grid(int64_t items, int32_t dp, int32_t max_blocks) {
   (void)dp;
-  const int64_t g = std::max<int64_t>(1, std::min<int64_t>(items, max_blocks));
-  return (int32_t)((g + kXcds - 1) / kXcds * kXcds);
+  return (int32_t)std::max<int64_t>(1, std::min<int64_t>(items, max_blocks));
 }
 
 }  // namespace hloc

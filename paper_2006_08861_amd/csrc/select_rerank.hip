@@ -20,7 +20,8 @@
 
 namespace hloc {
 
-constexpr int kWordCache = 16384;  // screen words of a frame kept in (dynamic) LDS
+constexpr int kWordCache = 28672;  // screen words of a frame kept in (dynamic) LDS
+constexpr int kBigFrame = 4096;    // candidate capacity above which a frame gets 1024 threads
 constexpr int kMaxSlots = 1024;    // region slots of a frame kept in (dynamic) LDS
 constexpr uint32_t kWordNone = 0xFFFFFFFFu;  // no candidate at this position
 constexpr int kDigitBits = 11;     // radix digit of the select (three passes cover 32 bits)
@@ -318,7 +319,8 @@ __device__ __forceinline__ uint32_t row_of(const int32_t *s_off, const int32_t *
   return (uint32_t)(reg_start[s_reg[lo]] + ((int32_t)p - s_off[lo]));
 }
 
-__global__ __launch_bounds__(256) void k_select_rerank(SelRerankArgs a) {
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
   __shared__ SelShared sh;
   extern __shared__ uint32_t dyn[];  // [slot offsets | slot regions | word cache]
   const int f = blockIdx.x;
@@ -331,12 +333,13 @@ __global__ __launch_bounds__(256) void k_select_rerank(SelRerankArgs a) {
   uint32_t *wc = dyn + 2 * nslots;
   const uint32_t *words = a.cand + (int64_t)f * a.cap;
   // the first words are requested together with the count (one round trip)
+  constexpr int EU = (kEarlyKeys + BLOCK - 1) / BLOCK;
   const int early = (int)min<int64_t>(a.cap, kEarlyKeys);
-  uint32_t ew[kEarlyKeys / 256];
+  uint32_t ew[EU];
 #pragma unroll
-  for (int u = 0; u < kEarlyKeys / 256; ++u) {
-    const int i = u * 256 + tid;
-    ew[u] = (i < early && tid < 256) ? words[i] : kWordNone;
+  for (int u = 0; u < EU; ++u) {
+    const int i = u * BLOCK + tid;
+    ew[u] = i < early ? words[i] : kWordNone;
   }
   for (int j = tid; j < nslots; j += blockDim.x) {
     s_off[j] = a.slot_off[(int64_t)f * nslots + j];
@@ -360,8 +363,8 @@ __global__ __launch_bounds__(256) void k_select_rerank(SelRerankArgs a) {
     }
   };
 #pragma unroll
-  for (int u = 0; u < kEarlyKeys / 256; ++u) account(u * 256 + tid, ew[u]);
-  for (int base = kEarlyKeys; base < n; base += 8 * blockDim.x) {
+  for (int u = 0; u < EU; ++u) account(u * BLOCK + tid, ew[u]);
+  for (int base = EU * BLOCK; base < n; base += 8 * blockDim.x) {
     uint32_t v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -552,9 +555,12 @@ hipError_t prepare_select_kernels() {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess || done_dev == dev) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_select_rerank),
-                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)select_lds_bytes(kMaxSlots, kWordCache));
+  for (const void *k : {reinterpret_cast<const void *>(&k_select_rerank<256>),
+                        reinterpret_cast<const void *>(&k_select_rerank<1024>)}) {
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)select_lds_bytes(kMaxSlots, kWordCache));
+    if (e != hipSuccess) return e;
+  }
   if (e == hipSuccess) done_dev = dev;
   return e;
 }
@@ -565,7 +571,12 @@ hipError_t launch_select_rerank(SelRerankArgs a, hipStream_t s) {
   if (a.nslots < 0 || a.nslots > kMaxSlots || (a.nslots > 0 && (!a.slot_off || !a.slot_reg)))
     return hipErrorInvalidValue;
   a.cache = (int32_t)std::min<int64_t>(a.cap, kWordCache);
-  return launch_kernel(k_select_rerank, dim3(a.nq), dim3(256),
+  // frames with many candidates: the word cache takes most of the LDS, so the
+  // block is alone on its compute unit; 1024 threads use all of it
+  if (a.cap > kBigFrame)
+    return launch_kernel(k_select_rerank<1024>, dim3(a.nq), dim3(1024),
+                         (uint32_t)select_lds_bytes(a.nslots, a.cache), s, a);
+  return launch_kernel(k_select_rerank<256>, dim3(a.nq), dim3(256),
                        (uint32_t)select_lds_bytes(a.nslots, a.cache), s, a);
 }
 

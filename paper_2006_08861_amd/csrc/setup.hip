@@ -26,25 +26,36 @@ hipError_t launch_gather_rows(const float *src, const int32_t *src_row, int64_t 
 
 // Squared norm of each row summed in FP64, stored rounded to fp32; the
 // largest norm goes to *max_norm (non-negative floats order like their bits).
+constexpr int kNormRowsPerWave = 16;
+
+// FP64 squared norm of each row (stored as fp32), kNormRowsPerWave rows per
+// wave; the largest norm goes to *max_norm with one atomic per block.
 __global__ void k_row_norms(const float *__restrict__ rows, int64_t n, int dp, float *n2,
                             float *max_norm) {
-  const int64_t i = blockIdx.x * 4 + wave_id();
-  if (i >= n) return;
-  const float *r = rows + i * dp;
-  double acc = 0.0;
-  for (int c = lane_id(); c < dp; c += 64) acc = fma((double)r[c], (double)r[c], acc);
-  acc = wave_sum_f64(acc);
-  if (lane_id() == 0) {
-    n2[i] = (float)acc;
-    atomicMax(reinterpret_cast<unsigned int *>(max_norm), __float_as_uint((float)sqrt(acc)));
+  __shared__ float s_m[4];
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + wave_id()) * kNormRowsPerWave;
+  float m = 0.f;
+  for (int64_t i = i0; i < min(n, i0 + kNormRowsPerWave); ++i) {
+    const float *r = rows + i * dp;
+    double acc = 0.0;
+    for (int c = lane_id(); c < dp; c += 64) acc = fma((double)r[c], (double)r[c], acc);
+    acc = wave_sum_f64(acc);
+    if (lane_id() == 0) n2[i] = (float)acc;
+    m = fmaxf(m, (float)sqrt(acc));
   }
+  if (lane_id() == 0) s_m[wave_id()] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(reinterpret_cast<unsigned int *>(max_norm),
+              __float_as_uint(fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]))));
 }
 
 hipError_t launch_row_norms(const float *rows, int64_t n, int32_t dp, float *n2,
                             float *max_norm, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  return launch_kernel(k_row_norms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, rows, n, dp, n2,
-                     max_norm);
+  const int64_t per_block = 4 * kNormRowsPerWave;
+  return launch_kernel(k_row_norms, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(256),
+                       0, s, rows, n, dp, n2, max_norm);
 }
 
 // Mean of each region's rows: one block per region, threads over columns,

@@ -230,8 +230,10 @@ def test_identical_representatives_fall_back(torch_cuda):
                                 16 + np.arange(100) % 12]).astype(np.int32)
     xy = rng.uniform(0, 20, size=(len(feats), 2))
     q = (base[:5] + 0.01).astype(np.float32)
-    st, info, _ = check_all(torch_cuda, feats, xy, region_of, 28, q, 6, 3, name="equal means")
-    assert info["coarse_fallbacks"] == 5
+    for precision in ("fp32", "bf16"):
+        st, info, _ = check_all(torch_cuda, feats, xy, region_of, 28, q, 6, 3,
+                                name=f"equal means, {precision} screens", precision=precision)
+        assert info["coarse_fallbacks"] == 5
 
 
 def test_user_representatives_and_relayout(torch_cuda):
@@ -413,8 +415,11 @@ def test_bf16_and_fp32_screens_agree_bitwise(torch_cuda):
     say("[case] bf16 vs fp32 screen on one database")
     db = make_db(w.feats, w.xy, w.region_of, w.n_regions_total, w.agg, mirrors=hloc.MIRROR_BF16)
     a = run_device(torch, db, w.q, w.k, w.n_reg, precision="fp32")
+    regs_a = db.last_regions()
     b = run_device(torch, db, w.q, w.k, w.n_reg, precision="bf16")
+    regs_b = db.last_regions()
     say(f"[ok] bf16 info {db.info()}")
+    np.testing.assert_array_equal(regs_a, regs_b)  # the bf16 coarse stage picks the same regions
     for key in ("idx", "dist", "tile", "flags", "xy"):
         assert a[key].tobytes() == b[key].tobytes(), key
     db.close()
