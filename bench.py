@@ -106,69 +106,44 @@ def per_dispatch_kib(path: str, name_prefix: str, counter: str,
 def counters_summary(a) -> None:
     """Prints the markdown counter summary of the fine screen (with the record
     line load_traffic reads) from four rocprofv3 --pmc CSVs: the benchmark's
-    FETCH_SIZE and WRITE_SIZE runs and the copy calibration's."""
+    FETCH_SIZE and WRITE_SIZE runs and the copy calibration's. The screen is
+    the narrow-item kernel plus the wide-item kernel; their per-dispatch
+    counts are added."""
     fetch_csv, write_csv, cf_csv, cw_csv = a.counters_summary
-    prefix = SCREEN_KERNELS[a.precision]
-    fk, nf = per_dispatch_kib(fetch_csv, prefix, "FETCH_SIZE", ", false>")
-    wk, nw = per_dispatch_kib(write_csv, prefix, "WRITE_SIZE", ", false>")
+    narrow = SCREEN_KERNELS[a.precision]
+    wide = "k_screen_wide_bf16<" if a.precision == "bf16" else "k_screen_wide<"
+    per = {}
+    for name, prefix, suffix in (("narrow", narrow, ", false>"), ("wide", wide, ">")):
+        fk, nf = per_dispatch_kib(fetch_csv, prefix, "FETCH_SIZE", suffix)
+        wk, nw = per_dispatch_kib(write_csv, prefix, "WRITE_SIZE", suffix)
+        per[name] = (prefix + ("NS, false>" if name == "narrow" else "NS>"), fk, nf, wk, nw)
     copy_bytes = a.copy_mib * (1 << 20)
     copy_kernel = "at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add"
     cfk, _ = per_dispatch_kib(cf_csv, copy_kernel, "FETCH_SIZE")
     cwk, _ = per_dispatch_kib(cw_csv, copy_kernel, "WRITE_SIZE")
-    fetch_scale = copy_bytes / 1024.0 / cfk
-    write_scale = copy_bytes / 1024.0 / cwk
-    fetch_scale, write_scale = round(fetch_scale, 3), round(write_scale, 3)
+    fetch_scale = round(copy_bytes / 1024.0 / cfk, 3)
+    write_scale = round(copy_bytes / 1024.0 / cwk, 3)
+    fk = sum(v[1] for v in per.values())
+    wk = sum(v[3] for v in per.values())
     traffic = 1024.0 * (fk * fetch_scale + wk * write_scale)
-    rec = dict(kernel=prefix + "NS, false>", workload=a.workload_name, fetch_kib=round(fk, 1),
-               write_kib=round(wk, 1), fetch_scale=fetch_scale, write_scale=write_scale,
-               sources=screen_digest())
+    rec = dict(kernel=" + ".join(v[0] for v in per.values()), workload=a.workload_name,
+               fetch_kib=round(fk, 1), write_kib=round(wk, 1), fetch_scale=fetch_scale,
+               write_scale=write_scale, sources=screen_digest())
     print(f"# Fine-screen HBM traffic, {a.precision} screen, {a.workload_name}\n")
     print("Commands (from the repository root, one counter per run):\n")
     print("```")
     for c in a.commands:
         print(c)
     print("```\n")
-    print("| Counter | Kernel | Dispatches | KiB per dispatch | Copy calibration | Bytes per dispatch |")
-    print("|---|---|---|---|---|---|")
-    print(f"| FETCH_SIZE | `{prefix}NS, false>` | {nf} | {fk:.1f} | {a.copy_mib} MiB copy reads "
-          f"{cfk:.0f} KiB: x{fetch_scale} | {fk * fetch_scale * 1024 / 1e6:.2f} MB |")
-    print(f"| WRITE_SIZE | `{prefix}NS, false>` | {nw} | {wk:.1f} | {a.copy_mib} MiB copy writes "
-          f"{cwk:.0f} KiB: x{write_scale} | {wk * write_scale * 1024 / 1e6:.2f} MB |")
-    print(f"\nHBM traffic per launch: {traffic / 1e6:.2f} MB.\n")
+    print(f"Copy calibration: a {a.copy_mib} MiB device copy reads {cfk:.0f} KiB by FETCH_SIZE "
+          f"(scale x{fetch_scale}) and writes {cwk:.0f} KiB by WRITE_SIZE (scale x{write_scale}).\n")
+    print("| Kernel | Dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | Bytes per dispatch (scaled) |")
+    print("|---|---|---|---|---|")
+    for kname, f_, nf, w_, nw in per.values():
+        print(f"| `{kname}` | {nf} | {f_:.1f} | {w_:.1f} | "
+              f"{1024 * (f_ * fetch_scale + w_ * write_scale) / 1e6:.2f} MB |")
+    print(f"\nHBM traffic per screen step (both kernels): {traffic / 1e6:.2f} MB.\n")
     print("record: " + json.dumps(rec))
-
-
-def cpu_baseline(w, gpu_idx, seconds: float):
-    """Time the FP64 oracle on the batch's frames, repeating the batch until
-    about `seconds` of single-threaded work, and check the GPU's lists on the
-    frames it covered."""
-    import oracle
-    done, passes, t_total = 0, 0, 0.0
-    m = min(len(w.q), 8)
-    ora = None
-    while t_total < seconds:
-        t0 = time.perf_counter()
-        res = oracle.retrieve(w.feats, w.region_of, w.n_regions_total, w.q[:m], w.k, w.n_reg)
-        offs = w.req_offsets
-        for r in range(len(offs) - 1):
-            if offs[r + 1] > m:
-                break
-            oracle.aggregate(res["idx"][offs[r]:offs[r + 1]].ravel(), w.xy, *w.agg)
-        dt = time.perf_counter() - t0
-        t_total += dt
-        done += m
-        passes += 1
-        if ora is None or m > len(ora["idx"]):
-            ora = res
-        if m < len(w.q):
-            m = min(len(w.q), max(m + 1, int(m * (seconds - t_total) / max(dt, 1e-3))))
-    mm = len(ora["idx"])
-    hits = sum(len(set(gpu_idx[i].tolist()) & set(ora["idx"][i].tolist())) for i in range(mm))
-    exact = sum(int(np.array_equal(gpu_idx[i], ora["idx"][i])) for i in range(mm))
-    return dict(value=done / t_total, unit="queries/s", cores=1, kind="oracle",
-                sample=f"{done} frames of {w.name} ({passes} passes over the first {mm} of "
-                       f"{len(w.q)} frames), single thread, {t_total:.1f} s"), \
-        hits / (mm * w.k), exact, mm
 
 
 def serve_bench(a) -> None:
@@ -411,7 +386,12 @@ def main():
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e3)
     lat = np.array(lat)
+    # the fine screen: the narrow-item kernel, plus the wide-item kernel that
+    # follows it when some region is kept by more than 16 frames
+    wide_items = info["items"] - info["narrow_items"]
     screen_ms = phases["screen"][0] / max(phases["screen"][1], 1)
+    if wide_items > 0:
+        screen_ms += phases["screen_wide"][0] / max(phases["screen_wide"][1], 1)
     achieved = screen_bytes / (screen_ms * 1e-3) / 1e9
     traffic, traffic_src = load_traffic(w.name, a.precision)
     gpu_idx = idx.cpu().numpy()
@@ -443,7 +423,9 @@ def main():
         "recall_at_k": recall,
         "exact_lists": None if base is None else f"{exact}/{m}",
         "roofline": {"bound": "hbm",
-                     "kernel": "k_screen_bf16<NS,false>" if a.precision == "bf16" else "k_screen_blk<NS,false>",
+                     "kernel": ("k_screen_bf16<NS,false>" if a.precision == "bf16"
+                                else "k_screen_blk<NS,false>")
+                               + (" + wide-item kernel" if wide_items > 0 else ""),
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else int(traffic),

@@ -167,7 +167,9 @@ int hloc_reserve(hloc_db *db, int32_t nq_max, int32_t nreq_max, int32_t k_max,
  * items of the fine screen, out[1] frames whose coarse selection needed the
  * exact FP64 fallback, out[2] frames whose top-k needed it, out[3] largest
  * candidate count of a frame, out[4] survivors per frame (k'), out[5] total
- * candidates screened. Writes min(n, 6) values. Errors: EINVAL, EDEVICE.
+ * candidates screened, out[6] narrow work items (regions kept by at most 16
+ * frames; out[0] - out[6] are wide items). Writes min(n, 7) values.
+ * Errors: EINVAL, EDEVICE.
  */
 int hloc_query_info(hloc_db *db, int64_t *out, int32_t n);
 
@@ -224,7 +226,10 @@ int hloc_ws_replay(hloc_ws *ws, void *stream);
  *   HLOC_PHASE_PREP      query norms and padded copy
  *   HLOC_PHASE_COARSE    coarse screen, then select + FP64 re-score of regions
  *   HLOC_PHASE_SCHED     region -> frames lists and work items
- *   HLOC_PHASE_SCREEN    fine screen (one kernel launch)
+ *   HLOC_PHASE_SCREEN    fine screen of the narrow work items (and of every item
+ *                        at padded lengths without a register kernel)
+ *   HLOC_PHASE_SCREEN_WIDE fine screen of the wide work items (regions kept by
+ *                        more than 16 frames)
  *   HLOC_PHASE_SELECT    per-frame select, FP64 rerank, certificate, exact fallback
  *   HLOC_PHASE_AGGREGATE aggregation of each request
  * (kernels of a phase dispatched with start/stop events). It covers the
@@ -241,7 +246,8 @@ enum {
   HLOC_PHASE_SCREEN = 3,
   HLOC_PHASE_SELECT = 4,
   HLOC_PHASE_AGGREGATE = 5,
-  HLOC_NUM_PHASES = 6
+  HLOC_PHASE_SCREEN_WIDE = 6,
+  HLOC_NUM_PHASES = 7
 };
 int hloc_profile(hloc_db *db, int32_t enable);
 int hloc_profile_read(hloc_db *db, double *ms, int64_t *calls, int32_t n);

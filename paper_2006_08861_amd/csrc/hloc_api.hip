@@ -112,7 +112,7 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
   p.cap2 = db->h_desc_prefix[p.nr];
   const int64_t maxch = (db->max_region + kRowsFine - 1) / kRowsFine;
   const int64_t b1 = (int64_t)nq * p.nr * maxch;
-  const int64_t b2 = db->chunks_fine * (((int64_t)nq + kGroup - 1) / kGroup);
+  const int64_t b2 = db->chunks_fine * (((int64_t)nq + kItemFrames - 1) / kItemFrames);
   p.items_bound = std::min(b1, b2);
   if (p.items_bound > INT32_MAX || (int64_t)nq * p.cap2 > ((int64_t)1 << 40))
     return fail(HLOC_EINVAL, "batch too large for one call (nq %d)", nq);
@@ -142,6 +142,7 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *byte
   CHK(fit(ws->regions, (size_t)nq * nr * sizeof(int32_t)));
   CHK(fit(ws->rcount, (size_t)db->R * sizeof(int32_t)));
   CHK(fit(ws->rfill, (size_t)db->R * sizeof(int32_t)));
+  CHK(fit(ws->vord, (size_t)db->R * sizeof(int32_t)));
   CHK(fit(ws->rq_off, (size_t)(db->R + 1) * sizeof(int32_t)));
   CHK(fit(ws->item_off, (size_t)(db->R + 1) * sizeof(int32_t)));
   CHK(fit(ws->cand_off, (size_t)nq * nr * sizeof(int32_t)));
@@ -273,7 +274,8 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   ph.begin(HLOC_PHASE_SCHED);
   int32_t *cand_off = as<int32_t>(ws->cand_off), *n_cand = as<int32_t>(ws->n_cand);
   HIPCHK(launch_sched(regions, p.nq, p.nr, db->R, db->reg_start, kRowsFine,
-                      as<int32_t>(ws->rcount), as<int32_t>(ws->rfill), as<int32_t>(ws->rq_off),
+                      as<int32_t>(ws->rcount), as<int32_t>(ws->rfill), as<int32_t>(ws->vord),
+                      as<int32_t>(ws->rq_off),
                       as<int32_t>(ws->item_off), cand_off, n_cand, misc + 0, as<int2>(ws->rq),
                       as<Item>(ws->items), s));
   ph.begin(HLOC_PHASE_SCREEN);
@@ -294,10 +296,10 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   if (bf16) {
     sb.rows16 = db->rows16;
     sb.qp16 = qp16;
-    HIPCHK(launch_screen_bf16(sb, p.grid2, s));
-  } else {
-    HIPCHK(launch_screen_f32(sb, p.grid2, s));
   }
+  HIPCHK(bf16 ? launch_screen_bf16(sb, p.grid2, s) : launch_screen_f32(sb, p.grid2, s));
+  ph.begin(HLOC_PHASE_SCREEN_WIDE);
+  HIPCHK(bf16 ? launch_screen_wide_bf16(sb, p.grid2, s) : launch_screen_wide_f32(sb, p.grid2, s));
   ph.begin(HLOC_PHASE_SELECT);
   SelRerankArgs rb{};
   rb.cand = as<uint32_t>(ws->cand2);
@@ -397,7 +399,7 @@ void drop_graph(hloc_ws *ws) {
 void free_ws(hloc_ws *ws) {
   if (!ws) return;
   drop_graph(ws);
-  WsBuf *bufs[] = {&ws->qp,       &ws->qn2,      &ws->cand1,    &ws->regions, &ws->rcount,
+  WsBuf *bufs[] = {&ws->vord,     &ws->qp,       &ws->qn2,      &ws->cand1,    &ws->regions, &ws->rcount,
                    &ws->rfill,    &ws->rq_off,   &ws->item_off, &ws->cand_off, &ws->n_cand,
                    &ws->misc,     &ws->rq,       &ws->items,    &ws->cand2,   &ws->agg_xy,
                    &ws->agg_tile, &ws->agg_flags, &ws->s_q,     &ws->s_off,   &ws->s_idx,
@@ -471,8 +473,8 @@ int info_of(hloc_ws *ws, int64_t *out, int32_t n) {
     HIPCHK(hipMemcpy(nc.data(), ws->n_cand.p, nc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     for (int32_t v : nc) total += v;
   }
-  const int64_t vals[6] = {misc[0], misc[1], misc[2], misc[3], ws->last_kp, total};
-  for (int32_t i = 0; i < std::min(n, 6); ++i) out[i] = vals[i];
+  const int64_t vals[7] = {misc[0], misc[1], misc[2], misc[3], ws->last_kp, total, misc[4]};
+  for (int32_t i = 0; i < std::min(n, 7); ++i) out[i] = vals[i];
   return HLOC_OK;
 }
 

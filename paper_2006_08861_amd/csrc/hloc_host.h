@@ -69,7 +69,7 @@ struct ProfRec {
 struct hloc_ws {
   hloc_db *db = nullptr;
   hipStream_t stream = nullptr;  // own stream (graph capture, host-pointer calls)
-  hloc::WsBuf qp, qn2, cand1, regions, rcount, rfill, rq_off, item_off, cand_off, n_cand, misc, rq,
+  hloc::WsBuf qp, qn2, cand1, regions, rcount, rfill, vord, rq_off, item_off, cand_off, n_cand, misc, rq,
       items, cand2, agg_xy, agg_tile, agg_flags, qp16, q_err, q_lon;
   hloc::WsBuf s_q, s_off, s_idx, s_dist, s_xy, s_tile, s_flags;  // staging of host-pointer calls
   int32_t last_nq = 0, last_nr = 0, last_kp = 0;

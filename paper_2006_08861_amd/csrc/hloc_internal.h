@@ -37,6 +37,7 @@ inline hipError_t launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t lds, h
 }
 
 constexpr int kGroup = 16;          // frames per MFMA column block of the screen
+constexpr int kItemFrames = 64;     // frames per screen work item (up to four column blocks)
 constexpr int kBlock = 256;         // threads per block of most kernels
 constexpr int kSelectLds = 4096;    // keys held in LDS by the select kernel
 constexpr uint64_t kKeyNone = ~0ull;  // empty slot / no candidate
@@ -50,7 +51,7 @@ inline int next_pow2_host(int v) {
 
 // One unit of fine-screen work: rows [row_begin, row_begin + nrows) of one
 // region (absolute row indices; chunk_row = offset of the chunk inside its
-// region) against frames rq[q0 .. q0 + gq).
+// region) against frames rq[q0 .. q0 + gq), gq <= kItemFrames.
 struct Item {
   int32_t row_begin;
   int32_t chunk_row;
@@ -87,8 +88,12 @@ struct ScreenArgs {
 hipError_t launch_prep_queries(const float *q, int32_t nq, int32_t d, int32_t dp, float *qp,
                                float *qn2, int32_t *zero16, uint16_t *qp16, float *q_err,
                                float *q_lon, hipStream_t s);
+// Dense screen, or the narrow list items (every list item where no register
+// kernel exists for the padded length); then the wide list items.
 hipError_t launch_screen_f32(const ScreenArgs &a, int32_t grid, hipStream_t s);
+hipError_t launch_screen_wide_f32(const ScreenArgs &a, int32_t grid, hipStream_t s);
 hipError_t launch_screen_bf16(const ScreenArgs &a, int32_t grid, hipStream_t s);
+hipError_t launch_screen_wide_bf16(const ScreenArgs &a, int32_t grid, hipStream_t s);
 bool bf16_screen_supports(int32_t dp);
 // bf16 copy of n rows; maxima of the per-row norms of the rounding error and
 // of the rounded row.
@@ -101,10 +106,13 @@ int32_t screen_grid(int64_t items, int32_t dp, int32_t max_blocks);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_broadcast_ids(const int32_t *ids, int32_t nr, int32_t nq, int32_t *regions,
                                 hipStream_t s);
+// Work items into items[0 .. n_items[0]): narrow ones (frames of regions kept
+// by at most kGroup frames) first, n_items[4] of them, then wide ones.
 hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t R,
                         const int64_t *reg_start, int32_t T, int32_t *rcount, int32_t *rfill,
-                        int32_t *rq_off, int32_t *item_off, int32_t *cand_off, int32_t *n_cand,
-                        int32_t *n_items, int2 *rq, Item *items, hipStream_t s);
+                        int32_t *vord, int32_t *rq_off, int32_t *item_off, int32_t *cand_off,
+                        int32_t *n_cand, int32_t *n_items, int2 *rq, Item *items,
+                        hipStream_t s);
 
 // Per frame: the L + 1 smallest screen words of cand[f][0 .. n(f)) (n(f) =
 // n_cand ? n_cand[f] : n_fixed; 0xFFFFFFFF entries are skipped; equal words

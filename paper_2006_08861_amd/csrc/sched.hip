@@ -1,10 +1,19 @@
 // Scheduling of the fine screen: the frame -> regions lists chosen by the
 // coarse stage are inverted into region -> frames lists, and every touched
-// region is cut into chunks of T rows crossed with groups of up to 16 frames.
-// This takes the place of the paper's one-stream-per-subspace launch
-// (Section 3.1): a region's rows are read once per group of frames that kept
-// it, and uneven regions become many equal-sized work items for one
-// persistent kernel. Every count lives in device memory; no host round trip.
+// region is cut into chunks of T rows crossed with groups of up to
+// kItemFrames frames. This takes the place of the paper's
+// one-stream-per-subspace launch (Section 3.1): uneven regions become many
+// equal-sized work items for persistent screen kernels, and every count lives
+// in device memory (no host round trip).
+//
+// Items come in two classes. A region kept by at most kGroup frames gives
+// narrow items (one MFMA column block of frames); a region kept by more
+// frames gives wide items of up to kItemFrames frames, screened by a kernel
+// that reads each row once for all of them. Narrow items are numbered first:
+// items [0, n_items[4]) are narrow, [n_items[4], n_items[0]) wide. Regions
+// are laid out in that order (narrow regions by id, then wide regions by id)
+// in vord, with their first item in iof (non-decreasing), so the owner of an
+// item is found by binary search.
 #include "hloc_device.h"
 #include "hloc_internal.h"
 
@@ -24,37 +33,129 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
   return launch_kernel(k_fill_i32, dim3(grid), dim3(256), 0, s, p, n, v);
 }
 
-// Region owning work item t: the last r with item_off[r] <= t, for
-// non-decreasing item_off with item_off[0] = 0 <= t < item_off[R]; that region
-// has at least one item (item_off[r + 1] > t).
-__device__ __forceinline__ int owner_region(const int32_t *item_off, int R, int t) {
+// Slot owning work item t: the last k with iof[k] <= t, for non-decreasing
+// iof with iof[0] = 0 <= t < iof[R]; that slot has at least one item.
+__device__ __forceinline__ int owner_slot(const int32_t *iof, int R, int t) {
   int lo = 0, hi = R;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (item_off[mid] <= t) lo = mid;
+    if (iof[mid] <= t) lo = mid;
     else hi = mid;
   }
   return lo;
 }
 
 __device__ __forceinline__ int items_of(int g, int64_t rows, int T) {
-  return g > 0 ? (int)((rows + T - 1) / T) * ((g + kGroup - 1) / kGroup) : 0;
+  return g > 0 ? (int)((rows + T - 1) / T) * ((g + kItemFrames - 1) / kItemFrames) : 0;
 }
 
 // Work item t of region r, whose frames are rq[q_begin, q_end): chunk-major,
 // frame groups inner, so consecutive items re-read the same rows.
 __device__ __forceinline__ Item make_item(int t, int r, int item_begin, int q_begin, int q_end,
                                           const int64_t *__restrict__ reg_start, int T) {
-  const int g = q_end - q_begin, ngr = (g + kGroup - 1) / kGroup;
+  const int g = q_end - q_begin, ngr = (g + kItemFrames - 1) / kItemFrames;
   const int local = t - item_begin, c = local / ngr, b = local - c * ngr;
   const int64_t r0 = reg_start[r];
   const int rows = (int)(reg_start[r + 1] - r0);
   Item it;
   it.row_begin = (int32_t)r0 + c * T;
   it.chunk_row = c * T;
-  it.q0 = q_begin + b * kGroup;
-  it.nrows_gq = (min(T, rows - c * T) << 16) | min(kGroup, g - b * kGroup);
+  it.q0 = q_begin + b * kItemFrames;
+  it.nrows_gq = (min(T, rows - c * T) << 16) | min(kItemFrames, g - b * kItemFrames);
   return it;
+}
+
+// Block-wide (blockDim.x <= 1024) scans over the regions, each thread taking a
+// contiguous range of them: rq_off (R + 1, first frame of each region in id
+// order), vord / iof (the regions in narrow-then-wide order and their first
+// item), n_items[0] (all items) and n_items[4] (narrow items). With fill set,
+// fill[r] = rq_off[r]. count may alias fill. s_red holds 72 ints of LDS.
+__device__ void sched_scan(const int32_t *count, int R, const int64_t *__restrict__ reg_start,
+                           int T, int32_t *rq_off, int32_t *vord, int32_t *iof,
+                           int32_t *n_items, int32_t *fill, int *s_red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int per = (R + nt - 1) / nt;
+  const int r0 = min(R, tid * per), r1 = min(R, r0 + per);
+  // frames, narrow items, wide items, narrow regions
+  int v[4] = {0, 0, 0, 0};
+  for (int r = r0; r < r1; ++r) {
+    const int g = count[r];
+    const int m = items_of(g, reg_start[r + 1] - reg_start[r], T);
+    v[0] += g;
+    if (g <= kGroup) {
+      v[1] += m;
+      v[3] += 1;
+    } else {
+      v[2] += m;
+    }
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+  int inc[4] = {v[0], v[1], v[2], v[3]};
+  for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int y = __shfl_up(inc[q], o);
+      if (lane >= o) inc[q] += y;
+    }
+  }
+  if (lane == 63) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_red[q * 16 + wv] = inc[q];
+  }
+  __syncthreads();
+  for (int i = 0; i < wv; ++i) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) inc[q] += s_red[q * 16 + i];
+  }
+  if (tid == nt - 1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_red[64 + q] = inc[q];
+  }
+  __syncthreads();
+  const int BN = s_red[65], CN = s_red[67];
+  int pa = inc[0] - v[0], pbn = inc[1] - v[1], pbw = inc[2] - v[2], pcn = inc[3] - v[3];
+  for (int r = r0; r < r1; ++r) {
+    const int g = count[r];
+    const int m = items_of(g, reg_start[r + 1] - reg_start[r], T);
+    rq_off[r] = pa;
+    if (fill) fill[r] = pa;
+    pa += g;
+    int pos;
+    if (g <= kGroup) {
+      pos = pcn;
+      iof[pos] = pbn;
+      pbn += m;
+      pcn += 1;
+    } else {
+      pos = CN + (r - pcn);  // wide regions before r: r minus the narrow ones
+      iof[pos] = BN + pbw;
+      pbw += m;
+    }
+    vord[pos] = r;
+  }
+  if (tid == nt - 1) {
+    rq_off[R] = inc[0];
+    iof[R] = inc[1] + inc[2];
+    n_items[0] = inc[1] + inc[2];
+    n_items[4] = inc[1];
+  }
+}
+
+// Exhaustive search (every non-empty region kept, the paper's whole-database
+// search): every frame gets the same region list.
+__global__ void k_broadcast_ids(const int32_t *__restrict__ ids, int nr, int64_t total,
+                                int32_t *__restrict__ regions) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x)
+    regions[t] = ids[t % nr];
+}
+
+hipError_t launch_broadcast_ids(const int32_t *ids, int32_t nr, int32_t nq, int32_t *regions,
+                                hipStream_t s) {
+  const int64_t total = (int64_t)nr * nq;
+  if (total <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  return launch_kernel(k_broadcast_ids, dim3(grid), dim3(256), 0, s, ids, nr, total, regions);
 }
 
 // Multi-kernel schedule for large region counts. Per frame: offset of each
@@ -76,55 +177,15 @@ __global__ void k_sched_count(const int32_t *__restrict__ regions, int nq, int n
   n_cand[f] = off;
 }
 
-// One block: exclusive scans over regions of the frame counts (-> rq_off,
-// R + 1 entries) and of the work-item counts (-> item_off, R + 1 entries);
-// clears rfill.
+// One block: the scans of sched_scan over the region counts; clears rfill.
 __global__ __launch_bounds__(1024) void k_sched_scan(const int32_t *__restrict__ rcount, int R,
                                                      const int64_t *__restrict__ reg_start, int T,
-                                                     int32_t *rq_off, int32_t *item_off,
-                                                     int32_t *n_items, int32_t *rfill) {
-  __shared__ int s_a[16], s_b[16];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int per = (R + nt - 1) / nt;
-  const int r0 = min(R, tid * per), r1 = min(R, r0 + per);
-  int sa = 0, sb = 0;
-  for (int r = r0; r < r1; ++r) {
-    const int g = rcount[r];
-    sa += g;
-    sb += items_of(g, reg_start[r + 1] - reg_start[r], T);
-  }
-  const int lane = tid & 63, wv = tid >> 6;
-  int ia = sa, ib = sb;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int ya = __shfl_up(ia, o), yb = __shfl_up(ib, o);
-    if (lane >= o) {
-      ia += ya;
-      ib += yb;
-    }
-  }
-  if (lane == 63) {
-    s_a[wv] = ia;
-    s_b[wv] = ib;
-  }
-  __syncthreads();
-  for (int i = 0; i < wv; ++i) {
-    ia += s_a[i];
-    ib += s_b[i];
-  }
-  int ba = ia - sa, bb = ib - sb;
-  for (int r = r0; r < r1; ++r) {
-    const int g = rcount[r];
-    rq_off[r] = ba;
-    item_off[r] = bb;
-    rfill[r] = 0;
-    ba += g;
-    bb += items_of(g, reg_start[r + 1] - reg_start[r], T);
-  }
-  if (tid == nt - 1) {
-    rq_off[R] = ia;
-    item_off[R] = ib;
-    n_items[0] = ib;
-  }
+                                                     int32_t *rq_off, int32_t *vord,
+                                                     int32_t *iof, int32_t *n_items,
+                                                     int32_t *rfill) {
+  __shared__ int s_red[72];
+  sched_scan(rcount, R, reg_start, T, rq_off, vord, iof, n_items, nullptr, s_red);
+  for (int r = threadIdx.x; r < R; r += blockDim.x) rfill[r] = 0;
 }
 
 __global__ void k_sched_scatter(const int32_t *__restrict__ regions, int nq, int nr, int R,
@@ -141,42 +202,27 @@ __global__ void k_sched_scatter(const int32_t *__restrict__ regions, int nq, int
 
 // One thread per work item (grid-stride), each finding its region by binary
 // search, so that a region kept by many frames is expanded by many threads.
-__global__ void k_sched_items(int R, const int32_t *__restrict__ item_off,
+__global__ void k_sched_items(int R, const int32_t *__restrict__ vord,
+                              const int32_t *__restrict__ iof,
                               const int32_t *__restrict__ rq_off,
                               const int64_t *__restrict__ reg_start, int T, Item *items) {
-  const int n = item_off[R];
+  const int n = iof[R];
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const int r = owner_region(item_off, R, t);
-    items[t] = make_item(t, r, item_off[r], rq_off[r], rq_off[r + 1], reg_start, T);
+    const int k = owner_slot(iof, R, t);
+    const int r = vord[k];
+    items[t] = make_item(t, r, iof[k], rq_off[r], rq_off[r + 1], reg_start, T);
   }
 }
 
-// Exhaustive search (every non-empty region kept, the paper's whole-database
-// search): every frame gets the same region list.
-__global__ void k_broadcast_ids(const int32_t *__restrict__ ids, int nr, int64_t total,
-                                int32_t *__restrict__ regions) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x)
-    regions[t] = ids[t % nr];
-}
-
-hipError_t launch_broadcast_ids(const int32_t *ids, int32_t nr, int32_t nq, int32_t *regions,
-                                hipStream_t s) {
-  const int64_t total = (int64_t)nr * nq;
-  if (total <= 0) return hipSuccess;
-  const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
-  return launch_kernel(k_broadcast_ids, dim3(grid), dim3(256), 0, s, ids, nr, total, regions);
-}
-
 // The whole schedule in one block for up to kFusedMaxR regions and
-// kFusedMaxPairs (frame, region) pairs: per-region
-// counts, fill pointers and item offsets live in LDS, so the histogram and the
-// scatter use LDS atomics (no contention on global memory when many frames
-// keep the same region), and work items are expanded one per thread.
-constexpr int kFusedMaxR = 16384;
+// kFusedMaxPairs (frame, region) pairs: per-region counts, fill pointers,
+// order and item offsets live in LDS, so the histogram and the scatter use
+// LDS atomics (no contention on global memory when many frames keep the same
+// region), and work items are expanded one per thread.
+constexpr int kFusedMaxR = 12288;
 constexpr int64_t kFusedMaxPairs = 8192;  // larger batches: the multi-kernel path is faster
 
-size_t fused_lds_bytes(int R) { return (size_t)(2 * R + 1) * sizeof(int); }
+size_t fused_lds_bytes(int R) { return (size_t)(3 * R + 1) * sizeof(int); }
 
 __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict__ regions, int nq,
                                                       int nr, int R,
@@ -185,9 +231,10 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
                                                       int32_t *n_cand, int32_t *n_items, int2 *rq,
                                                       Item *items) {
   extern __shared__ int s_mem[];
-  int *s_fill = s_mem;     // R: frame counts, then fill pointers
-  int *s_iof = s_mem + R;  // R + 1: item offsets
-  __shared__ int s_a[16], s_b[16];
+  int *s_fill = s_mem;         // R: frame counts, then fill pointers
+  int *s_vord = s_mem + R;     // R: regions in narrow-then-wide order
+  int *s_iof = s_mem + 2 * R;  // R + 1: first item of each slot of s_vord
+  __shared__ int s_red[72];
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int r = tid; r < R; r += nt) s_fill[r] = 0;
   __syncthreads();
@@ -215,48 +262,8 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
     n_cand[f] = off;
   }
   __syncthreads();
-  // exclusive scans of (frames, items) over regions: a contiguous range of
-  // regions per thread, shuffles within each wave, then the wave totals
-  const int per = (R + nt - 1) / nt;
-  const int r0 = min(R, tid * per), r1 = min(R, r0 + per);
-  int sa = 0, sb = 0;
-  for (int r = r0; r < r1; ++r) {
-    const int g = s_fill[r];
-    sa += g;
-    sb += items_of(g, reg_start[r + 1] - reg_start[r], T);
-  }
-  const int lane = tid & 63, wv = tid >> 6;
-  int ia = sa, ib = sb;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int ya = __shfl_up(ia, o), yb = __shfl_up(ib, o);
-    if (lane >= o) {
-      ia += ya;
-      ib += yb;
-    }
-  }
-  if (lane == 63) {
-    s_a[wv] = ia;
-    s_b[wv] = ib;
-  }
-  __syncthreads();
-  for (int i = 0; i < wv; ++i) {
-    ia += s_a[i];
-    ib += s_b[i];
-  }
-  int ba = ia - sa, bb = ib - sb;
-  for (int r = r0; r < r1; ++r) {
-    const int g = s_fill[r];
-    rq_off[r] = ba;
-    s_fill[r] = ba;
-    s_iof[r] = bb;
-    ba += g;
-    bb += items_of(g, reg_start[r + 1] - reg_start[r], T);
-  }
-  if (tid == nt - 1) {
-    rq_off[R] = ia;
-    s_iof[R] = ib;
-    n_items[0] = ib;
-  }
+  // counts -> fill pointers (each thread reads and rewrites only its own range)
+  sched_scan(s_fill, R, reg_start, T, rq_off, s_vord, s_iof, n_items, s_fill, s_red);
   __syncthreads();
   const int64_t pairs = (int64_t)nq * nr;
   for (int64_t t = tid; t < pairs; t += nt) {
@@ -266,12 +273,11 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
     rq[pos] = make_int2((int)(t / nr), cand_off[t]);
   }
   __syncthreads();
-  // after the scatter s_fill[r] is the end of region r's frames, which is
-  // also where region r + 1's frames begin
   const int n = s_iof[R];
   for (int t = tid; t < n; t += nt) {
-    const int r = owner_region(s_iof, R, t);
-    items[t] = make_item(t, r, s_iof[r], r > 0 ? s_fill[r - 1] : 0, s_fill[r], reg_start, T);
+    const int k = owner_slot(s_iof, R, t);
+    const int r = s_vord[k];
+    items[t] = make_item(t, r, s_iof[k], rq_off[r], rq_off[r + 1], reg_start, T);
   }
 }
 
@@ -283,8 +289,9 @@ hipError_t prepare_sched_kernels() {
 
 hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t R,
                         const int64_t *reg_start, int32_t T, int32_t *rcount, int32_t *rfill,
-                        int32_t *rq_off, int32_t *item_off, int32_t *cand_off, int32_t *n_cand,
-                        int32_t *n_items, int2 *rq, Item *items, hipStream_t s) {
+                        int32_t *vord, int32_t *rq_off, int32_t *item_off, int32_t *cand_off,
+                        int32_t *n_cand, int32_t *n_items, int2 *rq, Item *items,
+                        hipStream_t s) {
   const int64_t pairs = (int64_t)nq * nr;
   if (R <= kFusedMaxR && pairs <= kFusedMaxPairs) {
     return launch_kernel(k_sched_fused, dim3(1), dim3(1024), (uint32_t)fused_lds_bytes(R), s,
@@ -299,15 +306,15 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
       return e;
   }
   if ((e = launch_kernel(k_sched_scan, dim3(1), dim3(1024), 0, s, rcount, R, reg_start, T,
-                         rq_off, item_off, n_items, rfill)) != hipSuccess)
+                         rq_off, vord, item_off, n_items, rfill)) != hipSuccess)
     return e;
   if (pairs > 0) {
     if ((e = launch_kernel(k_sched_scatter, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0,
                            s, regions, nq, nr, R, cand_off, rq_off, rfill, rq)) != hipSuccess)
       return e;
   }
-  return launch_kernel(k_sched_items, dim3(1024), dim3(256), 0, s, R, item_off, rq_off, reg_start,
-                       T, items);
+  return launch_kernel(k_sched_items, dim3(1024), dim3(256), 0, s, R, vord, item_off, rq_off,
+                       reg_start, T, items);
 }
 
 }  // namespace hloc

@@ -74,20 +74,21 @@ hipError_t launch_rows_to_bf16(const float *src, int64_t n, int32_t dp, uint16_t
                        dim3(256), 0, s, src, n, dp, dst, max_err, max_norm);
 }
 
-// One item per block, one 16-row block per wave, as the fp32 register screen.
+// Dense items and narrow list items, one item per block, one 16-row block per
+// wave, as the fp32 register screen.
 template <int NS, bool DENSE>  // NS = dp / 32
 __global__ __launch_bounds__(256) void k_screen_bf16(ScreenArgs a) {
   constexpr int DP = NS * 32;
   const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
   const int i = lane & 15, g = lane >> 4;
-  int n_items, nchunks = 1;
+  int lo = 0, hi, nchunks = 1;
   if (DENSE) {
     nchunks = (a.nrows + a.rows_per_item - 1) / a.rows_per_item;
-    n_items = nchunks * ((a.nq + kGroup - 1) / kGroup);
+    hi = nchunks * ((a.nq + kGroup - 1) / kGroup);
   } else {
-    n_items = *a.n_items;
+    hi = a.n_items[4];  // the narrow items: at most kGroup frames each
   }
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
     int row_begin, chunk_row, nrows, gq, fr = 0;
     int64_t off = 0;
     if (DENSE) {
@@ -149,6 +150,81 @@ __global__ __launch_bounds__(256) void k_screen_bf16(ScreenArgs a) {
   }
 }
 
+// Wide list items, as the fp32 wide screen.
+template <int NS>  // NS = dp / 32
+__global__ __launch_bounds__(256) void k_screen_wide_bf16(ScreenArgs a) {
+  constexpr int DP = NS * 32;
+  constexpr int NG = kItemFrames / kGroup;
+  const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int lo = a.n_items[4], hi = a.n_items[0];
+  for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
+    const Item itm = a.items[it];
+    const int row_begin = itm.row_begin, chunk_row = itm.chunk_row;
+    const int nrows = itm.nrows_gq >> 16, gq = itm.nrows_gq & 0xFFFF;
+    const int ng = (gq + kGroup - 1) / kGroup;
+    int fr[NG];
+    int64_t off[NG];
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      fr[j] = 0;
+      off[j] = 0;
+      if (j * kGroup + i < gq) {
+        const int2 e = a.rq[itm.q0 + j * kGroup + i];
+        fr[j] = e.x;
+        off[j] = (int64_t)e.x * a.cap + e.y + chunk_row;
+      }
+    }
+    const int nrb = (nrows + 15) >> 4;
+    for (int rb = w; rb < nrb; rb += nw) {
+      const int rl = min(rb * 16 + i, nrows - 1);
+      const uint4 *rp = reinterpret_cast<const uint4 *>(a.rows16 + (int64_t)(row_begin + rl) * DP) + g;
+      const uint4 *qp[NG];
+#pragma unroll
+      for (int j = 0; j < NG; ++j)
+        qp[j] = reinterpret_cast<const uint4 *>(a.qp16 + (int64_t)fr[j] * DP) + g;
+      v4f acc[NG];
+#pragma unroll
+      for (int j = 0; j < NG; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+      for (int s = 0; s < NS; ++s) {
+        const uint4 av = rp[4 * s];
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+          if (j < ng) {
+            const uint4 bv = qp[j][4 * s];
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
+                                                             __builtin_bit_cast(v8bf, bv), acc[j],
+                                                             0, 0, 0);
+          }
+        }
+      }
+      float rn[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rn[r] = a.row_n2[row_begin + min(rb * 16 + 4 * g + r, nrows - 1)];
+#pragma unroll
+      for (int j = 0; j < NG; ++j) {
+        if (j < ng && j * kGroup + i < gq) {
+          const float qn = a.qn2[fr[j]];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = rb * 16 + 4 * g + r;
+            if (row < nrows) {
+              uint32_t word = 0xFFFFFFFFu;
+              if (!__builtin_isinf(rn[r])) {
+                float dd = (qn + rn[r]) - 2.f * acc[j][r];
+                dd = dd > 0.f ? dd : 0.f;
+                word = __float_as_uint(dd);
+              }
+              a.cand[off[j] + row] = word;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 template <int NS, bool DENSE>
 hipError_t launch_bf16_t(const ScreenArgs &a, int32_t grid, hipStream_t s) {
   return launch_kernel(k_screen_bf16<NS, DENSE>, dim3(grid), dim3(256), 0, s, a);
@@ -173,6 +249,29 @@ hipError_t launch_screen_bf16(const ScreenArgs &a, int32_t grid, hipStream_t s) 
     HLOC_BF16_CASE(384)
     HLOC_BF16_CASE(512)
 #undef HLOC_BF16_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_screen_wide_bf16(const ScreenArgs &a, int32_t grid, hipStream_t s) {
+  if (grid <= 0 || a.dense) return hipSuccess;
+  if (a.rows_per_item % 16 != 0) return hipErrorInvalidValue;
+  switch (a.dp) {
+#define HLOC_BF16_WIDE_CASE(DPV) \
+  case DPV:                      \
+    return launch_kernel(k_screen_wide_bf16<DPV / 32>, dim3(grid), dim3(256), 0, s, a);
+    HLOC_BF16_WIDE_CASE(32)
+    HLOC_BF16_WIDE_CASE(64)
+    HLOC_BF16_WIDE_CASE(96)
+    HLOC_BF16_WIDE_CASE(128)
+    HLOC_BF16_WIDE_CASE(160)
+    HLOC_BF16_WIDE_CASE(192)
+    HLOC_BF16_WIDE_CASE(256)
+    HLOC_BF16_WIDE_CASE(320)
+    HLOC_BF16_WIDE_CASE(384)
+    HLOC_BF16_WIDE_CASE(512)
+#undef HLOC_BF16_WIDE_CASE
     default:
       return hipErrorInvalidValue;
   }

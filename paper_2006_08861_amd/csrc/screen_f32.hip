@@ -3,9 +3,9 @@
 // Squared L2 distance of each frame to each candidate row, written as
 // |q|^2 + |d|^2 - 2 q.d with the dot products on the matrix cores (the
 // comparison of a frame with every row of a subspace, Section 3.1 /
-// Algorithm 1). A block of four waves takes one work item: up to 16 frames
-// (one MFMA column block, staged in LDS) against a chunk of rows; each wave
-// walks 16-row blocks of the chunk. Lane l holds row (l % 16) and the k-slice
+// Algorithm 1). A block of four waves takes one work item: up to kItemFrames
+// frames, 16 at a time (one MFMA column block), against a chunk of rows; each
+// wave walks 16-row blocks of the chunk. Lane l holds row (l % 16) and the k-slice
 // 4 * (l / 16) + 16 s + {0..3}, so one 16-byte load feeds four MFMAs and the
 // 16 rows of a block are read as 64-byte runs. The frame operand uses the
 // same k-slice, so the k order of the sum is identical for every frame slot:
@@ -81,110 +81,121 @@ __global__ __launch_bounds__(256) void k_screen_f32(ScreenArgs a) {
   int n_items, nchunks = 1;
   if (DENSE) {
     nchunks = (a.nrows + a.rows_per_item - 1) / a.rows_per_item;
-    n_items = nchunks * ((a.nq + kGroup - 1) / kGroup);
+    n_items = nchunks * ((a.nq + kItemFrames - 1) / kItemFrames);
   } else {
     n_items = *a.n_items;
   }
   const int i = lane & 15, g = lane >> 4;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-    int64_t row_begin;
-    int nrows, gq;
+    int64_t row_begin, chunk_row;
+    int nrows, gq, f0 = 0, q0 = 0;
     if (DENSE) {
-      const int c = it % nchunks, grp = it / nchunks;
+      const int c = it % nchunks;
+      f0 = (it / nchunks) * kItemFrames;
       row_begin = (int64_t)c * a.rows_per_item;
+      chunk_row = row_begin;
       nrows = min(a.rows_per_item, a.nrows - c * a.rows_per_item);
-      gq = min(kGroup, a.nq - grp * kGroup);
-      if (tid < kGroup) {
-        const int f = grp * kGroup + tid;
-        s_q[tid] = tid < gq ? f : 0;
-        s_off[tid] = (int64_t)f * a.cap + row_begin;
-        s_qn[tid] = tid < gq ? a.qn2[f] : 0.f;
-      }
+      gq = min(kItemFrames, a.nq - f0);
     } else {
       const Item itm = a.items[it];
       row_begin = itm.row_begin;
+      chunk_row = itm.chunk_row;
       nrows = itm.nrows_gq >> 16;
       gq = itm.nrows_gq & 0xFFFF;
+      q0 = itm.q0;
+    }
+    for (int j0 = 0; j0 < gq; j0 += kGroup) {
+      // this group's frames -> LDS
+      const int gs = min(kGroup, gq - j0);
       if (tid < kGroup) {
-        if (tid < gq) {
-          const int2 e = a.rq[itm.q0 + tid];
-          s_q[tid] = e.x;
-          s_off[tid] = (int64_t)e.x * a.cap + e.y + itm.chunk_row;
-          s_qn[tid] = a.qn2[e.x];
+        if (tid < gs) {
+          int f;
+          int64_t base;
+          if (DENSE) {
+            f = f0 + j0 + tid;
+            base = (int64_t)f * a.cap;
+          } else {
+            const int2 e = a.rq[q0 + j0 + tid];
+            f = e.x;
+            base = (int64_t)e.x * a.cap + e.y;
+          }
+          s_q[tid] = f;
+          s_off[tid] = base + chunk_row;
+          s_qn[tid] = a.qn2[f];
         } else {
           s_q[tid] = 0;
           s_off[tid] = 0;
           s_qn[tid] = 0.f;
         }
       }
-    }
-    __syncthreads();
-    for (int e = tid; e < kGroup * dp4; e += blockDim.x) {
-      const int j = e / dp4, c = e - j * dp4;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (j < gq) v = reinterpret_cast<const float4 *>(a.qp + (int64_t)s_q[j] * dp)[c];
-      *reinterpret_cast<float4 *>(qs + j * ldq + 4 * c) = v;
-    }
-    __syncthreads();
-    const float4 *qrow = reinterpret_cast<const float4 *>(qs + i * ldq) + g;
-    const int nrb = (nrows + 15) >> 4;
-    for (int rb = wave; rb < nrb; rb += 4) {
-      int rl = rb * 16 + i;
-      rl = rl < nrows ? rl : nrows - 1;
-      const float4 *rp = reinterpret_cast<const float4 *>(a.rows + (row_begin + rl) * dp) + g;
-      v4f acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
-      for (int s = 0; s < (dp >> 4); ++s) {
-        const float4 av = rp[4 * s];
-        const float4 bv = qrow[4 * s];
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc, 0, 0, 0);
+      __syncthreads();
+      for (int e = tid; e < kGroup * dp4; e += blockDim.x) {
+        const int j = e / dp4, c = e - j * dp4;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (j < gs) v = reinterpret_cast<const float4 *>(a.qp + (int64_t)s_q[j] * dp)[c];
+        *reinterpret_cast<float4 *>(qs + j * ldq + 4 * c) = v;
       }
-      // lane l holds dot(row 4*(l/16)+r of the block, frame l%16)
-      if (i < gq) {
-        const float qn = s_qn[i];
-        const int64_t off = s_off[i];
+      __syncthreads();
+      const float4 *qrow = reinterpret_cast<const float4 *>(qs + i * ldq) + g;
+      const int nrb = (nrows + 15) >> 4;
+      for (int rb = wave; rb < nrb; rb += 4) {
+        int rl = rb * 16 + i;
+        rl = rl < nrows ? rl : nrows - 1;
+        const float4 *rp = reinterpret_cast<const float4 *>(a.rows + (row_begin + rl) * dp) + g;
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+        for (int s = 0; s < (dp >> 4); ++s) {
+          const float4 av = rp[4 * s];
+          const float4 bv = qrow[4 * s];
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc, 0, 0, 0);
+        }
+        // lane l holds dot(row 4*(l/16)+r of the block, frame l%16)
+        if (i < gs) {
+          const float qn = s_qn[i];
+          const int64_t off = s_off[i];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = rb * 16 + 4 * g + r;
-          if (row < nrows) {
-            const int64_t grow = row_begin + row;
-            const float rn = a.row_n2[grow];
-            uint32_t word = 0xFFFFFFFFu;
-            if (!__builtin_isinf(rn)) {
-              float dd = (qn + rn) - 2.f * acc[r];
-              dd = dd > 0.f ? dd : 0.f;
-              word = __float_as_uint(dd);
+          for (int r = 0; r < 4; ++r) {
+            const int row = rb * 16 + 4 * g + r;
+            if (row < nrows) {
+              const int64_t grow = row_begin + row;
+              const float rn = a.row_n2[grow];
+              uint32_t word = 0xFFFFFFFFu;
+              if (!__builtin_isinf(rn)) {
+                float dd = (qn + rn) - 2.f * acc[r];
+                dd = dd > 0.f ? dd : 0.f;
+                word = __float_as_uint(dd);
+              }
+              a.cand[off + row] = word;
             }
-            a.cand[off + row] = word;
           }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
-// Register variant for padded lengths up to 512: one item per block, one
-// 16-row block per wave, no LDS and no barriers. Each wave keeps the frame
-// operand of the MFMA in registers (lane l holds frame l % 16's k-slice); its
-// row loads, frame loads and norms go out together once the item's frame list
-// has been read.
+// Register variant for padded lengths up to 512, dense items and narrow list
+// items (at most kGroup frames): one item per block, one 16-row block per
+// wave, no LDS and no barriers. Each wave keeps the frame operand of the MFMA
+// in registers (lane l holds frame l % 16's k-slice); its row loads, frame
+// loads and norms go out together once the item's frame list has been read.
 template <int NS, bool DENSE>
 __global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
   constexpr int DP = NS * 16;
   const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
   const int i = lane & 15, g = lane >> 4;
-  int n_items, nchunks = 1;
+  int lo = 0, hi, nchunks = 1;
   if (DENSE) {
     nchunks = (a.nrows + a.rows_per_item - 1) / a.rows_per_item;
-    n_items = nchunks * ((a.nq + kGroup - 1) / kGroup);
+    hi = nchunks * ((a.nq + kGroup - 1) / kGroup);
   } else {
-    n_items = *a.n_items;
+    hi = a.n_items[4];  // the narrow items: at most kGroup frames each
   }
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
     int row_begin, chunk_row, nrows, gq, fr = 0;
     int64_t off = 0;
     if (DENSE) {
@@ -250,6 +261,89 @@ __global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
   }
 }
 
+// Wide list items (a chunk of a region kept by more than kGroup frames, up to
+// kItemFrames of them): each wave takes one 16-row block of the chunk and
+// every frame group of the item at once, walking the padded length in
+// k-slices (one row slice and one slice per frame group per step), so each
+// row is read once for all the item's frames. The k order of every sum is the
+// same as in the narrow kernel: a frame's screen values do not depend on the
+// kernel or the item that computed them.
+template <int NS>
+__global__ __launch_bounds__(256) void k_screen_wide(ScreenArgs a) {
+  constexpr int DP = NS * 16;
+  constexpr int NG = kItemFrames / kGroup;
+  const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int lo = a.n_items[4], hi = a.n_items[0];
+  for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
+    const Item itm = a.items[it];
+    const int row_begin = itm.row_begin, chunk_row = itm.chunk_row;
+    const int nrows = itm.nrows_gq >> 16, gq = itm.nrows_gq & 0xFFFF;
+    const int ng = (gq + kGroup - 1) / kGroup;
+    int fr[NG];
+    int64_t off[NG];
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      fr[j] = 0;
+      off[j] = 0;
+      if (j * kGroup + i < gq) {
+        const int2 e = a.rq[itm.q0 + j * kGroup + i];
+        fr[j] = e.x;
+        off[j] = (int64_t)e.x * a.cap + e.y + chunk_row;
+      }
+    }
+    const int nrb = (nrows + 15) >> 4;
+    for (int rb = w; rb < nrb; rb += nw) {
+      const int rl = min(rb * 16 + i, nrows - 1);
+      const float4 *rp =
+          reinterpret_cast<const float4 *>(a.rows + (int64_t)(row_begin + rl) * DP) + g;
+      const float4 *qp[NG];
+#pragma unroll
+      for (int j = 0; j < NG; ++j)
+        qp[j] = reinterpret_cast<const float4 *>(a.qp + (int64_t)fr[j] * DP) + g;
+      v4f acc[NG];
+#pragma unroll
+      for (int j = 0; j < NG; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+      for (int s = 0; s < NS; ++s) {
+        const float4 av = rp[4 * s];
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+          if (j < ng) {
+            const float4 bv = qp[j][4 * s];
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc[j], 0, 0, 0);
+          }
+        }
+      }
+      float rn[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rn[r] = a.row_n2[row_begin + min(rb * 16 + 4 * g + r, nrows - 1)];
+#pragma unroll
+      for (int j = 0; j < NG; ++j) {
+        if (j < ng && j * kGroup + i < gq) {
+          const float qn = a.qn2[fr[j]];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = rb * 16 + 4 * g + r;
+            if (row < nrows) {
+              uint32_t word = 0xFFFFFFFFu;
+              if (!__builtin_isinf(rn[r])) {
+                float dd = (qn + rn[r]) - 2.f * acc[j][r];
+                dd = dd > 0.f ? dd : 0.f;
+                word = __float_as_uint(dd);
+              }
+              a.cand[off[j] + row] = word;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 template <int NS, bool DENSE>
 hipError_t launch_blk_t(const ScreenArgs &a, int32_t grid, hipStream_t s) {
   return launch_kernel(k_screen_blk<NS, DENSE>, dim3(grid), dim3(256), 0, s, a);
@@ -295,6 +389,18 @@ hipError_t launch_screen_f32(const ScreenArgs &a, int32_t grid, hipStream_t s) {
     }
   }
   return a.dense ? launch_screen_t<true>(a, grid, s) : launch_screen_t<false>(a, grid, s);
+}
+
+hipError_t launch_screen_wide_f32(const ScreenArgs &a, int32_t grid, hipStream_t s) {
+  if (grid <= 0 || a.dense || a.rows_per_item % 16 != 0) return hipSuccess;
+  switch (a.dp) {
+    case 32: return launch_kernel(k_screen_wide<2>, dim3(grid), dim3(256), 0, s, a);
+    case 64: return launch_kernel(k_screen_wide<4>, dim3(grid), dim3(256), 0, s, a);
+    case 128: return launch_kernel(k_screen_wide<8>, dim3(grid), dim3(256), 0, s, a);
+    case 256: return launch_kernel(k_screen_wide<16>, dim3(grid), dim3(256), 0, s, a);
+    case 512: return launch_kernel(k_screen_wide<32>, dim3(grid), dim3(256), 0, s, a);
+    default: return hipSuccess;  // the LDS kernel screened every item
+  }
 }
 
 // Number of blocks that covers `items` work items (one per block), up to

@@ -232,13 +232,11 @@ class HlocDB:
         return out
 
     def info(self) -> dict:
-        out = (ctypes.c_int64 * 6)()
-        _check(load_library().hloc_query_info(self._h, out, 6))
-        keys = ("items", "coarse_fallbacks", "fine_fallbacks", "max_candidates", "survivors",
-                "candidates")
-        return dict(zip(keys, list(out)))
+        out = (ctypes.c_int64 * len(_INFO_KEYS))()
+        _check(load_library().hloc_query_info(self._h, out, len(_INFO_KEYS)))
+        return dict(zip(_INFO_KEYS, list(out)))
 
-    PHASES = ("prep", "coarse", "sched", "screen", "select", "aggregate")
+    PHASES = ("prep", "coarse", "sched", "screen", "select", "aggregate", "screen_wide")
 
     def profile(self, enable: bool = True):
         """Start (clearing) or stop the per-phase event record."""
@@ -263,7 +261,7 @@ class HlocDB:
 
 
 _INFO_KEYS = ("items", "coarse_fallbacks", "fine_fallbacks", "max_candidates", "survivors",
-              "candidates")
+              "candidates", "narrow_items")
 
 
 class Workspace:
@@ -331,8 +329,8 @@ class Workspace:
         _check(load_library().hloc_ws_replay(self._h, ctypes.c_void_p(stream.cuda_stream)))
 
     def info(self) -> dict:
-        out = (ctypes.c_int64 * 6)()
-        _check(load_library().hloc_ws_query_info(self._h, out, 6))
+        out = (ctypes.c_int64 * len(_INFO_KEYS))()
+        _check(load_library().hloc_ws_query_info(self._h, out, len(_INFO_KEYS)))
         return dict(zip(_INFO_KEYS, list(out)))
 
 

@@ -440,9 +440,10 @@ def test_many_regions_multi_kernel_schedule(torch_cuda):
     assert st["recall"] == 1.0 and info["items"] > 0
 
 
-def test_region_kept_by_every_frame(torch_cuda):
-    # one large region kept by all 700 frames: 44 frame groups x 47 row chunks
-    # of work items expanded from a single region
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_region_kept_by_every_frame(torch_cuda, precision):
+    # one large region kept by all 700 frames: 11 groups of up to 64 frames x
+    # 47 row chunks of work items expanded from a single region
     rng = np.random.default_rng(22)
     sizes = np.array([3000] + [250] * 12)
     region_of = np.repeat(np.arange(len(sizes)), sizes).astype(np.int32)
@@ -453,6 +454,6 @@ def test_region_kept_by_every_frame(torch_cuda):
     xy = rng.uniform(0, 40, size=(n, 2))
     q = (feats[rng.integers(0, 3000, 700)] + 0.05 * rng.standard_normal((700, d))).astype(np.float32)
     st, info, _ = check_all(torch_cuda, feats, xy, region_of, len(sizes), q, 9, 3,
-                            name="one region kept by 700 frames")
+                            name="one region kept by 700 frames", precision=precision)
     assert st["recall"] == 1.0
-    assert info["items"] >= 44 * 47
+    assert info["items"] >= 11 * 47
