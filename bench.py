@@ -146,6 +146,39 @@ def counters_summary(a) -> None:
     print("record: " + json.dumps(rec))
 
 
+def cpu_baseline(w, gpu_idx, seconds: float):
+    """Time the FP64 oracle on the batch's frames, repeating the batch until
+    about `seconds` of single-threaded work, and check the GPU's lists on the
+    frames it covered."""
+    import oracle
+    done, passes, t_total = 0, 0, 0.0
+    m = min(len(w.q), 8)
+    ora = None
+    while t_total < seconds:
+        t0 = time.perf_counter()
+        res = oracle.retrieve(w.feats, w.region_of, w.n_regions_total, w.q[:m], w.k, w.n_reg)
+        offs = w.req_offsets
+        for r in range(len(offs) - 1):
+            if offs[r + 1] > m:
+                break
+            oracle.aggregate(res["idx"][offs[r]:offs[r + 1]].ravel(), w.xy, *w.agg)
+        dt = time.perf_counter() - t0
+        t_total += dt
+        done += m
+        passes += 1
+        if ora is None or m > len(ora["idx"]):
+            ora = res
+        if m < len(w.q):
+            m = min(len(w.q), max(m + 1, int(m * (seconds - t_total) / max(dt, 1e-3))))
+    mm = len(ora["idx"])
+    hits = sum(len(set(gpu_idx[i].tolist()) & set(ora["idx"][i].tolist())) for i in range(mm))
+    exact = sum(int(np.array_equal(gpu_idx[i], ora["idx"][i])) for i in range(mm))
+    return dict(value=done / t_total, unit="queries/s", cores=1, kind="oracle",
+                sample=f"{done} frames of {w.name} ({passes} passes over the first {mm} of "
+                       f"{len(w.q)} frames), single thread, {t_total:.1f} s"), \
+        hits / (mm * w.k), exact, mm
+
+
 def serve_bench(a) -> None:
     """Poisson arrivals of 1-16 frame requests (k in {8, 16, 32}) at a.serve
     requests/s into the request server for a.serve_seconds; prints one JSON

@@ -37,7 +37,7 @@ inline hipError_t launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t lds, h
 }
 
 constexpr int kGroup = 16;          // frames per MFMA column block of the screen
-constexpr int kItemFrames = 64;     // frames per screen work item (up to four column blocks)
+constexpr int kItemFrames = 256;    // frames per screen work item (wide items)
 constexpr int kBlock = 256;         // threads per block of most kernels
 constexpr int kSelectLds = 4096;    // keys held in LDS by the select kernel
 constexpr uint64_t kKeyNone = ~0ull;  // empty slot / no candidate
@@ -177,7 +177,8 @@ hipError_t launch_aggregate(const AggArgs &a, hipStream_t s);
 
 // Kernel attributes (LDS limits) for the current device; called once when a
 // database is built so that no attribute is set while a graph is captured.
-hipError_t prepare_screen_kernels();
+hipError_t prepare_screen_kernels();  // also the bf16 screens
+hipError_t prepare_screen_bf16_kernels();
 hipError_t prepare_select_kernels();
 hipError_t prepare_aggregate_kernels();
 hipError_t prepare_sched_kernels();

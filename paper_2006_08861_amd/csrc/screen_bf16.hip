@@ -150,79 +150,76 @@ __global__ __launch_bounds__(256) void k_screen_bf16(ScreenArgs a) {
   }
 }
 
-// Wide list items, as the fp32 wide screen.
+// Wide list items, as the fp32 wide screen: the chunk's bf16 rows staged in
+// LDS once, a 16-frame group per wave at a time.
 template <int NS>  // NS = dp / 32
 __global__ __launch_bounds__(256) void k_screen_wide_bf16(ScreenArgs a) {
   constexpr int DP = NS * 32;
-  constexpr int NG = kItemFrames / kGroup;
-  const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
+  constexpr int LDR = 4 * NS + 1;  // uint4 per LDS row, one of padding
+  extern __shared__ uint4 s_rows16[];  // 64 x LDR
+  __shared__ float s_rn[64];
+  const int tid = threadIdx.x, lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
   const int i = lane & 15, g = lane >> 4;
   const int lo = a.n_items[4], hi = a.n_items[0];
   for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
     const Item itm = a.items[it];
     const int row_begin = itm.row_begin, chunk_row = itm.chunk_row;
     const int nrows = itm.nrows_gq >> 16, gq = itm.nrows_gq & 0xFFFF;
-    const int ng = (gq + kGroup - 1) / kGroup;
-    int fr[NG];
-    int64_t off[NG];
-#pragma unroll
-    for (int j = 0; j < NG; ++j) {
-      fr[j] = 0;
-      off[j] = 0;
-      if (j * kGroup + i < gq) {
-        const int2 e = a.rq[itm.q0 + j * kGroup + i];
-        fr[j] = e.x;
-        off[j] = (int64_t)e.x * a.cap + e.y + chunk_row;
-      }
+    __syncthreads();  // the previous item's rows are no longer read
+    for (int e = tid; e < 64 * 4 * NS; e += blockDim.x) {
+      const int row = e / (4 * NS), c = e - row * (4 * NS);
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (row < nrows) v = reinterpret_cast<const uint4 *>(a.rows16 + (int64_t)(row_begin + row) * DP)[c];
+      s_rows16[row * LDR + c] = v;
     }
-    const int nrb = (nrows + 15) >> 4;
-    for (int rb = w; rb < nrb; rb += nw) {
-      const int rl = min(rb * 16 + i, nrows - 1);
-      const uint4 *rp = reinterpret_cast<const uint4 *>(a.rows16 + (int64_t)(row_begin + rl) * DP) + g;
-      const uint4 *qp[NG];
-#pragma unroll
-      for (int j = 0; j < NG; ++j)
-        qp[j] = reinterpret_cast<const uint4 *>(a.qp16 + (int64_t)fr[j] * DP) + g;
-      v4f acc[NG];
-#pragma unroll
-      for (int j = 0; j < NG; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-      for (int s = 0; s < NS; ++s) {
-        const uint4 av = rp[4 * s];
-#pragma unroll
-        for (int j = 0; j < NG; ++j) {
-          if (j < ng) {
-            const uint4 bv = qp[j][4 * s];
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
-                                                             __builtin_bit_cast(v8bf, bv), acc[j],
-                                                             0, 0, 0);
-          }
-        }
+    if (tid < 64) s_rn[tid] = tid < nrows ? a.row_n2[row_begin + tid] : 0.f;
+    __syncthreads();
+    for (int grp = w; grp * kGroup < gq; grp += nw) {
+      const int gs = min(kGroup, gq - grp * kGroup);
+      int fr = 0;
+      int64_t off = 0;
+      if (i < gs) {
+        const int2 e = a.rq[itm.q0 + grp * kGroup + i];
+        fr = e.x;
+        off = (int64_t)e.x * a.cap + e.y + chunk_row;
       }
-      float rn[4];
+      const uint4 *qp = reinterpret_cast<const uint4 *>(a.qp16 + (int64_t)fr * DP) + g;
+      uint4 bv[NS];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) rn[r] = a.row_n2[row_begin + min(rb * 16 + 4 * g + r, nrows - 1)];
+      for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
+      const float qn = a.qn2[fr];
+      for (int rb = 0; rb * 16 < nrows; ++rb) {
+        const uint4 *rp = s_rows16 + (rb * 16 + i) * LDR + g;
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int j = 0; j < NG; ++j) {
-        if (j < ng && j * kGroup + i < gq) {
-          const float qn = a.qn2[fr[j]];
+        for (int s = 0; s < NS; ++s)
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, rp[4 * s]),
+                                                        __builtin_bit_cast(v8bf, bv[s]), acc, 0,
+                                                        0, 0);
+        if (i < gs) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = rb * 16 + 4 * g + r;
             if (row < nrows) {
+              const float rn = s_rn[row];
               uint32_t word = 0xFFFFFFFFu;
-              if (!__builtin_isinf(rn[r])) {
-                float dd = (qn + rn[r]) - 2.f * acc[j][r];
+              if (!__builtin_isinf(rn)) {
+                float dd = (qn + rn) - 2.f * acc[r];
                 dd = dd > 0.f ? dd : 0.f;
                 word = __float_as_uint(dd);
               }
-              a.cand[off[j] + row] = word;
+              a.cand[off + row] = word;
             }
           }
         }
       }
     }
   }
+}
+
+template <int NS>
+size_t wide16_lds_bytes() {
+  return (size_t)64 * (4 * NS + 1) * sizeof(uint4);
 }
 
 template <int NS, bool DENSE>
@@ -256,11 +253,12 @@ hipError_t launch_screen_bf16(const ScreenArgs &a, int32_t grid, hipStream_t s) 
 
 hipError_t launch_screen_wide_bf16(const ScreenArgs &a, int32_t grid, hipStream_t s) {
   if (grid <= 0 || a.dense) return hipSuccess;
-  if (a.rows_per_item % 16 != 0) return hipErrorInvalidValue;
+  if (a.rows_per_item % 16 != 0 || a.rows_per_item > 64) return hipErrorInvalidValue;
   switch (a.dp) {
-#define HLOC_BF16_WIDE_CASE(DPV) \
-  case DPV:                      \
-    return launch_kernel(k_screen_wide_bf16<DPV / 32>, dim3(grid), dim3(256), 0, s, a);
+#define HLOC_BF16_WIDE_CASE(DPV)                                                         \
+  case DPV:                                                                              \
+    return launch_kernel(k_screen_wide_bf16<DPV / 32>, dim3(grid), dim3(256),              \
+                         (uint32_t)wide16_lds_bytes<DPV / 32>(), s, a);
     HLOC_BF16_WIDE_CASE(32)
     HLOC_BF16_WIDE_CASE(64)
     HLOC_BF16_WIDE_CASE(96)
@@ -275,6 +273,29 @@ hipError_t launch_screen_wide_bf16(const ScreenArgs &a, int32_t grid, hipStream_
     default:
       return hipErrorInvalidValue;
   }
+}
+
+// LDS limits of the wide bf16 kernels (above the 64 KB default).
+hipError_t prepare_screen_bf16_kernels() {
+#define HLOC_BF16_WIDE_ATTR(DPV)                                                          \
+  {                                                                                       \
+    const hipError_t e = hipFuncSetAttribute(                                             \
+        reinterpret_cast<const void *>(&k_screen_wide_bf16<DPV / 32>),                     \
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)wide16_lds_bytes<DPV / 32>());    \
+    if (e != hipSuccess) return e;                                                        \
+  }
+  HLOC_BF16_WIDE_ATTR(32)
+  HLOC_BF16_WIDE_ATTR(64)
+  HLOC_BF16_WIDE_ATTR(96)
+  HLOC_BF16_WIDE_ATTR(128)
+  HLOC_BF16_WIDE_ATTR(160)
+  HLOC_BF16_WIDE_ATTR(192)
+  HLOC_BF16_WIDE_ATTR(256)
+  HLOC_BF16_WIDE_ATTR(320)
+  HLOC_BF16_WIDE_ATTR(384)
+  HLOC_BF16_WIDE_ATTR(512)
+#undef HLOC_BF16_WIDE_ATTR
+  return hipSuccess;
 }
 
 bool bf16_screen_supports(int32_t dp) {

@@ -14,6 +14,7 @@
 #include "hloc_internal.h"
 
 #include <algorithm>
+#include <utility>
 
 namespace hloc {
 
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(256) void k_screen_f32(ScreenArgs a) {
   int n_items, nchunks = 1;
   if (DENSE) {
     nchunks = (a.nrows + a.rows_per_item - 1) / a.rows_per_item;
-    n_items = nchunks * ((a.nq + kItemFrames - 1) / kItemFrames);
+    n_items = nchunks * ((a.nq + kGroup - 1) / kGroup);
   } else {
     n_items = *a.n_items;
   }
@@ -91,11 +92,11 @@ __global__ __launch_bounds__(256) void k_screen_f32(ScreenArgs a) {
     int nrows, gq, f0 = 0, q0 = 0;
     if (DENSE) {
       const int c = it % nchunks;
-      f0 = (it / nchunks) * kItemFrames;
+      f0 = (it / nchunks) * kGroup;
       row_begin = (int64_t)c * a.rows_per_item;
       chunk_row = row_begin;
       nrows = min(a.rows_per_item, a.nrows - c * a.rows_per_item);
-      gq = min(kItemFrames, a.nq - f0);
+      gq = min(kGroup, a.nq - f0);
     } else {
       const Item itm = a.items[it];
       row_begin = itm.row_begin;
@@ -261,87 +262,91 @@ __global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
   }
 }
 
-// Wide list items (a chunk of a region kept by more than kGroup frames, up to
-// kItemFrames of them): each wave takes one 16-row block of the chunk and
-// every frame group of the item at once, walking the padded length in
-// k-slices (one row slice and one slice per frame group per step), so each
-// row is read once for all the item's frames. The k order of every sum is the
-// same as in the narrow kernel: a frame's screen values do not depend on the
-// kernel or the item that computed them.
+// Wide list items: a 64-row chunk of a region kept by more than kGroup frames,
+// against up to kItemFrames of them. The block stages the chunk's rows and
+// norms in LDS once; each wave takes a 16-frame group at a time, holds that
+// group's frame operand in registers and runs it against the four 16-row
+// blocks read from LDS. Every row is read from memory once per item and every
+// frame once per item. The k order of every sum is the same as in the narrow
+// kernel: a frame's screen values do not depend on the kernel that computed
+// them.
 template <int NS>
 __global__ __launch_bounds__(256) void k_screen_wide(ScreenArgs a) {
   constexpr int DP = NS * 16;
-  constexpr int NG = kItemFrames / kGroup;
-  const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
+  constexpr int LDR = 4 * NS + 1;  // float4 per LDS row, one of padding
+  extern __shared__ float4 s_rows[];  // 64 x LDR
+  __shared__ float s_rn[64];
+  const int tid = threadIdx.x, lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
   const int i = lane & 15, g = lane >> 4;
   const int lo = a.n_items[4], hi = a.n_items[0];
   for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
     const Item itm = a.items[it];
     const int row_begin = itm.row_begin, chunk_row = itm.chunk_row;
     const int nrows = itm.nrows_gq >> 16, gq = itm.nrows_gq & 0xFFFF;
-    const int ng = (gq + kGroup - 1) / kGroup;
-    int fr[NG];
-    int64_t off[NG];
-#pragma unroll
-    for (int j = 0; j < NG; ++j) {
-      fr[j] = 0;
-      off[j] = 0;
-      if (j * kGroup + i < gq) {
-        const int2 e = a.rq[itm.q0 + j * kGroup + i];
-        fr[j] = e.x;
-        off[j] = (int64_t)e.x * a.cap + e.y + chunk_row;
-      }
+    __syncthreads();  // the previous item's rows are no longer read
+    for (int e = tid; e < 64 * 4 * NS; e += blockDim.x) {
+      const int row = e / (4 * NS), c = e - row * (4 * NS);
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (row < nrows) v = reinterpret_cast<const float4 *>(a.rows + (int64_t)(row_begin + row) * DP)[c];
+      s_rows[row * LDR + c] = v;
     }
-    const int nrb = (nrows + 15) >> 4;
-    for (int rb = w; rb < nrb; rb += nw) {
-      const int rl = min(rb * 16 + i, nrows - 1);
-      const float4 *rp =
-          reinterpret_cast<const float4 *>(a.rows + (int64_t)(row_begin + rl) * DP) + g;
-      const float4 *qp[NG];
-#pragma unroll
-      for (int j = 0; j < NG; ++j)
-        qp[j] = reinterpret_cast<const float4 *>(a.qp + (int64_t)fr[j] * DP) + g;
-      v4f acc[NG];
-#pragma unroll
-      for (int j = 0; j < NG; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-      for (int s = 0; s < NS; ++s) {
-        const float4 av = rp[4 * s];
-#pragma unroll
-        for (int j = 0; j < NG; ++j) {
-          if (j < ng) {
-            const float4 bv = qp[j][4 * s];
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc[j], 0, 0, 0);
-          }
-        }
+    if (tid < 64) s_rn[tid] = tid < nrows ? a.row_n2[row_begin + tid] : 0.f;
+    __syncthreads();
+    for (int grp = w; grp * kGroup < gq; grp += nw) {
+      const int gs = min(kGroup, gq - grp * kGroup);
+      int fr = 0;
+      int64_t off = 0;
+      if (i < gs) {
+        const int2 e = a.rq[itm.q0 + grp * kGroup + i];
+        fr = e.x;
+        off = (int64_t)e.x * a.cap + e.y + chunk_row;
       }
-      float rn[4];
+      const float4 *qp = reinterpret_cast<const float4 *>(a.qp + (int64_t)fr * DP) + g;
+      float4 bv[NS];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) rn[r] = a.row_n2[row_begin + min(rb * 16 + 4 * g + r, nrows - 1)];
+      for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
+      const float qn = a.qn2[fr];
+      for (int rb = 0; rb * 16 < nrows; ++rb) {
+        const float4 *rp = s_rows + (rb * 16 + i) * LDR + g;
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int j = 0; j < NG; ++j) {
-        if (j < ng && j * kGroup + i < gq) {
-          const float qn = a.qn2[fr[j]];
+        for (int s = 0; s < NS; ++s) {
+          const float4 av = rp[4 * s];
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv[s].x, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv[s].y, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv[s].z, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv[s].w, acc, 0, 0, 0);
+        }
+        if (i < gs) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = rb * 16 + 4 * g + r;
             if (row < nrows) {
+              const float rn = s_rn[row];
               uint32_t word = 0xFFFFFFFFu;
-              if (!__builtin_isinf(rn[r])) {
-                float dd = (qn + rn[r]) - 2.f * acc[j][r];
+              if (!__builtin_isinf(rn)) {
+                float dd = (qn + rn) - 2.f * acc[r];
                 dd = dd > 0.f ? dd : 0.f;
                 word = __float_as_uint(dd);
               }
-              a.cand[off[j] + row] = word;
+              a.cand[off + row] = word;
             }
           }
         }
       }
     }
   }
+}
+
+template <int NS>
+size_t wide_lds_bytes() {
+  return (size_t)64 * (4 * NS + 1) * sizeof(float4);
+}
+
+template <int NS>
+hipError_t launch_wide_t(const ScreenArgs &a, int32_t grid, hipStream_t s) {
+  return launch_kernel(k_screen_wide<NS>, dim3(grid), dim3(256), (uint32_t)wide_lds_bytes<NS>(), s,
+                       a);
 }
 
 template <int NS, bool DENSE>
@@ -366,6 +371,18 @@ hipError_t prepare_screen_kernels() {
     e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     if (e != hipSuccess) return e;
   }
+  const std::pair<const void *, size_t> wide[] = {
+      {reinterpret_cast<const void *>(&k_screen_wide<2>), wide_lds_bytes<2>()},
+      {reinterpret_cast<const void *>(&k_screen_wide<4>), wide_lds_bytes<4>()},
+      {reinterpret_cast<const void *>(&k_screen_wide<8>), wide_lds_bytes<8>()},
+      {reinterpret_cast<const void *>(&k_screen_wide<16>), wide_lds_bytes<16>()},
+      {reinterpret_cast<const void *>(&k_screen_wide<32>), wide_lds_bytes<32>()}};
+  for (const auto &kw : wide) {
+    e = hipFuncSetAttribute(kw.first, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kw.second);
+    if (e != hipSuccess) return e;
+  }
+  e = prepare_screen_bf16_kernels();
+  if (e != hipSuccess) return e;
   done_dev = dev;
   return hipSuccess;
 }
@@ -393,12 +410,13 @@ hipError_t launch_screen_f32(const ScreenArgs &a, int32_t grid, hipStream_t s) {
 
 hipError_t launch_screen_wide_f32(const ScreenArgs &a, int32_t grid, hipStream_t s) {
   if (grid <= 0 || a.dense || a.rows_per_item % 16 != 0) return hipSuccess;
+  if (a.rows_per_item > 64) return hipErrorInvalidValue;  // the LDS stage holds 64 rows
   switch (a.dp) {
-    case 32: return launch_kernel(k_screen_wide<2>, dim3(grid), dim3(256), 0, s, a);
-    case 64: return launch_kernel(k_screen_wide<4>, dim3(grid), dim3(256), 0, s, a);
-    case 128: return launch_kernel(k_screen_wide<8>, dim3(grid), dim3(256), 0, s, a);
-    case 256: return launch_kernel(k_screen_wide<16>, dim3(grid), dim3(256), 0, s, a);
-    case 512: return launch_kernel(k_screen_wide<32>, dim3(grid), dim3(256), 0, s, a);
+    case 32: return launch_wide_t<2>(a, grid, s);
+    case 64: return launch_wide_t<4>(a, grid, s);
+    case 128: return launch_wide_t<8>(a, grid, s);
+    case 256: return launch_wide_t<16>(a, grid, s);
+    case 512: return launch_wide_t<32>(a, grid, s);
     default: return hipSuccess;  // the LDS kernel screened every item
   }
 }

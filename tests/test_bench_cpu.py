@@ -1,0 +1,76 @@
+"""bench.py pieces that run without a GPU: the one-GPU guard, the oracle
+baseline leg, and the counter summary / traffic record round trip."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+import oracle  # noqa: E402
+from paper_2006_08861_amd import workload  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_cpu_baseline_times_the_oracle():
+    w = workload.make_workload(0, nq=6)
+    ref = oracle.retrieve(w.feats, w.region_of, w.n_regions_total, w.q, w.k, w.n_reg)
+    base, recall, exact, m = bench.cpu_baseline(w, np.asarray(ref["idx"]), 0.2)
+    assert base["kind"] == "oracle" and base["cores"] == 1 and base["value"] > 0
+    assert recall == 1.0 and exact == m and m >= 1
+
+
+def _csv(path, rows):
+    with open(path, "w", newline="") as f:
+        wr = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        wr.writeheader()
+        for r in rows:
+            wr.writerow(r)
+
+
+def test_counter_summary_round_trip(tmp_path, monkeypatch, capsys):
+    narrow = "void hloc::k_screen_blk<16, false>(hloc::ScreenArgs)"
+    wide = "void hloc::k_screen_wide<16>(hloc::ScreenArgs)"
+    copy = ("void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add"
+            "<float>, std::array<char*, 2ul> >(int)")
+    _csv(tmp_path / "f.csv", [dict(Kernel_Name=narrow, Counter_Name="FETCH_SIZE", Counter_Value=100),
+                              dict(Kernel_Name=narrow, Counter_Name="FETCH_SIZE", Counter_Value=300),
+                              dict(Kernel_Name=wide, Counter_Name="FETCH_SIZE", Counter_Value=10)])
+    _csv(tmp_path / "w.csv", [dict(Kernel_Name=narrow, Counter_Name="WRITE_SIZE", Counter_Value=8),
+                              dict(Kernel_Name=wide, Counter_Name="WRITE_SIZE", Counter_Value=2)])
+    _csv(tmp_path / "cf.csv", [dict(Kernel_Name=copy, Counter_Name="FETCH_SIZE", Counter_Value=512)])
+    _csv(tmp_path / "cw.csv", [dict(Kernel_Name=copy, Counter_Name="WRITE_SIZE", Counter_Value=1024)])
+
+    class A:
+        counters_summary = [str(tmp_path / n) for n in ("f.csv", "w.csv", "cf.csv", "cw.csv")]
+        precision = "fp32"
+        copy_mib = 1
+        workload_name = "unit"
+        commands = ["cmd"]
+
+    bench.counters_summary(A)
+    text = capsys.readouterr().out
+    rec = json.loads(text.split("record: ")[1])
+    # narrow mean 200 KiB + wide 10 KiB fetched, scaled by 1 MiB / 512 KiB = 2
+    assert rec["fetch_kib"] == 210.0 and rec["fetch_scale"] == 2.0
+    assert rec["write_kib"] == 10.0 and rec["write_scale"] == 1.0
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "counters_screen_fp32_unit.md").write_text(text)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "screen_digest", lambda: rec["sources"])
+    b, src = bench.load_traffic("unit", "fp32")
+    assert b == 1024.0 * (210.0 * 2.0 + 10.0 * 1.0)
+    monkeypatch.setattr(bench, "screen_digest", lambda: "changed")
+    b, src = bench.load_traffic("unit", "fp32")
+    assert b is None and "changed" in src

@@ -442,7 +442,7 @@ def test_many_regions_multi_kernel_schedule(torch_cuda):
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_region_kept_by_every_frame(torch_cuda, precision):
-    # one large region kept by all 700 frames: 11 groups of up to 64 frames x
+    # one large region kept by all 700 frames: 3 groups of up to 256 frames x
     # 47 row chunks of work items expanded from a single region
     rng = np.random.default_rng(22)
     sizes = np.array([3000] + [250] * 12)
@@ -456,4 +456,4 @@ def test_region_kept_by_every_frame(torch_cuda, precision):
     st, info, _ = check_all(torch_cuda, feats, xy, region_of, len(sizes), q, 9, 3,
                             name="one region kept by 700 frames", precision=precision)
     assert st["recall"] == 1.0
-    assert info["items"] >= 11 * 47
+    assert info["items"] >= 3 * 47  # groups of up to 256 frames
