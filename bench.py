@@ -47,10 +47,13 @@ def log(*a):
 # the fine screen's sources: hardware counters taken on it stay valid while
 # these files are unchanged
 SCREEN_SOURCES = ("paper_2006_08861_amd/csrc/screen_f32.hip",
-                  "paper_2006_08861_amd/csrc/screen_bf16.hip",
+                  "paper_2006_08861_amd/csrc/screen_lp.hip",
                   "paper_2006_08861_amd/csrc/hloc_device.h",
                   "paper_2006_08861_amd/csrc/hloc_internal.h")
-SCREEN_KERNELS = {"fp32": "k_screen_blk<", "bf16": "k_screen_bf16<"}
+SCREEN_KERNELS = {"fp32": "k_screen_blk<", "bf16": "k_screen_lp<1, ", "fp8": "k_screen_lp<2, "}
+WIDE_KERNELS = {"fp32": "k_screen_wide<", "bf16": "k_screen_wide_lp<1, ", "fp8": "k_screen_wide_lp<2, "}
+MIRRORS = {"fp32": lambda h: 0, "bf16": lambda h: h.MIRROR_BF16, "fp8": lambda h: h.MIRROR_FP8}
+DTYPES = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}
 
 
 def screen_digest() -> str:
@@ -111,7 +114,7 @@ def counters_summary(a) -> None:
     counts are added."""
     fetch_csv, write_csv, cf_csv, cw_csv = a.counters_summary
     narrow = SCREEN_KERNELS[a.precision]
-    wide = "k_screen_wide_bf16<" if a.precision == "bf16" else "k_screen_wide<"
+    wide = WIDE_KERNELS[a.precision]
     per = {}
     for name, prefix, suffix in (("narrow", narrow, ", false>"), ("wide", wide, ">")):
         fk, nf = per_dispatch_kib(fetch_csv, prefix, "FETCH_SIZE", suffix)
@@ -194,7 +197,7 @@ def serve_bench(a) -> None:
     log(f"[serve] workload {w.name}: n={len(w.feats)} d={w.feats.shape[1]} "
         f"regions={w.n_regions_total} request pool={len(w.req_offsets) - 1} "
         f"({time.perf_counter() - t0:.1f} s)")
-    db = hloc.HlocDB(w.feats, w.xy, mirrors=hloc.MIRROR_BF16 if a.precision == "bf16" else 0)
+    db = hloc.HlocDB(w.feats, w.xy, mirrors=MIRRORS[a.precision](hloc))
     db.set_regions(w.region_of, w.n_regions_total)
     db.set_aggregation(*w.agg)
     srv = hloc.Server(db, k=32, n_regions=w.n_reg, precision=a.precision,
@@ -259,7 +262,7 @@ def serve_bench(a) -> None:
         "offered_req_per_s": a.serve, "value": len(lat) / wall, "unit": "requests/s",
         "frames_per_s": done_frames[0] / wall, "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)), "refused": refused[0], "seconds": wall,
-        "dtype": "f32" if a.precision == "fp32" else "bf16", "data": "synthetic",
+        "dtype": DTYPES[a.precision], "data": "synthetic",
         "config": {"workload": w.name, "n": int(len(w.feats)), "d": int(w.feats.shape[1]),
                    "regions": int(w.n_regions_total), "n_regions": int(w.n_reg),
                    "max_batch_frames": a.serve_batch, "slots": st["slots"],
@@ -274,7 +277,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", type=int, default=1, help="index of workload.SHAPES")
     ap.add_argument("--nq", type=int, default=None, help="override the batch size")
-    ap.add_argument("--precision", choices=("fp32", "bf16"), default="fp32",
+    ap.add_argument("--precision", choices=("fp32", "bf16", "fp8"), default="fp32",
                     help="fine-screen precision (the rerank is FP64 either way)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--latency-reps", type=int, default=200)
@@ -330,7 +333,7 @@ def main():
     log(f"[bench] workload {w.name}: n={len(w.feats)} d={w.feats.shape[1]} "
         f"regions={w.n_regions_total} frames={len(w.q)} requests={len(w.req_offsets) - 1} "
         f"({time.perf_counter() - t0:.1f} s)")
-    db = hloc.HlocDB(w.feats, w.xy, mirrors=hloc.MIRROR_BF16 if a.precision == "bf16" else 0)
+    db = hloc.HlocDB(w.feats, w.xy, mirrors=MIRRORS[a.precision](hloc))
     db.set_regions(w.region_of, w.n_regions_total)
     db.set_aggregation(*w.agg)
     nq, k, nreq = len(w.q), w.k, len(w.req_offsets) - 1
@@ -363,7 +366,7 @@ def main():
     sizes = np.bincount(w.region_of, minlength=w.n_regions_total)
     unique_rows = int(sizes[np.unique(regions)].sum())
     d = w.feats.shape[1]
-    row_bytes = 2 * d if a.precision == "bf16" else 4 * d
+    row_bytes = {"fp32": 4 * d, "bf16": 2 * d, "fp8": d + 4}[a.precision]  # fp8: + scale
     screen_bytes = unique_rows * (row_bytes + 4) + info["candidates"] * 4 + nq * row_bytes
 
     # throughput: K back-to-back steps, nothing recorded between kernels
@@ -443,7 +446,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if a.precision == "fp32" else "bf16",
+        "dtype": DTYPES[a.precision],
         "data": "synthetic",
         "config": {"workload": w.name, "n": int(len(w.feats)), "d": int(d),
                    "regions": int(w.n_regions_total), "frames_per_step": int(nq),
@@ -456,8 +459,7 @@ def main():
         "recall_at_k": recall,
         "exact_lists": None if base is None else f"{exact}/{m}",
         "roofline": {"bound": "hbm",
-                     "kernel": ("k_screen_bf16<NS,false>" if a.precision == "bf16"
-                                else "k_screen_blk<NS,false>")
+                     "kernel": SCREEN_KERNELS[a.precision] + "NS, false>"
                                + (" + wide-item kernel" if wide_items > 0 else ""),
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

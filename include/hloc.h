@@ -51,13 +51,15 @@ typedef enum {
 } hloc_status;
 
 /* Precision of the screens. HLOC_BF16 screens rows and region
- * representatives from bf16 copies (the database must be built with
- * HLOC_MIRROR_BF16). Whatever the screen, the returned top-k is decided by an
- * FP64 rerank of the survivors (k + 16 of them behind fp32, 4k behind bf16)
- * and the regions by an FP64 re-score of the best n_regions + 8, each with a
+ * representatives from bf16 copies (database built with HLOC_MIRROR_BF16),
+ * HLOC_FP8 from OCP e4m3 copies with one fp32 scale per vector (max |v| / 448;
+ * database built with HLOC_MIRROR_FP8; padded length a multiple of 64).
+ * Whatever the screen, the returned top-k is decided by an FP64 rerank of the
+ * survivors (k + 16 of them behind fp32, 4k behind bf16 and fp8) and the
+ * regions by an FP64 re-score of the best n_regions + 8, each with a
  * certificate: candidates the screen's error bound cannot exclude are
- * re-scored too, so the result is the same for every precision. HLOC_FP8 is
- * not available yet. */
+ * re-scored too, so the result is the same for every precision (a looser
+ * bound only costs more re-scoring). */
 typedef enum { HLOC_FP32 = 0, HLOC_BF16 = 1, HLOC_FP8 = 2 } hloc_precision;
 
 /* Per-request flags written by the aggregation (bit set). */
@@ -68,7 +70,7 @@ enum {
 };
 
 /* Low-precision copies of the rows kept beside the fp32 rows (build flags). */
-enum { HLOC_MIRROR_BF16 = 1 };
+enum { HLOC_MIRROR_BF16 = 1, HLOC_MIRROR_FP8 = 2 };
 
 /* Limits. */
 #define HLOC_MAX_DIM 1024            /* d */
@@ -84,7 +86,9 @@ enum { HLOC_MIRROR_BF16 = 1 };
  *   xy    : host, n x 2 float64 metres (x west->east, y south->north), finite.
  *   n     : 1 .. 2^31-1 rows;  d : 1 .. HLOC_MAX_DIM.
  *   mirrors: HLOC_MIRROR_* bits: HLOC_MIRROR_BF16 keeps a bf16 copy of the rows
- *            (half the bytes) for the HLOC_BF16 screen; 0 for fp32 only.
+ *            (half the bytes) for the HLOC_BF16 screen, HLOC_MIRROR_FP8 an
+ *            e4m3 copy with a scale per row (a quarter) for HLOC_FP8; 0 for
+ *            fp32 only.
  *   out   : receives the new handle (set to NULL on error).
  * Errors: EINVAL (sizes, NULL pointers, non-finite values), EUNSUPPORTED
  * (unknown mirror flag), ENOMEM, EDEVICE.

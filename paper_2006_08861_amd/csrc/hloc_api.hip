@@ -80,11 +80,13 @@ void dev_free(T *&p) {
 int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32_t nreq,
               int32_t precision, Plan *pl) {
   if (!db->has_regions) return fail(HLOC_ESTATE, "hloc_set_regions has not been called");
-  if (precision == HLOC_BF16) {
-    if (!db->rows16)
-      return fail(HLOC_EUNSUPPORTED, "the bf16 screen needs a database built with HLOC_MIRROR_BF16");
-    if (!bf16_screen_supports(db->dp))
-      return fail(HLOC_EUNSUPPORTED, "the bf16 screen does not support padded length %d", db->dp);
+  if (precision == HLOC_BF16 || precision == HLOC_FP8) {
+    const char *name = precision == HLOC_BF16 ? "bf16" : "fp8";
+    if (!db->lp[precision].rows)
+      return fail(HLOC_EUNSUPPORTED, "the %s screen needs a database built with its mirror", name);
+    if (!lp_screen_supports(precision, db->dp))
+      return fail(HLOC_EUNSUPPORTED, "the %s screen does not support padded length %d", name,
+                  db->dp);
   } else if (precision != HLOC_FP32) {
     return fail(HLOC_EUNSUPPORTED, "screen precision %d is not available in this build", precision);
   }
@@ -108,7 +110,7 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
   }
   // survivors re-scored in FP64: k + 16 behind the fp32 screen, 4k behind bf16
   p.kp = std::min(precision == HLOC_FP32 ? k + kOversample : std::max(4 * k, k + kOversample),
-                  kMaxSurvivors);
+                  kMaxSurvivors);  // 4k behind the bf16 and fp8 screens
   p.cap2 = db->h_desc_prefix[p.nr];
   const int64_t maxch = (db->max_region + kRowsFine - 1) / kRowsFine;
   const int64_t b1 = (int64_t)nq * p.nr * maxch;
@@ -151,8 +153,9 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *byte
   CHK(fit(ws->rq, (size_t)nq * nr * sizeof(int2)));
   CHK(fit(ws->items, (size_t)std::max<int64_t>(p.items_bound, 1) * sizeof(Item)));
   CHK(fit(ws->cand2, (size_t)nq * std::max<int64_t>(p.cap2, 1) * sizeof(uint32_t)));
-  if (db->rows16) {
-    CHK(fit(ws->qp16, (size_t)nq * db->dp * sizeof(uint16_t)));
+  if (db->lp[HLOC_BF16].rows || db->lp[HLOC_FP8].rows) {
+    CHK(fit(ws->q_lp, (size_t)nq * db->dp * (db->lp[HLOC_BF16].rows ? 2 : 1)));
+    CHK(fit(ws->q_scale, (size_t)nq * sizeof(float)));
     CHK(fit(ws->q_err, (size_t)nq * sizeof(float)));
     CHK(fit(ws->q_lon, (size_t)nq * sizeof(float)));
   }
@@ -216,11 +219,17 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   int32_t *regions = as<int32_t>(ws->regions);
   Phaser ph(ws);
   ph.begin(HLOC_PHASE_PREP);
-  const bool bf16 = p.precision == HLOC_BF16;
-  uint16_t *qp16 = bf16 ? as<uint16_t>(ws->qp16) : nullptr;
-  HIPCHK(launch_prep_queries(q, p.nq, db->d, db->dp, qp, qn2, misc, qp16,
-                             bf16 ? as<float>(ws->q_err) : nullptr,
-                             bf16 ? as<float>(ws->q_lon) : nullptr, s));
+  // low-precision screens: the frames rounded the same way as the rows
+  const int fmt = p.precision == HLOC_FP32 ? 0 : p.precision;
+  const LpMirror *lpm = fmt ? &db->lp[fmt] : nullptr;
+  HIPCHK(launch_prep_queries(q, p.nq, db->d, db->dp, qp, qn2, misc, s));
+  if (fmt)
+    HIPCHK(launch_frames_to_lp(fmt, qp, p.nq, db->dp, ws->q_lp.p, as<float>(ws->q_scale),
+                               as<float>(ws->q_err), as<float>(ws->q_lon), s));
+  // fp32 accumulation of rounded products: |q~||d~| <= 1.004 |q||d| for bf16,
+  // <= (1 + 2^-4)^2 |q||d| for fp8 (relative rounding of at most 2^-4 per
+  // value; subnormals are absolute and covered by the rounding-error terms)
+  const double lo_fp32 = fmt == HLOC_FP8 ? 1.15 : 1.01;
   ph.begin(HLOC_PHASE_COARSE);
   const double coef = (db->dp + 16) * kUnit32 * 1.001;
   if (!p.exhaustive) {
@@ -236,11 +245,13 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     sa.dense = 1;
     sa.nrows = db->R;
     sa.nq = p.nq;
-    const bool coarse16 = bf16 && db->rep16;
-    if (coarse16) {
-      sa.rows16 = db->rep16;
-      sa.qp16 = qp16;
-      HIPCHK(launch_screen_bf16(sa, p.grid1, s));
+    const bool coarse_lp = fmt && lpm->reps;
+    if (coarse_lp) {
+      sa.rows_lp = lpm->reps;
+      sa.q_lp = ws->q_lp.p;
+      sa.row_scale = lpm->rep_scale;
+      sa.q_scale = as<float>(ws->q_scale);
+      HIPCHK(launch_screen_lp(fmt, sa, p.grid1, s));
     } else {
       HIPCHK(launch_screen_f32(sa, p.grid1, s));
     }
@@ -256,13 +267,13 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     ra.qn2 = qn2;
     ra.err_coef = coef;
     ra.max_norm = (double)db->h_rep_max * (1.0 + 1e-6);
-    if (coarse16) {
+    if (coarse_lp) {
       ra.q_err = as<float>(ws->q_err);
       ra.q_lon = as<float>(ws->q_lon);
-      ra.lo_dmax = (double)db->h_rep16_err * (1.0 + 1e-6);
-      ra.lo_nmax = (double)db->h_rep16_norm * (1.0 + 1e-6);
+      ra.lo_dmax = (double)lpm->rep_err * (1.0 + 1e-6);
+      ra.lo_nmax = (double)lpm->rep_norm * (1.0 + 1e-6);
       ra.lo_coef = 2.0 * (1.0 + 1e-6);
-      ra.err_coef = coef * 1.01;
+      ra.err_coef = coef * lo_fp32;
     }
     ra.nq = p.nq;
     ra.reg_out = regions;
@@ -293,13 +304,15 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   sb.n_items = misc + 0;
   sb.rq = as<int2>(ws->rq);
   sb.reg_start = db->reg_start;
-  if (bf16) {
-    sb.rows16 = db->rows16;
-    sb.qp16 = qp16;
+  if (fmt) {
+    sb.rows_lp = lpm->rows;
+    sb.q_lp = ws->q_lp.p;
+    sb.row_scale = lpm->scale;
+    sb.q_scale = as<float>(ws->q_scale);
   }
-  HIPCHK(bf16 ? launch_screen_bf16(sb, p.grid2, s) : launch_screen_f32(sb, p.grid2, s));
+  HIPCHK(fmt ? launch_screen_lp(fmt, sb, p.grid2, s) : launch_screen_f32(sb, p.grid2, s));
   ph.begin(HLOC_PHASE_SCREEN_WIDE);
-  HIPCHK(bf16 ? launch_screen_wide_bf16(sb, p.grid2, s) : launch_screen_wide_f32(sb, p.grid2, s));
+  HIPCHK(fmt ? launch_screen_wide_lp(fmt, sb, p.grid2, s) : launch_screen_wide_f32(sb, p.grid2, s));
   ph.begin(HLOC_PHASE_SELECT);
   SelRerankArgs rb{};
   rb.cand = as<uint32_t>(ws->cand2);
@@ -321,15 +334,15 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   rb.qn2 = qn2;
   rb.err_coef = coef;
   rb.max_norm = (double)db->h_row_max * (1.0 + 1e-6);
-  if (bf16) {
-    // the bf16 roundings enter the screen through q~.d~ - q.d =
+  if (fmt) {
+    // the roundings enter the screen through q~.d~ - q.d =
     // q~.(d~-d) + (q~-q).d~ - (q~-q).(d~-d), doubled by the -2 q.d term
     rb.q_err = as<float>(ws->q_err);
     rb.q_lon = as<float>(ws->q_lon);
-    rb.lo_dmax = (double)db->h_bf16_err * (1.0 + 1e-6);
-    rb.lo_nmax = (double)db->h_bf16_norm * (1.0 + 1e-6);
+    rb.lo_dmax = (double)lpm->err * (1.0 + 1e-6);
+    rb.lo_nmax = (double)lpm->norm * (1.0 + 1e-6);
     rb.lo_coef = 2.0 * (1.0 + 1e-6);
-    rb.err_coef = coef * 1.01;  // fp32 accumulation of bf16 products (|q~||d~| <= 1.004 |q||d|)
+    rb.err_coef = coef * lo_fp32;
   }
   rb.nq = p.nq;
   rb.idx_out = idx;
@@ -403,8 +416,8 @@ void free_ws(hloc_ws *ws) {
                    &ws->rfill,    &ws->rq_off,   &ws->item_off, &ws->cand_off, &ws->n_cand,
                    &ws->misc,     &ws->rq,       &ws->items,    &ws->cand2,   &ws->agg_xy,
                    &ws->agg_tile, &ws->agg_flags, &ws->s_q,     &ws->s_off,   &ws->s_idx,
-                   &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags, &ws->qp16,
-                   &ws->q_err,    &ws->q_lon};
+                   &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags, &ws->q_lp,
+                   &ws->q_scale,  &ws->q_err,    &ws->q_lon};
   for (WsBuf *b : bufs) free_buf(*b);
   for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
   if (ws->stream) (void)hipStreamDestroy(ws->stream);
@@ -423,11 +436,26 @@ int new_ws(hloc_db *db, hloc_ws **out) {
   return HLOC_OK;
 }
 
+// Releases a low-precision mirror: the representatives' copy, and with
+// rows_too the rows' copy as well.
+void free_lp(LpMirror &m, bool rows_too) {
+  if (m.reps) (void)hipFree(m.reps);
+  if (m.rep_scale) (void)hipFree(m.rep_scale);
+  m.reps = nullptr;
+  m.rep_scale = nullptr;
+  if (rows_too) {
+    if (m.rows) (void)hipFree(m.rows);
+    if (m.scale) (void)hipFree(m.scale);
+    m.rows = nullptr;
+    m.scale = nullptr;
+  }
+}
+
 void free_db_data(hloc_db *db) {
   free_ws(db->ws0);
   db->ws0 = nullptr;
   dev_free(db->rows);
-  dev_free(db->rows16);
+  for (LpMirror &m : db->lp) free_lp(m, true);
   dev_free(db->row_n2);
   dev_free(db->perm);
   dev_free(db->xy);
@@ -438,7 +466,6 @@ void free_db_data(hloc_db *db) {
   dev_free(db->rep64);
   dev_free(db->rep32);
   dev_free(db->rep_n2);
-  dev_free(db->rep16);
   if (db->stream) (void)hipStreamDestroy(db->stream);
   db->stream = nullptr;
 }
@@ -491,7 +518,7 @@ int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, ui
   if (!feats || !xy) return fail(HLOC_EINVAL, "feats and xy must be non-NULL");
   if (n < 1 || n > INT32_MAX) return fail(HLOC_EINVAL, "n must be in 1..2^31-1 (got %lld)", (long long)n);
   if (d < 1 || d > HLOC_MAX_DIM) return fail(HLOC_EINVAL, "d must be in 1..%d (got %d)", HLOC_MAX_DIM, d);
-  if (mirrors & ~(uint32_t)HLOC_MIRROR_BF16)
+  if (mirrors & ~(uint32_t)(HLOC_MIRROR_BF16 | HLOC_MIRROR_FP8))
     return fail(HLOC_EUNSUPPORTED, "mirror flags 0x%x are not available in this build", mirrors);
   const int64_t nd = n * (int64_t)d;
   for (int64_t i = 0; i < nd; ++i)
@@ -530,7 +557,7 @@ int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, ui
   if (pe != hipSuccess) return bail(fail(HLOC_EDEVICE, "kernel set-up failed: %s", hipGetErrorString(pe)));
   if ((rc = dev_alloc(&db->rows, (size_t)n * db->dp)) || (rc = dev_alloc(&db->row_n2, (size_t)n)) ||
       (rc = dev_alloc(&db->perm, (size_t)n)) || (rc = dev_alloc(&db->xy, (size_t)n * 2)) ||
-      (rc = dev_alloc(&db->tiles, (size_t)n)) || (rc = dev_alloc(&db->norm_max, 8)))
+      (rc = dev_alloc(&db->tiles, (size_t)n)) || (rc = dev_alloc(&db->norm_max, kNormSlots)))
     return bail(rc);
   float *tmp = nullptr;
   if ((rc = dev_alloc(&tmp, (size_t)nd))) return bail(rc);
@@ -539,7 +566,7 @@ int hloc_build_db(const float *feats, int64_t n, int32_t d, const double *xy, ui
   hipError_t e = hipMemcpy(tmp, feats, (size_t)nd * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(db->perm, db->h_perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(db->xy, xy, (size_t)n * 2 * sizeof(double), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemsetAsync(db->norm_max, 0, 8 * sizeof(float), db->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(db->norm_max, 0, kNormSlots * sizeof(float), db->stream);
   if (e == hipSuccess) e = launch_gather_rows(tmp, db->perm, n, d, d, db->rows, db->dp, db->stream);
   if (e == hipSuccess) e = launch_row_norms(db->rows, n, db->dp, db->row_n2, db->norm_max, db->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(db->stream);
@@ -587,7 +614,7 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   dev_free(db->rep64);
   dev_free(db->rep32);
   dev_free(db->rep_n2);
-  dev_free(db->rep16);
+  for (LpMirror &m : db->lp) free_lp(m, true);
   db->has_regions = false;
   int rc;
   float *new_rows = nullptr;
@@ -618,13 +645,16 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   HIPCHK(hipMemcpy(db->perm, new_perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(db->reg_start, start.data(), (size_t)(R + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(db->nonempty_ids, ids.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  HIPCHK(hipMemsetAsync(db->norm_max, 0, 8 * sizeof(float), db->stream));
+  HIPCHK(hipMemsetAsync(db->norm_max, 0, kNormSlots * sizeof(float), db->stream));
   HIPCHK(launch_row_norms(db->rows, n, db->dp, db->row_n2, db->norm_max, db->stream));
-  dev_free(db->rows16);
-  if (db->mirrors & HLOC_MIRROR_BF16) {
-    if ((rc = dev_alloc(&db->rows16, (size_t)n * db->dp))) return rc;
-    HIPCHK(launch_rows_to_bf16(db->rows, n, db->dp, db->rows16, db->norm_max + 2,
-                               db->norm_max + 3, db->stream));
+  for (int fmt : {HLOC_BF16, HLOC_FP8}) {
+    if (!(db->mirrors & (fmt == HLOC_BF16 ? HLOC_MIRROR_BF16 : HLOC_MIRROR_FP8))) continue;
+    LpMirror &m = db->lp[fmt];
+    float *mx = db->norm_max + 4 * fmt - 2;
+    if ((rc = dev_alloc(reinterpret_cast<uint8_t **>(&m.rows), (size_t)n * db->dp * lp_bytes(fmt))))
+      return rc;
+    if (fmt == HLOC_FP8 && (rc = dev_alloc(&m.scale, (size_t)n))) return rc;
+    HIPCHK(launch_rows_to_lp(fmt, db->rows, n, db->dp, m.rows, m.scale, mx, mx + 1, db->stream));
   }
   if (reps) {
     std::vector<double> r64((size_t)R * db->dp, 0.0);
@@ -636,20 +666,28 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   }
   HIPCHK(launch_rep_finish(db->rep64, db->reg_start, R, db->dp, db->rep32, db->rep_n2,
                            db->norm_max + 1, db->stream));
-  if (db->mirrors & HLOC_MIRROR_BF16) {
-    if ((rc = dev_alloc(&db->rep16, (size_t)R * db->dp))) return rc;
-    HIPCHK(launch_rows_to_bf16(db->rep32, R, db->dp, db->rep16, db->norm_max + 4,
-                               db->norm_max + 5, db->stream));
+  for (int fmt : {HLOC_BF16, HLOC_FP8}) {
+    LpMirror &m = db->lp[fmt];
+    if (!m.rows) continue;
+    float *mx = db->norm_max + 4 * fmt - 2;
+    if ((rc = dev_alloc(reinterpret_cast<uint8_t **>(&m.reps), (size_t)R * db->dp * lp_bytes(fmt))))
+      return rc;
+    if (fmt == HLOC_FP8 && (rc = dev_alloc(&m.rep_scale, (size_t)R))) return rc;
+    HIPCHK(launch_rows_to_lp(fmt, db->rep32, R, db->dp, m.reps, m.rep_scale, mx + 2, mx + 3,
+                             db->stream));
   }
-  float mx[6];
+  float mx[kNormSlots];
   HIPCHK(hipMemcpyAsync(mx, db->norm_max, sizeof mx, hipMemcpyDeviceToHost, db->stream));
   HIPCHK(hipStreamSynchronize(db->stream));
   db->h_row_max = mx[0];
   db->h_rep_max = mx[1];
-  db->h_bf16_err = mx[2];
-  db->h_bf16_norm = mx[3];
-  db->h_rep16_err = mx[4];
-  db->h_rep16_norm = mx[5];
+  for (int fmt : {HLOC_BF16, HLOC_FP8}) {
+    const float *v = mx + 4 * fmt - 2;
+    db->lp[fmt].err = v[0];
+    db->lp[fmt].norm = v[1];
+    db->lp[fmt].rep_err = v[2];
+    db->lp[fmt].rep_norm = v[3];
+  }
   db->R = R;
   db->R_nonempty = (int32_t)ids.size();
   db->h_reg_start = start;

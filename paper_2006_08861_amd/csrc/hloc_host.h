@@ -62,6 +62,22 @@ struct ProfRec {
   hipEvent_t a, b;
 };
 
+// A low-precision copy of the rows and the representatives (bf16, or fp8 with
+// a scale per vector) and the largest norms of its rounding errors and of the
+// rounded vectors.
+struct LpMirror {
+  void *rows = nullptr;
+  float *scale = nullptr;
+  void *reps = nullptr;
+  float *rep_scale = nullptr;
+  float err = 0.f, norm = 0.f, rep_err = 0.f, rep_norm = 0.f;
+};
+
+// Bytes per value of a low-precision format (HLOC_BF16 / HLOC_FP8).
+inline int lp_bytes(int fmt) { return fmt == HLOC_BF16 ? 2 : 1; }
+
+constexpr int kNormSlots = 10;  // largest-norm slots of a database (see hloc_db)
+
 }  // namespace hloc
 
 // Scratch memory, counters, profile record and captured graph of one batch in
@@ -70,7 +86,7 @@ struct hloc_ws {
   hloc_db *db = nullptr;
   hipStream_t stream = nullptr;  // own stream (graph capture, host-pointer calls)
   hloc::WsBuf qp, qn2, cand1, regions, rcount, rfill, vord, rq_off, item_off, cand_off, n_cand, misc, rq,
-      items, cand2, agg_xy, agg_tile, agg_flags, qp16, q_err, q_lon;
+      items, cand2, agg_xy, agg_tile, agg_flags, q_lp, q_scale, q_err, q_lon;
   hloc::WsBuf s_q, s_off, s_idx, s_dist, s_xy, s_tile, s_flags;  // staging of host-pointer calls
   int32_t last_nq = 0, last_nr = 0, last_kp = 0;
   bool prof_on = false;
@@ -92,14 +108,13 @@ struct hloc_db {
   int32_t *perm = nullptr;    // device row -> original index
   double *xy = nullptr;       // n x 2 by original index
   int2 *tiles = nullptr;      // n by original index
-  // largest norms: [0] rows, [1] representatives, [2] bf16 rounding error of
-  // the rows, [3] bf16 rows, [4] bf16 rounding error of the representatives,
-  // [5] bf16 representatives
+  // largest norms: [0] rows, [1] representatives, then for format f (1 bf16,
+  // 2 fp8) at 4 f - 2: rounding error of the rows, rounded rows, rounding
+  // error of the representatives, rounded representatives
   float *norm_max = nullptr;
   float h_row_max = 0.f, h_rep_max = 0.f;
   uint32_t mirrors = 0;        // HLOC_MIRROR_* copies kept beside the fp32 rows
-  uint16_t *rows16 = nullptr;  // bf16 copy of rows
-  float h_bf16_err = 0.f, h_bf16_norm = 0.f;
+  hloc::LpMirror lp[3];        // [HLOC_BF16], [HLOC_FP8]
   std::vector<int32_t> h_perm;
   double max_abs_coord = 0.0;
   bool has_regions = false;
@@ -113,8 +128,6 @@ struct hloc_db {
   double *rep64 = nullptr;
   float *rep32 = nullptr;
   float *rep_n2 = nullptr;
-  uint16_t *rep16 = nullptr;  // bf16 copy of rep32 (with the bf16 mirror)
-  float h_rep16_err = 0.f, h_rep16_norm = 0.f;
   double cell = 0.5, radius = 0.0;
   int32_t top_c = 1, rho = 0, pct = 0;
   hloc_ws *ws0 = nullptr;  // workspace of the calls that take no workspace

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hloc.h"
+
 #include <algorithm>
 
 namespace hloc {
@@ -59,11 +61,14 @@ struct Item {
   int32_t nrows_gq;  // nrows << 16 | gq
 };
 
-// Dense or listed screen of rows against padded frames (fp32 or bf16 copies).
+// Dense or listed screen of rows against padded frames (fp32, or bf16 / fp8
+// copies).
 struct ScreenArgs {
   const float *rows;      // nrows x dp, row-major
-  const uint16_t *rows16; // bf16 copy of rows (bf16 screen)
-  const uint16_t *qp16;   // bf16 copy of qp (bf16 screen)
+  const void *rows_lp;    // low-precision copy of rows (bf16 / fp8 screens)
+  const void *q_lp;       // low-precision copy of qp
+  const float *row_scale; // fp8: per-row scale
+  const float *q_scale;   // fp8: per-frame scale
   const float *row_n2;    // nrows squared norms (+inf marks a row never to select)
   int32_t dp;             // padded row length (multiple of 32)
   const float *qp;        // frames x dp
@@ -83,22 +88,24 @@ struct ScreenArgs {
 };
 
 // Padded copy and squared norm of each frame; block 0 also clears zero16[0..16).
-// With qp16 set, also the bf16 rounding of each frame, the norm of its rounding
-// error (q_err) and of the rounded frame (q_lon).
 hipError_t launch_prep_queries(const float *q, int32_t nq, int32_t d, int32_t dp, float *qp,
-                               float *qn2, int32_t *zero16, uint16_t *qp16, float *q_err,
-                               float *q_lon, hipStream_t s);
+                               float *qn2, int32_t *zero16, hipStream_t s);
 // Dense screen, or the narrow list items (every list item where no register
 // kernel exists for the padded length); then the wide list items.
 hipError_t launch_screen_f32(const ScreenArgs &a, int32_t grid, hipStream_t s);
 hipError_t launch_screen_wide_f32(const ScreenArgs &a, int32_t grid, hipStream_t s);
-hipError_t launch_screen_bf16(const ScreenArgs &a, int32_t grid, hipStream_t s);
-hipError_t launch_screen_wide_bf16(const ScreenArgs &a, int32_t grid, hipStream_t s);
-bool bf16_screen_supports(int32_t dp);
-// bf16 copy of n rows; maxima of the per-row norms of the rounding error and
-// of the rounded row.
-hipError_t launch_rows_to_bf16(const float *src, int64_t n, int32_t dp, uint16_t *dst,
-                               float *max_err, float *max_norm, hipStream_t s);
+// Low-precision screens, fmt = HLOC_BF16 or HLOC_FP8.
+hipError_t launch_screen_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipStream_t s);
+hipError_t launch_screen_wide_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipStream_t s);
+bool lp_screen_supports(int32_t fmt, int32_t dp);
+// Low-precision copy of n rows (fp8: with a scale per row); maxima of the
+// per-row norms of the rounding error and of the rounded row.
+hipError_t launch_rows_to_lp(int32_t fmt, const float *src, int64_t n, int32_t dp, void *dst,
+                             float *scale, float *max_err, float *max_norm, hipStream_t s);
+// The same for the padded frames, with per-frame norms of the rounding error
+// (q_err) and of the rounded frame (q_lon).
+hipError_t launch_frames_to_lp(int32_t fmt, const float *qp, int32_t nq, int32_t dp, void *dst,
+                               float *scale, float *q_err, float *q_lon, hipStream_t s);
 // Blocks to launch for `items` work items of the screen at padded length dp.
 int32_t screen_grid(int64_t items, int32_t dp, int32_t max_blocks);
 
@@ -177,8 +184,8 @@ hipError_t launch_aggregate(const AggArgs &a, hipStream_t s);
 
 // Kernel attributes (LDS limits) for the current device; called once when a
 // database is built so that no attribute is set while a graph is captured.
-hipError_t prepare_screen_kernels();  // also the bf16 screens
-hipError_t prepare_screen_bf16_kernels();
+hipError_t prepare_screen_kernels();  // also the low-precision screens
+hipError_t prepare_screen_lp_kernels();
 hipError_t prepare_select_kernels();
 hipError_t prepare_aggregate_kernels();
 hipError_t prepare_sched_kernels();

@@ -23,10 +23,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_prep_queries(const float *__restrict__ q, int nq, int d,
                                                       int dp, float *__restrict__ qp,
                                                       float *__restrict__ qn2,
-                                                      int32_t *__restrict__ zero16,
-                                                      uint16_t *__restrict__ qp16,
-                                                      float *__restrict__ q_err,
-                                                      float *__restrict__ q_lon) {
+                                                      int32_t *__restrict__ zero16) {
   if (blockIdx.x == 0 && threadIdx.x < 16 && zero16) zero16[threadIdx.x] = 0;
   const int f = blockIdx.x * 4 + wave_id();
   const int lane = lane_id();
@@ -34,40 +31,20 @@ __global__ __launch_bounds__(256) void k_prep_queries(const float *__restrict__ 
   const float *src = q + (int64_t)f * d;
   float *dst = qp + (int64_t)f * dp;
   float acc = 0.f;
-  double e2 = 0.0, l2 = 0.0;
   for (int c = lane; c < dp; c += 64) {
     const float v = c < d ? src[c] : 0.f;
     dst[c] = v;
     acc = fmaf(v, v, acc);
-    if (qp16) {
-      const uint32_t u = __float_as_uint(v);
-      const uint16_t h = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-      qp16[(int64_t)f * dp + c] = h;
-      const double t = (double)__uint_as_float((uint32_t)h << 16);
-      e2 = fma(t - (double)v, t - (double)v, e2);
-      l2 = fma(t, t, l2);
-    }
   }
   acc = wave_sum_f32(acc);
-  if (qp16) {
-    e2 = wave_sum_f64(e2);
-    l2 = wave_sum_f64(l2);
-  }
-  if (lane == 0) {
-    qn2[f] = acc;
-    if (qp16) {
-      q_err[f] = (float)sqrt(e2) * (1.0f + 1e-6f);
-      q_lon[f] = (float)sqrt(l2) * (1.0f + 1e-6f);
-    }
-  }
+  if (lane == 0) qn2[f] = acc;
 }
 
 hipError_t launch_prep_queries(const float *q, int32_t nq, int32_t d, int32_t dp, float *qp,
-                               float *qn2, int32_t *zero16, uint16_t *qp16, float *q_err,
-                               float *q_lon, hipStream_t s) {
+                               float *qn2, int32_t *zero16, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
   return launch_kernel(k_prep_queries, dim3((nq + 3) / 4), dim3(256), 0, s, q, nq, d, dp, qp, qn2,
-                       zero16, qp16, q_err, q_lon);
+                       zero16);
 }
 
 template <bool DENSE>
@@ -381,7 +358,7 @@ hipError_t prepare_screen_kernels() {
     e = hipFuncSetAttribute(kw.first, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kw.second);
     if (e != hipSuccess) return e;
   }
-  e = prepare_screen_bf16_kernels();
+  e = prepare_screen_lp_kernels();
   if (e != hipSuccess) return e;
   done_dev = dev;
   return hipSuccess;

@@ -1,0 +1,441 @@
+// Low-precision distance screens on MFMA and the copies they read: bf16
+// (v_mfma_f32_16x16x32_bf16) and OCP fp8 e4m3 with one fp32 scale per vector
+// (v_mfma_f32_16x16x32_fp8_fp8).
+//
+// Same work items and lane layout as the fp32 register screen, with fewer
+// bytes per row: lane l holds row (l % 16) and frame (l % 16) and takes the
+// 16-byte pieces 4 s + l / 16 of their rows, so the 16 rows of a block are
+// read as 64-byte runs. A bf16 piece (8 values) feeds one MFMA, an fp8 piece
+// (16 values) two; rows and frames use the same assignment of values to MFMA
+// k slots, so every piece of a row meets the same piece of the frame.
+// Products are accumulated in fp32 (fp8 products are exact in fp32); the fp8
+// sum is multiplied by the frame's and the row's scale. The screen value is
+// |q|^2 + |d|^2 - 2 q~.d~ with the norms of the fp32 vectors and the dot
+// product of their roundings q~, d~ (for fp8: scale times the e4m3 value);
+// its error against the exact distance is bounded by the select kernel from
+// |q~ - q| and |q~| (per frame, from the prep kernel) and the largest
+// |d~ - d| and |d~| over the rows (from the copy kernels below).
+#include "hloc_device.h"
+#include "hloc_internal.h"
+
+namespace hloc {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr float kFp8Max = 448.f;  // largest finite OCP e4m3 value
+
+// Round-to-nearest-even fp32 -> bf16 bits (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Value of an OCP e4m3 byte (sign, 4 exponent bits of bias 7, 3 mantissa
+// bits; exponent 0 is subnormal). The two NaN codes are never produced here.
+__device__ __forceinline__ float fp8_to_f32(uint32_t b) {
+  const int e = (b >> 3) & 15, m = b & 7;
+  const float v = e == 0 ? ldexpf((float)m, -9) : ldexpf((float)(8 + m), e - 10);
+  return (b & 0x80) ? -v : v;
+}
+
+// Nearest e4m3 bytes of x0 and x1 (|x| <= 448), in the low two bytes.
+__device__ __forceinline__ uint32_t fp8_pair(float x0, float x1) {
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x0, x1, 0, false) & 0xFFFFu;
+}
+
+__device__ __forceinline__ float clamp_fp8(float x) { return fminf(fmaxf(x, -kFp8Max), kFp8Max); }
+
+constexpr int kLpRowsPerWave = 16;
+
+// Low-precision copy of n rows of dp floats, kLpRowsPerWave rows per wave.
+// bf16: dst holds dp 16-bit values per row. fp8: dst holds dp bytes per row
+// and scale[i] = max |row| / 448 (1 for a zero row), the row being
+// scale[i] * e4m3(row / scale[i]). Per-row FP64 norms of the rounding error
+// and of the rounded row; maxima into max_err / max_norm (float bits, one
+// atomic per block).
+template <int FMT>
+__global__ void k_rows_to_lp(const float *__restrict__ src, int64_t n, int dp, void *dst_,
+                             float *__restrict__ scale, float *max_err, float *max_norm) {
+  __shared__ float s_e[4], s_n[4];
+  const int lane = lane_id();
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + wave_id()) * kLpRowsPerWave;
+  float me = 0.f, mn = 0.f;
+  for (int64_t i = i0; i < min(n, i0 + kLpRowsPerWave); ++i) {
+    const float *r = src + i * dp;
+    double e2 = 0.0, n2 = 0.0;
+    if (FMT == HLOC_BF16) {
+      uint16_t *o = static_cast<uint16_t *>(dst_) + i * dp;
+      for (int c = lane; c < dp; c += 64) {
+        const uint16_t h = bf16_rne(r[c]);
+        o[c] = h;
+        const double t = (double)bf16_to_f32(h);
+        e2 = fma(t - (double)r[c], t - (double)r[c], e2);
+        n2 = fma(t, t, n2);
+      }
+    } else {
+      uint8_t *o = static_cast<uint8_t *>(dst_) + i * dp;
+      float amax = 0.f;
+      for (int c = lane; c < dp; c += 64) amax = fmaxf(amax, fabsf(r[c]));
+      for (int o2 = 32; o2 > 0; o2 >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o2));
+      const float sc = amax > 0.f ? amax / kFp8Max : 1.f;
+      const float inv = amax > 0.f ? kFp8Max / amax : 1.f;
+      if (lane == 0) scale[i] = sc;
+      // two values per lane per step: dp is a multiple of 32
+      for (int c = 2 * lane; c < dp; c += 128) {
+        const uint32_t p = fp8_pair(clamp_fp8(r[c] * inv), clamp_fp8(r[c + 1] * inv));
+        o[c] = (uint8_t)p;
+        o[c + 1] = (uint8_t)(p >> 8);
+        const double t0 = (double)fp8_to_f32(p & 0xFF) * sc, t1 = (double)fp8_to_f32(p >> 8) * sc;
+        e2 = fma(t0 - (double)r[c], t0 - (double)r[c], e2);
+        e2 = fma(t1 - (double)r[c + 1], t1 - (double)r[c + 1], e2);
+        n2 = fma(t0, t0, n2);
+        n2 = fma(t1, t1, n2);
+      }
+    }
+    e2 = wave_sum_f64(e2);
+    n2 = wave_sum_f64(n2);
+    me = fmaxf(me, (float)sqrt(e2));
+    mn = fmaxf(mn, (float)sqrt(n2));
+  }
+  if (lane == 0) {
+    s_e[wave_id()] = me;
+    s_n[wave_id()] = mn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      s_e[0] = fmaxf(s_e[0], s_e[w]);
+      s_n[0] = fmaxf(s_n[0], s_n[w]);
+    }
+    atomicMax(reinterpret_cast<unsigned int *>(max_err), __float_as_uint(s_e[0]));
+    atomicMax(reinterpret_cast<unsigned int *>(max_norm), __float_as_uint(s_n[0]));
+  }
+}
+
+hipError_t launch_rows_to_lp(int32_t fmt, const float *src, int64_t n, int32_t dp, void *dst,
+                             float *scale, float *max_err, float *max_norm, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + 4 * kLpRowsPerWave - 1) / (4 * kLpRowsPerWave)));
+  if (fmt == HLOC_BF16)
+    return launch_kernel(k_rows_to_lp<HLOC_BF16>, grid, dim3(256), 0, s, src, n, dp, dst, scale,
+                         max_err, max_norm);
+  if (fmt == HLOC_FP8)
+    return launch_kernel(k_rows_to_lp<HLOC_FP8>, grid, dim3(256), 0, s, src, n, dp, dst, scale,
+                         max_err, max_norm);
+  return hipErrorInvalidValue;
+}
+
+// Per-frame copies for the low-precision screens: the same rounding as the
+// rows (fp8: a scale per frame), and the norms of the rounding error (q_err)
+// and of the rounded frame (q_lon), rounded up. One wave per frame.
+template <int FMT>
+__global__ void k_frames_to_lp(const float *__restrict__ qp, int nq, int dp, void *dst_,
+                               float *__restrict__ scale, float *__restrict__ q_err,
+                               float *__restrict__ q_lon) {
+  const int f = blockIdx.x * 4 + wave_id(), lane = lane_id();
+  if (f >= nq) return;
+  const float *r = qp + (int64_t)f * dp;
+  double e2 = 0.0, n2 = 0.0;
+  if (FMT == HLOC_BF16) {
+    uint16_t *o = static_cast<uint16_t *>(dst_) + (int64_t)f * dp;
+    for (int c = lane; c < dp; c += 64) {
+      const uint16_t h = bf16_rne(r[c]);
+      o[c] = h;
+      const double t = (double)bf16_to_f32(h);
+      e2 = fma(t - (double)r[c], t - (double)r[c], e2);
+      n2 = fma(t, t, n2);
+    }
+  } else {
+    uint8_t *o = static_cast<uint8_t *>(dst_) + (int64_t)f * dp;
+    float amax = 0.f;
+    for (int c = lane; c < dp; c += 64) amax = fmaxf(amax, fabsf(r[c]));
+    for (int o2 = 32; o2 > 0; o2 >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o2));
+    const float sc = amax > 0.f ? amax / kFp8Max : 1.f;
+    const float inv = amax > 0.f ? kFp8Max / amax : 1.f;
+    if (lane == 0) scale[f] = sc;
+    for (int c = 2 * lane; c < dp; c += 128) {
+      const uint32_t p = fp8_pair(clamp_fp8(r[c] * inv), clamp_fp8(r[c + 1] * inv));
+      o[c] = (uint8_t)p;
+      o[c + 1] = (uint8_t)(p >> 8);
+      const double t0 = (double)fp8_to_f32(p & 0xFF) * sc, t1 = (double)fp8_to_f32(p >> 8) * sc;
+      e2 = fma(t0 - (double)r[c], t0 - (double)r[c], e2);
+      e2 = fma(t1 - (double)r[c + 1], t1 - (double)r[c + 1], e2);
+      n2 = fma(t0, t0, n2);
+      n2 = fma(t1, t1, n2);
+    }
+  }
+  e2 = wave_sum_f64(e2);
+  n2 = wave_sum_f64(n2);
+  if (lane == 0) {
+    q_err[f] = (float)sqrt(e2) * (1.0f + 1e-6f);
+    q_lon[f] = (float)sqrt(n2) * (1.0f + 1e-6f);
+  }
+}
+
+hipError_t launch_frames_to_lp(int32_t fmt, const float *qp, int32_t nq, int32_t dp, void *dst,
+                               float *scale, float *q_err, float *q_lon, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((nq + 3) / 4));
+  if (fmt == HLOC_BF16)
+    return launch_kernel(k_frames_to_lp<HLOC_BF16>, grid, dim3(256), 0, s, qp, nq, dp, dst, scale,
+                         q_err, q_lon);
+  if (fmt == HLOC_FP8)
+    return launch_kernel(k_frames_to_lp<HLOC_FP8>, grid, dim3(256), 0, s, qp, nq, dp, dst, scale,
+                         q_err, q_lon);
+  return hipErrorInvalidValue;
+}
+
+// One 16-byte piece of a row against the same piece of a frame.
+template <int FMT>
+__device__ __forceinline__ v4f lp_mfma(uint4 a, uint4 b, v4f acc) {
+  if (FMT == HLOC_BF16) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                   __builtin_bit_cast(v8bf, b), acc, 0, 0, 0);
+  } else {
+    const long a0 = (long)(((uint64_t)a.y << 32) | a.x), a1 = (long)(((uint64_t)a.w << 32) | a.z);
+    const long b0 = (long)(((uint64_t)b.y << 32) | b.x), b1 = (long)(((uint64_t)b.w << 32) | b.z);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, acc, 0, 0, 0);
+  }
+}
+
+// Screen word of a row with squared norm rn against a frame with squared norm
+// qn, from the low-precision dot product (times the two scales for fp8).
+template <int FMT>
+__device__ __forceinline__ uint32_t lp_word(float qn, float rn, float acc, float qs, float rs) {
+  if (__builtin_isinf(rn)) return 0xFFFFFFFFu;
+  const float dot = FMT == HLOC_FP8 ? acc * (qs * rs) : acc;
+  float dd = (qn + rn) - 2.f * dot;
+  dd = dd > 0.f ? dd : 0.f;
+  return __float_as_uint(dd);
+}
+
+// Dense items and narrow list items, one item per block, one 16-row block per
+// wave, as the fp32 register screen. NS = 16-byte pieces per lane and row
+// (row bytes / 64).
+template <int FMT, int NS, bool DENSE>
+__global__ __launch_bounds__(256) void k_screen_lp(ScreenArgs a) {
+  constexpr int ROWU4 = 4 * NS;  // 16-byte pieces per row
+  const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const uint4 *rows = static_cast<const uint4 *>(a.rows_lp);
+  const uint4 *frames = static_cast<const uint4 *>(a.q_lp);
+  int lo = 0, hi, nchunks = 1;
+  if (DENSE) {
+    nchunks = (a.nrows + a.rows_per_item - 1) / a.rows_per_item;
+    hi = nchunks * ((a.nq + kGroup - 1) / kGroup);
+  } else {
+    hi = a.n_items[4];  // the narrow items: at most kGroup frames each
+  }
+  for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
+    int row_begin, chunk_row, nrows, gq, fr = 0;
+    int64_t off = 0;
+    if (DENSE) {
+      const int c = it % nchunks, grp = it / nchunks;
+      row_begin = c * a.rows_per_item;
+      chunk_row = row_begin;
+      nrows = min(a.rows_per_item, a.nrows - row_begin);
+      gq = min(kGroup, a.nq - grp * kGroup);
+      fr = grp * kGroup + i;
+      off = (int64_t)fr * a.cap + chunk_row;
+    } else {
+      const Item itm = a.items[it];
+      row_begin = itm.row_begin;
+      chunk_row = itm.chunk_row;
+      nrows = itm.nrows_gq >> 16;
+      gq = itm.nrows_gq & 0xFFFF;
+      if (i < gq) {
+        const int2 e = a.rq[itm.q0 + i];
+        fr = e.x;
+        off = (int64_t)e.x * a.cap + e.y + chunk_row;
+      }
+    }
+    if (i >= gq) fr = 0;
+    const int nrb = (nrows + 15) >> 4;
+    for (int rb = w; rb < nrb; rb += nw) {
+      const int rl = min(rb * 16 + i, nrows - 1);
+      const uint4 *rp = rows + (int64_t)(row_begin + rl) * ROWU4 + g;
+      const uint4 *qp = frames + (int64_t)fr * ROWU4 + g;
+      uint4 av[NS], bv[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) av[s] = rp[4 * s];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
+      const float qn = a.qn2[fr];
+      const float qs = FMT == HLOC_FP8 ? a.q_scale[fr] : 1.f;
+      v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc = lp_mfma<FMT>(av[s], bv[s], acc);
+      if (i < gq) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rb * 16 + 4 * g + r;
+          if (row < nrows) {
+            const int grow = row_begin + row;
+            const float rs = FMT == HLOC_FP8 ? a.row_scale[grow] : 1.f;
+            a.cand[off + row] = lp_word<FMT>(qn, a.row_n2[grow], acc[r], qs, rs);
+          }
+        }
+      }
+    }
+  }
+}
+
+// Wide list items, as the fp32 wide screen: the chunk's rows (and fp8 scales)
+// staged in LDS once, a 16-frame group per wave at a time.
+template <int FMT, int NS>
+__global__ __launch_bounds__(256) void k_screen_wide_lp(ScreenArgs a) {
+  constexpr int ROWU4 = 4 * NS;
+  constexpr int LDR = ROWU4 + 1;  // pieces per LDS row, one of padding
+  extern __shared__ uint4 s_rows[];  // 64 x LDR
+  __shared__ float s_rn[64], s_rs[64];
+  const int tid = threadIdx.x, lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const uint4 *rows = static_cast<const uint4 *>(a.rows_lp);
+  const uint4 *frames = static_cast<const uint4 *>(a.q_lp);
+  const int lo = a.n_items[4], hi = a.n_items[0];
+  for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
+    const Item itm = a.items[it];
+    const int row_begin = itm.row_begin, chunk_row = itm.chunk_row;
+    const int nrows = itm.nrows_gq >> 16, gq = itm.nrows_gq & 0xFFFF;
+    __syncthreads();  // the previous item's rows are no longer read
+    for (int e = tid; e < 64 * ROWU4; e += blockDim.x) {
+      const int row = e / ROWU4, c = e - row * ROWU4;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (row < nrows) v = rows[(int64_t)(row_begin + row) * ROWU4 + c];
+      s_rows[row * LDR + c] = v;
+    }
+    if (tid < 64) {
+      s_rn[tid] = tid < nrows ? a.row_n2[row_begin + tid] : 0.f;
+      s_rs[tid] = (FMT == HLOC_FP8 && tid < nrows) ? a.row_scale[row_begin + tid] : 1.f;
+    }
+    __syncthreads();
+    for (int grp = w; grp * kGroup < gq; grp += nw) {
+      const int gs = min(kGroup, gq - grp * kGroup);
+      int fr = 0;
+      int64_t off = 0;
+      if (i < gs) {
+        const int2 e = a.rq[itm.q0 + grp * kGroup + i];
+        fr = e.x;
+        off = (int64_t)e.x * a.cap + e.y + chunk_row;
+      }
+      const uint4 *qp = frames + (int64_t)fr * ROWU4 + g;
+      uint4 bv[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
+      const float qn = a.qn2[fr];
+      const float qs = FMT == HLOC_FP8 ? a.q_scale[fr] : 1.f;
+      for (int rb = 0; rb * 16 < nrows; ++rb) {
+        const uint4 *rp = s_rows + (rb * 16 + i) * LDR + g;
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc = lp_mfma<FMT>(rp[4 * s], bv[s], acc);
+        if (i < gs) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = rb * 16 + 4 * g + r;
+            if (row < nrows) a.cand[off + row] = lp_word<FMT>(qn, s_rn[row], acc[r], qs, s_rs[row]);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int NS>
+size_t wide_lp_lds_bytes() {
+  return (size_t)64 * (4 * NS + 1) * sizeof(uint4);
+}
+
+// Pieces per lane for a padded length: bf16 rows take dp / 32, fp8 rows
+// dp / 64 (0: no kernel for this length).
+int lp_pieces(int32_t fmt, int32_t dp) {
+  const int bytes = fmt == HLOC_BF16 ? 2 * dp : fmt == HLOC_FP8 ? dp : 0;
+  if (bytes <= 0 || bytes % 64 != 0) return 0;
+  switch (bytes / 64) {
+    case 1: case 2: case 3: case 4: case 5: case 6: case 8: case 10: case 12: case 16:
+      return bytes / 64;
+    default:
+      return 0;
+  }
+}
+
+bool lp_screen_supports(int32_t fmt, int32_t dp) { return lp_pieces(fmt, dp) > 0; }
+
+template <int FMT, int NS>
+hipError_t launch_lp_ns(const ScreenArgs &a, int32_t grid, bool wide, hipStream_t s) {
+  if (wide)
+    return launch_kernel(k_screen_wide_lp<FMT, NS>, dim3(grid), dim3(256),
+                         (uint32_t)wide_lp_lds_bytes<NS>(), s, a);
+  return a.dense ? launch_kernel(k_screen_lp<FMT, NS, true>, dim3(grid), dim3(256), 0, s, a)
+                 : launch_kernel(k_screen_lp<FMT, NS, false>, dim3(grid), dim3(256), 0, s, a);
+}
+
+template <int FMT>
+hipError_t launch_lp_fmt(const ScreenArgs &a, int32_t grid, bool wide, hipStream_t s) {
+  switch (lp_pieces(FMT, a.dp)) {
+#define HLOC_LP_CASE(N) \
+  case N:               \
+    return launch_lp_ns<FMT, N>(a, grid, wide, s);
+    HLOC_LP_CASE(1)
+    HLOC_LP_CASE(2)
+    HLOC_LP_CASE(3)
+    HLOC_LP_CASE(4)
+    HLOC_LP_CASE(5)
+    HLOC_LP_CASE(6)
+    HLOC_LP_CASE(8)
+    HLOC_LP_CASE(10)
+    HLOC_LP_CASE(12)
+    HLOC_LP_CASE(16)
+#undef HLOC_LP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_screen_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (a.rows_per_item % 16 != 0) return hipErrorInvalidValue;
+  if (fmt == HLOC_BF16) return launch_lp_fmt<HLOC_BF16>(a, grid, false, s);
+  if (fmt == HLOC_FP8) return launch_lp_fmt<HLOC_FP8>(a, grid, false, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_screen_wide_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipStream_t s) {
+  if (grid <= 0 || a.dense) return hipSuccess;
+  if (a.rows_per_item % 16 != 0 || a.rows_per_item > 64) return hipErrorInvalidValue;
+  if (fmt == HLOC_BF16) return launch_lp_fmt<HLOC_BF16>(a, grid, true, s);
+  if (fmt == HLOC_FP8) return launch_lp_fmt<HLOC_FP8>(a, grid, true, s);
+  return hipErrorInvalidValue;
+}
+
+// LDS limits of the wide kernels (above the 64 KB default).
+hipError_t prepare_screen_lp_kernels() {
+#define HLOC_LP_ATTR(F, N)                                                                 \
+  {                                                                                        \
+    const hipError_t e = hipFuncSetAttribute(                                              \
+        reinterpret_cast<const void *>(&k_screen_wide_lp<F, N>),                           \
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)wide_lp_lds_bytes<N>());          \
+    if (e != hipSuccess) return e;                                                         \
+  }
+#define HLOC_LP_ATTRS(F) \
+  HLOC_LP_ATTR(F, 1)     \
+  HLOC_LP_ATTR(F, 2)     \
+  HLOC_LP_ATTR(F, 3)     \
+  HLOC_LP_ATTR(F, 4)     \
+  HLOC_LP_ATTR(F, 5)     \
+  HLOC_LP_ATTR(F, 6)     \
+  HLOC_LP_ATTR(F, 8)     \
+  HLOC_LP_ATTR(F, 10)    \
+  HLOC_LP_ATTR(F, 12)    \
+  HLOC_LP_ATTR(F, 16)
+  HLOC_LP_ATTRS(HLOC_BF16)
+  HLOC_LP_ATTRS(HLOC_FP8)
+#undef HLOC_LP_ATTRS
+#undef HLOC_LP_ATTR
+  return hipSuccess;
+}
+
+}  // namespace hloc

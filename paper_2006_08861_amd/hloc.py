@@ -28,7 +28,7 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", ESTATE: "ESTATE",
 FP32, BF16, FP8 = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8}
 FLAG_LOW_CONFIDENCE, FLAG_EMPTY, FLAG_BAD_REQUEST = 1, 2, 4
-MIRROR_BF16 = 1
+MIRROR_BF16, MIRROR_FP8 = 1, 2
 
 _lib = None
 

@@ -19,6 +19,7 @@ from paper_2006_08861_amd import hloc, workload
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+MIRRORS = {"fp32": 0, "bf16": hloc.MIRROR_BF16, "fp8": hloc.MIRROR_FP8}
 
 
 def say(*a):
@@ -56,8 +57,7 @@ def check_all(torch, feats, xy, region_of, R, q, k, n_reg, offs=None, agg=(0.5, 
               reps=None, name="", precision="fp32"):
     say(f"[case] {name}: n={len(feats)} d={feats.shape[1]} R={R} nq={len(q)} k={k} "
         f"n_reg={n_reg} screen={precision}")
-    db = make_db(feats, xy, region_of, R, agg, reps,
-                 mirrors=hloc.MIRROR_BF16 if precision == "bf16" else 0)
+    db = make_db(feats, xy, region_of, R, agg, reps, mirrors=MIRRORS[precision])
     offs = np.arange(len(q) + 1) if offs is None else np.asarray(offs)
     out = run_device(torch, db, q, k, n_reg, offs, precision=precision)
     regs = db.last_regions()
@@ -382,46 +382,62 @@ def test_concurrent_workspaces_match_alone(torch_cuda, fp32_shape):
 
 
 # ------------------------------------------------------------- bf16 screen
-def test_bf16_screen_fp32_shape(torch_cuda):
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_lp_screen_fp32_shape(torch_cuda, precision):
     w = workload.make_workload(1)
     st, info, _ = check_all(torch_cuda, w.feats, w.xy, w.region_of, w.n_regions_total, w.q, w.k,
-                            w.n_reg, w.req_offsets, w.agg, name="fp32-200k-d256", precision="bf16")
+                            w.n_reg, w.req_offsets, w.agg, name="fp32-200k-d256",
+                            precision=precision)
     assert st["recall"] == 1.0
 
 
-def test_bf16_screen_multiframe_d512(torch_cuda):
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_lp_screen_multiframe_d512(torch_cuda, precision):
     w = workload.make_workload(3, nq=48, n=20_000)
     st, info, _ = check_all(torch_cuda, w.feats, w.xy, w.region_of, w.n_regions_total, w.q, w.k,
-                            w.n_reg, w.req_offsets, w.agg, name="8-frame d512", precision="bf16")
+                            w.n_reg, w.req_offsets, w.agg, name="8-frame d512",
+                            precision=precision)
     assert st["recall"] == 1.0
 
 
-def test_bf16_screen_ragged_and_duplicates(torch_cuda):
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_lp_screen_ragged_and_duplicates(torch_cuda, precision):
     rng, feats, xy, region_of = _random_db(31, 1500, 37, 40, empty=6)
     q = (feats[rng.integers(0, 1500, 45)] + 0.3 * rng.standard_normal((45, 37))).astype(np.float32)
-    st, _, _ = check_all(torch_cuda, feats, xy, region_of, 40, q, 7, 3, name="d37", precision="bf16")
+    st, _, _ = check_all(torch_cuda, feats, xy, region_of, 40, q, 7, 3, name="d37",
+                         precision=precision)
     assert st["recall"] == 1.0
     dup = rng.choice(1500, 300, replace=False)
     feats[dup] = feats[dup[0]]
     st, info, out = check_all(torch_cuda, feats, xy, region_of, 40, feats[dup[:2]], 10, 40,
-                              name="duplicates", precision="bf16")
+                              name="duplicates", precision=precision)
     assert out["idx"][0].tolist() == sorted(dup.tolist())[:10]
 
 
-def test_bf16_and_fp32_screens_agree_bitwise(torch_cuda):
-    # both screens end in the same certified FP64 rerank: identical results
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_lp_and_fp32_screens_agree_bitwise(torch_cuda, precision):
+    # every screen ends in the same certified FP64 rerank: identical results
     torch = torch_cuda
     w = workload.make_workload(1, nq=128)
-    say("[case] bf16 vs fp32 screen on one database")
-    db = make_db(w.feats, w.xy, w.region_of, w.n_regions_total, w.agg, mirrors=hloc.MIRROR_BF16)
+    say(f"[case] {precision} vs fp32 screen on one database")
+    db = make_db(w.feats, w.xy, w.region_of, w.n_regions_total, w.agg, mirrors=MIRRORS[precision])
     a = run_device(torch, db, w.q, w.k, w.n_reg, precision="fp32")
     regs_a = db.last_regions()
-    b = run_device(torch, db, w.q, w.k, w.n_reg, precision="bf16")
+    b = run_device(torch, db, w.q, w.k, w.n_reg, precision=precision)
     regs_b = db.last_regions()
-    say(f"[ok] bf16 info {db.info()}")
-    np.testing.assert_array_equal(regs_a, regs_b)  # the bf16 coarse stage picks the same regions
+    say(f"[ok] {precision} info {db.info()}")
+    np.testing.assert_array_equal(regs_a, regs_b)  # the low-precision coarse stage agrees
     for key in ("idx", "dist", "tile", "flags", "xy"):
         assert a[key].tobytes() == b[key].tobytes(), key
+    db.close()
+
+
+def test_fp8_needs_a_multiple_of_64(torch_cuda):
+    rng, feats, xy, region_of = _random_db(32, 300, 20, 6)  # padded length 32
+    db = make_db(feats, xy, region_of, 6, mirrors=hloc.MIRROR_FP8)
+    with pytest.raises(hloc.HlocError) as e:
+        run_device(torch_cuda, db, feats[:4], 3, 2, precision="fp8")
+    assert e.value.code == hloc.EUNSUPPORTED
     db.close()
 
 
@@ -440,14 +456,14 @@ def test_many_regions_multi_kernel_schedule(torch_cuda):
     assert st["recall"] == 1.0 and info["items"] > 0
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
 def test_region_kept_by_every_frame(torch_cuda, precision):
     # one large region kept by all 700 frames: 3 groups of up to 256 frames x
     # 47 row chunks of work items expanded from a single region
     rng = np.random.default_rng(22)
     sizes = np.array([3000] + [250] * 12)
     region_of = np.repeat(np.arange(len(sizes)), sizes).astype(np.int32)
-    n, d = len(region_of), 32
+    n, d = len(region_of), 64
     feats = rng.standard_normal((n, d)).astype(np.float32)
     feats[:3000] *= 0.2  # the big region sits near the origin, close to every query,
     feats[3000:] += 0.6  # the others are shifted away from it
