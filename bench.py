@@ -284,6 +284,8 @@ def main():
     ap.add_argument("--workspaces", type=int, default=4,
                     help="batches in flight in the pipelined loop (one workspace and stream each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default fine-screen tiles instead of timing the candidates")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (reference for "
                          "hardware byte counters) and exit")
@@ -352,6 +354,12 @@ def main():
             hloc.PRECISIONS[a.precision],
             P(idx.data_ptr()), P(dist.data_ptr()), P(xy.data_ptr()), P(tile.data_ptr()),
             P(flags.data_ptr()), P(stream.cuda_stream))
+
+    tiles = None
+    if not a.no_autotune:
+        # fine-screen tiles for this shape, timed on the batch itself
+        tiles = db.autotune(q, k, w.n_reg, a.precision, reps=5)
+        log(f"[bench] tiles {tiles}")
 
     def step():
         rc = lib.hloc_query_batch_async(*args)
@@ -451,7 +459,8 @@ def main():
         "config": {"workload": w.name, "n": int(len(w.feats)), "d": int(d),
                    "regions": int(w.n_regions_total), "frames_per_step": int(nq),
                    "requests_per_step": int(nreq), "n_regions": int(w.n_reg), "k": int(k),
-                   "screen": a.precision, "rerank": "f64", "aggregation": list(w.agg)},
+                   "screen": a.precision, "rerank": "f64", "aggregation": list(w.agg),
+                   "tiles": db.tiles()},
         "pipeline": {"workspaces": W, "graphs": True, "value_from": "eager" if wall == wall_eager else "pipelined"},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),

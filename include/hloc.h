@@ -257,6 +257,29 @@ int hloc_profile(hloc_db *db, int32_t enable);
 int hloc_profile_read(hloc_db *db, double *ms, int64_t *calls, int32_t n);
 
 /*
+ * Tiles of the fine screen: rows per work item (a multiple of 16, at most 64;
+ * regions are cut into chunks of this many rows) and blocks per compute unit
+ * of the persistent screen launches (1 .. 32). They change the speed only:
+ * results are the same for every choice. Default 64 and 8.
+ *   hloc_set_tiles / hloc_get_tiles   set or read a database's tiles
+ *                                     (EINVAL out of range or NULL).
+ *   hloc_autotune   times every candidate (rows 16, 32, 48, 64 x blocks 2, 4,
+ *                   8, 16) on a sample batch q (device memory, nq frames) with
+ *                   the given k, n_regions and precision, `reps` timed runs
+ *                   each after one warm-up, keeps the fastest (median time)
+ *                   and writes it to *best and its time to *best_ms.
+ *                   Allocates scratch outputs. Errors: as hloc_query_batch.
+ */
+typedef struct {
+  int32_t rows_per_item;
+  int32_t blocks_per_cu;
+} hloc_tiles;
+int hloc_set_tiles(hloc_db *db, const hloc_tiles *tiles);
+int hloc_get_tiles(hloc_db *db, hloc_tiles *tiles);
+int hloc_autotune(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t n_regions,
+                  int32_t precision, int32_t reps, hloc_tiles *best, double *best_ms);
+
+/*
  * Request server: continuous batching of localization requests (the
  * client/server request model of Section 3.1: a request brings the frames
  * around one position, the server returns each frame's top-N candidates and

@@ -112,13 +112,13 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
   p.kp = std::min(precision == HLOC_FP32 ? k + kOversample : std::max(4 * k, k + kOversample),
                   kMaxSurvivors);  // 4k behind the bf16 and fp8 screens
   p.cap2 = db->h_desc_prefix[p.nr];
-  const int64_t maxch = (db->max_region + kRowsFine - 1) / kRowsFine;
+  const int64_t maxch = (db->max_region + db->tile_rows - 1) / db->tile_rows;
   const int64_t b1 = (int64_t)nq * p.nr * maxch;
   const int64_t b2 = db->chunks_fine * (((int64_t)nq + kItemFrames - 1) / kItemFrames);
   p.items_bound = std::min(b1, b2);
   if (p.items_bound > INT32_MAX || (int64_t)nq * p.cap2 > ((int64_t)1 << 40))
     return fail(HLOC_EINVAL, "batch too large for one call (nq %d)", nq);
-  const int32_t max_blocks = db->num_cu * 8;
+  const int32_t max_blocks = db->num_cu * db->tile_blocks;
   p.grid2 = screen_grid(p.items_bound, db->dp, max_blocks);
   const int64_t dense_items =
       (((int64_t)db->R + kRowsCoarse - 1) / kRowsCoarse) * (((int64_t)nq + kGroup - 1) / kGroup);
@@ -284,7 +284,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   }
   ph.begin(HLOC_PHASE_SCHED);
   int32_t *cand_off = as<int32_t>(ws->cand_off), *n_cand = as<int32_t>(ws->n_cand);
-  HIPCHK(launch_sched(regions, p.nq, p.nr, db->R, db->reg_start, kRowsFine,
+  HIPCHK(launch_sched(regions, p.nq, p.nr, db->R, db->reg_start, db->tile_rows,
                       as<int32_t>(ws->rcount), as<int32_t>(ws->rfill), as<int32_t>(ws->vord),
                       as<int32_t>(ws->rq_off),
                       as<int32_t>(ws->item_off), cand_off, n_cand, misc + 0, as<int2>(ws->rq),
@@ -298,7 +298,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   sb.qn2 = qn2;
   sb.cand = as<uint32_t>(ws->cand2);
   sb.cap = p.cap2;
-  sb.rows_per_item = kRowsFine;
+  sb.rows_per_item = db->tile_rows;
   sb.dense = 0;
   sb.items = as<Item>(ws->items);
   sb.n_items = misc + 0;
@@ -434,6 +434,14 @@ int new_ws(hloc_db *db, hloc_ws **out) {
   }
   *out = ws;
   return HLOC_OK;
+}
+
+// Sum over regions of ceil(size / rows).
+int64_t count_chunks(const hloc_db *db, int32_t rows) {
+  int64_t c = 0;
+  for (size_t r = 0; r + 1 < db->h_reg_start.size(); ++r)
+    c += (db->h_reg_start[r + 1] - db->h_reg_start[r] + rows - 1) / rows;
+  return c;
 }
 
 // Releases a low-precision mirror: the representatives' copy, and with
@@ -696,8 +704,7 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   db->h_desc_prefix.assign(R + 1, 0);
   for (int32_t r = 0; r < R; ++r) db->h_desc_prefix[r + 1] = db->h_desc_prefix[r] + desc[r];
   db->max_region = desc.empty() ? 0 : desc[0];
-  db->chunks_fine = 0;
-  for (int32_t r = 0; r < R; ++r) db->chunks_fine += (sizes[r] + kRowsFine - 1) / kRowsFine;
+  db->chunks_fine = count_chunks(db, db->tile_rows);
   db->has_regions = true;
   return HLOC_OK;
 }
@@ -866,6 +873,85 @@ int hloc_query_batch(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t
     if (flags) HIPCHK(hipMemcpyAsync(flags, ws->s_flags.p, (size_t)nreq * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   }
   HIPCHK(hipStreamSynchronize(s));
+  return HLOC_OK;
+}
+
+int hloc_set_tiles(hloc_db *db, const hloc_tiles *tiles) {
+  if (!db || !tiles) return fail(HLOC_EINVAL, "db and tiles must be non-NULL");
+  const int32_t rows = tiles->rows_per_item, blocks = tiles->blocks_per_cu;
+  if (rows < 16 || rows > kRowsFine || rows % 16 != 0)
+    return fail(HLOC_EINVAL, "rows_per_item must be 16, 32, 48 or 64 (got %d)", rows);
+  if (blocks < 1 || blocks > 32) return fail(HLOC_EINVAL, "blocks_per_cu must be in 1..32");
+  db->tile_rows = rows;
+  db->tile_blocks = blocks;
+  db->chunks_fine = count_chunks(db, rows);
+  return HLOC_OK;
+}
+
+int hloc_get_tiles(hloc_db *db, hloc_tiles *tiles) {
+  if (!db || !tiles) return fail(HLOC_EINVAL, "db and tiles must be non-NULL");
+  tiles->rows_per_item = db->tile_rows;
+  tiles->blocks_per_cu = db->tile_blocks;
+  return HLOC_OK;
+}
+
+int hloc_autotune(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t n_regions,
+                  int32_t precision, int32_t reps, hloc_tiles *best, double *best_ms) {
+  if (!db || !q || !best) return fail(HLOC_EINVAL, "db, q and best must be non-NULL");
+  if (nq < 1 || reps < 1) return fail(HLOC_EINVAL, "nq and reps must be >= 1");
+  Plan p0;
+  CHK(make_plan(db, nq, k, n_regions, nq, precision, &p0));
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  const hloc_tiles start{db->tile_rows, db->tile_blocks};
+  int64_t *idx = nullptr;
+  float *dist = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&](int rc) {
+    if (idx) (void)hipFree(idx);
+    if (dist) (void)hipFree(dist);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc != HLOC_OK) (void)hloc_set_tiles(db, &start);
+    return rc;
+  };
+  if (dev_alloc(&idx, (size_t)nq * k) || dev_alloc(&dist, (size_t)nq * k)) return cleanup(HLOC_ENOMEM);
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return cleanup(fail(HLOC_EDEVICE, "hipEventCreate failed"));
+  hloc_ws *ws = db->ws0;
+  const hipStream_t s = ws->stream;
+  double best_t = HUGE_VAL;
+  hloc_tiles bt = start;
+  std::vector<float> times((size_t)reps);
+  for (int32_t rows : {16, 32, 48, 64}) {
+    for (int32_t blocks : {2, 4, 8, 16}) {
+      const hloc_tiles t{rows, blocks};
+      int rc = hloc_set_tiles(db, &t);
+      Plan p;
+      if (rc == HLOC_OK) rc = make_plan(db, nq, k, n_regions, nq, precision, &p);
+      // warm-up (sizes the workspace), then the timed runs
+      if (rc == HLOC_OK) rc = enqueue_query(ws, p, q, nullptr, nullptr, idx, dist, nullptr, nullptr, nullptr, s);
+      if (rc == HLOC_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(HLOC_EDEVICE, "warm-up failed");
+      for (int32_t r = 0; rc == HLOC_OK && r < reps; ++r) {
+        if (hipEventRecord(e0, s) != hipSuccess) rc = fail(HLOC_EDEVICE, "hipEventRecord failed");
+        if (rc == HLOC_OK)
+          rc = enqueue_query(ws, p, q, nullptr, nullptr, idx, dist, nullptr, nullptr, nullptr, s);
+        if (rc == HLOC_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&times[r], e0, e1) != hipSuccess))
+          rc = fail(HLOC_EDEVICE, "timing failed");
+      }
+      if (rc != HLOC_OK) return cleanup(rc);
+      std::sort(times.begin(), times.end());
+      const double med = times[times.size() / 2];
+      if (med < best_t) {
+        best_t = med;
+        bt = t;
+      }
+    }
+  }
+  CHK(cleanup(hloc_set_tiles(db, &bt)));
+  *best = bt;
+  if (best_ms) *best_ms = best_t;
   return HLOC_OK;
 }
 

@@ -37,6 +37,11 @@ _I32, _I64, _U32, _F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes
 _U64 = ctypes.c_uint64
 
 
+class Tiles(ctypes.Structure):
+    """hloc_tiles."""
+    _fields_ = [("rows_per_item", _I32), ("blocks_per_cu", _I32)]
+
+
 class ServerConfig(ctypes.Structure):
     """hloc_server_config."""
     _fields_ = [("k", _I32), ("n_regions", _I32), ("precision", _I32),
@@ -64,6 +69,10 @@ _SIGNATURES = {
     "hloc_ws_replay": (ctypes.c_int, [_P, _P]),
     "hloc_profile": (ctypes.c_int, [_P, _I32]),
     "hloc_profile_read": (ctypes.c_int, [_P, _P, _P, _I32]),
+    "hloc_set_tiles": (ctypes.c_int, [_P, ctypes.POINTER(Tiles)]),
+    "hloc_get_tiles": (ctypes.c_int, [_P, ctypes.POINTER(Tiles)]),
+    "hloc_autotune": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _I32, _I32, ctypes.POINTER(Tiles),
+                                     ctypes.POINTER(_F64)]),
     "hloc_server_create": (ctypes.c_int, [_P, ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
     "hloc_server_submit": (ctypes.c_int, [_P, _P, _I32, _I32, ctypes.POINTER(_U64)]),
     "hloc_server_wait": (ctypes.c_int, [_P, _U64, _I32, _P, _P, _P, _P, _P,
@@ -235,6 +244,45 @@ class HlocDB:
         out = (ctypes.c_int64 * len(_INFO_KEYS))()
         _check(load_library().hloc_query_info(self._h, out, len(_INFO_KEYS)))
         return dict(zip(_INFO_KEYS, list(out)))
+
+    def set_tiles(self, rows_per_item: int, blocks_per_cu: int):
+        _check(load_library().hloc_set_tiles(self._h, ctypes.byref(Tiles(rows_per_item,
+                                                                          blocks_per_cu))))
+
+    def tiles(self) -> dict:
+        t = Tiles()
+        _check(load_library().hloc_get_tiles(self._h, ctypes.byref(t)))
+        return dict(rows_per_item=t.rows_per_item, blocks_per_cu=t.blocks_per_cu)
+
+    def autotune(self, q, k: int, n_regions: int, precision="fp32", reps: int = 5,
+                 cache: str | None = None) -> dict:
+        """Choose the fine-screen tiles for batches like q (a CUDA tensor):
+        from the JSON cache when it holds this device and shape, else by
+        timing every candidate in the library (hloc_autotune), then stored."""
+        import json
+        import torch
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        key = json.dumps([torch.cuda.get_device_name(q.device), self.n, self.d,
+                          self.n_regions_total, int(q.shape[0]), k, n_regions, prec])
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if key in table:
+            t = table[key]
+            self.set_tiles(t["rows_per_item"], t["blocks_per_cu"])
+            return dict(t, source="cache")
+        best, ms = Tiles(), ctypes.c_double()
+        _check(load_library().hloc_autotune(self._h, ctypes.c_void_p(q.data_ptr()), q.shape[0],
+                                            k, n_regions, prec, reps, ctypes.byref(best),
+                                            ctypes.byref(ms)))
+        t = dict(rows_per_item=best.rows_per_item, blocks_per_cu=best.blocks_per_cu,
+                 batch_ms=ms.value)
+        if cache:
+            table[key] = t
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1)
+        return dict(t, source="tuned")
 
     PHASES = ("prep", "coarse", "sched", "screen", "select", "aggregate", "screen_wide")
 

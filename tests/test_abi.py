@@ -94,6 +94,15 @@ def test_calls_on_null_database():
     assert "NULL" in lib.hloc_last_error().decode()
 
 
+def test_tile_calls_on_null_handles():
+    lib = _lib()
+    t = hloc.Tiles(32, 4)
+    assert lib.hloc_set_tiles(None, ctypes.byref(t)) == hloc.EINVAL
+    assert lib.hloc_get_tiles(None, ctypes.byref(t)) == hloc.EINVAL
+    ms = ctypes.c_double()
+    assert lib.hloc_autotune(None, None, 1, 1, 1, 0, 1, ctypes.byref(t), ctypes.byref(ms)) == hloc.EINVAL
+
+
 def test_server_calls_on_null_handles():
     lib = _lib()
     cfg = hloc.ServerConfig(16, 8, 0, 64, 2, 4096, 0)

@@ -473,3 +473,63 @@ def test_region_kept_by_every_frame(torch_cuda, precision):
                             name="one region kept by 700 frames", precision=precision)
     assert st["recall"] == 1.0
     assert info["items"] >= 3 * 47  # groups of up to 256 frames
+
+
+# ------------------------------------------------------------- tiles and the tuner
+def test_tiles_do_not_change_results(torch_cuda, tmp_path):
+    # the fine-screen tiles change the work items, never the results
+    torch = torch_cuda
+    w = workload.make_workload(1, nq=128)
+    db = make_db(w.feats, w.xy, w.region_of, w.n_regions_total, w.agg)
+    say("[case] results under every tile choice, then the tuner")
+    ref = run_device(torch, db, w.q, w.k, w.n_reg)
+    for rows, blocks in ((16, 2), (32, 16), (48, 4), (64, 8)):
+        db.set_tiles(rows, blocks)
+        assert db.tiles() == dict(rows_per_item=rows, blocks_per_cu=blocks)
+        out = run_device(torch, db, w.q, w.k, w.n_reg)
+        for key in ref:
+            assert out[key].tobytes() == ref[key].tobytes(), (rows, blocks, key)
+    for bad in ((80, 8), (24, 8), (64, 0), (64, 33)):
+        with pytest.raises(hloc.HlocError) as e:
+            db.set_tiles(*bad)
+        assert e.value.code == hloc.EINVAL
+    qd = torch.from_numpy(w.q).to("cuda:0")
+    cache = str(tmp_path / "tiles.json")
+    t1 = db.autotune(qd, w.k, w.n_reg, cache=cache, reps=2)
+    assert t1["source"] == "tuned" and t1["rows_per_item"] in (16, 32, 48, 64)
+    assert db.tiles() == dict(rows_per_item=t1["rows_per_item"], blocks_per_cu=t1["blocks_per_cu"])
+    t2 = db.autotune(qd, w.k, w.n_reg, cache=cache)
+    assert t2["source"] == "cache" and t2["rows_per_item"] == t1["rows_per_item"]
+    out = run_device(torch, db, w.q, w.k, w.n_reg)
+    for key in ref:
+        assert out[key].tobytes() == ref[key].tobytes(), key
+    say(f"[ok] tuner chose {t1}")
+    db.close()
+
+
+@pytest.mark.parametrize("rows", [16, 32])
+def test_wide_items_with_short_chunks(torch_cuda, rows):
+    # the wide kernel stages chunks of fewer than 64 rows too
+    rng = np.random.default_rng(23)
+    sizes = np.array([1000] + [120] * 8)
+    region_of = np.repeat(np.arange(len(sizes)), sizes).astype(np.int32)
+    n, d = len(region_of), 64
+    feats = rng.standard_normal((n, d)).astype(np.float32)
+    feats[:1000] *= 0.2
+    feats[1000:] += 0.6
+    xy = rng.uniform(0, 40, size=(n, 2))
+    q = (feats[rng.integers(0, 1000, 300)] + 0.05 * rng.standard_normal((300, d))).astype(np.float32)
+    say(f"[case] 300 frames on one region, {rows}-row chunks")
+    db = make_db(feats, xy, region_of, len(sizes), mirrors=hloc.MIRROR_BF16)
+    db.set_tiles(rows, 8)
+    for precision in ("fp32", "bf16"):
+        out = run_device(torch_cuda, db, q, 9, 2, precision=precision)
+        regs = db.last_regions()
+        info = db.info()
+        ora = oracle.localize(feats, xy, region_of, len(sizes), q, np.arange(len(q) + 1), 9, 2,
+                              (0.5, 1, 0.0, 0))
+        st = judge_frames(out["idx"], out["dist"], regs, ora, feats, region_of, len(sizes), q, 9)
+        say(f"[ok] {precision}: {st} info={info}")
+        assert st["recall"] == 1.0 and info["items"] > info["narrow_items"]
+    db.close()
+
