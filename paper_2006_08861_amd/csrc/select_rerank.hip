@@ -24,7 +24,7 @@ constexpr int kWordCache = 28672;  // screen words of a frame kept in (dynamic) 
 constexpr int kBigFrame = 4096;    // candidate capacity above which a frame gets 1024 threads
 constexpr int kMaxSlots = 1024;    // region slots of a frame kept in (dynamic) LDS
 constexpr uint32_t kWordNone = 0xFFFFFFFFu;  // no candidate at this position
-constexpr int kDigitBits = 11;     // radix digit of the select (three passes cover 32 bits)
+constexpr int kDigitBits = 12;     // radix digit of the select (two passes cover 24 bits)
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
