@@ -286,6 +286,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default fine-screen tiles instead of timing the candidates")
+    ap.add_argument("--tiles", default=None, metavar="ROWS,BLOCKS",
+                    help="use these fine-screen tiles (rows per item, blocks per CU) untuned")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (reference for "
                          "hardware byte counters) and exit")
@@ -356,7 +358,10 @@ def main():
             P(flags.data_ptr()), P(stream.cuda_stream))
 
     tiles = None
-    if not a.no_autotune:
+    if a.tiles:
+        rows, blocks = (int(v) for v in a.tiles.split(","))
+        db.set_tiles(rows, blocks)
+    elif not a.no_autotune:
         # fine-screen tiles for this shape, timed on the batch itself
         tiles = db.autotune(q, k, w.n_reg, a.precision, reps=5)
         log(f"[bench] tiles {tiles}")

@@ -245,15 +245,19 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     sa.dense = 1;
     sa.nrows = db->R;
     sa.nq = p.nq;
+    // large batches: 64 representatives staged in LDS against 256 frames at a
+    // time (the wide kernels' dense mode) instead of re-reading them per 16
     const bool coarse_lp = fmt && lpm->reps;
+    const bool wide_dense = p.nq >= kWideDenseFrames && (coarse_lp || f32_wide_supports(db->dp));
     if (coarse_lp) {
       sa.rows_lp = lpm->reps;
       sa.q_lp = ws->q_lp.p;
       sa.row_scale = lpm->rep_scale;
       sa.q_scale = as<float>(ws->q_scale);
-      HIPCHK(launch_screen_lp(fmt, sa, p.grid1, s));
+      HIPCHK(wide_dense ? launch_screen_wide_lp(fmt, sa, p.grid1, s)
+                        : launch_screen_lp(fmt, sa, p.grid1, s));
     } else {
-      HIPCHK(launch_screen_f32(sa, p.grid1, s));
+      HIPCHK(wide_dense ? launch_screen_wide_f32(sa, p.grid1, s) : launch_screen_f32(sa, p.grid1, s));
     }
     SelRerankArgs ra{};
     ra.cand = as<uint32_t>(ws->cand1);

@@ -50,6 +50,7 @@ constexpr int kRegionMargin = 8;    // extra regions re-scored in FP64 by the co
 constexpr int kOversample = 16;     // extra rows re-scored in FP64 by the fine stage
 constexpr int kRowsCoarse = 64;     // rows (representatives) per coarse work item
 constexpr int kRowsFine = 64;       // rows per fine work item
+constexpr int kWideDenseFrames = 512;  // batches from which the coarse screen uses the wide kernels
 constexpr double kUnit32 = 5.9604644775390625e-08;  // 2^-24
 
 template <class T>

@@ -87,6 +87,61 @@ struct ScreenArgs {
   const int64_t *reg_start;
 };
 
+// Work item of the wide screens: a chunk of rows against up to kItemFrames
+// frames, either list item it of the narrow-then-wide order, or dense item it
+// (chunk it % nchunks of all rows against frames from (it / nchunks) *
+// kItemFrames).
+struct WideItem {
+  int row_begin, chunk_row, nrows, gq, q0, f0;
+};
+
+// Items [*lo, return value) of a wide screen launch.
+__device__ __forceinline__ int wide_range(const ScreenArgs &a, int *lo) {
+  if (a.dense) {
+    *lo = 0;
+    const int nchunks = (a.nrows + a.rows_per_item - 1) / a.rows_per_item;
+    return nchunks * ((a.nq + kItemFrames - 1) / kItemFrames);
+  }
+  *lo = a.n_items[4];
+  return a.n_items[0];
+}
+
+__device__ __forceinline__ WideItem wide_item(const ScreenArgs &a, int it) {
+  WideItem w;
+  if (a.dense) {
+    const int nchunks = (a.nrows + a.rows_per_item - 1) / a.rows_per_item;
+    const int c = it % nchunks;
+    w.f0 = (it / nchunks) * kItemFrames;
+    w.row_begin = c * a.rows_per_item;
+    w.chunk_row = w.row_begin;
+    w.nrows = min(a.rows_per_item, a.nrows - w.row_begin);
+    w.gq = min(kItemFrames, a.nq - w.f0);
+    w.q0 = 0;
+  } else {
+    const Item itm = a.items[it];
+    w.row_begin = itm.row_begin;
+    w.chunk_row = itm.chunk_row;
+    w.nrows = itm.nrows_gq >> 16;
+    w.gq = itm.nrows_gq & 0xFFFF;
+    w.q0 = itm.q0;
+    w.f0 = 0;
+  }
+  return w;
+}
+
+// Frame j of a wide item (j < gq) and where its screen words go.
+__device__ __forceinline__ void wide_frame(const ScreenArgs &a, const WideItem &w, int j, int *fr,
+                                           int64_t *off) {
+  if (a.dense) {
+    *fr = w.f0 + j;
+    *off = (int64_t)(*fr) * a.cap + w.chunk_row;
+  } else {
+    const int2 e = a.rq[w.q0 + j];
+    *fr = e.x;
+    *off = (int64_t)e.x * a.cap + e.y + w.chunk_row;
+  }
+}
+
 // Padded copy and squared norm of each frame; block 0 also clears zero16[0..16).
 hipError_t launch_prep_queries(const float *q, int32_t nq, int32_t d, int32_t dp, float *qp,
                                float *qn2, int32_t *zero16, hipStream_t s);
@@ -94,6 +149,7 @@ hipError_t launch_prep_queries(const float *q, int32_t nq, int32_t d, int32_t dp
 // kernel exists for the padded length); then the wide list items.
 hipError_t launch_screen_f32(const ScreenArgs &a, int32_t grid, hipStream_t s);
 hipError_t launch_screen_wide_f32(const ScreenArgs &a, int32_t grid, hipStream_t s);
+bool f32_wide_supports(int32_t dp);  // a register wide kernel exists for this padded length
 // Low-precision screens, fmt = HLOC_BF16 or HLOC_FP8.
 hipError_t launch_screen_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipStream_t s);
 hipError_t launch_screen_wide_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipStream_t s);

@@ -255,11 +255,12 @@ __global__ __launch_bounds__(256) void k_screen_wide(ScreenArgs a) {
   __shared__ float s_rn[64];
   const int tid = threadIdx.x, lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
   const int i = lane & 15, g = lane >> 4;
-  const int lo = a.n_items[4], hi = a.n_items[0];
+  int lo;
+  const int hi = wide_range(a, &lo);
   for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
-    const Item itm = a.items[it];
-    const int row_begin = itm.row_begin, chunk_row = itm.chunk_row;
-    const int nrows = itm.nrows_gq >> 16, gq = itm.nrows_gq & 0xFFFF;
+    const WideItem wi = wide_item(a, it);
+    const int row_begin = wi.row_begin;
+    const int nrows = wi.nrows, gq = wi.gq;
     __syncthreads();  // the previous item's rows are no longer read
     for (int e = tid; e < 64 * 4 * NS; e += blockDim.x) {
       const int row = e / (4 * NS), c = e - row * (4 * NS);
@@ -273,11 +274,7 @@ __global__ __launch_bounds__(256) void k_screen_wide(ScreenArgs a) {
       const int gs = min(kGroup, gq - grp * kGroup);
       int fr = 0;
       int64_t off = 0;
-      if (i < gs) {
-        const int2 e = a.rq[itm.q0 + grp * kGroup + i];
-        fr = e.x;
-        off = (int64_t)e.x * a.cap + e.y + chunk_row;
-      }
+      if (i < gs) wide_frame(a, wi, grp * kGroup + i, &fr, &off);
       const float4 *qp = reinterpret_cast<const float4 *>(a.qp + (int64_t)fr * DP) + g;
       float4 bv[NS];
 #pragma unroll
@@ -385,8 +382,12 @@ hipError_t launch_screen_f32(const ScreenArgs &a, int32_t grid, hipStream_t s) {
   return a.dense ? launch_screen_t<true>(a, grid, s) : launch_screen_t<false>(a, grid, s);
 }
 
+bool f32_wide_supports(int32_t dp) {
+  return dp == 32 || dp == 64 || dp == 128 || dp == 256 || dp == 512;
+}
+
 hipError_t launch_screen_wide_f32(const ScreenArgs &a, int32_t grid, hipStream_t s) {
-  if (grid <= 0 || a.dense || a.rows_per_item % 16 != 0) return hipSuccess;
+  if (grid <= 0 || a.rows_per_item % 16 != 0) return hipSuccess;
   if (a.rows_per_item > 64) return hipErrorInvalidValue;  // the LDS stage holds 64 rows
   switch (a.dp) {
     case 32: return launch_wide_t<2>(a, grid, s);

@@ -295,11 +295,12 @@ __global__ __launch_bounds__(256) void k_screen_wide_lp(ScreenArgs a) {
   const int i = lane & 15, g = lane >> 4;
   const uint4 *rows = static_cast<const uint4 *>(a.rows_lp);
   const uint4 *frames = static_cast<const uint4 *>(a.q_lp);
-  const int lo = a.n_items[4], hi = a.n_items[0];
+  int lo;
+  const int hi = wide_range(a, &lo);
   for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
-    const Item itm = a.items[it];
-    const int row_begin = itm.row_begin, chunk_row = itm.chunk_row;
-    const int nrows = itm.nrows_gq >> 16, gq = itm.nrows_gq & 0xFFFF;
+    const WideItem wi = wide_item(a, it);
+    const int row_begin = wi.row_begin;
+    const int nrows = wi.nrows, gq = wi.gq;
     __syncthreads();  // the previous item's rows are no longer read
     for (int e = tid; e < 64 * ROWU4; e += blockDim.x) {
       const int row = e / ROWU4, c = e - row * ROWU4;
@@ -316,11 +317,7 @@ __global__ __launch_bounds__(256) void k_screen_wide_lp(ScreenArgs a) {
       const int gs = min(kGroup, gq - grp * kGroup);
       int fr = 0;
       int64_t off = 0;
-      if (i < gs) {
-        const int2 e = a.rq[itm.q0 + grp * kGroup + i];
-        fr = e.x;
-        off = (int64_t)e.x * a.cap + e.y + chunk_row;
-      }
+      if (i < gs) wide_frame(a, wi, grp * kGroup + i, &fr, &off);
       const uint4 *qp = frames + (int64_t)fr * ROWU4 + g;
       uint4 bv[NS];
 #pragma unroll
@@ -404,7 +401,7 @@ hipError_t launch_screen_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipS
 }
 
 hipError_t launch_screen_wide_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipStream_t s) {
-  if (grid <= 0 || a.dense) return hipSuccess;
+  if (grid <= 0) return hipSuccess;
   if (a.rows_per_item % 16 != 0 || a.rows_per_item > 64) return hipErrorInvalidValue;
   if (fmt == HLOC_BF16) return launch_lp_fmt<HLOC_BF16>(a, grid, true, s);
   if (fmt == HLOC_FP8) return launch_lp_fmt<HLOC_FP8>(a, grid, true, s);
