@@ -1,11 +1,14 @@
 // Top candidates per frame ("select top candidates", Algorithm 1), one block
 // per frame, in one kernel:
-//   1. select: the L + 1 smallest screen words (float bits of the screen
-//      distance, one per candidate position; the bits of a non-negative float
-//      order like its value), ties between equal words going to the smaller
-//      position. The words are cached in LDS; a radix select finds the word of
-//      the (L+1)-th (leading bits shared by the smallest and largest word
-//      skipped, the rest resolved kDigitBits per pass with an LDS histogram);
+//   1. select: the L + 1 smallest (screen word, position) pairs, the word
+//      being the float bits of the screen distance (the bits of a
+//      non-negative float order like its value). The words are cached in
+//      LDS; one histogram of the kDigitBits leading bits below the prefix
+//      shared by the smallest and the largest word finds the bucket of the
+//      (L+1)-th, and the words of that bucket and of all below it (usually a
+//      few more than L + 1) are collected and sorted. If they are too many, a
+//      radix select over kDigitBits per pass finds the (L+1)-th word and the
+//      survivors are gathered in position order;
 //   2. rerank: the positions of the L smallest (the survivors) are mapped to
 //      source rows through the frame's region slots, then FP64 direct sum of
 //      (q_i - d_i)^2, ordered by (distance, tie id) with tie id = original row
@@ -395,23 +398,76 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
   const int L = a.L;
   const int nsurv = min(L, nvalid);
   const bool rejected = nvalid > L;
-  // the (L+1)-th smallest (word, position): its word tw by radix select; the
-  // survivors are every word below tw and the first take_eq positions whose
-  // word equals tw
+  // The L smallest (word, position) pairs become the survivors and the
+  // (L+1)-th, (tw, tpos), the best rejected one: every rejected position has
+  // a word above tw, or tw and a position from tpos on.
   uint32_t tw = kWordNone;
-  int take_eq = 0;
-  if (rejected) {
-    int krem, eq;
-    tw = block_select_u32(word_at, n, vmin, vmax, L + 1, sh, &krem, &eq);
-    take_eq = krem - 1;
-  }
-  const int n_lt = nsurv - take_eq;
-  // each thread takes a contiguous run of positions, so that one block scan
-  // orders both the survivors below tw and the positions equal to tw
+  int tpos = n;
   const int per = (n + blockDim.x - 1) / blockDim.x;
   const int i0 = min(n, tid * per), i1 = min(n, i0 + per);
-  int eq_base;
-  {
+  bool done = false;
+  if (rejected && vmin != vmax) {
+    // one histogram of the leading bits below the prefix shared by all
+    // words; the words of the bucket holding the (L+1)-th and of every
+    // bucket under it are then few: collect and sort them
+    const int pre = __clz(vmin ^ vmax);
+    const int bits = min(kDigitBits, 32 - pre), shift = 32 - pre - bits;
+    const uint32_t mask = (1u << bits) - 1u;
+    for (int t = tid; t < (1 << bits); t += blockDim.x) sh.hist[t] = 0;
+    if (tid == 0) sh.krem = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += blockDim.x) {
+      const uint32_t v = word_at(i);
+      if (v != kWordNone) atomicAdd(&sh.hist[(v >> shift) & mask], 1);
+    }
+    __syncthreads();
+    const int nb = 1 << bits, pb = (nb + blockDim.x - 1) / blockDim.x, b0 = tid * pb;
+    int mine = 0;
+    for (int b = b0; b < min(nb, b0 + pb); ++b) mine += sh.hist[b];
+    const int incl = block_incl_scan(mine, sh.red_i);
+    int excl = incl - mine;
+    if (mine > 0 && excl < L + 1 && L + 1 <= incl) {
+      for (int b = b0; b < min(nb, b0 + pb); ++b) {
+        excl += sh.hist[b];
+        if (excl >= L + 1) {
+          sh.word = (uint32_t)b;
+          sh.eq = excl;  // words in buckets up to b
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t bstar = sh.word;
+    const int m = sh.eq;
+    if (m <= kMaxSurvivors) {
+      for (int i = i0; i < i1; ++i) {
+        const uint32_t v = word_at(i);
+        if (v != kWordNone && ((v >> shift) & mask) <= bstar) {
+          const int slot = atomicAdd(&sh.krem, 1);
+          sh.sort_hi[slot] = v;
+          sh.sort_lo[slot] = (uint32_t)i;
+        }
+      }
+      __syncthreads();
+      sort_pairs(sh, m);  // by (word, position)
+      for (int t = tid; t < L; t += blockDim.x) sh.sel[t] = sh.sort_lo[t];
+      tw = (uint32_t)sh.sort_hi[L];
+      tpos = (int)sh.sort_lo[L];
+      __syncthreads();
+      done = true;
+    }
+  }
+  if (!done) {
+    // radix select of the (L+1)-th word tw, then the survivors in position
+    // order: every word below tw and the first take_eq positions whose word
+    // equals tw (all valid words when none is rejected)
+    int take_eq = 0;
+    if (rejected) {
+      int krem, eq;
+      tw = block_select_u32(word_at, n, vmin, vmax, L + 1, sh, &krem, &eq);
+      take_eq = krem - 1;
+    }
+    const int n_lt = nsurv - take_eq;
     int mlt = 0, meq = 0;
     for (int i = i0; i < i1; ++i) {
       const uint32_t v = word_at(i);
@@ -421,16 +477,18 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
     int ilt = mlt, ieq = meq;
     block_incl_scan2(ilt, ieq, sh.red_i, sh.red_j);
     int plt = ilt - mlt, peq = ieq - meq;
-    eq_base = peq;
     for (int i = i0; i < i1; ++i) {
       const uint32_t v = word_at(i);
       if (v < tw) {
         sh.sel[plt++] = (uint32_t)i;
       } else if (rejected && v == tw) {
         if (peq < take_eq) sh.sel[n_lt + peq] = (uint32_t)i;
+        if (peq == take_eq) sh.krem = i;  // the first rejected position with word tw
         ++peq;
       }
     }
+    __syncthreads();
+    if (rejected) tpos = sh.krem;
     __syncthreads();
   }
   for (int s = tid; s < nsurv; s += blockDim.x)
@@ -471,24 +529,20 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
     // the band: rejected positions (above tw, or equal to tw past the first
     // take_eq) with a word up to tau_w (>= tw)
     const uint32_t tau_w = sh.word;
-    auto in_band = [&](uint32_t v, int &peq) {
-      if (v == tw) return peq++ >= take_eq;
-      return v > tw && v <= tau_w;
+    auto in_band = [&](uint32_t v, int i) {
+      return v == tw ? i >= tpos : (v > tw && v <= tau_w);
     };
     int mine = 0;
-    {
-      int peq = eq_base;
-      for (int i = i0; i < i1; ++i) mine += in_band(word_at(i), peq);
-    }
+    for (int i = i0; i < i1; ++i) mine += in_band(word_at(i), i);
     const int incl = block_incl_scan(mine, sh.red_i);
     __syncthreads();
     if (tid == blockDim.x - 1) sh.krem = incl;
     __syncthreads();
     const int total_band = sh.krem;
     if (nsurv + total_band <= kMaxSurvivors) {
-      int pos = nsurv + incl - mine, peq = eq_base;
+      int pos = nsurv + incl - mine;
       for (int i = i0; i < i1; ++i)
-        if (in_band(word_at(i), peq)) sh.sel[pos++] = (uint32_t)i;
+        if (in_band(word_at(i), i)) sh.sel[pos++] = (uint32_t)i;
       __syncthreads();
       for (int s = nsurv + tid; s < nsurv + total_band; s += blockDim.x)
         sh.srow[s] = row_of(s_off, s_reg, nslots, a.reg_start, sh.sel[s]);
