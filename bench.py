@@ -50,6 +50,8 @@ SCREEN_SOURCES = ("paper_2006_08861_amd/csrc/screen_f32.hip",
                   "paper_2006_08861_amd/csrc/screen_lp.hip",
                   "paper_2006_08861_amd/csrc/hloc_device.h",
                   "paper_2006_08861_amd/csrc/hloc_internal.h")
+# name prefixes of the narrow-item list kernels (their names end in ", false>":
+# not dense) and of the wide-item kernels
 SCREEN_KERNELS = {"fp32": "k_screen_blk<", "bf16": "k_screen_lp<1, ", "fp8": "k_screen_lp<2, "}
 WIDE_KERNELS = {"fp32": "k_screen_wide<", "bf16": "k_screen_wide_lp<1, ", "fp8": "k_screen_wide_lp<2, "}
 MIRRORS = {"fp32": lambda h: 0, "bf16": lambda h: h.MIRROR_BF16, "fp8": lambda h: h.MIRROR_FP8}
@@ -68,21 +70,34 @@ def counters_path(workload: str, precision: str) -> str:
     return os.path.join(ROOT, "profiles", f"counters_screen_{precision}_{workload}.md")
 
 
-def load_traffic(workload: str, precision: str):
+def narrow_label(precision: str, rows_per_item: int) -> str:
+    """The narrow-item kernel's template as it runs with these tiles (the fp32
+    kernel hoists the frame operand for items of more than 64 rows)."""
+    if precision == "fp32":
+        return f"k_screen_blk<NS, {'true' if rows_per_item > 64 else 'false'}, false>"
+    return SCREEN_KERNELS[precision] + "NS, false>"
+
+
+def load_traffic(workload: str, precision: str, rows_per_item: int):
     """HBM bytes per launch of the fine screen from the committed counter
     summary: FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
-    same counter reads for a plain device copy. None when there is no summary
-    for this workload or the screen's sources changed since it was taken."""
+    same counter reads for a plain device copy. The summary holds one record
+    per rows-per-item tile (the work items, hence the re-reads, depend on it).
+    None when there is no record for this workload and tile or the screen's
+    sources changed since it was taken."""
     path = counters_path(workload, precision)
     if not os.path.exists(path):
         return None, "no counter summary for this workload"
-    rec = None
+    recs = []
     with open(path) as f:
         for line in f:
             if line.startswith("record: "):
-                rec = json.loads(line[len("record: "):])
-    if rec is None:
+                recs.append(json.loads(line[len("record: "):]))
+    if not recs:
         return None, f"{os.path.relpath(path, ROOT)} holds no record line"
+    rec = next((r for r in recs if r.get("rows_per_item") == rows_per_item), None)
+    if rec is None:
+        return None, f"no counters taken with {rows_per_item}-row items"
     if rec["sources"] != screen_digest():
         return None, "screen sources changed since the counters were taken"
     b = 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
@@ -109,9 +124,12 @@ def per_dispatch_kib(path: str, name_prefix: str, counter: str,
 def counters_summary(a) -> None:
     """Prints the markdown counter summary of the fine screen (with the record
     line load_traffic reads) from four rocprofv3 --pmc CSVs: the benchmark's
-    FETCH_SIZE and WRITE_SIZE runs and the copy calibration's. The screen is
-    the narrow-item kernel plus the wide-item kernel; their per-dispatch
-    counts are added."""
+    FETCH_SIZE and WRITE_SIZE runs (untuned, with the tiles of --tiles) and the
+    copy calibration's. The screen is the narrow-item kernel plus the
+    wide-item kernel; their per-dispatch counts are added."""
+    if not a.tiles:
+        raise SystemExit("--counters-summary needs --tiles: the tiles the counted runs used")
+    rows = int(a.tiles.split(",")[0])
     fetch_csv, write_csv, cf_csv, cw_csv = a.counters_summary
     narrow = SCREEN_KERNELS[a.precision]
     wide = WIDE_KERNELS[a.precision]
@@ -119,7 +137,8 @@ def counters_summary(a) -> None:
     for name, prefix, suffix in (("narrow", narrow, ", false>"), ("wide", wide, ">")):
         fk, nf = per_dispatch_kib(fetch_csv, prefix, "FETCH_SIZE", suffix)
         wk, nw = per_dispatch_kib(write_csv, prefix, "WRITE_SIZE", suffix)
-        per[name] = (prefix + ("NS, false>" if name == "narrow" else "NS>"), fk, nf, wk, nw)
+        label = narrow_label(a.precision, rows) if name == "narrow" else prefix + "NS>"
+        per[name] = (label, fk, nf, wk, nw)
     copy_bytes = a.copy_mib * (1 << 20)
     copy_kernel = "at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add"
     cfk, _ = per_dispatch_kib(cf_csv, copy_kernel, "FETCH_SIZE")
@@ -130,9 +149,15 @@ def counters_summary(a) -> None:
     wk = sum(v[3] for v in per.values())
     traffic = 1024.0 * (fk * fetch_scale + wk * write_scale)
     rec = dict(kernel=" + ".join(v[0] for v in per.values()), workload=a.workload_name,
-               fetch_kib=round(fk, 1), write_kib=round(wk, 1), fetch_scale=fetch_scale,
-               write_scale=write_scale, sources=screen_digest())
-    print(f"# Fine-screen HBM traffic, {a.precision} screen, {a.workload_name}\n")
+               rows_per_item=rows, tiles=a.tiles, fetch_kib=round(fk, 1), write_kib=round(wk, 1),
+               fetch_scale=fetch_scale, write_scale=write_scale, sources=screen_digest())
+    if a.counters_append:
+        print(f"\n## Tiles {a.tiles} (rows per item, blocks per compute unit)\n")
+    else:
+        print(f"# Fine-screen HBM traffic, {a.precision} screen, {a.workload_name}\n")
+        print("One section per tile choice; the benchmark reads the record line of the "
+              "rows-per-item tile it runs with.\n")
+        print(f"## Tiles {a.tiles} (rows per item, blocks per compute unit)\n")
     print("Commands (from the repository root, one counter per run):\n")
     print("```")
     for c in a.commands:
@@ -297,6 +322,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy size of the calibration CSVs")
     ap.add_argument("--workload-name", default="fp32-200k-d256")
     ap.add_argument("--commands", nargs="*", default=[], help="commands quoted in the summary")
+    ap.add_argument("--counters-append", action="store_true",
+                    help="print only the section of one more tile choice (appended to a summary)")
     ap.add_argument("--serve", type=float, default=0.0, metavar="REQ_PER_S",
                     help="only run the request server under Poisson arrivals at this rate")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -442,7 +469,7 @@ def main():
     if wide_items > 0:
         screen_ms += phases["screen_wide"][0] / max(phases["screen_wide"][1], 1)
     achieved = screen_bytes / (screen_ms * 1e-3) / 1e9
-    traffic, traffic_src = load_traffic(w.name, a.precision)
+    traffic, traffic_src = load_traffic(w.name, a.precision, db.tiles()["rows_per_item"])
     gpu_idx = idx.cpu().numpy()
 
     base, recall, exact, m = (None, None, None, 0)
@@ -473,7 +500,7 @@ def main():
         "recall_at_k": recall,
         "exact_lists": None if base is None else f"{exact}/{m}",
         "roofline": {"bound": "hbm",
-                     "kernel": SCREEN_KERNELS[a.precision] + "NS, false>"
+                     "kernel": narrow_label(a.precision, db.tiles()["rows_per_item"])
                                + (" + wide-item kernel" if wide_items > 0 else ""),
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -257,13 +257,14 @@ int hloc_profile(hloc_db *db, int32_t enable);
 int hloc_profile_read(hloc_db *db, double *ms, int64_t *calls, int32_t n);
 
 /*
- * Tiles of the fine screen: rows per work item (a multiple of 16, at most 64;
- * regions are cut into chunks of this many rows) and blocks per compute unit
- * of the persistent screen launches (1 .. 32). They change the speed only:
- * results are the same for every choice. Default 64 and 8.
+ * Tiles of the fine screen: rows per work item (a multiple of 16, at most 128;
+ * regions are cut into chunks of this many rows, at most 64 for regions kept
+ * by more than 16 frames) and blocks per compute unit of the persistent screen
+ * launches (1 .. 32). They change the speed only: results are the same for
+ * every choice. Default 64 and 8.
  *   hloc_set_tiles / hloc_get_tiles   set or read a database's tiles
  *                                     (EINVAL out of range or NULL).
- *   hloc_autotune   times every candidate (rows 16, 32, 48, 64 x blocks 2, 4,
+ *   hloc_autotune   times every candidate (rows 32, 64, 96, 128 x blocks 4,
  *                   8, 16) on a sample batch q (device memory, nq frames) with
  *                   the given k, n_regions and precision, `reps` timed runs
  *                   each after one warm-up, keeps the fastest (median time)

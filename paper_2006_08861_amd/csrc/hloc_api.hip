@@ -112,7 +112,8 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
   p.kp = std::min(precision == HLOC_FP32 ? k + kOversample : std::max(4 * k, k + kOversample),
                   kMaxSurvivors);  // 4k behind the bf16 and fp8 screens
   p.cap2 = db->h_desc_prefix[p.nr];
-  const int64_t maxch = (db->max_region + db->tile_rows - 1) / db->tile_rows;
+  const int32_t crow = std::min(db->tile_rows, kWideRows);  // the shorter chunks bound the items
+  const int64_t maxch = (db->max_region + crow - 1) / crow;
   const int64_t b1 = (int64_t)nq * p.nr * maxch;
   const int64_t b2 = db->chunks_fine * (((int64_t)nq + kItemFrames - 1) / kItemFrames);
   p.items_bound = std::min(b1, b2);
@@ -708,7 +709,7 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   db->h_desc_prefix.assign(R + 1, 0);
   for (int32_t r = 0; r < R; ++r) db->h_desc_prefix[r + 1] = db->h_desc_prefix[r] + desc[r];
   db->max_region = desc.empty() ? 0 : desc[0];
-  db->chunks_fine = count_chunks(db, db->tile_rows);
+  db->chunks_fine = count_chunks(db, std::min(db->tile_rows, kWideRows));
   db->has_regions = true;
   return HLOC_OK;
 }
@@ -883,12 +884,13 @@ int hloc_query_batch(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t
 int hloc_set_tiles(hloc_db *db, const hloc_tiles *tiles) {
   if (!db || !tiles) return fail(HLOC_EINVAL, "db and tiles must be non-NULL");
   const int32_t rows = tiles->rows_per_item, blocks = tiles->blocks_per_cu;
-  if (rows < 16 || rows > kRowsFine || rows % 16 != 0)
-    return fail(HLOC_EINVAL, "rows_per_item must be 16, 32, 48 or 64 (got %d)", rows);
+  if (rows < 16 || rows > kMaxItemRows || rows % 16 != 0)
+    return fail(HLOC_EINVAL, "rows_per_item must be a multiple of 16 in 16..%d (got %d)",
+                kMaxItemRows, rows);
   if (blocks < 1 || blocks > 32) return fail(HLOC_EINVAL, "blocks_per_cu must be in 1..32");
   db->tile_rows = rows;
   db->tile_blocks = blocks;
-  db->chunks_fine = count_chunks(db, rows);
+  db->chunks_fine = count_chunks(db, std::min(rows, kWideRows));
   return HLOC_OK;
 }
 
@@ -927,8 +929,8 @@ int hloc_autotune(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t n_
   double best_t = HUGE_VAL;
   hloc_tiles bt = start;
   std::vector<float> times((size_t)reps);
-  for (int32_t rows : {16, 32, 48, 64}) {
-    for (int32_t blocks : {2, 4, 8, 16}) {
+  for (int32_t rows : {32, 64, 96, 128}) {
+    for (int32_t blocks : {4, 8, 16}) {
       const hloc_tiles t{rows, blocks};
       int rc = hloc_set_tiles(db, &t);
       Plan p;

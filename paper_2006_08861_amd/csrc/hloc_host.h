@@ -124,8 +124,8 @@ struct hloc_db {
   int64_t *reg_start = nullptr;
   std::vector<int64_t> h_reg_start;
   std::vector<int64_t> h_desc_prefix;  // sum of the j largest region sizes, j = 0..R
-  int64_t chunks_fine = 0;             // sum over regions of ceil(size / tile_rows)
-  int32_t tile_rows = hloc::kRowsFine; // rows per fine work item (multiple of 16, <= 64)
+  int64_t chunks_fine = 0;             // sum over regions of ceil(size / min(tile_rows, 64))
+  int32_t tile_rows = hloc::kRowsFine; // rows per narrow fine work item (multiple of 16, <= 128)
   int32_t tile_blocks = 8;             // blocks per compute unit of the screen launches
   int32_t *nonempty_ids = nullptr;
   double *rep64 = nullptr;

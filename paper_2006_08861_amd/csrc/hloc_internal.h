@@ -40,6 +40,8 @@ inline hipError_t launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t lds, h
 
 constexpr int kGroup = 16;          // frames per MFMA column block of the screen
 constexpr int kItemFrames = 256;    // frames per screen work item (wide items)
+constexpr int kWideRows = 64;       // rows per wide work item (the LDS stage of the wide kernels)
+constexpr int kMaxItemRows = 128;   // rows per narrow work item at most
 constexpr int kBlock = 256;         // threads per block of most kernels
 constexpr int kSelectLds = 4096;    // keys held in LDS by the select kernel
 constexpr uint64_t kKeyNone = ~0ull;  // empty slot / no candidate

@@ -1,7 +1,7 @@
 // Scheduling of the fine screen: the frame -> regions lists chosen by the
 // coarse stage are inverted into region -> frames lists, and every touched
-// region is cut into chunks of T rows crossed with groups of up to
-// kItemFrames frames. This takes the place of the paper's
+// region is cut into chunks of T rows (at most kWideRows for wide regions)
+// crossed with groups of up to kItemFrames frames. This takes the place of the paper's
 // one-stream-per-subspace launch (Section 3.1): uneven regions become many
 // equal-sized work items for persistent screen kernels, and every count lives
 // in device memory (no host round trip).
@@ -45,8 +45,15 @@ __device__ __forceinline__ int owner_slot(const int32_t *iof, int R, int t) {
   return lo;
 }
 
+// Rows per chunk of a region kept by g frames: T for narrow regions, at most
+// kWideRows (the wide kernels' LDS stage) for wide ones.
+__device__ __forceinline__ int chunk_rows(int g, int T) {
+  return g <= kGroup ? T : min(T, kWideRows);
+}
+
 __device__ __forceinline__ int items_of(int g, int64_t rows, int T) {
-  return g > 0 ? (int)((rows + T - 1) / T) * ((g + kItemFrames - 1) / kItemFrames) : 0;
+  const int C = chunk_rows(g, T);
+  return g > 0 ? (int)((rows + C - 1) / C) * ((g + kItemFrames - 1) / kItemFrames) : 0;
 }
 
 // Work item t of region r, whose frames are rq[q_begin, q_end): chunk-major,
@@ -54,14 +61,15 @@ __device__ __forceinline__ int items_of(int g, int64_t rows, int T) {
 __device__ __forceinline__ Item make_item(int t, int r, int item_begin, int q_begin, int q_end,
                                           const int64_t *__restrict__ reg_start, int T) {
   const int g = q_end - q_begin, ngr = (g + kItemFrames - 1) / kItemFrames;
+  const int C = chunk_rows(g, T);
   const int local = t - item_begin, c = local / ngr, b = local - c * ngr;
   const int64_t r0 = reg_start[r];
   const int rows = (int)(reg_start[r + 1] - r0);
   Item it;
-  it.row_begin = (int32_t)r0 + c * T;
-  it.chunk_row = c * T;
+  it.row_begin = (int32_t)r0 + c * C;
+  it.chunk_row = c * C;
   it.q0 = q_begin + b * kItemFrames;
-  it.nrows_gq = (min(T, rows - c * T) << 16) | min(kItemFrames, g - b * kItemFrames);
+  it.nrows_gq = (min(C, rows - c * C) << 16) | min(kItemFrames, g - b * kItemFrames);
   return it;
 }
 

@@ -157,11 +157,13 @@ __global__ __launch_bounds__(256) void k_screen_f32(ScreenArgs a) {
 }
 
 // Register variant for padded lengths up to 512, dense items and narrow list
-// items (at most kGroup frames): one item per block, one 16-row block per
-// wave, no LDS and no barriers. Each wave keeps the frame operand of the MFMA
-// in registers (lane l holds frame l % 16's k-slice); its row loads, frame
-// loads and norms go out together once the item's frame list has been read.
-template <int NS, bool DENSE>
+// items (at most kGroup frames): one item per block, 16-row blocks dealt to
+// its waves, no LDS and no barriers. Each wave keeps the frame operand of the
+// MFMA in registers (lane l holds frame l % 16's k-slice); its row loads,
+// frame loads and norms go out together once the item's frame list has been
+// read. HOIST (items of more than 64 rows: several row blocks per wave) loads
+// the frame operand once per item instead of once per row block.
+template <int NS, bool HOIST, bool DENSE>
 __global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
   constexpr int DP = NS * 16;
   const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
@@ -199,16 +201,25 @@ __global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
     }
     if (i >= gq) fr = 0;
     const int nrb = (nrows + 15) >> 4;
+    const float4 *qp = reinterpret_cast<const float4 *>(a.qp + (int64_t)fr * DP) + g;
+    // with several row blocks per wave (HOIST: items longer than 64 rows) the
+    // frame operand is loaded once per item; otherwise beside each row block
+    float4 bv[NS];
+    if (HOIST && w < nrb) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
+    }
     for (int rb = w; rb < nrb; rb += nw) {
       const int rl = min(rb * 16 + i, nrows - 1);
       const float4 *rp =
           reinterpret_cast<const float4 *>(a.rows + (int64_t)(row_begin + rl) * DP) + g;
-      const float4 *qp = reinterpret_cast<const float4 *>(a.qp + (int64_t)fr * DP) + g;
-      float4 av[NS], bv[NS];
+      float4 av[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) av[s] = rp[4 * s];
+      if (!HOIST) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
+        for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
+      }
       const float qn = a.qn2[fr];
       v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -325,7 +336,9 @@ hipError_t launch_wide_t(const ScreenArgs &a, int32_t grid, hipStream_t s) {
 
 template <int NS, bool DENSE>
 hipError_t launch_blk_t(const ScreenArgs &a, int32_t grid, hipStream_t s) {
-  return launch_kernel(k_screen_blk<NS, DENSE>, dim3(grid), dim3(256), 0, s, a);
+  if (a.rows_per_item > 64)
+    return launch_kernel(k_screen_blk<NS, true, DENSE>, dim3(grid), dim3(256), 0, s, a);
+  return launch_kernel(k_screen_blk<NS, false, DENSE>, dim3(grid), dim3(256), 0, s, a);
 }
 
 template <bool DENSE>
@@ -388,7 +401,9 @@ bool f32_wide_supports(int32_t dp) {
 
 hipError_t launch_screen_wide_f32(const ScreenArgs &a, int32_t grid, hipStream_t s) {
   if (grid <= 0 || a.rows_per_item % 16 != 0) return hipSuccess;
-  if (a.rows_per_item > 64) return hipErrorInvalidValue;  // the LDS stage holds 64 rows
+  // list items of wide regions hold at most kWideRows rows (the LDS stage);
+  // dense items hold rows_per_item
+  if (a.dense && a.rows_per_item > kWideRows) return hipErrorInvalidValue;
   switch (a.dp) {
     case 32: return launch_wide_t<2>(a, grid, s);
     case 64: return launch_wide_t<4>(a, grid, s);

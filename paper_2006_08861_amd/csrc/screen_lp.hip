@@ -402,7 +402,8 @@ hipError_t launch_screen_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipS
 
 hipError_t launch_screen_wide_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  if (a.rows_per_item % 16 != 0 || a.rows_per_item > 64) return hipErrorInvalidValue;
+  if (a.rows_per_item % 16 != 0 || (a.dense && a.rows_per_item > kWideRows))
+    return hipErrorInvalidValue;
   if (fmt == HLOC_BF16) return launch_lp_fmt<HLOC_BF16>(a, grid, true, s);
   if (fmt == HLOC_FP8) return launch_lp_fmt<HLOC_FP8>(a, grid, true, s);
   return hipErrorInvalidValue;

@@ -39,15 +39,25 @@ def _csv(path, rows):
 
 
 def test_counter_summary_round_trip(tmp_path, monkeypatch, capsys):
-    narrow = "void hloc::k_screen_blk<16, false>(hloc::ScreenArgs)"
+    # one record per rows-per-item tile; the dense (coarse) dispatches of the
+    # same template are not counted
+    narrow = "void hloc::k_screen_blk<16, false, false>(hloc::ScreenArgs)"
+    hoist = "void hloc::k_screen_blk<16, true, false>(hloc::ScreenArgs)"
+    dense = "void hloc::k_screen_blk<16, false, true>(hloc::ScreenArgs)"
     wide = "void hloc::k_screen_wide<16>(hloc::ScreenArgs)"
     copy = ("void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add"
             "<float>, std::array<char*, 2ul> >(int)")
     _csv(tmp_path / "f.csv", [dict(Kernel_Name=narrow, Counter_Name="FETCH_SIZE", Counter_Value=100),
                               dict(Kernel_Name=narrow, Counter_Name="FETCH_SIZE", Counter_Value=300),
+                              dict(Kernel_Name=dense, Counter_Name="FETCH_SIZE", Counter_Value=9000),
                               dict(Kernel_Name=wide, Counter_Name="FETCH_SIZE", Counter_Value=10)])
     _csv(tmp_path / "w.csv", [dict(Kernel_Name=narrow, Counter_Name="WRITE_SIZE", Counter_Value=8),
+                              dict(Kernel_Name=dense, Counter_Name="WRITE_SIZE", Counter_Value=900),
                               dict(Kernel_Name=wide, Counter_Name="WRITE_SIZE", Counter_Value=2)])
+    _csv(tmp_path / "f2.csv", [dict(Kernel_Name=hoist, Counter_Name="FETCH_SIZE", Counter_Value=150),
+                               dict(Kernel_Name=wide, Counter_Name="FETCH_SIZE", Counter_Value=10)])
+    _csv(tmp_path / "w2.csv", [dict(Kernel_Name=hoist, Counter_Name="WRITE_SIZE", Counter_Value=6),
+                               dict(Kernel_Name=wide, Counter_Name="WRITE_SIZE", Counter_Value=2)])
     _csv(tmp_path / "cf.csv", [dict(Kernel_Name=copy, Counter_Name="FETCH_SIZE", Counter_Value=512)])
     _csv(tmp_path / "cw.csv", [dict(Kernel_Name=copy, Counter_Name="WRITE_SIZE", Counter_Value=1024)])
 
@@ -57,20 +67,33 @@ def test_counter_summary_round_trip(tmp_path, monkeypatch, capsys):
         copy_mib = 1
         workload_name = "unit"
         commands = ["cmd"]
+        tiles = "64,16"
+        counters_append = False
 
     bench.counters_summary(A)
+    A.counters_summary = [str(tmp_path / n) for n in ("f2.csv", "w2.csv", "cf.csv", "cw.csv")]
+    A.tiles, A.counters_append = "128,4", True
+    bench.counters_summary(A)
     text = capsys.readouterr().out
-    rec = json.loads(text.split("record: ")[1])
+    recs = [json.loads(line[len("record: "):]) for line in text.splitlines()
+            if line.startswith("record: ")]
+    assert [r["rows_per_item"] for r in recs] == [64, 128]
+    assert "k_screen_blk<NS, true, false>" in recs[1]["kernel"]
     # narrow mean 200 KiB + wide 10 KiB fetched, scaled by 1 MiB / 512 KiB = 2
-    assert rec["fetch_kib"] == 210.0 and rec["fetch_scale"] == 2.0
-    assert rec["write_kib"] == 10.0 and rec["write_scale"] == 1.0
+    assert recs[0]["fetch_kib"] == 210.0 and recs[0]["fetch_scale"] == 2.0
+    assert recs[0]["write_kib"] == 10.0 and recs[0]["write_scale"] == 1.0
+    assert recs[1]["fetch_kib"] == 160.0 and recs[1]["write_kib"] == 8.0
     prof = tmp_path / "profiles"
     prof.mkdir()
     (prof / "counters_screen_fp32_unit.md").write_text(text)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "screen_digest", lambda: rec["sources"])
-    b, src = bench.load_traffic("unit", "fp32")
+    monkeypatch.setattr(bench, "screen_digest", lambda: recs[0]["sources"])
+    b, src = bench.load_traffic("unit", "fp32", 64)
     assert b == 1024.0 * (210.0 * 2.0 + 10.0 * 1.0)
+    b, src = bench.load_traffic("unit", "fp32", 128)
+    assert b == 1024.0 * (160.0 * 2.0 + 8.0 * 1.0)
+    b, src = bench.load_traffic("unit", "fp32", 32)
+    assert b is None and "32-row" in src
     monkeypatch.setattr(bench, "screen_digest", lambda: "changed")
-    b, src = bench.load_traffic("unit", "fp32")
+    b, src = bench.load_traffic("unit", "fp32", 64)
     assert b is None and "changed" in src

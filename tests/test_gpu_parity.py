@@ -483,20 +483,20 @@ def test_tiles_do_not_change_results(torch_cuda, tmp_path):
     db = make_db(w.feats, w.xy, w.region_of, w.n_regions_total, w.agg)
     say("[case] results under every tile choice, then the tuner")
     ref = run_device(torch, db, w.q, w.k, w.n_reg)
-    for rows, blocks in ((16, 2), (32, 16), (48, 4), (64, 8)):
+    for rows, blocks in ((16, 2), (32, 16), (48, 4), (64, 8), (96, 8), (128, 16)):
         db.set_tiles(rows, blocks)
         assert db.tiles() == dict(rows_per_item=rows, blocks_per_cu=blocks)
         out = run_device(torch, db, w.q, w.k, w.n_reg)
         for key in ref:
             assert out[key].tobytes() == ref[key].tobytes(), (rows, blocks, key)
-    for bad in ((80, 8), (24, 8), (64, 0), (64, 33)):
+    for bad in ((144, 8), (24, 8), (0, 8), (64, 0), (64, 33)):
         with pytest.raises(hloc.HlocError) as e:
             db.set_tiles(*bad)
         assert e.value.code == hloc.EINVAL
     qd = torch.from_numpy(w.q).to("cuda:0")
     cache = str(tmp_path / "tiles.json")
     t1 = db.autotune(qd, w.k, w.n_reg, cache=cache, reps=2)
-    assert t1["source"] == "tuned" and t1["rows_per_item"] in (16, 32, 48, 64)
+    assert t1["source"] == "tuned" and t1["rows_per_item"] in (32, 64, 96, 128)
     assert db.tiles() == dict(rows_per_item=t1["rows_per_item"], blocks_per_cu=t1["blocks_per_cu"])
     t2 = db.autotune(qd, w.k, w.n_reg, cache=cache)
     assert t2["source"] == "cache" and t2["rows_per_item"] == t1["rows_per_item"]
@@ -507,9 +507,10 @@ def test_tiles_do_not_change_results(torch_cuda, tmp_path):
     db.close()
 
 
-@pytest.mark.parametrize("rows", [16, 32])
+@pytest.mark.parametrize("rows", [16, 32, 128])
 def test_wide_items_with_short_chunks(torch_cuda, rows):
-    # the wide kernel stages chunks of fewer than 64 rows too
+    # the wide kernel stages chunks of fewer than 64 rows too; with 128-row
+    # tiles the narrow items take 128 rows and the wide ones 64
     rng = np.random.default_rng(23)
     sizes = np.array([1000] + [120] * 8)
     region_of = np.repeat(np.arange(len(sizes)), sizes).astype(np.int32)
