@@ -149,6 +149,7 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *byte
   CHK(fit(ws->rq_off, (size_t)(db->R + 1) * sizeof(int32_t)));
   CHK(fit(ws->item_off, (size_t)(db->R + 1) * sizeof(int32_t)));
   CHK(fit(ws->cand_off, (size_t)nq * nr * sizeof(int32_t)));
+  CHK(fit(ws->slot_row, (size_t)nq * nr * sizeof(int32_t)));
   CHK(fit(ws->n_cand, (size_t)nq * sizeof(int32_t)));
   CHK(fit(ws->misc, 16 * sizeof(int32_t)));
   CHK(fit(ws->rq, (size_t)nq * nr * sizeof(int2)));
@@ -292,8 +293,8 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   HIPCHK(launch_sched(regions, p.nq, p.nr, db->R, db->reg_start, db->tile_rows,
                       as<int32_t>(ws->rcount), as<int32_t>(ws->rfill), as<int32_t>(ws->vord),
                       as<int32_t>(ws->rq_off),
-                      as<int32_t>(ws->item_off), cand_off, n_cand, misc + 0, as<int2>(ws->rq),
-                      as<Item>(ws->items), s));
+                      as<int32_t>(ws->item_off), cand_off, as<int32_t>(ws->slot_row), n_cand,
+                      misc + 0, as<int2>(ws->rq), as<Item>(ws->items), s));
   ph.begin(HLOC_PHASE_SCREEN);
   ScreenArgs sb{};
   sb.rows = db->rows;
@@ -327,8 +328,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   // is the row itself
   rb.nslots = p.exhaustive ? 0 : p.nr;
   rb.slot_off = cand_off;
-  rb.slot_reg = regions;
-  rb.reg_start = db->reg_start;
+  rb.slot_row = as<int32_t>(ws->slot_row);
   rb.n_cand = n_cand;
   rb.L = p.kp;
   rb.m = p.k;
@@ -422,7 +422,7 @@ void free_ws(hloc_ws *ws) {
                    &ws->misc,     &ws->rq,       &ws->items,    &ws->cand2,   &ws->agg_xy,
                    &ws->agg_tile, &ws->agg_flags, &ws->s_q,     &ws->s_off,   &ws->s_idx,
                    &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags, &ws->q_lp,
-                   &ws->q_scale,  &ws->q_err,    &ws->q_lon};
+                   &ws->q_scale,  &ws->q_err,    &ws->q_lon,   &ws->slot_row};
   for (WsBuf *b : bufs) free_buf(*b);
   for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
   if (ws->stream) (void)hipStreamDestroy(ws->stream);

@@ -176,23 +176,23 @@ hipError_t launch_broadcast_ids(const int32_t *ids, int32_t nr, int32_t nq, int3
 hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t R,
                         const int64_t *reg_start, int32_t T, int32_t *rcount, int32_t *rfill,
                         int32_t *vord, int32_t *rq_off, int32_t *item_off, int32_t *cand_off,
-                        int32_t *n_cand, int32_t *n_items, int2 *rq, Item *items,
-                        hipStream_t s);
+                        int32_t *slot_row, int32_t *n_cand, int32_t *n_items, int2 *rq,
+                        Item *items, hipStream_t s);
 
 // Per frame: the L + 1 smallest screen words of cand[f][0 .. n(f)) (n(f) =
 // n_cand ? n_cand[f] : n_fixed; 0xFFFFFFFF entries are skipped; equal words
 // ordered by position), FP64 rerank of the L smallest, top m by (distance,
 // tie id), certificate against the (L + 1)-th, and the exact FP64 pass over
 // all candidates when it fails. Candidate positions map to source rows through
-// the frame's region slots (slot j: region slot_reg[f][j] from position
-// slot_off[f][j]), or are the rows themselves when nslots is 0.
+// the frame's region slots (slot j: the rows from slot_row[f][j] on, at
+// positions from slot_off[f][j] on), or are the rows themselves when nslots
+// is 0.
 struct SelRerankArgs {
   const uint32_t *cand;
   int64_t cap;
   const int32_t *slot_off;   // nq x nslots
-  const int32_t *slot_reg;   // nq x nslots
+  const int32_t *slot_row;   // nq x nslots
   int32_t nslots;            // <= 1024
-  const int64_t *reg_start;  // first row of each region
   int32_t cache;             // words kept in LDS (set by the launcher)
   const int32_t *n_cand;
   int32_t n_fixed;

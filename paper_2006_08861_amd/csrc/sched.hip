@@ -167,18 +167,22 @@ hipError_t launch_broadcast_ids(const int32_t *ids, int32_t nr, int32_t nq, int3
 }
 
 // Multi-kernel schedule for large region counts. Per frame: offset of each
-// kept region in the frame's candidate list, and the list length. Per region:
-// how many frames kept it.
+// kept region in the frame's candidate list and its first row, and the list
+// length. Per region: how many frames kept it.
 __global__ void k_sched_count(const int32_t *__restrict__ regions, int nq, int nr, int R,
                               const int64_t *__restrict__ reg_start, int32_t *rcount,
-                              int32_t *cand_off, int32_t *n_cand) {
+                              int32_t *cand_off, int32_t *slot_row, int32_t *n_cand) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nq) return;
   int off = 0;
   for (int j = 0; j < nr; ++j) {
     const int r = regions[(int64_t)f * nr + j];
     cand_off[(int64_t)f * nr + j] = off;
-    if (r < 0 || r >= R) continue;
+    if (r < 0 || r >= R) {
+      slot_row[(int64_t)f * nr + j] = 0;
+      continue;
+    }
+    slot_row[(int64_t)f * nr + j] = (int32_t)reg_start[r];
     off += (int)(reg_start[r + 1] - reg_start[r]);
     atomicAdd(&rcount[r], 1);
   }
@@ -236,8 +240,8 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
                                                       int nr, int R,
                                                       const int64_t *__restrict__ reg_start, int T,
                                                       int32_t *rq_off, int32_t *cand_off,
-                                                      int32_t *n_cand, int32_t *n_items, int2 *rq,
-                                                      Item *items) {
+                                                      int32_t *slot_row, int32_t *n_cand,
+                                                      int32_t *n_items, int2 *rq, Item *items) {
   extern __shared__ int s_mem[];
   int *s_fill = s_mem;         // R: frame counts, then fill pointers
   int *s_vord = s_mem + R;     // R: regions in narrow-then-wide order
@@ -250,19 +254,22 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
     int off = 0;
     for (int j0 = 0; j0 < nr; j0 += 8) {
       // ids, then sizes, then updates: eight loads in flight per step
-      int r[8], sz[8];
+      int r[8], sz[8], r0[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         r[u] = j0 + u < nr ? regions[(int64_t)f * nr + j0 + u] : -1;
         if (r[u] >= R) r[u] = -1;
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        sz[u] = r[u] >= 0 ? (int)(reg_start[r[u] + 1] - reg_start[r[u]]) : 0;
+      for (int u = 0; u < 8; ++u) {
+        r0[u] = r[u] >= 0 ? (int)reg_start[r[u]] : 0;
+        sz[u] = r[u] >= 0 ? (int)(reg_start[r[u] + 1] - r0[u]) : 0;
+      }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         if (j0 + u >= nr) break;
         cand_off[(int64_t)f * nr + j0 + u] = off;
+        slot_row[(int64_t)f * nr + j0 + u] = r0[u];
         off += sz[u];
         if (r[u] >= 0) atomicAdd(&s_fill[r[u]], 1);
       }
@@ -298,19 +305,19 @@ hipError_t prepare_sched_kernels() {
 hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t R,
                         const int64_t *reg_start, int32_t T, int32_t *rcount, int32_t *rfill,
                         int32_t *vord, int32_t *rq_off, int32_t *item_off, int32_t *cand_off,
-                        int32_t *n_cand, int32_t *n_items, int2 *rq, Item *items,
-                        hipStream_t s) {
+                        int32_t *slot_row, int32_t *n_cand, int32_t *n_items, int2 *rq,
+                        Item *items, hipStream_t s) {
   const int64_t pairs = (int64_t)nq * nr;
   if (R <= kFusedMaxR && pairs <= kFusedMaxPairs) {
     return launch_kernel(k_sched_fused, dim3(1), dim3(1024), (uint32_t)fused_lds_bytes(R), s,
-                         regions, nq, nr, R, reg_start, T, rq_off, cand_off, n_cand, n_items, rq,
-                         items);
+                         regions, nq, nr, R, reg_start, T, rq_off, cand_off, slot_row, n_cand,
+                         n_items, rq, items);
   }
   hipError_t e = launch_fill_i32(rcount, R, 0, s);
   if (e != hipSuccess) return e;
   if (nq > 0) {
     if ((e = launch_kernel(k_sched_count, dim3((nq + 255) / 256), dim3(256), 0, s, regions, nq,
-                           nr, R, reg_start, rcount, cand_off, n_cand)) != hipSuccess)
+                           nr, R, reg_start, rcount, cand_off, slot_row, n_cand)) != hipSuccess)
       return e;
   }
   if ((e = launch_kernel(k_sched_scan, dim3(1), dim3(1024), 0, s, rcount, R, reg_start, T,

@@ -42,22 +42,6 @@ __device__ __forceinline__ int wave_sum_i32(int v) {
   return v;
 }
 
-// FP64 squared distance of the padded fp32 frame to an FP64 source row, one
-// wave; each lane sums its slice in order, then a fixed butterfly.
-__device__ __forceinline__ double wave_dist_f64(const double *__restrict__ rp,
-                                                const float *__restrict__ qrow, int dp) {
-  const int lane = lane_id();
-  double acc = 0.0;
-  for (int c = lane * 2; c < dp; c += 128) {
-    const double2 x = *reinterpret_cast<const double2 *>(rp + c);
-    const float2 y = *reinterpret_cast<const float2 *>(qrow + c);
-    double t;
-    t = (double)y.x - x.x; acc = fma(t, t, acc);
-    t = (double)y.y - x.y; acc = fma(t, t, acc);
-  }
-  return wave_sum_f64(acc);
-}
-
 // Sequential FP64 distance of one row (one thread; used by the fallback).
 __device__ __forceinline__ double thread_dist(const SelRerankArgs &a, const float *qrow,
                                               uint32_t row) {
@@ -83,11 +67,12 @@ struct SelShared {
   uint32_t srow[kMaxSurvivors];     // their source rows
   uint64_t sort_hi[kMaxSurvivors];
   uint32_t sort_lo[kMaxSurvivors];
-  int hist[1 << kDigitBits];
+  alignas(16) int hist[1 << kDigitBits];
   int red_i[16];
   int red_j[16];
   uint32_t red_u[16];
   uint32_t red_v[16];
+  uint64_t red_k[16];
   uint32_t word;
   int krem;
   int eq;
@@ -199,119 +184,180 @@ __device__ uint32_t block_select_u32(Get get, int n, uint32_t lo, uint32_t hi, i
   return prefix;
 }
 
-// Ascending bitonic sort of 64 (hi, lo) pairs, one per lane, by shuffles.
-__device__ __forceinline__ void wave_sort64_pairs(uint64_t &hi, uint32_t &lo) {
-  const int lane = lane_id();
-  for (int size = 2; size <= 64; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      const uint64_t ohi = (uint64_t)__shfl_xor((long long)hi, stride);
-      const uint32_t olo = (uint32_t)__shfl_xor((int)lo, stride);
-      const bool up = (lane & size) == 0;
-      const bool lower = (lane & stride) == 0;
-      const bool other_less = ohi < hi || (ohi == hi && olo < lo);
-      const bool take = (lower == up) ? other_less : !other_less;
-      if (take) {
-        hi = ohi;
-        lo = olo;
-      }
-    }
+constexpr int kRowBatch = 8;    // survivor rows fetched together by one wave
+constexpr int kEarlyKeys = 2048;  // keys requested before the count is known
+constexpr int kRankSort = 256;  // entries up to which sort_pairs ranks instead of merging
+constexpr int kCollectRounds = 8;  // positions per lane held in registers by the collect
+
+// Sums over the wave of kRowBatch (8) values per lane at once: three halving
+// exchanges (lanes 32 apart swap half of their values, then 16, then 8 apart)
+// leave each lane one partial sum, of row 4 b5 + 2 b4 + b3 (bits of the lane
+// index), which a butterfly over the 8 lanes of its group completes. 10
+// exchanges instead of 48, in a fixed order; on return every lane holds the
+// total of the row that its lane index names (lane >> 3).
+template <int H, int O>
+__device__ __forceinline__ void halve_rows(double (&acc)[kRowBatch], int lane) {
+  const bool up = (lane & O) != 0;
+#pragma unroll
+  for (int r = 0; r < H; ++r) {
+    const double keep = up ? acc[r + H] : acc[r];
+    const double send = up ? acc[r] : acc[r + H];
+    acc[r] = keep + __shfl_xor(send, O);
   }
 }
 
-constexpr int kRowBatch = 8;    // survivor rows fetched together by one wave
-constexpr int kEarlyKeys = 1024;  // keys requested before the count is known
+__device__ __forceinline__ double wave_sum8_f64(double (&acc)[kRowBatch]) {
+  static_assert(kRowBatch == 8, "three halving steps");
+  const int lane = lane_id();
+  halve_rows<4, 32>(acc, lane);
+  halve_rows<2, 16>(acc, lane);
+  halve_rows<1, 8>(acc, lane);
+  double v = acc[0];
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 1);
+  return v;
+}
 
 // FP64 distances of the frame to source rows sh.srow[s0 .. s1) into
-// sort_hi / sort_lo[s] (distance bits, tie id). For fp32 sources each wave
-// fetches kRowBatch rows at once with the frame slice reused across them.
+// sort_hi / sort_lo[s] (distance bits, tie id). Each wave fetches kRowBatch
+// rows at once with the frame slice reused across them; a lane sums its
+// slice of each row in order (4 consecutive values per 256), then
+// wave_sum8_f64 adds the lanes. LEAN (1024-thread blocks, at most 128
+// VGPRs) fetches the FP64 rows in two halves; the sums are the same.
+template <bool LEAN>
 __device__ void rerank_range(const SelRerankArgs &a, SelShared &sh, const float *qrow, int s0,
                              int s1) {
   const int w = wave_id(), lane = lane_id(), nw = blockDim.x >> 6;
-  if (a.src32) {
-    const int nch = a.dp >> 8;    // float4 chunks of 256 values per lane pass
-    const int tail = a.dp & 255;  // remaining values (multiple of 32)
-    for (int b = s0 + w * kRowBatch; b < s1; b += nw * kRowBatch) {
-      double acc[kRowBatch];
-      const float *rp[kRowBatch];
-      uint32_t tie[kRowBatch];
+  const int nch = a.dp >> 8;    // chunks of 256 values: 4 per lane
+  const int tail = a.dp & 255;  // remaining values (multiple of 16)
+  for (int b = s0 + w * kRowBatch; b < s1; b += nw * kRowBatch) {
+    double acc[kRowBatch];
+    uint32_t row[kRowBatch];
 #pragma unroll
-      for (int r = 0; r < kRowBatch; ++r) {
-        acc[r] = 0.0;
-        const uint32_t row = sh.srow[min(b + r, s1 - 1)];
-        rp[r] = a.src32 + (int64_t)row * a.dp;
-        tie[r] = (lane == r && a.tie_of) ? (uint32_t)a.tie_of[row] : row;
-      }
-      for (int c = 0; c <= nch; ++c) {
-        const int col = c * 256 + lane * 4;
-        if (c == nch && (tail == 0 || col >= a.dp)) break;
-        const float4 y = *reinterpret_cast<const float4 *>(qrow + col);
-        float4 x[kRowBatch];
+    for (int r = 0; r < kRowBatch; ++r) {
+      acc[r] = 0.0;
+      row[r] = sh.srow[min(b + r, s1 - 1)];
+    }
+    for (int c = 0; c <= nch; ++c) {
+      const int col = c * 256 + lane * 4;
+      if (c == nch && (tail == 0 || col >= a.dp)) break;
+      const float4 y = *reinterpret_cast<const float4 *>(qrow + col);
+      const double y0 = y.x, y1 = y.y, y2 = y.z, y3 = y.w;
+      if (a.src32) {
+        float4 v[kRowBatch];
 #pragma unroll
-        for (int r = 0; r < kRowBatch; ++r) x[r] = *reinterpret_cast<const float4 *>(rp[r] + col);
+        for (int r = 0; r < kRowBatch; ++r)
+          v[r] = *reinterpret_cast<const float4 *>(a.src32 + (int64_t)row[r] * a.dp + col);
 #pragma unroll
         for (int r = 0; r < kRowBatch; ++r) {
           double t;
-          t = (double)y.x - (double)x[r].x; acc[r] = fma(t, t, acc[r]);
-          t = (double)y.y - (double)x[r].y; acc[r] = fma(t, t, acc[r]);
-          t = (double)y.z - (double)x[r].z; acc[r] = fma(t, t, acc[r]);
-          t = (double)y.w - (double)x[r].w; acc[r] = fma(t, t, acc[r]);
+          t = y0 - (double)v[r].x; acc[r] = fma(t, t, acc[r]);
+          t = y1 - (double)v[r].y; acc[r] = fma(t, t, acc[r]);
+          t = y2 - (double)v[r].z; acc[r] = fma(t, t, acc[r]);
+          t = y3 - (double)v[r].w; acc[r] = fma(t, t, acc[r]);
         }
-      }
+      } else if (LEAN) {
 #pragma unroll
-      for (int r = 0; r < kRowBatch; ++r) acc[r] = wave_sum_f64(acc[r]);
+        for (int hf = 0; hf < 2; ++hf) {
+          double2 v[kRowBatch];
 #pragma unroll
-      for (int r = 0; r < kRowBatch; ++r) {
-        const int sidx = b + r;
-        if (lane == r && sidx < s1) {
-          sh.sort_hi[sidx] = (uint64_t)__double_as_longlong(acc[r]);
-          sh.sort_lo[sidx] = tie[r];
+          for (int r = 0; r < kRowBatch; ++r)
+            v[r] = reinterpret_cast<const double2 *>(a.src64 + (int64_t)row[r] * a.dp + col)[hf];
+          const double ya = hf ? y2 : y0, yb = hf ? y3 : y1;
+          __builtin_amdgcn_sched_barrier(0);  // keep the halves apart (register budget)
+#pragma unroll
+          for (int r = 0; r < kRowBatch; ++r) {
+            double t;
+            t = ya - v[r].x; acc[r] = fma(t, t, acc[r]);
+            t = yb - v[r].y; acc[r] = fma(t, t, acc[r]);
+          }
+        }
+      } else {
+        double2 v[kRowBatch][2];
+#pragma unroll
+        for (int r = 0; r < kRowBatch; ++r) {
+          const double2 *rp = reinterpret_cast<const double2 *>(a.src64 + (int64_t)row[r] * a.dp + col);
+          v[r][0] = rp[0];
+          v[r][1] = rp[1];
+        }
+#pragma unroll
+        for (int r = 0; r < kRowBatch; ++r) {
+          double t;
+          t = y0 - v[r][0].x; acc[r] = fma(t, t, acc[r]);
+          t = y1 - v[r][0].y; acc[r] = fma(t, t, acc[r]);
+          t = y2 - v[r][1].x; acc[r] = fma(t, t, acc[r]);
+          t = y3 - v[r][1].y; acc[r] = fma(t, t, acc[r]);
         }
       }
     }
-  } else {
-    for (int sidx = s0 + w; sidx < s1; sidx += nw) {
-      const uint32_t row = sh.srow[sidx];
-      const double d = wave_dist_f64(a.src64 + (int64_t)row * a.dp, qrow, a.dp);
-      if (lane == 0) {
-        sh.sort_hi[sidx] = (uint64_t)__double_as_longlong(d);
-        sh.sort_lo[sidx] = a.tie_of ? (uint32_t)a.tie_of[row] : row;
-      }
+    const double d = wave_sum8_f64(acc);
+    const int r = lane >> 3, sidx = b + r;
+    if ((lane & 7) == 0 && sidx < s1) {
+      const uint32_t rw = sh.srow[sidx];
+      sh.sort_hi[sidx] = (uint64_t)__double_as_longlong(d);
+      sh.sort_lo[sidx] = a.tie_of ? (uint32_t)a.tie_of[rw] : rw;
     }
   }
 }
 
-// Sorts sort_hi / sort_lo[0, cnt) ascending (padding to a power of two with
-// empty entries): by shuffles in one wave up to 64 entries, else in LDS.
+// Sorts sort_hi / sort_lo[0, cnt) ascending; the pairs are distinct (the
+// second member is a candidate position or the tie id of a distinct row).
+// Up to kRankSort entries: G threads per entry (G consecutive lanes, G =
+// blockDim / next_pow2(cnt), at most 64) each count the entries of a slice
+// that order before it, the lanes add their counts and the entry is stored
+// at that rank. Above, a bitonic merge in LDS over the entries padded to a
+// power of two with empty ones.
 __device__ void sort_pairs(SelShared &sh, int cnt) {
-  const int tid = threadIdx.x, w = wave_id(), lane = lane_id();
-  const int P = next_pow2(cnt > 0 ? cnt : 1);
+  const int tid = threadIdx.x;
+  if (cnt <= kRankSort && cnt <= (int)blockDim.x) {
+    __syncthreads();
+    const int G = min(64, (int)blockDim.x / next_pow2(max(cnt, 1)));
+    const int e = tid / G, part = tid - e * G;
+    uint64_t hi = 0;
+    uint32_t lo = 0;
+    int rank = 0;
+    if (e < cnt) {
+      hi = sh.sort_hi[e];
+      lo = sh.sort_lo[e];
+      const int per = (cnt + G - 1) / G, j0 = part * per, j1 = min(cnt, j0 + per);
+      for (int j = j0; j < j1; j += 4) {
+        uint64_t yh[4];
+        uint32_t yl[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int jj = min(j + u, j1 - 1);
+          yh[u] = sh.sort_hi[jj];
+          yl[u] = sh.sort_lo[jj];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          rank += (j + u < j1) & ((yh[u] < hi) | ((yh[u] == hi) & (yl[u] < lo)));
+      }
+    }
+    for (int o = 1; o < G; o <<= 1) rank += __shfl_xor(rank, o);
+    __syncthreads();
+    if (e < cnt && part == 0) {
+      sh.sort_hi[rank] = hi;
+      sh.sort_lo[rank] = lo;
+    }
+    __syncthreads();
+    return;
+  }
+  const int P = next_pow2(cnt);
   for (int t = cnt + tid; t < P; t += blockDim.x) {
     sh.sort_hi[t] = kKeyNone;
     sh.sort_lo[t] = 0xFFFFFFFFu;
   }
-  __syncthreads();
-  if (P <= 64) {
-    if (w == 0) {
-      uint64_t hi = lane < P ? sh.sort_hi[lane] : kKeyNone;
-      uint32_t lo = lane < P ? sh.sort_lo[lane] : 0xFFFFFFFFu;
-      wave_sort64_pairs(hi, lo);
-      if (lane < P) {
-        sh.sort_hi[lane] = hi;
-        sh.sort_lo[lane] = lo;
-      }
-    }
-    __syncthreads();
-  } else {
-    block_sort_pairs(sh.sort_hi, sh.sort_lo, P);
-  }
+  block_sort_pairs(sh.sort_hi, sh.sort_lo, P);
 }
 
 // Source row of candidate position p of a frame: with region slots, slot j
-// holds the rows of region s_reg[j] at positions s_off[j] .. (s_off[0] = 0,
+// holds the rows from s_row[j] on at positions s_off[j] .. (s_off[0] = 0,
 // non-decreasing; the slot holding p is the last with s_off[j] <= p, and it
 // is never empty); without slots the position is the row.
-__device__ __forceinline__ uint32_t row_of(const int32_t *s_off, const int32_t *s_reg, int nslots,
-                                           const int64_t *__restrict__ reg_start, uint32_t p) {
+__device__ __forceinline__ uint32_t row_of(const int32_t *s_off, const int32_t *s_row, int nslots,
+                                           uint32_t p) {
   if (nslots == 0) return p;
   int lo = 0, hi = nslots;
   while (hi - lo > 1) {
@@ -319,7 +365,7 @@ __device__ __forceinline__ uint32_t row_of(const int32_t *s_off, const int32_t *
     if (s_off[mid] <= (int32_t)p) lo = mid;
     else hi = mid;
   }
-  return (uint32_t)(reg_start[s_reg[lo]] + ((int32_t)p - s_off[lo]));
+  return (uint32_t)(s_row[lo] + ((int32_t)p - s_off[lo]));
 }
 
 template <int BLOCK>
@@ -332,7 +378,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
   const int nw = blockDim.x >> 6;
   const int nslots = a.nslots;
   int32_t *s_off = reinterpret_cast<int32_t *>(dyn);
-  int32_t *s_reg = s_off + nslots;
+  int32_t *s_row = s_off + nslots;
   uint32_t *wc = dyn + 2 * nslots;
   const uint32_t *words = a.cand + (int64_t)f * a.cap;
   // the first words are requested together with the count (one round trip)
@@ -344,9 +390,14 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
     const int i = u * BLOCK + tid;
     ew[u] = i < early ? words[i] : kWordNone;
   }
+  // the select's histogram and counter, cleared while the words are in flight
+  static_assert((1 << kDigitBits) % (4 * BLOCK) == 0, "whole int4 per thread");
+  for (int t = tid; t < (1 << kDigitBits) / 4; t += BLOCK)
+    reinterpret_cast<int4 *>(sh.hist)[t] = make_int4(0, 0, 0, 0);
+  if (tid == 0) sh.krem = 0;
   for (int j = tid; j < nslots; j += blockDim.x) {
     s_off[j] = a.slot_off[(int64_t)f * nslots + j];
-    s_reg[j] = a.slot_reg[(int64_t)f * nslots + j];
+    s_row[j] = a.slot_row[(int64_t)f * nslots + j];
   }
   const int n = a.n_cand ? a.n_cand[f] : a.n_fixed;
   const int C = min(n, a.cache);  // positions [0, C) cached, the rest read from memory
@@ -413,26 +464,40 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
     const int pre = __clz(vmin ^ vmax);
     const int bits = min(kDigitBits, 32 - pre), shift = 32 - pre - bits;
     const uint32_t mask = (1u << bits) - 1u;
-    for (int t = tid; t < (1 << bits); t += blockDim.x) sh.hist[t] = 0;
-    if (tid == 0) sh.krem = 0;
-    __syncthreads();
-    for (int i = tid; i < n; i += blockDim.x) {
+    // (histogram and counter cleared at the start)
+#pragma unroll 4
+    for (int i = tid; i < n; i += BLOCK) {
       const uint32_t v = word_at(i);
       if (v != kWordNone) atomicAdd(&sh.hist[(v >> shift) & mask], 1);
     }
     __syncthreads();
-    const int nb = 1 << bits, pb = (nb + blockDim.x - 1) / blockDim.x, b0 = tid * pb;
+    // each thread holds PB consecutive bins in registers (bins from 1 << bits
+    // on are zero), scans their sums over the block and, if its run holds the
+    // (L+1)-th word, finds the bucket there
+    constexpr int PB = (1 << kDigitBits) / BLOCK;
+    int hv[PB];
+#pragma unroll
+    for (int u = 0; u < PB; u += 4) {
+      const int4 h = reinterpret_cast<const int4 *>(sh.hist + tid * PB)[u / 4];
+      hv[u] = h.x;
+      hv[u + 1] = h.y;
+      hv[u + 2] = h.z;
+      hv[u + 3] = h.w;
+    }
     int mine = 0;
-    for (int b = b0; b < min(nb, b0 + pb); ++b) mine += sh.hist[b];
+#pragma unroll
+    for (int u = 0; u < PB; ++u) mine += hv[u];
     const int incl = block_incl_scan(mine, sh.red_i);
     int excl = incl - mine;
     if (mine > 0 && excl < L + 1 && L + 1 <= incl) {
-      for (int b = b0; b < min(nb, b0 + pb); ++b) {
-        excl += sh.hist[b];
-        if (excl >= L + 1) {
-          sh.word = (uint32_t)b;
-          sh.eq = excl;  // words in buckets up to b
-          break;
+      bool found = false;
+#pragma unroll
+      for (int u = 0; u < PB; ++u) {
+        excl += hv[u];
+        if (!found && excl >= L + 1) {
+          found = true;
+          sh.word = (uint32_t)(tid * PB + u);
+          sh.eq = excl;  // words in buckets up to this one
         }
       }
     }
@@ -440,19 +505,84 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
     const uint32_t bstar = sh.word;
     const int m = sh.eq;
     if (m <= kMaxSurvivors) {
-      for (int i = i0; i < i1; ++i) {
-        const uint32_t v = word_at(i);
-        if (v != kWordNone && ((v >> shift) & mask) <= bstar) {
-          const int slot = atomicAdd(&sh.krem, 1);
-          sh.sort_hi[slot] = v;
-          sh.sort_lo[slot] = (uint32_t)i;
+      // the words of buckets up to bstar, compacted by wave ballots: count,
+      // one atomic per wave for its base, then place (any order). Up to
+      // kCollectRounds positions per lane (half with 1024 threads) stay in
+      // registers between the two.
+      auto keep = [&](int i, uint32_t &v) {
+        v = i < n ? word_at(i) : kWordNone;
+        return v != kWordNone && ((v >> shift) & mask) <= bstar;
+      };
+      constexpr int CR = BLOCK >= 1024 ? kCollectRounds / 2 : kCollectRounds;
+      if (n <= CR * BLOCK) {
+        uint32_t v[CR];
+        uint64_t bal[CR];
+        int wcount = 0;
+#pragma unroll
+        for (int u = 0; u < CR; ++u) {
+          bal[u] = __ballot(keep(u * BLOCK + w * 64 + lane, v[u]));
+          wcount += __popcll(bal[u]);
+        }
+        int base = 0;
+        if (lane == 0 && wcount > 0) base = atomicAdd(&sh.krem, wcount);
+        base = __shfl(base, 0);
+#pragma unroll
+        for (int u = 0; u < CR; ++u) {
+          if ((bal[u] >> lane) & 1ull) {
+            const int slot = base + __popcll(bal[u] & ((1ull << lane) - 1ull));
+            sh.sort_hi[slot] = v[u];
+            sh.sort_lo[slot] = (uint32_t)(u * BLOCK + w * 64 + lane);
+          }
+          base += __popcll(bal[u]);
+        }
+      } else {
+        int wcount = 0;
+        for (int b0 = w * 64; b0 < n; b0 += BLOCK) {
+          uint32_t v;
+          wcount += __popcll(__ballot(keep(b0 + lane, v)));
+        }
+        int base = 0;
+        if (lane == 0 && wcount > 0) base = atomicAdd(&sh.krem, wcount);
+        base = __shfl(base, 0);
+        for (int b0 = w * 64; b0 < n; b0 += BLOCK) {
+          uint32_t v;
+          const bool k = keep(b0 + lane, v);
+          const uint64_t bal = __ballot(k);
+          if (k) {
+            const int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
+            sh.sort_hi[slot] = v;
+            sh.sort_lo[slot] = (uint32_t)(b0 + lane);
+          }
+          base += __popcll(bal);
         }
       }
       __syncthreads();
-      sort_pairs(sh, m);  // by (word, position)
-      for (int t = tid; t < L; t += blockDim.x) sh.sel[t] = sh.sort_lo[t];
-      tw = (uint32_t)sh.sort_hi[L];
-      tpos = (int)sh.sort_lo[L];
+      if (m == L + 1 && m <= BLOCK) {
+        // usually: the (L+1)-th is the largest of the collected pairs (a
+        // block maximum of word << 32 | position) and every other survives
+        uint64_t key = 0;
+        if (tid < m) key = (sh.sort_hi[tid] << 32) | sh.sort_lo[tid];
+        uint64_t mx = key;
+        for (int o = 32; o > 0; o >>= 1) {
+          const uint64_t y = (uint64_t)__shfl_xor((long long)mx, o);
+          mx = y > mx ? y : mx;
+        }
+        if (lane == 0) sh.red_k[w] = mx;
+        __syncthreads();
+        mx = 0;
+        for (int i = 0; i < nw; ++i) mx = sh.red_k[i] > mx ? sh.red_k[i] : mx;
+        if (tid < m && key == mx) sh.eq = tid;
+        __syncthreads();
+        const int imax = sh.eq;
+        if (tid < m && key != mx) sh.sel[tid == L ? imax : tid] = (uint32_t)key;
+        tw = (uint32_t)(mx >> 32);
+        tpos = (int)(uint32_t)mx;
+      } else {
+        sort_pairs(sh, m);  // by (word, position)
+        for (int t = tid; t < L; t += blockDim.x) sh.sel[t] = sh.sort_lo[t];
+        tw = (uint32_t)sh.sort_hi[L];
+        tpos = (int)sh.sort_lo[L];
+      }
       __syncthreads();
       done = true;
     }
@@ -492,11 +622,11 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
     __syncthreads();
   }
   for (int s = tid; s < nsurv; s += blockDim.x)
-    sh.srow[s] = row_of(s_off, s_reg, nslots, a.reg_start, sh.sel[s]);
+    sh.srow[s] = row_of(s_off, s_row, nslots, sh.sel[s]);
   __syncthreads();
   // FP64 rerank of the survivors, sorted by (distance, tie id)
   const float *qrow = a.qp + (int64_t)f * a.dp;
-  rerank_range(a, sh, qrow, 0, nsurv);
+  rerank_range<BLOCK == 1024>(a, sh, qrow, 0, nsurv);
   __syncthreads();
   sort_pairs(sh, nsurv);
   // certificate: a rejected candidate can only beat the m-th reranked
@@ -545,9 +675,9 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
         if (in_band(word_at(i), i)) sh.sel[pos++] = (uint32_t)i;
       __syncthreads();
       for (int s = nsurv + tid; s < nsurv + total_band; s += blockDim.x)
-        sh.srow[s] = row_of(s_off, s_reg, nslots, a.reg_start, sh.sel[s]);
+        sh.srow[s] = row_of(s_off, s_row, nslots, sh.sel[s]);
       __syncthreads();
-      rerank_range(a, sh, qrow, nsurv, nsurv + total_band);
+      rerank_range<BLOCK == 1024>(a, sh, qrow, nsurv, nsurv + total_band);
       __syncthreads();
       sort_pairs(sh, nsurv + total_band);
       have = min(nsurv + total_band, a.m);
@@ -566,7 +696,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
         uint32_t lo = 0xFFFFFFFFu;
         if (i < n && tid < 256) {
           if (word_at(i) != kWordNone) {
-            const uint32_t row = row_of(s_off, s_reg, nslots, a.reg_start, (uint32_t)i);
+            const uint32_t row = row_of(s_off, s_row, nslots, (uint32_t)i);
             hi = (uint64_t)__double_as_longlong(thread_dist(a, qrow, row));
             lo = a.tie_of ? (uint32_t)a.tie_of[row] : row;
           }
@@ -622,7 +752,7 @@ hipError_t prepare_select_kernels() {
 hipError_t launch_select_rerank(SelRerankArgs a, hipStream_t s) {
   if (a.nq <= 0) return hipSuccess;
   if (a.L > kMaxSurvivors || a.L < a.m || a.m > 256) return hipErrorInvalidValue;
-  if (a.nslots < 0 || a.nslots > kMaxSlots || (a.nslots > 0 && (!a.slot_off || !a.slot_reg)))
+  if (a.nslots < 0 || a.nslots > kMaxSlots || (a.nslots > 0 && (!a.slot_off || !a.slot_row)))
     return hipErrorInvalidValue;
   a.cache = (int32_t)std::min<int64_t>(a.cap, kWordCache);
   // frames with many candidates: the word cache takes most of the LDS, so the
