@@ -256,10 +256,11 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
       sa.q_lp = ws->q_lp.p;
       sa.row_scale = lpm->rep_scale;
       sa.q_scale = as<float>(ws->q_scale);
-      HIPCHK(wide_dense ? launch_screen_wide_lp(fmt, sa, p.grid1, s)
+      HIPCHK(wide_dense ? launch_screen_wide_lp(fmt, sa, p.grid1, db->num_cu, s)
                         : launch_screen_lp(fmt, sa, p.grid1, s));
     } else {
-      HIPCHK(wide_dense ? launch_screen_wide_f32(sa, p.grid1, s) : launch_screen_f32(sa, p.grid1, s));
+      HIPCHK(wide_dense ? launch_screen_wide_f32(sa, p.grid1, db->num_cu, s)
+                        : launch_screen_f32(sa, p.grid1, s));
     }
     SelRerankArgs ra{};
     ra.cand = as<uint32_t>(ws->cand1);
@@ -318,7 +319,8 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   }
   HIPCHK(fmt ? launch_screen_lp(fmt, sb, p.grid2, s) : launch_screen_f32(sb, p.grid2, s));
   ph.begin(HLOC_PHASE_SCREEN_WIDE);
-  HIPCHK(fmt ? launch_screen_wide_lp(fmt, sb, p.grid2, s) : launch_screen_wide_f32(sb, p.grid2, s));
+  HIPCHK(fmt ? launch_screen_wide_lp(fmt, sb, p.grid2, db->num_cu, s)
+             : launch_screen_wide_f32(sb, p.grid2, db->num_cu, s));
   ph.begin(HLOC_PHASE_SELECT);
   SelRerankArgs rb{};
   rb.cand = as<uint32_t>(ws->cand2);

@@ -39,6 +39,7 @@ inline hipError_t launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t lds, h
 }
 
 constexpr int kGroup = 16;          // frames per MFMA column block of the screen
+constexpr int kLdsPerCu = 160 * 1024;  // LDS of one compute unit (gfx950)
 constexpr int kItemFrames = 256;    // frames per screen work item (wide items)
 constexpr int kWideRows = 64;       // rows per wide work item (the LDS stage of the wide kernels)
 constexpr int kMaxItemRows = 128;   // rows per narrow work item at most
@@ -150,11 +151,14 @@ hipError_t launch_prep_queries(const float *q, int32_t nq, int32_t d, int32_t dp
 // Dense screen, or the narrow list items (every list item where no register
 // kernel exists for the padded length); then the wide list items.
 hipError_t launch_screen_f32(const ScreenArgs &a, int32_t grid, hipStream_t s);
-hipError_t launch_screen_wide_f32(const ScreenArgs &a, int32_t grid, hipStream_t s);
+// The wide kernels launch at most as many blocks as their LDS stage lets
+// reside on num_cu compute units (the rest would only find no item left).
+hipError_t launch_screen_wide_f32(const ScreenArgs &a, int32_t grid, int32_t num_cu, hipStream_t s);
 bool f32_wide_supports(int32_t dp);  // a register wide kernel exists for this padded length
 // Low-precision screens, fmt = HLOC_BF16 or HLOC_FP8.
 hipError_t launch_screen_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipStream_t s);
-hipError_t launch_screen_wide_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipStream_t s);
+hipError_t launch_screen_wide_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, int32_t num_cu,
+                                 hipStream_t s);
 bool lp_screen_supports(int32_t fmt, int32_t dp);
 // Low-precision copy of n rows (fp8: with a scale per row); maxima of the
 // per-row norms of the rounding error and of the rounded row.

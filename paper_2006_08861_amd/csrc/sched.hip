@@ -56,17 +56,16 @@ __device__ __forceinline__ int items_of(int g, int64_t rows, int T) {
   return g > 0 ? (int)((rows + C - 1) / C) * ((g + kItemFrames - 1) / kItemFrames) : 0;
 }
 
-// Work item t of region r, whose frames are rq[q_begin, q_end): chunk-major,
-// frame groups inner, so consecutive items re-read the same rows.
-__device__ __forceinline__ Item make_item(int t, int r, int item_begin, int q_begin, int q_end,
-                                          const int64_t *__restrict__ reg_start, int T) {
+// Work item t of a region whose rows are [r0, r0 + rows) and whose frames are
+// rq[q_begin, q_end): chunk-major, frame groups inner, so consecutive items
+// re-read the same rows.
+__device__ __forceinline__ Item make_item(int t, int item_begin, int q_begin, int q_end, int r0,
+                                          int rows, int T) {
   const int g = q_end - q_begin, ngr = (g + kItemFrames - 1) / kItemFrames;
   const int C = chunk_rows(g, T);
   const int local = t - item_begin, c = local / ngr, b = local - c * ngr;
-  const int64_t r0 = reg_start[r];
-  const int rows = (int)(reg_start[r + 1] - r0);
   Item it;
-  it.row_begin = (int32_t)r0 + c * C;
+  it.row_begin = r0 + c * C;
   it.chunk_row = c * C;
   it.q0 = q_begin + b * kItemFrames;
   it.nrows_gq = (min(C, rows - c * C) << 16) | min(kItemFrames, g - b * kItemFrames);
@@ -78,7 +77,9 @@ __device__ __forceinline__ Item make_item(int t, int r, int item_begin, int q_be
 // order), vord / iof (the regions in narrow-then-wide order and their first
 // item), n_items[0] (all items) and n_items[4] (narrow items). With fill set,
 // fill[r] = rq_off[r]. count may alias fill. s_red holds 72 ints of LDS.
-__device__ void sched_scan(const int32_t *count, int R, const int64_t *__restrict__ reg_start,
+// reg_start: first row of each region (R + 1 entries, device or LDS).
+template <class RS>
+__device__ void sched_scan(const int32_t *count, int R, const RS *__restrict__ reg_start,
                            int T, int32_t *rq_off, int32_t *vord, int32_t *iof,
                            int32_t *n_items, int32_t *fill, int *s_red) {
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -222,19 +223,23 @@ __global__ void k_sched_items(int R, const int32_t *__restrict__ vord,
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     const int k = owner_slot(iof, R, t);
     const int r = vord[k];
-    items[t] = make_item(t, r, iof[k], rq_off[r], rq_off[r + 1], reg_start, T);
+    const int64_t r0 = reg_start[r];
+    items[t] = make_item(t, iof[k], rq_off[r], rq_off[r + 1], (int)r0, (int)(reg_start[r + 1] - r0), T);
   }
 }
 
 // The whole schedule in one block for up to kFusedMaxR regions and
 // kFusedMaxPairs (frame, region) pairs: per-region counts, fill pointers,
-// order and item offsets live in LDS, so the histogram and the scatter use
-// LDS atomics (no contention on global memory when many frames keep the same
-// region), and work items are expanded one per thread.
-constexpr int kFusedMaxR = 12288;
+// order, item offsets and the regions' first rows live in LDS, so the
+// histogram and the scatter use LDS atomics (no contention on global memory
+// when many frames keep the same region), no step waits on a global read of
+// a value written earlier in the kernel, and work items are expanded one per
+// thread.
+constexpr int kFusedMaxR = 8192;
 constexpr int64_t kFusedMaxPairs = 8192;  // larger batches: the multi-kernel path is faster
+constexpr int kFusedRegs = 8;             // regions per frame kept in registers between steps
 
-size_t fused_lds_bytes(int R) { return (size_t)(3 * R + 1) * sizeof(int); }
+size_t fused_lds_bytes(int R) { return (size_t)(4 * R + 2) * sizeof(int); }
 
 __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict__ regions, int nq,
                                                       int nr, int R,
@@ -243,56 +248,93 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
                                                       int32_t *slot_row, int32_t *n_cand,
                                                       int32_t *n_items, int2 *rq, Item *items) {
   extern __shared__ int s_mem[];
-  int *s_fill = s_mem;         // R: frame counts, then fill pointers
+  int *s_fill = s_mem;         // R: frame counts, then fill pointers, then ends
   int *s_vord = s_mem + R;     // R: regions in narrow-then-wide order
   int *s_iof = s_mem + 2 * R;  // R + 1: first item of each slot of s_vord
+  int *s_rs = s_mem + 3 * R + 1;  // R + 1: first row of each region
   __shared__ int s_red[72];
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int r = tid; r < R; r += nt) s_fill[r] = 0;
-  __syncthreads();
-  for (int f = tid; f < nq; f += nt) {
-    int off = 0;
-    for (int j0 = 0; j0 < nr; j0 += 8) {
-      // ids, then sizes, then updates: eight loads in flight per step
-      int r[8], sz[8], r0[8];
+  // with one frame per thread and at most kFusedRegs regions per frame, the
+  // frame's region ids and list offsets stay in registers for the scatter
+  const bool regs = nq <= nt && nr <= kFusedRegs;
+  int r[kFusedRegs], co[kFusedRegs];
+  if (regs && tid < nq) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        r[u] = j0 + u < nr ? regions[(int64_t)f * nr + j0 + u] : -1;
-        if (r[u] >= R) r[u] = -1;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        r0[u] = r[u] >= 0 ? (int)reg_start[r[u]] : 0;
-        sz[u] = r[u] >= 0 ? (int)(reg_start[r[u] + 1] - r0[u]) : 0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (j0 + u >= nr) break;
-        cand_off[(int64_t)f * nr + j0 + u] = off;
-        slot_row[(int64_t)f * nr + j0 + u] = r0[u];
-        off += sz[u];
-        if (r[u] >= 0) atomicAdd(&s_fill[r[u]], 1);
-      }
+    for (int u = 0; u < kFusedRegs; ++u) {
+      r[u] = u < nr ? regions[(int64_t)tid * nr + u] : -1;
+      if (r[u] >= R) r[u] = -1;
     }
-    n_cand[f] = off;
+  }
+  for (int i = tid; i <= R; i += nt) s_rs[i] = (int)reg_start[i];
+  for (int i = tid; i < R; i += nt) s_fill[i] = 0;
+  __syncthreads();
+  if (regs) {
+    if (tid < nq) {
+      int off = 0;
+#pragma unroll
+      for (int u = 0; u < kFusedRegs; ++u) {
+        if (u >= nr) break;
+        const int r0 = r[u] >= 0 ? s_rs[r[u]] : 0;
+        co[u] = off;
+        cand_off[(int64_t)tid * nr + u] = off;
+        slot_row[(int64_t)tid * nr + u] = r0;
+        if (r[u] >= 0) {
+          off += s_rs[r[u] + 1] - r0;
+          atomicAdd(&s_fill[r[u]], 1);
+        }
+      }
+      n_cand[tid] = off;
+    }
+  } else {
+    for (int f = tid; f < nq; f += nt) {
+      int off = 0;
+      for (int j = 0; j < nr; ++j) {
+        int rj = regions[(int64_t)f * nr + j];
+        if (rj >= R) rj = -1;
+        const int r0 = rj >= 0 ? s_rs[rj] : 0;
+        cand_off[(int64_t)f * nr + j] = off;
+        slot_row[(int64_t)f * nr + j] = r0;
+        if (rj >= 0) {
+          off += s_rs[rj + 1] - r0;
+          atomicAdd(&s_fill[rj], 1);
+        }
+      }
+      n_cand[f] = off;
+    }
   }
   __syncthreads();
   // counts -> fill pointers (each thread reads and rewrites only its own range)
-  sched_scan(s_fill, R, reg_start, T, rq_off, s_vord, s_iof, n_items, s_fill, s_red);
+  sched_scan(s_fill, R, s_rs, T, rq_off, s_vord, s_iof, n_items, s_fill, s_red);
   __syncthreads();
-  const int64_t pairs = (int64_t)nq * nr;
-  for (int64_t t = tid; t < pairs; t += nt) {
-    const int r = regions[t];
-    if (r < 0 || r >= R) continue;
-    const int pos = atomicAdd(&s_fill[r], 1);
-    rq[pos] = make_int2((int)(t / nr), cand_off[t]);
+  if (regs) {
+    if (tid < nq) {
+#pragma unroll
+      for (int u = 0; u < kFusedRegs; ++u) {
+        if (u >= nr) break;
+        if (r[u] < 0) continue;
+        const int pos = atomicAdd(&s_fill[r[u]], 1);
+        rq[pos] = make_int2(tid, co[u]);
+      }
+    }
+  } else {
+    // (cand_off was written by this thread for its own frames)
+    for (int f = tid; f < nq; f += nt) {
+      for (int j = 0; j < nr; ++j) {
+        const int rj = regions[(int64_t)f * nr + j];
+        if (rj < 0 || rj >= R) continue;
+        const int pos = atomicAdd(&s_fill[rj], 1);
+        rq[pos] = make_int2(f, cand_off[(int64_t)f * nr + j]);
+      }
+    }
   }
   __syncthreads();
+  // s_fill[r] now ends region r's frames: they are rq[s_fill[r - 1], s_fill[r])
   const int n = s_iof[R];
   for (int t = tid; t < n; t += nt) {
     const int k = owner_slot(s_iof, R, t);
-    const int r = s_vord[k];
-    items[t] = make_item(t, r, s_iof[k], rq_off[r], rq_off[r + 1], reg_start, T);
+    const int rr = s_vord[k];
+    const int q0 = rr > 0 ? s_fill[rr - 1] : 0;
+    items[t] = make_item(t, s_iof[k], q0, s_fill[rr], s_rs[rr], s_rs[rr + 1] - s_rs[rr], T);
   }
 }
 

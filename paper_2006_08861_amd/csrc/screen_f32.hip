@@ -329,7 +329,9 @@ size_t wide_lds_bytes() {
 }
 
 template <int NS>
-hipError_t launch_wide_t(const ScreenArgs &a, int32_t grid, hipStream_t s) {
+hipError_t launch_wide_t(const ScreenArgs &a, int32_t grid, int32_t num_cu, hipStream_t s) {
+  const int64_t resident = (int64_t)num_cu * std::max<int64_t>(1, kLdsPerCu / wide_lds_bytes<NS>());
+  grid = (int32_t)std::min<int64_t>(grid, resident);
   return launch_kernel(k_screen_wide<NS>, dim3(grid), dim3(256), (uint32_t)wide_lds_bytes<NS>(), s,
                        a);
 }
@@ -399,17 +401,17 @@ bool f32_wide_supports(int32_t dp) {
   return dp == 32 || dp == 64 || dp == 128 || dp == 256 || dp == 512;
 }
 
-hipError_t launch_screen_wide_f32(const ScreenArgs &a, int32_t grid, hipStream_t s) {
+hipError_t launch_screen_wide_f32(const ScreenArgs &a, int32_t grid, int32_t num_cu, hipStream_t s) {
   if (grid <= 0 || a.rows_per_item % 16 != 0) return hipSuccess;
   // list items of wide regions hold at most kWideRows rows (the LDS stage);
   // dense items hold rows_per_item
   if (a.dense && a.rows_per_item > kWideRows) return hipErrorInvalidValue;
   switch (a.dp) {
-    case 32: return launch_wide_t<2>(a, grid, s);
-    case 64: return launch_wide_t<4>(a, grid, s);
-    case 128: return launch_wide_t<8>(a, grid, s);
-    case 256: return launch_wide_t<16>(a, grid, s);
-    case 512: return launch_wide_t<32>(a, grid, s);
+    case 32: return launch_wide_t<2>(a, grid, num_cu, s);
+    case 64: return launch_wide_t<4>(a, grid, num_cu, s);
+    case 128: return launch_wide_t<8>(a, grid, num_cu, s);
+    case 256: return launch_wide_t<16>(a, grid, num_cu, s);
+    case 512: return launch_wide_t<32>(a, grid, num_cu, s);
     default: return hipSuccess;  // the LDS kernel screened every item
   }
 }

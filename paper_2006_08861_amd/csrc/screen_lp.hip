@@ -18,6 +18,8 @@
 #include "hloc_device.h"
 #include "hloc_internal.h"
 
+#include <algorithm>
+
 namespace hloc {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -362,20 +364,24 @@ int lp_pieces(int32_t fmt, int32_t dp) {
 bool lp_screen_supports(int32_t fmt, int32_t dp) { return lp_pieces(fmt, dp) > 0; }
 
 template <int FMT, int NS>
-hipError_t launch_lp_ns(const ScreenArgs &a, int32_t grid, bool wide, hipStream_t s) {
-  if (wide)
-    return launch_kernel(k_screen_wide_lp<FMT, NS>, dim3(grid), dim3(256),
-                         (uint32_t)wide_lp_lds_bytes<NS>(), s, a);
+hipError_t launch_lp_ns(const ScreenArgs &a, int32_t grid, int32_t wide_cu, hipStream_t s) {
+  if (wide_cu > 0) {
+    const int64_t resident =
+        (int64_t)wide_cu * std::max<int64_t>(1, kLdsPerCu / wide_lp_lds_bytes<NS>());
+    return launch_kernel(k_screen_wide_lp<FMT, NS>, dim3((int32_t)std::min<int64_t>(grid, resident)),
+                         dim3(256), (uint32_t)wide_lp_lds_bytes<NS>(), s, a);
+  }
   return a.dense ? launch_kernel(k_screen_lp<FMT, NS, true>, dim3(grid), dim3(256), 0, s, a)
                  : launch_kernel(k_screen_lp<FMT, NS, false>, dim3(grid), dim3(256), 0, s, a);
 }
 
+// wide_cu: compute units for the wide kernel, 0 for the narrow one
 template <int FMT>
-hipError_t launch_lp_fmt(const ScreenArgs &a, int32_t grid, bool wide, hipStream_t s) {
+hipError_t launch_lp_fmt(const ScreenArgs &a, int32_t grid, int32_t wide_cu, hipStream_t s) {
   switch (lp_pieces(FMT, a.dp)) {
 #define HLOC_LP_CASE(N) \
   case N:               \
-    return launch_lp_ns<FMT, N>(a, grid, wide, s);
+    return launch_lp_ns<FMT, N>(a, grid, wide_cu, s);
     HLOC_LP_CASE(1)
     HLOC_LP_CASE(2)
     HLOC_LP_CASE(3)
@@ -395,17 +401,19 @@ hipError_t launch_lp_fmt(const ScreenArgs &a, int32_t grid, bool wide, hipStream
 hipError_t launch_screen_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   if (a.rows_per_item % 16 != 0) return hipErrorInvalidValue;
-  if (fmt == HLOC_BF16) return launch_lp_fmt<HLOC_BF16>(a, grid, false, s);
-  if (fmt == HLOC_FP8) return launch_lp_fmt<HLOC_FP8>(a, grid, false, s);
+  if (fmt == HLOC_BF16) return launch_lp_fmt<HLOC_BF16>(a, grid, 0, s);
+  if (fmt == HLOC_FP8) return launch_lp_fmt<HLOC_FP8>(a, grid, 0, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_screen_wide_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipStream_t s) {
+hipError_t launch_screen_wide_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, int32_t num_cu,
+                                 hipStream_t s) {
   if (grid <= 0) return hipSuccess;
+  num_cu = std::max(num_cu, 1);
   if (a.rows_per_item % 16 != 0 || (a.dense && a.rows_per_item > kWideRows))
     return hipErrorInvalidValue;
-  if (fmt == HLOC_BF16) return launch_lp_fmt<HLOC_BF16>(a, grid, true, s);
-  if (fmt == HLOC_FP8) return launch_lp_fmt<HLOC_FP8>(a, grid, true, s);
+  if (fmt == HLOC_BF16) return launch_lp_fmt<HLOC_BF16>(a, grid, num_cu, s);
+  if (fmt == HLOC_FP8) return launch_lp_fmt<HLOC_FP8>(a, grid, num_cu, s);
   return hipErrorInvalidValue;
 }
 
