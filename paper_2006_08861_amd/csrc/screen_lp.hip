@@ -231,9 +231,18 @@ __global__ __launch_bounds__(256) void k_screen_lp(ScreenArgs a) {
   } else {
     hi = a.n_items[4];  // the narrow items: at most kGroup frames each
   }
+  // list items: the next item's descriptor and frame entry are fetched while
+  // the current one is screened
+  Item nx{};
+  int2 ne = make_int2(0, 0);
+  if (!DENSE && lo + (int)blockIdx.x < hi) {
+    nx = a.items[lo + blockIdx.x];
+    if (i < (nx.nrows_gq & 0xFFFF)) ne = a.rq[nx.q0 + i];
+  }
   for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
     int row_begin, chunk_row, nrows, gq, fr = 0;
     int64_t off = 0;
+    const int itn = it + gridDim.x;
     if (DENSE) {
       const int c = it % nchunks, grp = it / nchunks;
       row_begin = c * a.rows_per_item;
@@ -243,16 +252,15 @@ __global__ __launch_bounds__(256) void k_screen_lp(ScreenArgs a) {
       fr = grp * kGroup + i;
       off = (int64_t)fr * a.cap + chunk_row;
     } else {
-      const Item itm = a.items[it];
-      row_begin = itm.row_begin;
-      chunk_row = itm.chunk_row;
-      nrows = itm.nrows_gq >> 16;
-      gq = itm.nrows_gq & 0xFFFF;
+      row_begin = nx.row_begin;
+      chunk_row = nx.chunk_row;
+      nrows = nx.nrows_gq >> 16;
+      gq = nx.nrows_gq & 0xFFFF;
       if (i < gq) {
-        const int2 e = a.rq[itm.q0 + i];
-        fr = e.x;
-        off = (int64_t)e.x * a.cap + e.y + chunk_row;
+        fr = ne.x;
+        off = (int64_t)ne.x * a.cap + ne.y + chunk_row;
       }
+      if (itn < hi) nx = a.items[itn];
     }
     if (i >= gq) fr = 0;
     const int nrb = (nrows + 15) >> 4;
@@ -281,6 +289,14 @@ __global__ __launch_bounds__(256) void k_screen_lp(ScreenArgs a) {
           }
         }
       }
+      if (!DENSE && rb == w && itn < hi) {
+        ne = make_int2(0, 0);
+        if (i < (nx.nrows_gq & 0xFFFF)) ne = a.rq[nx.q0 + i];
+      }
+    }
+    if (!DENSE && w >= nrb && itn < hi) {
+      ne = make_int2(0, 0);
+      if (i < (nx.nrows_gq & 0xFFFF)) ne = a.rq[nx.q0 + i];
     }
   }
 }
