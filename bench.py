@@ -104,18 +104,30 @@ def load_traffic(workload: str, precision: str, rows_per_item: int):
     return b, os.path.relpath(path, ROOT)
 
 
+def _kname(r) -> str:
+    return r["Kernel_Name"].split("(")[0].replace("void ", "").replace("hloc::", "")
+
+
 def per_dispatch_kib(path: str, name_prefix: str, counter: str,
-                     suffix: str = "") -> tuple[float, int]:
+                     suffix: str = "", after: tuple[str, str] | None = None) -> tuple[float, int]:
     """Mean counter value (KiB) per dispatch of the kernels whose name starts
     with name_prefix (after an optional namespace) and ends with suffix in a
-    rocprofv3 counter CSV."""
-    vals = []
+    rocprofv3 counter CSV. With after = (prefix, suffix), only dispatches
+    whose previous dispatch (by Dispatch_Id) of a screen kernel matches it
+    count: the fine stage's wide-item launch follows its narrow-item launch,
+    while the coarse stage's dense launch of the same wide kernel does not."""
     with open(path) as f:
-        for r in csv.DictReader(f):
-            name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("hloc::", "")
-            if name.startswith(name_prefix) and name.endswith(suffix) and \
-                    r["Counter_Name"] == counter:
+        rows = [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r.get("Dispatch_Id") or 0))
+    vals = []
+    prev = ""
+    for r in rows:
+        name = _kname(r)
+        if name.startswith(name_prefix) and name.endswith(suffix):
+            if after is None or (prev.startswith(after[0]) and prev.endswith(after[1])):
                 vals.append(float(r["Counter_Value"]))
+        if "screen" in name:
+            prev = name
     if not vals:
         raise SystemExit(f"no {counter} rows for {name_prefix} in {path}")
     return sum(vals) / len(vals), len(vals)
@@ -134,9 +146,10 @@ def counters_summary(a) -> None:
     narrow = SCREEN_KERNELS[a.precision]
     wide = WIDE_KERNELS[a.precision]
     per = {}
-    for name, prefix, suffix in (("narrow", narrow, ", false>"), ("wide", wide, ">")):
-        fk, nf = per_dispatch_kib(fetch_csv, prefix, "FETCH_SIZE", suffix)
-        wk, nw = per_dispatch_kib(write_csv, prefix, "WRITE_SIZE", suffix)
+    for name, prefix, suffix, after in (("narrow", narrow, ", false>", None),
+                                        ("wide", wide, ">", (narrow, ", false>"))):
+        fk, nf = per_dispatch_kib(fetch_csv, prefix, "FETCH_SIZE", suffix, after)
+        wk, nw = per_dispatch_kib(write_csv, prefix, "WRITE_SIZE", suffix, after)
         label = narrow_label(a.precision, rows) if name == "narrow" else prefix + "NS>"
         per[name] = (label, fk, nf, wk, nw)
     copy_bytes = a.copy_mib * (1 << 20)

@@ -32,7 +32,8 @@ def test_cpu_baseline_times_the_oracle():
 
 def _csv(path, rows):
     with open(path, "w", newline="") as f:
-        wr = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        wr = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name",
+                                           "Counter_Value"])
         wr.writeheader()
         for r in rows:
             wr.writerow(r)
@@ -47,13 +48,15 @@ def test_counter_summary_round_trip(tmp_path, monkeypatch, capsys):
     wide = "void hloc::k_screen_wide<16>(hloc::ScreenArgs)"
     copy = ("void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add"
             "<float>, std::array<char*, 2ul> >(int)")
-    _csv(tmp_path / "f.csv", [dict(Kernel_Name=narrow, Counter_Name="FETCH_SIZE", Counter_Value=100),
-                              dict(Kernel_Name=narrow, Counter_Name="FETCH_SIZE", Counter_Value=300),
-                              dict(Kernel_Name=dense, Counter_Name="FETCH_SIZE", Counter_Value=9000),
-                              dict(Kernel_Name=wide, Counter_Name="FETCH_SIZE", Counter_Value=10)])
-    _csv(tmp_path / "w.csv", [dict(Kernel_Name=narrow, Counter_Name="WRITE_SIZE", Counter_Value=8),
-                              dict(Kernel_Name=dense, Counter_Name="WRITE_SIZE", Counter_Value=900),
-                              dict(Kernel_Name=wide, Counter_Name="WRITE_SIZE", Counter_Value=2)])
+    # per step: the coarse stage (dense narrow kernel, or the wide kernel in
+    # dense mode for large batches), then the fine narrow and wide launches;
+    # only the wide launch that follows a narrow list launch is the fine one
+    steps = [(dense, 9000, 900), (wide, 7777, 777), (narrow, 100, 8), (wide, 10, 2),
+             (dense, 9000, 900), (wide, 7777, 777), (narrow, 300, 8), (wide, 10, 2)]
+    _csv(tmp_path / "f.csv", [dict(Dispatch_Id=j + 1, Kernel_Name=k, Counter_Name="FETCH_SIZE",
+                                   Counter_Value=fv) for j, (k, fv, _) in enumerate(steps)])
+    _csv(tmp_path / "w.csv", [dict(Dispatch_Id=j + 1, Kernel_Name=k, Counter_Name="WRITE_SIZE",
+                                   Counter_Value=wv) for j, (k, _, wv) in enumerate(steps)])
     _csv(tmp_path / "f2.csv", [dict(Kernel_Name=hoist, Counter_Name="FETCH_SIZE", Counter_Value=150),
                                dict(Kernel_Name=wide, Counter_Name="FETCH_SIZE", Counter_Value=10)])
     _csv(tmp_path / "w2.csv", [dict(Kernel_Name=hoist, Counter_Name="WRITE_SIZE", Counter_Value=6),
