@@ -132,17 +132,23 @@ __device__ __forceinline__ WideItem wide_item(const ScreenArgs &a, int it) {
   return w;
 }
 
-// Frame j of a wide item (j < gq) and where its screen words go.
-__device__ __forceinline__ void wide_frame(const ScreenArgs &a, const WideItem &w, int j, int *fr,
-                                           int64_t *off) {
+// Frame j of a wide item (j < gq) and where its screen words go; e is the
+// frame's rq entry (list items, from wide_entry).
+__device__ __forceinline__ void wide_frame(const ScreenArgs &a, const WideItem &w, int j, int2 e,
+                                           int *fr, int64_t *off) {
   if (a.dense) {
     *fr = w.f0 + j;
     *off = (int64_t)(*fr) * a.cap + w.chunk_row;
   } else {
-    const int2 e = a.rq[w.q0 + j];
     *fr = e.x;
     *off = (int64_t)e.x * a.cap + e.y + w.chunk_row;
   }
+}
+
+// rq entry of frame j of a wide list item (zeros past its frames or in
+// dense mode).
+__device__ __forceinline__ int2 wide_entry(const ScreenArgs &a, const WideItem &w, int j) {
+  return !a.dense && j < w.gq ? a.rq[w.q0 + j] : make_int2(0, 0);
 }
 
 // Padded copy and squared norm of each frame; block 0 also clears zero16[0..16).

@@ -282,31 +282,71 @@ __global__ __launch_bounds__(256) void k_screen_wide(ScreenArgs a) {
   __shared__ float s_rn[64];
   const int tid = threadIdx.x, lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
   const int i = lane & 15, g = lane >> 4;
+  // the chunk of the block's next item is read into registers (16 pieces
+  // per thread at a time) while the current one is screened, with the rq
+  // entry of each lane's frame in the wave's first group; with 512-long rows
+  // (32 pieces per thread) the chunk is read after the current item, 16
+  // pieces at a time
+  constexpr int PER = 64 * 4 * NS / 256;  // float4 pieces per thread (256 threads)
+  constexpr bool AHEAD = PER <= 16;
+  constexpr int BUF = AHEAD ? PER : 16;
+  static_assert(PER % BUF == 0, "whole batches");
+  float4 pv[BUF];
+  float prn = 0.f;
+  WideItem wn{};
+  int2 pe = make_int2(0, 0);
+  auto load = [&](int u0) {
+#pragma unroll
+    for (int u = 0; u < BUF; ++u) {
+      const int e = tid + (u0 + u) * 256, row = e / (4 * NS), c = e - row * (4 * NS);
+      pv[u] = row < wn.nrows
+                  ? reinterpret_cast<const float4 *>(a.rows + (int64_t)(wn.row_begin + row) * DP)[c]
+                  : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto store = [&](int u0) {
+#pragma unroll
+    for (int u = 0; u < BUF; ++u) {
+      const int e = tid + (u0 + u) * 256, row = e / (4 * NS), c = e - row * (4 * NS);
+      s_rows[row * LDR + c] = pv[u];
+    }
+  };
+  auto fetch = [&](int item) {
+    wn = wide_item(a, item);
+    pe = wide_entry(a, wn, w * kGroup + i);
+    if (AHEAD) load(0);
+    if (tid < 64) prn = tid < wn.nrows ? a.row_n2[wn.row_begin + tid] : 0.f;
+  };
   int lo;
   const int hi = wide_range(a, &lo);
+  if (lo + (int)blockIdx.x < hi) fetch(lo + blockIdx.x);
   for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
-    const WideItem wi = wide_item(a, it);
-    const int row_begin = wi.row_begin;
+    const WideItem wi = wn;
     const int nrows = wi.nrows, gq = wi.gq;
+    int2 ce = pe;
     __syncthreads();  // the previous item's rows are no longer read
-    for (int e = tid; e < 64 * 4 * NS; e += blockDim.x) {
-      const int row = e / (4 * NS), c = e - row * (4 * NS);
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (row < nrows) v = reinterpret_cast<const float4 *>(a.rows + (int64_t)(row_begin + row) * DP)[c];
-      s_rows[row * LDR + c] = v;
+    if (AHEAD) {
+      store(0);
+    } else {
+      for (int u0 = 0; u0 < PER; u0 += BUF) {
+        load(u0);
+        store(u0);
+      }
     }
-    if (tid < 64) s_rn[tid] = tid < nrows ? a.row_n2[row_begin + tid] : 0.f;
+    if (tid < 64) s_rn[tid] = prn;
     __syncthreads();
+    if (it + (int)gridDim.x < hi) fetch(it + gridDim.x);
     for (int grp = w; grp * kGroup < gq; grp += nw) {
       const int gs = min(kGroup, gq - grp * kGroup);
       int fr = 0;
       int64_t off = 0;
-      if (i < gs) wide_frame(a, wi, grp * kGroup + i, &fr, &off);
+      if (i < gs) wide_frame(a, wi, grp * kGroup + i, ce, &fr, &off);
       const float4 *qp = reinterpret_cast<const float4 *>(a.qp + (int64_t)fr * DP) + g;
       float4 bv[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
       const float qn = a.qn2[fr];
+      ce = wide_entry(a, wi, (grp + nw) * kGroup + i);  // the wave's next group
       for (int rb = 0; rb * 16 < nrows; ++rb) {
         const float4 *rp = s_rows + (rb * 16 + i) * LDR + g;
         v4f acc = {0.f, 0.f, 0.f, 0.f};

@@ -313,35 +313,60 @@ __global__ __launch_bounds__(256) void k_screen_wide_lp(ScreenArgs a) {
   const int i = lane & 15, g = lane >> 4;
   const uint4 *rows = static_cast<const uint4 *>(a.rows_lp);
   const uint4 *frames = static_cast<const uint4 *>(a.q_lp);
-  int lo;
-  const int hi = wide_range(a, &lo);
-  for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
-    const WideItem wi = wide_item(a, it);
-    const int row_begin = wi.row_begin;
-    const int nrows = wi.nrows, gq = wi.gq;
-    __syncthreads();  // the previous item's rows are no longer read
-    for (int e = tid; e < 64 * ROWU4; e += blockDim.x) {
-      const int row = e / ROWU4, c = e - row * ROWU4;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (row < nrows) v = rows[(int64_t)(row_begin + row) * ROWU4 + c];
-      s_rows[row * LDR + c] = v;
+  // the chunk of the block's next item is read into registers (all of a
+  // thread's pieces at once) while the current one is screened, with the rq
+  // entry of each lane's frame in the wave's first group
+  constexpr int PER = 64 * ROWU4 / 256;  // pieces per thread (256 threads)
+  static_assert(64 * ROWU4 % 256 == 0, "whole pieces per thread");
+  uint4 pv[PER];
+  float prn = 0.f, prs = 1.f;
+  WideItem wn{};
+  int2 pe = make_int2(0, 0);
+  auto fetch = [&](int item) {
+    wn = wide_item(a, item);
+    pe = wide_entry(a, wn, w * kGroup + i);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * 256, row = e / ROWU4, c = e - row * ROWU4;
+      pv[u] = row < wn.nrows ? rows[(int64_t)(wn.row_begin + row) * ROWU4 + c]
+                             : make_uint4(0u, 0u, 0u, 0u);
     }
     if (tid < 64) {
-      s_rn[tid] = tid < nrows ? a.row_n2[row_begin + tid] : 0.f;
-      s_rs[tid] = (FMT == HLOC_FP8 && tid < nrows) ? a.row_scale[row_begin + tid] : 1.f;
+      prn = tid < wn.nrows ? a.row_n2[wn.row_begin + tid] : 0.f;
+      prs = (FMT == HLOC_FP8 && tid < wn.nrows) ? a.row_scale[wn.row_begin + tid] : 1.f;
+    }
+  };
+  int lo;
+  const int hi = wide_range(a, &lo);
+  if (lo + (int)blockIdx.x < hi) fetch(lo + blockIdx.x);
+  for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
+    const WideItem wi = wn;
+    const int nrows = wi.nrows, gq = wi.gq;
+    int2 ce = pe;
+    __syncthreads();  // the previous item's rows are no longer read
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * 256, row = e / ROWU4, c = e - row * ROWU4;
+      s_rows[row * LDR + c] = pv[u];
+    }
+    if (tid < 64) {
+      s_rn[tid] = prn;
+      s_rs[tid] = prs;
     }
     __syncthreads();
+    if (it + (int)gridDim.x < hi) fetch(it + gridDim.x);
     for (int grp = w; grp * kGroup < gq; grp += nw) {
       const int gs = min(kGroup, gq - grp * kGroup);
       int fr = 0;
       int64_t off = 0;
-      if (i < gs) wide_frame(a, wi, grp * kGroup + i, &fr, &off);
+      if (i < gs) wide_frame(a, wi, grp * kGroup + i, ce, &fr, &off);
       const uint4 *qp = frames + (int64_t)fr * ROWU4 + g;
       uint4 bv[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
       const float qn = a.qn2[fr];
       const float qs = FMT == HLOC_FP8 ? a.q_scale[fr] : 1.f;
+      ce = wide_entry(a, wi, (grp + nw) * kGroup + i);  // the wave's next group
       for (int rb = 0; rb * 16 < nrows; ++rb) {
         const uint4 *rp = s_rows + (rb * 16 + i) * LDR + g;
         v4f acc = {0.f, 0.f, 0.f, 0.f};

@@ -487,6 +487,25 @@ def test_region_kept_by_every_frame(torch_cuda, precision):
     assert info["items"] >= 3 * 47  # groups of up to 256 frames
 
 
+@pytest.mark.parametrize("d", [256, 512])
+def test_wide_items_long_rows(torch_cuda, d):
+    # wide items at the lengths where the fp32 wide kernel loads the next
+    # frame group's operand ahead (256) and where it does not (512)
+    rng = np.random.default_rng(24)
+    sizes = np.array([700] + [90] * 10)
+    region_of = np.repeat(np.arange(len(sizes)), sizes).astype(np.int32)
+    n = len(region_of)
+    feats = rng.standard_normal((n, d)).astype(np.float32)
+    feats[:700] *= 0.2
+    feats[700:] += 0.3
+    xy = rng.uniform(0, 40, size=(n, 2))
+    q = (feats[rng.integers(0, 700, 90)] + 0.05 * rng.standard_normal((90, d))).astype(np.float32)
+    st, info, _ = check_all(torch_cuda, feats, xy, region_of, len(sizes), q, 9, 2,
+                            name=f"one region kept by 90 frames, d{d}")
+    assert st["recall"] == 1.0
+    assert info["items"] > info["narrow_items"]
+
+
 # ------------------------------------------------------------- tiles and the tuner
 def test_tiles_do_not_change_results(torch_cuda, tmp_path):
     # the fine-screen tiles change the work items, never the results
