@@ -38,6 +38,7 @@ if ROOT not in sys.path:
 
 METRIC = "localization queries/sec at recall@k=1.0 vs FP64 oracle; HBM GB/s % peak; p99 ms"
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}  # dense, per screen dtype
 
 
 def log(*a):
@@ -483,6 +484,14 @@ def main():
         screen_ms += phases["screen_wide"][0] / max(phases["screen_wide"][1], 1)
     achieved = screen_bytes / (screen_ms * 1e-3) / 1e9
     traffic, traffic_src = load_traffic(w.name, a.precision, db.tiles()["rows_per_item"])
+    # the coarse screen is the dense (GEMM-shaped) part: nq x R distances
+    coarse_ms = phases["coarse"][0] / max(phases["coarse"][1], 1)
+    s1_flops = 2.0 * nq * w.n_regions_total * d
+    s1_tf = s1_flops / (coarse_ms * 1e-3) / 1e12 if coarse_ms > 0 else 0.0
+    stage1 = {"kernel": "coarse screen (" + ("wide" if nq >= 512 else "narrow") + " kernel, dense)",
+              "flops": s1_flops, "avg_launch_ms": coarse_ms, "achieved": s1_tf,
+              "peak": MFMA_PEAK_TFLOPS[a.precision], "unit": "TFLOP/s",
+              "frac": s1_tf / MFMA_PEAK_TFLOPS[a.precision]}
     gpu_idx = idx.cpu().numpy()
 
     base, recall, exact, m = (None, None, None, 0)
@@ -520,11 +529,13 @@ def main():
                      "traffic": None if traffic is None else int(traffic),
                      "traffic_source": traffic_src, "bytes_per_launch": int(screen_bytes),
                      "avg_launch_ms": screen_ms},
+        "stage1_mfma": stage1,
         "phases_ms": {p: v[0] / max(v[1], 1) for p, v in phases.items()},
         "ms_per_step_event_timed": wall_prof * 1e3 / a.steps,
         "modes": {"eager_one_stream_ms_per_step": wall_eager * 1e3 / a.steps,
                   f"graphs_{W}_streams_ms_per_step": wall_pipe * 1e3 / a.steps},
-        "fallbacks": {"coarse": info["coarse_fallbacks"], "fine": info["fine_fallbacks"]},
+        "fallbacks": {"coarse": info["coarse_fallbacks"], "fine": info["fine_fallbacks"],
+                      "chunked_bands": info["chunked_bands"], "band_rows": info["band_rows"]},
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

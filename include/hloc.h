@@ -168,11 +168,14 @@ int hloc_reserve(hloc_db *db, int32_t nq_max, int32_t nreq_max, int32_t k_max,
 
 /*
  * Per-database counters of the last query call (waits for it): out[0] work
- * items of the fine screen, out[1] frames whose coarse selection needed the
- * exact FP64 fallback, out[2] frames whose top-k needed it, out[3] largest
+ * items of the fine screen, out[1] frames whose coarse selection failed its
+ * certificate (so the band of uncertain regions was re-scored in FP64),
+ * out[2] frames whose top-k did (the band of uncertain rows), out[3] largest
  * candidate count of a frame, out[4] survivors per frame (k'), out[5] total
  * candidates screened, out[6] narrow work items (regions kept by at most 16
- * frames; out[0] - out[6] are wide items). Writes min(n, 7) values.
+ * frames; out[0] - out[6] are wide items), out[7] frames whose band was too
+ * large for one pass and was re-scored in chunks, out[8] rows re-scored in
+ * bands over all frames. Writes min(n, 9) values.
  * Errors: EINVAL, EDEVICE.
  */
 int hloc_query_info(hloc_db *db, int64_t *out, int32_t n);
@@ -228,7 +231,8 @@ int hloc_ws_replay(hloc_ws *ws, void *stream);
  * Device-time profile of the query path, measured with HIP events recorded on
  * the query's stream around each phase:
  *   HLOC_PHASE_PREP      query norms and padded copy
- *   HLOC_PHASE_COARSE    coarse screen, then select + FP64 re-score of regions
+ *   HLOC_PHASE_COARSE    coarse screen against the region representatives
+ *   HLOC_PHASE_COARSE_SELECT select + FP64 re-score of the regions of each frame
  *   HLOC_PHASE_SCHED     region -> frames lists and work items
  *   HLOC_PHASE_SCREEN    fine screen of the narrow work items (and of every item
  *                        at padded lengths without a register kernel)
@@ -251,7 +255,8 @@ enum {
   HLOC_PHASE_SELECT = 4,
   HLOC_PHASE_AGGREGATE = 5,
   HLOC_PHASE_SCREEN_WIDE = 6,
-  HLOC_NUM_PHASES = 7
+  HLOC_PHASE_COARSE_SELECT = 7,
+  HLOC_NUM_PHASES = 8
 };
 int hloc_profile(hloc_db *db, int32_t enable);
 int hloc_profile_read(hloc_db *db, double *ms, int64_t *calls, int32_t n);

@@ -262,6 +262,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
       HIPCHK(wide_dense ? launch_screen_wide_f32(sa, p.grid1, db->num_cu, s)
                         : launch_screen_f32(sa, p.grid1, s));
     }
+    ph.begin(HLOC_PHASE_COARSE_SELECT);
     SelRerankArgs ra{};
     ra.cand = as<uint32_t>(ws->cand1);
     ra.cap = db->R;
@@ -356,6 +357,8 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   rb.dist_out = dist;
   rb.stat_fallback = misc + 2;
   rb.stat_max = misc + 3;
+  rb.stat_chunked = misc + 6;
+  rb.stat_band = misc + 7;
   HIPCHK(launch_select_rerank(rb, s));
   ph.end();
   if (want_agg && p.nreq > 0) {
@@ -515,8 +518,9 @@ int info_of(hloc_ws *ws, int64_t *out, int32_t n) {
     HIPCHK(hipMemcpy(nc.data(), ws->n_cand.p, nc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     for (int32_t v : nc) total += v;
   }
-  const int64_t vals[7] = {misc[0], misc[1], misc[2], misc[3], ws->last_kp, total, misc[4]};
-  for (int32_t i = 0; i < std::min(n, 7); ++i) out[i] = vals[i];
+  const int64_t vals[9] = {misc[0], misc[1], misc[2],     misc[3], ws->last_kp,
+                           total,   misc[4], misc[6], (int64_t)(uint32_t)misc[7]};
+  for (int32_t i = 0; i < std::min(n, 9); ++i) out[i] = vals[i];
   return HLOC_OK;
 }
 

@@ -192,8 +192,8 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
 // Per frame: the L + 1 smallest screen words of cand[f][0 .. n(f)) (n(f) =
 // n_cand ? n_cand[f] : n_fixed; 0xFFFFFFFF entries are skipped; equal words
 // ordered by position), FP64 rerank of the L smallest, top m by (distance,
-// tie id), certificate against the (L + 1)-th, and the exact FP64 pass over
-// all candidates when it fails. Candidate positions map to source rows through
+// tie id), certificate against the (L + 1)-th, and the FP64 re-score of the
+// band of uncertain candidates when it fails. Candidate positions map to source rows through
 // the frame's region slots (slot j: the rows from slot_row[f][j] on, at
 // positions from slot_off[f][j] on), or are the rows themselves when nslots
 // is 0.
@@ -226,7 +226,9 @@ struct SelRerankArgs {
   int64_t *idx_out;        // fine: nq x m original indices
   float *dist_out;         // fine: nq x m
   int32_t *reg_out;        // coarse: nq x m region ids
-  int32_t *stat_fallback;  // frames that needed the exact pass
+  int32_t *stat_fallback;  // frames whose certificate failed (band re-scored)
+  int32_t *stat_chunked;   // frames whose band was re-scored in several chunks (or NULL)
+  int32_t *stat_band;      // sum of the band sizes (or NULL)
   int32_t *stat_max;       // largest candidate count (or NULL)
 };
 hipError_t launch_select_rerank(SelRerankArgs a, hipStream_t s);

@@ -16,7 +16,8 @@
 //   3. certificate: the (L+1)-th word is the best rejected screen distance; if
 //      it minus the screen's error bound does not exceed the m-th reranked
 //      distance, the block also re-scores every rejected candidate within that
-//      bound (or, if there are too many, all of them) and counts the frame.
+//      bound (in chunks merged with the best m if there are many) and counts
+//      the frame.
 // Distances are squared L2 (same order as the Euclidean distance of Section 4).
 #include "hloc_device.h"
 #include "hloc_internal.h"
@@ -40,26 +41,6 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 __device__ __forceinline__ int wave_sum_i32(int v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
-}
-
-// Sequential FP64 distance of one row (one thread; used by the fallback).
-__device__ __forceinline__ double thread_dist(const SelRerankArgs &a, const float *qrow,
-                                              uint32_t row) {
-  double acc = 0.0;
-  if (a.src64) {
-    const double *rp = a.src64 + (int64_t)row * a.dp;
-    for (int c = 0; c < a.dp; ++c) {
-      const double t = (double)qrow[c] - rp[c];
-      acc = fma(t, t, acc);
-    }
-  } else {
-    const float *rp = a.src32 + (int64_t)row * a.dp;
-    for (int c = 0; c < a.dp; ++c) {
-      const double t = (double)qrow[c] - (double)rp[c];
-      acc = fma(t, t, acc);
-    }
-  }
-  return acc;
 }
 
 struct SelShared {
@@ -632,8 +613,8 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
   // certificate: a rejected candidate can only beat the m-th reranked
   // distance dm if its screen distance is within the screen's error bound e
   // of dm. If the best rejected one is not beyond dm + e, every rejected
-  // candidate up to dm + e (the band) is re-scored too; if the band does not
-  // fit, every candidate is.
+  // candidate up to dm + e (the band) is re-scored too, in chunks if it does
+  // not fit at once.
   if (tid == 0) {
     sh.flag = 0;
     if (rejected && a.m > 0) {
@@ -682,39 +663,37 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
       sort_pairs(sh, nsurv + total_band);
       have = min(nsurv + total_band, a.m);
     } else {
-      // exact FP64 top m over every candidate, merged 256 at a time into a
-      // sorted best list held in sort_hi / sort_lo[0, Pm)
-      const int Pm = next_pow2(a.m);
-      const int Q = next_pow2(Pm + 256);
-      for (int t = tid; t < Q; t += blockDim.x) {
-        sh.sort_hi[t] = kKeyNone;
-        sh.sort_lo[t] = 0xFFFFFFFFu;
-      }
-      for (int base = 0; base < n; base += 256) {
-        const int i = base + tid;
-        uint64_t hi = kKeyNone;
-        uint32_t lo = 0xFFFFFFFFu;
-        if (i < n && tid < 256) {
-          if (word_at(i) != kWordNone) {
-            const uint32_t row = row_of(s_off, s_row, nslots, (uint32_t)i);
-            hi = (uint64_t)__double_as_longlong(thread_dist(a, qrow, row));
-            lo = a.tie_of ? (uint32_t)a.tie_of[row] : row;
+      // a band too large for one pass: re-scored in chunks of up to
+      // kMaxSurvivors - m positions, each merged with the best m so far
+      // (the sorted survivors' first m to begin with). Every candidate that
+      // can still enter the top m has a word up to tau_w, so this is exact.
+      const int m = a.m, chunk = kMaxSurvivors - m, excl = incl - mine;
+      int kept = min(nsurv, m);  // sort_hi / sort_lo[0, kept): the best so far, sorted
+      if (tid == 0 && a.stat_chunked) atomicAdd(a.stat_chunked, 1);
+      for (int c0 = 0; c0 < total_band; c0 += chunk) {
+        const int cnt = min(chunk, total_band - c0);
+        // this thread's band positions ranked [c0, c0 + cnt) in position order
+        if (excl < c0 + cnt && excl + mine > c0) {
+          int r = excl;
+          for (int i = i0; i < i1 && r < c0 + cnt; ++i) {
+            if (in_band(word_at(i), i)) {
+              if (r >= c0) sh.sel[kept + r - c0] = (uint32_t)i;
+              ++r;
+            }
           }
         }
         __syncthreads();
-        for (int t = Pm + tid; t < Q; t += blockDim.x) {
-          sh.sort_hi[t] = kKeyNone;
-          sh.sort_lo[t] = 0xFFFFFFFFu;
-        }
+        for (int t = kept + tid; t < kept + cnt; t += blockDim.x)
+          sh.srow[t] = row_of(s_off, s_row, nslots, sh.sel[t]);
         __syncthreads();
-        if (tid < 256) {
-          sh.sort_hi[Pm + tid] = hi;
-          sh.sort_lo[Pm + tid] = lo;
-        }
-        block_sort_pairs(sh.sort_hi, sh.sort_lo, Q);
+        rerank_range<BLOCK == 1024>(a, sh, qrow, kept, kept + cnt);
+        __syncthreads();
+        sort_pairs(sh, kept + cnt);
+        kept = min(kept + cnt, m);
       }
-      have = min(nvalid, a.m);
+      have = kept;
     }
+    if (tid == 0 && a.stat_band) atomicAdd(a.stat_band, total_band);
   }
   for (int i = tid; i < a.m; i += blockDim.x) {
     const bool ok = i < have;

@@ -284,7 +284,8 @@ class HlocDB:
                 json.dump(table, f, indent=1)
         return dict(t, source="tuned")
 
-    PHASES = ("prep", "coarse", "sched", "screen", "select", "aggregate", "screen_wide")
+    PHASES = ("prep", "coarse", "sched", "screen", "select", "aggregate", "screen_wide",
+              "coarse_select")
 
     def profile(self, enable: bool = True):
         """Start (clearing) or stop the per-phase event record."""
@@ -309,7 +310,7 @@ class HlocDB:
 
 
 _INFO_KEYS = ("items", "coarse_fallbacks", "fine_fallbacks", "max_candidates", "survivors",
-              "candidates", "narrow_items")
+              "candidates", "narrow_items", "chunked_bands", "band_rows")
 
 
 class Workspace:

@@ -506,6 +506,24 @@ def test_wide_items_long_rows(torch_cuda, d):
     assert info["items"] > info["narrow_items"]
 
 
+@pytest.mark.parametrize("precision", ["fp8", "bf16"])
+def test_band_in_chunks(torch_cuda, precision):
+    # rows all about equally far from the frames: the low-precision screen's
+    # certificate fails and its band holds more rows than one pass fits, so
+    # the band is re-scored in chunks (still exact)
+    rng = np.random.default_rng(25)
+    n, d = 6000, 64
+    base = rng.standard_normal(d)
+    feats = (base + 0.02 * rng.standard_normal((n, d))).astype(np.float32)
+    region_of = (np.arange(n) // 1500).astype(np.int32)
+    xy = rng.uniform(0, 40, size=(n, 2))
+    q = (base + 0.02 * rng.standard_normal((20, d))).astype(np.float32)
+    st, info, _ = check_all(torch_cuda, feats, xy, region_of, 4, q, 16, 2,
+                            name=f"band in chunks, {precision}", precision=precision)
+    assert st["recall"] == 1.0
+    assert info["chunked_bands"] > 0 and info["band_rows"] > 1024
+
+
 # ------------------------------------------------------------- tiles and the tuner
 def test_tiles_do_not_change_results(torch_cuda, tmp_path):
     # the fine-screen tiles change the work items, never the results
