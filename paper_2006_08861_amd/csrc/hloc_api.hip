@@ -161,6 +161,12 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *byte
     CHK(fit(ws->q_err, (size_t)nq * sizeof(float)));
     CHK(fit(ws->q_lon, (size_t)nq * sizeof(float)));
   }
+  if (db->lp[HLOC_FP8].rows && db->lp[HLOC_BF16].reps) {
+    CHK(fit(ws->c_lp, (size_t)nq * db->dp * 2));
+    CHK(fit(ws->c_scale, (size_t)nq * sizeof(float)));
+    CHK(fit(ws->c_err, (size_t)nq * sizeof(float)));
+    CHK(fit(ws->c_lon, (size_t)nq * sizeof(float)));
+  }
   if (agg_internal) {
     const int64_t nreq = std::max(p.nreq, 1);
     CHK(fit(ws->agg_xy, (size_t)nreq * 2 * sizeof(double)));
@@ -224,10 +230,20 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   // low-precision screens: the frames rounded the same way as the rows
   const int fmt = p.precision == HLOC_FP32 ? 0 : p.precision;
   const LpMirror *lpm = fmt ? &db->lp[fmt] : nullptr;
+  // the coarse screen of fp8 queries runs on bf16 copies when there are any
+  const bool coarse_bf16 = fmt == HLOC_FP8 && db->lp[HLOC_BF16].reps;
+  const int cfmt = coarse_bf16 ? HLOC_BF16 : fmt;
+  const LpMirror *cpm = cfmt ? &db->lp[cfmt] : nullptr;
+  void *c_lp = coarse_bf16 ? ws->c_lp.p : ws->q_lp.p;
+  float *c_scale = as<float>(coarse_bf16 ? ws->c_scale : ws->q_scale);
+  float *c_err = as<float>(coarse_bf16 ? ws->c_err : ws->q_err);
+  float *c_lon = as<float>(coarse_bf16 ? ws->c_lon : ws->q_lon);
   HIPCHK(launch_prep_queries(q, p.nq, db->d, db->dp, qp, qn2, misc, s));
   if (fmt)
     HIPCHK(launch_frames_to_lp(fmt, qp, p.nq, db->dp, ws->q_lp.p, as<float>(ws->q_scale),
                                as<float>(ws->q_err), as<float>(ws->q_lon), s));
+  if (coarse_bf16 && !p.exhaustive)
+    HIPCHK(launch_frames_to_lp(HLOC_BF16, qp, p.nq, db->dp, c_lp, c_scale, c_err, c_lon, s));
   // fp32 accumulation of rounded products: |q~||d~| <= 1.004 |q||d| for bf16,
   // <= (1 + 2^-4)^2 |q||d| for fp8 (relative rounding of at most 2^-4 per
   // value; subnormals are absolute and covered by the rounding-error terms)
@@ -249,15 +265,15 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     sa.nq = p.nq;
     // large batches: 64 representatives staged in LDS against 256 frames at a
     // time (the wide kernels' dense mode) instead of re-reading them per 16
-    const bool coarse_lp = fmt && lpm->reps;
+    const bool coarse_lp = cfmt && cpm->reps;
     const bool wide_dense = p.nq >= kWideDenseFrames && (coarse_lp || f32_wide_supports(db->dp));
     if (coarse_lp) {
-      sa.rows_lp = lpm->reps;
-      sa.q_lp = ws->q_lp.p;
-      sa.row_scale = lpm->rep_scale;
-      sa.q_scale = as<float>(ws->q_scale);
-      HIPCHK(wide_dense ? launch_screen_wide_lp(fmt, sa, p.grid1, db->num_cu, s)
-                        : launch_screen_lp(fmt, sa, p.grid1, s));
+      sa.rows_lp = cpm->reps;
+      sa.q_lp = c_lp;
+      sa.row_scale = cpm->rep_scale;
+      sa.q_scale = c_scale;
+      HIPCHK(wide_dense ? launch_screen_wide_lp(cfmt, sa, p.grid1, db->num_cu, s)
+                        : launch_screen_lp(cfmt, sa, p.grid1, s));
     } else {
       HIPCHK(wide_dense ? launch_screen_wide_f32(sa, p.grid1, db->num_cu, s)
                         : launch_screen_f32(sa, p.grid1, s));
@@ -276,12 +292,12 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     ra.err_coef = coef;
     ra.max_norm = (double)db->h_rep_max * (1.0 + 1e-6);
     if (coarse_lp) {
-      ra.q_err = as<float>(ws->q_err);
-      ra.q_lon = as<float>(ws->q_lon);
-      ra.lo_dmax = (double)lpm->rep_err * (1.0 + 1e-6);
-      ra.lo_nmax = (double)lpm->rep_norm * (1.0 + 1e-6);
+      ra.q_err = c_err;
+      ra.q_lon = c_lon;
+      ra.lo_dmax = (double)cpm->rep_err * (1.0 + 1e-6);
+      ra.lo_nmax = (double)cpm->rep_norm * (1.0 + 1e-6);
       ra.lo_coef = 2.0 * (1.0 + 1e-6);
-      ra.err_coef = coef * lo_fp32;
+      ra.err_coef = coef * (cfmt == HLOC_FP8 ? 1.15 : 1.01);
     }
     ra.nq = p.nq;
     ra.reg_out = regions;
@@ -427,7 +443,8 @@ void free_ws(hloc_ws *ws) {
                    &ws->misc,     &ws->rq,       &ws->items,    &ws->cand2,   &ws->agg_xy,
                    &ws->agg_tile, &ws->agg_flags, &ws->s_q,     &ws->s_off,   &ws->s_idx,
                    &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags, &ws->q_lp,
-                   &ws->q_scale,  &ws->q_err,    &ws->q_lon,   &ws->slot_row};
+                   &ws->q_scale,  &ws->q_err,    &ws->q_lon,   &ws->slot_row,
+                   &ws->c_lp,     &ws->c_scale,  &ws->c_err,   &ws->c_lon};
   for (WsBuf *b : bufs) free_buf(*b);
   for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
   if (ws->stream) (void)hipStreamDestroy(ws->stream);
@@ -685,9 +702,12 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   }
   HIPCHK(launch_rep_finish(db->rep64, db->reg_start, R, db->dp, db->rep32, db->rep_n2,
                            db->norm_max + 1, db->stream));
+  // representatives: in each mirrored format; bf16 ones also beside an fp8
+  // mirror, for the coarse screen of fp8 queries (a bound 32 times tighter
+  // than fp8's, at 4 MB for 4,096 x 512)
   for (int fmt : {HLOC_BF16, HLOC_FP8}) {
     LpMirror &m = db->lp[fmt];
-    if (!m.rows) continue;
+    if (!m.rows && !(fmt == HLOC_BF16 && db->lp[HLOC_FP8].rows)) continue;
     float *mx = db->norm_max + 4 * fmt - 2;
     if ((rc = dev_alloc(reinterpret_cast<uint8_t **>(&m.reps), (size_t)R * db->dp * lp_bytes(fmt))))
       return rc;

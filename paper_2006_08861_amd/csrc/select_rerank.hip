@@ -349,12 +349,22 @@ __device__ __forceinline__ uint32_t row_of(const int32_t *s_off, const int32_t *
   return (uint32_t)(s_row[lo] + ((int32_t)p - s_off[lo]));
 }
 
+// Frame of block b in XCD-major order. Blocks go to the 8 XCDs round-robin
+// (b % 8), so XCD x takes the contiguous run of frames starting at
+// x * (n / 8) + min(x, n % 8): the frames of a request, which share most of
+// their candidate rows, run on one XCD and share its L2.
+__device__ __forceinline__ int xcd_frame(int b, int n) {
+  constexpr int kXcd = 8;
+  const int x = b % kXcd, j = b / kXcd, q = n / kXcd, r = n % kXcd;
+  return x * q + min(x, r) + j;
+}
+
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
   __shared__ SelShared sh;
   extern __shared__ uint32_t dyn[];  // [slot offsets | slot regions | word cache]
-  const int f = blockIdx.x;
-  if (f >= a.nq) return;
+  if ((int)blockIdx.x >= a.nq) return;
+  const int f = xcd_frame(blockIdx.x, a.nq);
   const int tid = threadIdx.x, w = wave_id(), lane = lane_id();
   const int nw = blockDim.x >> 6;
   const int nslots = a.nslots;
