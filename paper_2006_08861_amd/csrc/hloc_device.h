@@ -10,6 +10,17 @@ namespace hloc {
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// Four consecutive screen words written with one 16-byte store at any 4-byte
+// aligned address (global memory takes unaligned vector accesses on gfx950).
+struct __attribute__((packed, aligned(4))) Words4 {
+  uint32_t w[4];
+};
+
+__device__ __forceinline__ void store_words4(uint32_t *p, uint32_t a, uint32_t b, uint32_t c,
+                                             uint32_t d) {
+  *reinterpret_cast<Words4 *>(p) = Words4{{a, b, c, d}};
+}
+
 // Ascending bitonic sort of n (power of two) keys in LDS by the whole block.
 __device__ inline void block_sort_u64(uint64_t *a, int n) {
   for (int size = 2; size <= n; size <<= 1) {

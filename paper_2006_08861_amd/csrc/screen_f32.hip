@@ -359,19 +359,26 @@ __global__ __launch_bounds__(256) void k_screen_wide(ScreenArgs a) {
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv[s].w, acc, 0, 0, 0);
         }
         if (i < gs) {
+          // the lane's four rows are consecutive words of its frame's list
+          const int row0 = rb * 16 + 4 * g;
+          uint32_t wd[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = rb * 16 + 4 * g + r;
-            if (row < nrows) {
-              const float rn = s_rn[row];
-              uint32_t word = 0xFFFFFFFFu;
-              if (!__builtin_isinf(rn)) {
-                float dd = (qn + rn) - 2.f * acc[r];
-                dd = dd > 0.f ? dd : 0.f;
-                word = __float_as_uint(dd);
-              }
-              a.cand[off + row] = word;
+            const float rn = s_rn[min(row0 + r, 63)];
+            uint32_t word = 0xFFFFFFFFu;
+            if (!__builtin_isinf(rn)) {
+              float dd = (qn + rn) - 2.f * acc[r];
+              dd = dd > 0.f ? dd : 0.f;
+              word = __float_as_uint(dd);
             }
+            wd[r] = word;
+          }
+          if (row0 + 3 < nrows) {
+            store_words4(a.cand + off + row0, wd[0], wd[1], wd[2], wd[3]);
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (row0 + r < nrows) a.cand[off + row0 + r] = wd[r];
           }
         }
       }

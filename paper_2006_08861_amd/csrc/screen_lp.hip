@@ -373,10 +373,20 @@ __global__ __launch_bounds__(256) void k_screen_wide_lp(ScreenArgs a) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) acc = lp_mfma<FMT>(rp[4 * s], bv[s], acc);
         if (i < gs) {
+          // the lane's four rows are consecutive words of its frame's list
+          const int row0 = rb * 16 + 4 * g;
+          uint32_t wd[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = rb * 16 + 4 * g + r;
-            if (row < nrows) a.cand[off + row] = lp_word<FMT>(qn, s_rn[row], acc[r], qs, s_rs[row]);
+            const int row = min(row0 + r, 63);
+            wd[r] = lp_word<FMT>(qn, s_rn[row], acc[r], qs, s_rs[row]);
+          }
+          if (row0 + 3 < nrows) {
+            store_words4(a.cand + off + row0, wd[0], wd[1], wd[2], wd[3]);
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (row0 + r < nrows) a.cand[off + row0 + r] = wd[r];
           }
         }
       }
