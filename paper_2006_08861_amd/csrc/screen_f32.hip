@@ -238,20 +238,26 @@ __global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].w, bv[s].w, acc, 0, 0, 0);
       }
       if (i < gq) {
+        // the lane's four rows are consecutive words of its frame's list
+        const int row0 = rb * 16 + 4 * g;
+        uint32_t wd[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = rb * 16 + 4 * g + r;
-          if (row < nrows) {
-            const int grow = row_begin + row;
-            const float rn = a.row_n2[grow];
-            uint32_t word = 0xFFFFFFFFu;
-            if (!__builtin_isinf(rn)) {
-              float dd = (qn + rn) - 2.f * acc[r];
-              dd = dd > 0.f ? dd : 0.f;
-              word = __float_as_uint(dd);
-            }
-            a.cand[off + row] = word;
+          const float rn = a.row_n2[row_begin + min(row0 + r, nrows - 1)];
+          uint32_t word = 0xFFFFFFFFu;
+          if (!__builtin_isinf(rn)) {
+            float dd = (qn + rn) - 2.f * acc[r];
+            dd = dd > 0.f ? dd : 0.f;
+            word = __float_as_uint(dd);
           }
+          wd[r] = word;
+        }
+        if (row0 + 3 < nrows) {
+          store_words4(a.cand + off + row0, wd[0], wd[1], wd[2], wd[3]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (row0 + r < nrows) a.cand[off + row0 + r] = wd[r];
         }
       }
       if (!DENSE && rb == w && itn < hi) {

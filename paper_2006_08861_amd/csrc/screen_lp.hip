@@ -279,14 +279,21 @@ __global__ __launch_bounds__(256) void k_screen_lp(ScreenArgs a) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) acc = lp_mfma<FMT>(av[s], bv[s], acc);
       if (i < gq) {
+        // the lane's four rows are consecutive words of its frame's list
+        const int row0 = rb * 16 + 4 * g;
+        uint32_t wd[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = rb * 16 + 4 * g + r;
-          if (row < nrows) {
-            const int grow = row_begin + row;
-            const float rs = FMT == HLOC_FP8 ? a.row_scale[grow] : 1.f;
-            a.cand[off + row] = lp_word<FMT>(qn, a.row_n2[grow], acc[r], qs, rs);
-          }
+          const int grow = row_begin + min(row0 + r, nrows - 1);
+          const float rs = FMT == HLOC_FP8 ? a.row_scale[grow] : 1.f;
+          wd[r] = lp_word<FMT>(qn, a.row_n2[grow], acc[r], qs, rs);
+        }
+        if (row0 + 3 < nrows) {
+          store_words4(a.cand + off + row0, wd[0], wd[1], wd[2], wd[3]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (row0 + r < nrows) a.cand[off + row0 + r] = wd[r];
         }
       }
       if (!DENSE && rb == w && itn < hi) {
