@@ -488,10 +488,13 @@ def main():
     coarse_ms = phases["coarse"][0] / max(phases["coarse"][1], 1)
     s1_flops = 2.0 * nq * w.n_regions_total * d
     s1_tf = s1_flops / (coarse_ms * 1e-3) / 1e12 if coarse_ms > 0 else 0.0
+    # fp8 queries screen the representatives in bf16 (bf16 copies are kept
+    # beside an fp8 mirror)
+    s1_dtype = "bf16" if a.precision == "fp8" else a.precision
     stage1 = {"kernel": "coarse screen (" + ("wide" if nq >= 512 else "narrow") + " kernel, dense)",
-              "flops": s1_flops, "avg_launch_ms": coarse_ms, "achieved": s1_tf,
-              "peak": MFMA_PEAK_TFLOPS[a.precision], "unit": "TFLOP/s",
-              "frac": s1_tf / MFMA_PEAK_TFLOPS[a.precision]}
+              "dtype": s1_dtype, "flops": s1_flops, "avg_launch_ms": coarse_ms, "achieved": s1_tf,
+              "peak": MFMA_PEAK_TFLOPS[s1_dtype], "unit": "TFLOP/s",
+              "frac": s1_tf / MFMA_PEAK_TFLOPS[s1_dtype]}
     gpu_idx = idx.cpu().numpy()
 
     base, recall, exact, m = (None, None, None, 0)
