@@ -333,6 +333,43 @@ __device__ void sort_pairs(SelShared &sh, int cnt) {
   block_sort_pairs(sh.sort_hi, sh.sort_lo, P);
 }
 
+// Entries [s, s + nb) (re-scored band rows, unsorted) merged into the sorted
+// [0, s), s >= m: only band entries ordered before the m-th of [0, s) can
+// enter the best m, so they are copied (through the select's histogram,
+// free by now) behind the first m and those m + few are sorted;
+// sort_hi / sort_lo[0, m) then hold the best m of all s + nb.
+__device__ __noinline__ void merge_band(SelShared &sh, int s, int nb, int m) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const uint64_t mh = sh.sort_hi[m - 1];
+  const uint32_t ml = sh.sort_lo[m - 1];
+  auto before = [&](int t) {
+    const uint64_t h = sh.sort_hi[t];
+    return h < mh || (h == mh && sh.sort_lo[t] < ml);
+  };
+  int c = 0;
+  for (int t = s + tid; t < s + nb; t += nt) c += before(t);
+  const int incl = block_incl_scan(c, sh.red_i);
+  if (tid == nt - 1) sh.eq = incl;
+  int pos = incl - c;
+  uint32_t *tmp = reinterpret_cast<uint32_t *>(sh.hist);  // 3 words per entry (nb <= 1024)
+  for (int t = s + tid; t < s + nb; t += nt) {
+    if (before(t)) {
+      const uint64_t h = sh.sort_hi[t];
+      tmp[3 * pos] = (uint32_t)h;
+      tmp[3 * pos + 1] = (uint32_t)(h >> 32);
+      tmp[3 * pos + 2] = sh.sort_lo[t];
+      ++pos;
+    }
+  }
+  __syncthreads();
+  const int few = sh.eq;
+  for (int i = tid; i < few; i += nt) {
+    sh.sort_hi[m + i] = ((uint64_t)tmp[3 * i + 1] << 32) | tmp[3 * i];
+    sh.sort_lo[m + i] = tmp[3 * i + 2];
+  }
+  sort_pairs(sh, m + few);  // (begins with a barrier)
+}
+
 // Source row of candidate position p of a frame: with region slots, slot j
 // holds the rows from s_row[j] on at positions s_off[j] .. (s_off[0] = 0,
 // non-decreasing; the slot holding p is the last with s_off[j] <= p, and it
@@ -670,7 +707,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
       __syncthreads();
       rerank_range<BLOCK == 1024>(a, sh, qrow, nsurv, nsurv + total_band);
       __syncthreads();
-      sort_pairs(sh, nsurv + total_band);
+      merge_band(sh, nsurv, total_band, a.m);
       have = min(nsurv + total_band, a.m);
     } else {
       // a band too large for one pass: re-scored in chunks of up to
@@ -698,7 +735,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
         __syncthreads();
         rerank_range<BLOCK == 1024>(a, sh, qrow, kept, kept + cnt);
         __syncthreads();
-        sort_pairs(sh, kept + cnt);
+        merge_band(sh, kept, cnt, m);
         kept = min(kept + cnt, m);
       }
       have = kept;
