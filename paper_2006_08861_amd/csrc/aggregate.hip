@@ -18,6 +18,8 @@
 #include "hloc_device.h"
 #include "hloc_internal.h"
 
+#include <algorithm>
+
 namespace hloc {
 
 constexpr int kAggMax = 4096;  // pooled candidates of one request
@@ -26,15 +28,25 @@ constexpr int kFlagLow = 1, kFlagEmpty = 2, kFlagBad = 4;
 __device__ __forceinline__ uint32_t flip(int32_t v) { return (uint32_t)v ^ 0x80000000u; }
 __device__ __forceinline__ int32_t unflip(uint32_t v) { return (int32_t)(v ^ 0x80000000u); }
 
-__global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
-  extern __shared__ uint64_t lds[];
-  uint64_t *s_key = lds;               // kAggMax sorted tile keys
-  uint64_t *s_rank = lds + kAggMax;    // kAggMax rank keys
-  int *s_pos = reinterpret_cast<int *>(lds + 2 * kAggMax);  // kAggMax + 1 run starts
-  __shared__ int scratch[16];
-  __shared__ int s_circle[64];
-  const int req = blockIdx.x;
-  if (req >= a.nreq) return;
+constexpr int kAggSmall = 512;  // pooled candidates up to which a request takes the small kernel
+
+// Pooled candidates of request req (0 for an empty or malformed request).
+__device__ __forceinline__ int pooled_of(const AggArgs &a, int req) {
+  const int f0 = a.req_offsets ? a.req_offsets[req] : req;
+  const int f1 = a.req_offsets ? a.req_offsets[req + 1] : req + 1;
+  const int kr = a.req_k ? a.req_k[req] : a.k;
+  if (f0 < 0 || f1 < f0 || f1 > a.nq || kr < 1 || kr > a.k) return 0;
+  return (int)min<int64_t>((int64_t)(f1 - f0) * kr, (int64_t)kAggMax + 1);
+}
+
+// Algorithm 2 for one request with LDS lists of CAP entries (the request
+// pools at most CAP candidates, or is malformed).
+template <int CAP>
+__device__ void aggregate_one(const AggArgs &a, int req, uint64_t *lds, int *scratch,
+                              int *s_circle) {
+  uint64_t *s_key = lds;           // CAP sorted tile keys
+  uint64_t *s_rank = lds + CAP;    // CAP rank keys
+  int *s_pos = reinterpret_cast<int *>(lds + 2 * CAP);  // CAP + 1 run starts
   const int tid = threadIdx.x;
   int f0, f1;
   if (a.req_offsets) {
@@ -46,7 +58,7 @@ __global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
   }
   const int kr = a.req_k ? a.req_k[req] : a.k;  // candidates pooled per frame
   const bool bad = f0 < 0 || f1 < f0 || f1 > a.nq || kr < 1 || kr > a.k ||
-                   (int64_t)(f1 - f0) * kr > (int64_t)kAggMax;
+                   (int64_t)(f1 - f0) * kr > (int64_t)CAP;
   if (bad) {
     if (tid == 0) {
       a.tile[2 * req] = 0;
@@ -145,7 +157,46 @@ __global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
   }
 }
 
-constexpr size_t kAggLds = 2 * kAggMax * sizeof(uint64_t) + (kAggMax + 1) * sizeof(int);
+template <int CAP>
+constexpr size_t agg_lds() {
+  return 2 * CAP * sizeof(uint64_t) + (CAP + 1) * sizeof(int);
+}
+
+// One block per request. Requests pooling more than kAggSmall candidates
+// (up to kAggMax) are listed for k_aggregate_big instead: the small LDS
+// lets many blocks share a compute unit.
+__global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
+  __shared__ uint64_t lds[agg_lds<kAggSmall>() / sizeof(uint64_t) + 1];
+  __shared__ int scratch[16];
+  __shared__ int s_circle[64];
+  const int req = blockIdx.x;
+  if (req >= a.nreq) return;
+  const int P = pooled_of(a, req);
+  if (P > kAggSmall && P <= kAggMax) {
+    if (threadIdx.x == 0) a.big_list[atomicAdd(a.big_count, 1)] = req;
+    return;
+  }
+  aggregate_one<kAggSmall>(a, req, lds, scratch, s_circle);
+}
+
+// The listed requests, a persistent grid over them; without a list, request
+// blockIdx.x (every request of a batch that fits one round of blocks).
+__global__ __launch_bounds__(256) void k_aggregate_big(AggArgs a) {
+  extern __shared__ uint64_t lds_big[];
+  __shared__ int scratch[16];
+  __shared__ int s_circle[64];
+  if (!a.big_list) {
+    if ((int)blockIdx.x < a.nreq) aggregate_one<kAggMax>(a, blockIdx.x, lds_big, scratch, s_circle);
+    return;
+  }
+  const int n = *a.big_count;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    __syncthreads();  // the previous request's lists are no longer read
+    aggregate_one<kAggMax>(a, a.big_list[i], lds_big, scratch, s_circle);
+  }
+}
+
+constexpr size_t kAggLds = agg_lds<kAggMax>();
 
 // LDS limit of the aggregation kernel, set once per device.
 hipError_t prepare_aggregate_kernels() {
@@ -153,7 +204,7 @@ hipError_t prepare_aggregate_kernels() {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess || done_dev == dev) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_aggregate),
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_aggregate_big),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kAggLds);
   if (e == hipSuccess) done_dev = dev;
   return e;
@@ -162,7 +213,17 @@ hipError_t prepare_aggregate_kernels() {
 hipError_t launch_aggregate(const AggArgs &a, hipStream_t s) {
   if (a.nreq <= 0) return hipSuccess;
   if (a.top_c < 1 || a.top_c > 64) return hipErrorInvalidValue;
-  return launch_kernel(k_aggregate, dim3(a.nreq), dim3(256), kAggLds, s, a);
+  const int32_t cus = std::max(a.num_cu, 1);
+  if (a.nreq <= cus) {
+    // one round of blocks: a single launch with the large lists
+    AggArgs b = a;
+    b.big_list = nullptr;
+    return launch_kernel(k_aggregate_big, dim3(a.nreq), dim3(256), kAggLds, s, b);
+  }
+  hipError_t e = launch_kernel(k_aggregate, dim3(a.nreq), dim3(256), 0, s, a);
+  if (e != hipSuccess) return e;
+  // one resident block per compute unit at most (the lists take 82 KB of LDS)
+  return launch_kernel(k_aggregate_big, dim3(cus), dim3(256), kAggLds, s, a);
 }
 
 }  // namespace hloc

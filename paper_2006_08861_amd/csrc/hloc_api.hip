@@ -167,6 +167,7 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *byte
     CHK(fit(ws->c_err, (size_t)nq * sizeof(float)));
     CHK(fit(ws->c_lon, (size_t)nq * sizeof(float)));
   }
+  CHK(fit(ws->agg_big, (size_t)std::max(p.nreq, 1) * sizeof(int32_t)));
   if (agg_internal) {
     const int64_t nreq = std::max(p.nreq, 1);
     CHK(fit(ws->agg_xy, (size_t)nreq * 2 * sizeof(double)));
@@ -393,6 +394,9 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     ag.xy = xy ? xy : as<double>(ws->agg_xy);
     ag.tile = tile ? tile : as<int32_t>(ws->agg_tile);
     ag.flags = flags ? flags : as<int32_t>(ws->agg_flags);
+    ag.big_list = as<int32_t>(ws->agg_big);
+    ag.big_count = misc + 8;
+    ag.num_cu = db->num_cu;
     ph.begin(HLOC_PHASE_AGGREGATE);
     HIPCHK(launch_aggregate(ag, s));
   }
@@ -444,7 +448,7 @@ void free_ws(hloc_ws *ws) {
                    &ws->agg_tile, &ws->agg_flags, &ws->s_q,     &ws->s_off,   &ws->s_idx,
                    &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags, &ws->q_lp,
                    &ws->q_scale,  &ws->q_err,    &ws->q_lon,   &ws->slot_row,
-                   &ws->c_lp,     &ws->c_scale,  &ws->c_err,   &ws->c_lon};
+                   &ws->c_lp,     &ws->c_scale,  &ws->c_err,   &ws->c_lon,   &ws->agg_big};
   for (WsBuf *b : bufs) free_buf(*b);
   for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
   if (ws->stream) (void)hipStreamDestroy(ws->stream);

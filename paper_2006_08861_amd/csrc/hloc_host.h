@@ -88,7 +88,8 @@ struct hloc_ws {
   hipStream_t stream = nullptr;  // own stream (graph capture, host-pointer calls)
   hloc::WsBuf qp, qn2, cand1, regions, rcount, rfill, vord, rq_off, item_off, cand_off, n_cand, misc, rq,
       items, cand2, agg_xy, agg_tile, agg_flags, q_lp, q_scale, q_err, q_lon, slot_row,
-      c_lp, c_scale, c_err, c_lon;  // bf16 frame copy for the coarse screen of fp8 queries
+      c_lp, c_scale, c_err, c_lon,  // bf16 frame copy for the coarse screen of fp8 queries
+      agg_big;                      // requests for the large-list aggregation kernel
   hloc::WsBuf s_q, s_off, s_idx, s_dist, s_xy, s_tile, s_flags;  // staging of host-pointer calls
   int32_t last_nq = 0, last_nr = 0, last_kp = 0;
   bool prof_on = false;

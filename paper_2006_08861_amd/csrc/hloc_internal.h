@@ -249,6 +249,9 @@ struct AggArgs {
   double *xy;
   int32_t *tile;
   int32_t *flags;
+  int32_t *big_list;   // nreq: requests pooling more than 512 candidates
+  int32_t *big_count;  // zero on entry
+  int32_t num_cu;
 };
 hipError_t launch_aggregate(const AggArgs &a, hipStream_t s);
 

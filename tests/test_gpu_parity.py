@@ -174,6 +174,26 @@ def test_schedule_paths(torch_cuda, nq, n_reg):
     assert st["recall"] == 1.0
 
 
+@pytest.mark.parametrize("many", [False, True])
+def test_requests_with_large_pools(torch_cuda, many):
+    # requests pooling more than 512 candidates: with at most one request per
+    # compute unit one launch takes every request; with more, they are listed
+    # for the large-list kernel and the others take the small one
+    rng, feats, xy, region_of = _random_db(5, 5000, 32, 50)
+    if many:
+        sizes = [16 if r % 50 == 0 else 1 for r in range(300)] + [24]
+    else:
+        sizes = [16, 1, 16, 7, 24]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    nq = int(offs[-1])
+    q = (feats[rng.integers(0, 5000, nq)] + 0.2 * rng.standard_normal((nq, 32))).astype(np.float32)
+    st, _, out = check_all(torch_cuda, feats, xy, region_of, 50, q, 40, 5, offs,
+                           agg=(0.5, 3, 1.0, 20),
+                           name=f"pools of 40 to 960 candidates, {len(sizes)} requests")
+    assert st["recall"] == 1.0
+    assert np.all(out["flags"] & 6 == 0)  # neither empty nor rejected
+
+
 def test_exhaustive_mode(torch_cuda):
     rng, feats, xy, region_of = _random_db(2, 2000, 24, 20)
     q = rng.standard_normal((33, 24)).astype(np.float32)
