@@ -176,16 +176,27 @@ __global__ void k_sched_count(const int32_t *__restrict__ regions, int nq, int n
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nq) return;
   int off = 0;
-  for (int j = 0; j < nr; ++j) {
-    const int r = regions[(int64_t)f * nr + j];
-    cand_off[(int64_t)f * nr + j] = off;
-    if (r < 0 || r >= R) {
-      slot_row[(int64_t)f * nr + j] = 0;
-      continue;
+  for (int j0 = 0; j0 < nr; j0 += 8) {
+    // ids, then first rows and sizes, then updates: eight loads in flight per step
+    int r[8], r0[8], sz[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      r[u] = j0 + u < nr ? regions[(int64_t)f * nr + j0 + u] : -1;
+      if (r[u] >= R) r[u] = -1;
     }
-    slot_row[(int64_t)f * nr + j] = (int32_t)reg_start[r];
-    off += (int)(reg_start[r + 1] - reg_start[r]);
-    atomicAdd(&rcount[r], 1);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      r0[u] = r[u] >= 0 ? (int)reg_start[r[u]] : 0;
+      sz[u] = r[u] >= 0 ? (int)(reg_start[r[u] + 1] - r0[u]) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (j0 + u >= nr) break;
+      cand_off[(int64_t)f * nr + j0 + u] = off;
+      slot_row[(int64_t)f * nr + j0 + u] = r0[u];
+      off += sz[u];
+      if (r[u] >= 0) atomicAdd(&rcount[r[u]], 1);
+    }
   }
   n_cand[f] = off;
 }
@@ -358,7 +369,7 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
   hipError_t e = launch_fill_i32(rcount, R, 0, s);
   if (e != hipSuccess) return e;
   if (nq > 0) {
-    if ((e = launch_kernel(k_sched_count, dim3((nq + 255) / 256), dim3(256), 0, s, regions, nq,
+    if ((e = launch_kernel(k_sched_count, dim3((nq + 63) / 64), dim3(64), 0, s, regions, nq,
                            nr, R, reg_start, rcount, cand_off, slot_row, n_cand)) != hipSuccess)
       return e;
   }
