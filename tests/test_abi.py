@@ -133,3 +133,16 @@ def test_header_limits_match_binding_constants():
                       ("HLOC_EBUSY", hloc.EBUSY), ("HLOC_ETIMEDOUT", hloc.ETIMEDOUT),
                       ("HLOC_FLAG_EMPTY", hloc.FLAG_EMPTY), ("HLOC_MIRROR_BF16", hloc.MIRROR_BF16)):
         assert f"{name} = {val}" in text
+
+
+def test_phase_and_info_counts_match_header():
+    # the binding names one profile phase per HLOC_PHASE_* and reads as many
+    # query counters as the header documents
+    import re
+    with open(hloc.HEADER) as f:
+        text = f.read()
+    n_phases = int(re.search(r"HLOC_NUM_PHASES = (\d+)", text).group(1))
+    assert len(hloc.HlocDB.PHASES) == n_phases
+    n_info = int(re.search(r"Writes min\(n, (\d+)\) values", text).group(1))
+    assert len(hloc._INFO_KEYS) == n_info
+
