@@ -170,11 +170,12 @@ hipError_t launch_broadcast_ids(const int32_t *ids, int32_t nr, int32_t nq, int3
 // Multi-kernel schedule for large region counts. Per frame: offset of each
 // kept region in the frame's candidate list and its first row, and the list
 // length. Per region: how many frames kept it.
-__global__ void k_sched_count(const int32_t *__restrict__ regions, int nq, int nr, int R,
-                              const int64_t *__restrict__ reg_start, int32_t *rcount,
-                              int32_t *cand_off, int32_t *slot_row, int32_t *n_cand) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nq) return;
+// Frame f's candidate-list offsets, slot rows and length; counts its regions
+// in cnt.
+__device__ __forceinline__ void count_frame(const int32_t *__restrict__ regions, int f, int nr,
+                                            int R, const int64_t *__restrict__ reg_start,
+                                            int32_t *cnt, int32_t *cand_off, int32_t *slot_row,
+                                            int32_t *n_cand) {
   int off = 0;
   for (int j0 = 0; j0 < nr; j0 += 8) {
     // ids, then first rows and sizes, then updates: eight loads in flight per step
@@ -195,10 +196,33 @@ __global__ void k_sched_count(const int32_t *__restrict__ regions, int nq, int n
       cand_off[(int64_t)f * nr + j0 + u] = off;
       slot_row[(int64_t)f * nr + j0 + u] = r0[u];
       off += sz[u];
-      if (r[u] >= 0) atomicAdd(&rcount[r[u]], 1);
+      if (r[u] >= 0) atomicAdd(&cnt[r[u]], 1);
     }
   }
   n_cand[f] = off;
+}
+
+// With LDS (R <= kHistR) the block counts in LDS and adds each nonzero count
+// to rcount once: a region kept by many frames (one 2,048-frame batch of the
+// 2 M-row shape has one kept by 1,367) would otherwise take that many
+// atomics on one word, one after another.
+template <bool LDS>
+__global__ void k_sched_count(const int32_t *__restrict__ regions, int nq, int nr, int R,
+                              const int64_t *__restrict__ reg_start, int32_t *rcount,
+                              int32_t *cand_off, int32_t *slot_row, int32_t *n_cand) {
+  extern __shared__ int32_t s_cnt[];  // R (LDS mode)
+  if (LDS) {
+    for (int i = threadIdx.x; i < R; i += blockDim.x) s_cnt[i] = 0;
+    __syncthreads();
+  }
+  int32_t *cnt = LDS ? s_cnt : rcount;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < nq) count_frame(regions, f, nr, R, reg_start, cnt, cand_off, slot_row, n_cand);
+  if (LDS) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < R; i += blockDim.x)
+      if (s_cnt[i]) atomicAdd(&rcount[i], s_cnt[i]);
+  }
 }
 
 // One block: the scans of sched_scan over the region counts; clears rfill.
@@ -212,16 +236,33 @@ __global__ __launch_bounds__(1024) void k_sched_scan(const int32_t *__restrict__
   for (int r = threadIdx.x; r < R; r += blockDim.x) rfill[r] = 0;
 }
 
+// Each (frame, region) pair into its region's frame list. With LDS
+// (R <= kHistR) the block ranks its pairs per region in LDS and reserves one
+// range per region it touches with a single atomic.
+template <bool LDS>
 __global__ void k_sched_scatter(const int32_t *__restrict__ regions, int nq, int nr, int R,
                                 const int32_t *__restrict__ cand_off,
                                 const int32_t *__restrict__ rq_off, int32_t *rfill, int2 *rq) {
+  extern __shared__ int32_t s_sc[];  // R counts, then R bases (LDS mode)
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= (int64_t)nq * nr) return;
-  const int f = (int)(t / nr);
-  const int r = regions[t];
-  if (r < 0 || r >= R) return;
-  const int pos = rq_off[r] + atomicAdd(&rfill[r], 1);
-  rq[pos] = make_int2(f, cand_off[t]);
+  const bool in = t < (int64_t)nq * nr;
+  const int r = in ? regions[t] : -1;
+  const bool ok = r >= 0 && r < R;
+  if (!LDS) {
+    if (!ok) return;
+    const int pos = rq_off[r] + atomicAdd(&rfill[r], 1);
+    rq[pos] = make_int2((int)(t / nr), cand_off[t]);
+    return;
+  }
+  int32_t *s_cnt = s_sc, *s_base = s_sc + R;
+  for (int i = threadIdx.x; i < R; i += blockDim.x) s_cnt[i] = 0;
+  __syncthreads();
+  const int local = ok ? atomicAdd(&s_cnt[r], 1) : 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < R; i += blockDim.x)
+    if (s_cnt[i]) s_base[i] = rq_off[i] + atomicAdd(&rfill[i], s_cnt[i]);
+  __syncthreads();
+  if (ok) rq[s_base[r] + local] = make_int2((int)(t / nr), cand_off[t]);
 }
 
 // One thread per work item (grid-stride), each finding its region by binary
@@ -247,6 +288,7 @@ __global__ void k_sched_items(int R, const int32_t *__restrict__ vord,
 // a value written earlier in the kernel, and work items are expanded one per
 // thread.
 constexpr int kFusedMaxR = 8192;
+constexpr int kHistR = 8192;  // regions up to which the multi-kernel schedule counts in LDS
 constexpr int64_t kFusedMaxPairs = 8192;  // larger batches: the multi-kernel path is faster
 constexpr int kFusedRegs = 8;             // regions per frame kept in registers between steps
 
@@ -368,18 +410,25 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
   }
   hipError_t e = launch_fill_i32(rcount, R, 0, s);
   if (e != hipSuccess) return e;
+  const bool hist = R <= kHistR;
   if (nq > 0) {
-    if ((e = launch_kernel(k_sched_count, dim3((nq + 63) / 64), dim3(64), 0, s, regions, nq,
-                           nr, R, reg_start, rcount, cand_off, slot_row, n_cand)) != hipSuccess)
-      return e;
+    e = hist ? launch_kernel(k_sched_count<true>, dim3((nq + 255) / 256), dim3(256),
+                             (uint32_t)(R * sizeof(int32_t)), s, regions, nq, nr, R, reg_start,
+                             rcount, cand_off, slot_row, n_cand)
+             : launch_kernel(k_sched_count<false>, dim3((nq + 63) / 64), dim3(64), 0, s, regions,
+                             nq, nr, R, reg_start, rcount, cand_off, slot_row, n_cand);
+    if (e != hipSuccess) return e;
   }
   if ((e = launch_kernel(k_sched_scan, dim3(1), dim3(1024), 0, s, rcount, R, reg_start, T,
                          rq_off, vord, item_off, n_items, rfill)) != hipSuccess)
     return e;
   if (pairs > 0) {
-    if ((e = launch_kernel(k_sched_scatter, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0,
-                           s, regions, nq, nr, R, cand_off, rq_off, rfill, rq)) != hipSuccess)
-      return e;
+    e = hist ? launch_kernel(k_sched_scatter<true>, dim3((unsigned)((pairs + 1023) / 1024)),
+                             dim3(1024), (uint32_t)(2 * R * sizeof(int32_t)), s, regions, nq, nr,
+                             R, cand_off, rq_off, rfill, rq)
+             : launch_kernel(k_sched_scatter<false>, dim3((unsigned)((pairs + 255) / 256)),
+                             dim3(256), 0, s, regions, nq, nr, R, cand_off, rq_off, rfill, rq);
+    if (e != hipSuccess) return e;
   }
   return launch_kernel(k_sched_items, dim3(1024), dim3(256), 0, s, R, vord, item_off, rq_off,
                        reg_start, T, items);

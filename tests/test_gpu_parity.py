@@ -162,11 +162,13 @@ def test_ragged_dims_empty_regions(torch_cuda):
         assert st["recall"] == 1.0
 
 
-@pytest.mark.parametrize("nq,n_reg", [(1500, 4), (600, 12), (300, 8)])
+@pytest.mark.parametrize("nq,n_reg", [(1500, 4), (600, 12), (300, 8), (1200, 8)])
 def test_schedule_paths(torch_cuda, nq, n_reg):
     # the one-block schedule keeps a frame's regions in registers when every
     # frame has its own thread and keeps at most 8 regions; more frames than
-    # threads, or more regions per frame, take its general loop
+    # threads, or more regions per frame, take its general loop; more than
+    # 8,192 (frame, region) pairs over few regions take the multi-kernel
+    # schedule with per-block LDS counts
     rng, feats, xy, region_of = _random_db(4, 4000, 48, 120, empty=5)
     q = (feats[rng.integers(0, 4000, nq)] + 0.2 * rng.standard_normal((nq, 48))).astype(np.float32)
     st, _, _ = check_all(torch_cuda, feats, xy, region_of, 120, q, 9, n_reg,
