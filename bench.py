@@ -468,14 +468,19 @@ def main():
     wall_prof = time.perf_counter() - t1
     phases = db.profile_read()
     db.profile(False)
-    # latency: one batch at a time, host to host
-    lat = []
+    # latency: one batch at a time, host to host, and on the device (HIP
+    # events on the query stream around the batch)
+    lat, lat_dev = [], []
     for _ in range(a.latency_reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t1 = time.perf_counter()
+        e0.record(stream)
         step()
+        e1.record(stream)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e3)
-    lat = np.array(lat)
+        lat_dev.append(e0.elapsed_time(e1))
+    lat, lat_dev = np.array(lat), np.array(lat_dev)
     # the fine screen: the narrow-item kernel, plus the wide-item kernel that
     # follows it when some region is kept by more than 16 frames
     wide_items = info["items"] - info["narrow_items"]
@@ -522,6 +527,8 @@ def main():
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "latency": f"host-to-host time of one batch, {len(lat)} batches run one at a time",
+        "device_p50_ms": float(np.percentile(lat_dev, 50)),
+        "device_p99_ms": float(np.percentile(lat_dev, 99)),
         "recall_at_k": recall,
         "exact_lists": None if base is None else f"{exact}/{m}",
         "roofline": {"bound": "hbm",
