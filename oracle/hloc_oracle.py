@@ -26,6 +26,9 @@ for Indoor Localization" (ICMR 2016).
   and the first of the TopC best tiles whose tolerance circle holds more than
   tolerPer of all candidates is the location estimate.
 
+* Omnidirectional feature (Section 3): the magnitude of the discrete Fourier
+  transform of a 1-D panoramic signal, bins 0 .. d-1 (`fft_magnitude`).
+
 Readings where the paper is silent (each repeated in the design notes):
 distances are squared L2 (same ranking as Euclidean); ties rank by (d^2,
 original row index) and regions by (d^2, region id); fewer than k candidates pad
@@ -226,3 +229,31 @@ def localize(feats, xy, region_of, n_regions_total, q, req_offsets, k, n_reg, ag
         tile[i], pos[i], flags[i] = (ix, iy), (x, y), fl
     res.update(tile=tile, pos=pos, flags=flags)
     return res
+
+
+# ------------------------------------------------- omnidirectional feature
+def fft_magnitude(signals, d: int) -> np.ndarray:
+    """Rotation-invariant omnidirectional feature (Section 3): the magnitude
+    of the discrete Fourier transform of a 1-D panoramic signal.
+
+    For each row x of `signals` (m x L, L >= 2) returns
+        |X_j| = | sum_{t < L} x_t exp(-2 pi i j t / L) |,  j = 0 .. d-1,
+    with 1 <= d <= L/2 + 1 (the remaining bins mirror these for real x).
+    Written out from the definition in FP64, with no fast transform: the
+    angle of each term is reduced exactly (j t mod L) before the cosine and
+    sine, the two real sums are a plain matrix product, and the magnitude is
+    sqrt(re^2 + im^2). A circular shift of x (a rotation of the panorama)
+    multiplies X_j by a unit phase and leaves |X_j| unchanged.
+    """
+    x = np.asarray(signals, dtype=np.float64)
+    if x.ndim != 2 or x.shape[1] < 2:
+        raise ValueError("signals must be m x L with L >= 2")
+    L = x.shape[1]
+    if not 1 <= d <= L // 2 + 1:
+        raise ValueError(f"d must be in 1..{L // 2 + 1}")
+    j = np.arange(d, dtype=np.int64)[:, None]
+    t = np.arange(L, dtype=np.int64)[None, :]
+    angle = (2.0 * math.pi / L) * ((j * t) % L)
+    re = x @ np.cos(angle).T
+    im = -(x @ np.sin(angle).T)
+    return np.sqrt(re * re + im * im)

@@ -16,6 +16,9 @@ available, so this module draws stand-ins with the same structure:
   replaced by decoys from another region (the paper's scene-similarity problem,
   Section 3).
 
+* panoramic signals: 1-D omnidirectional signals (one grey level per viewing
+  direction) for the Fourier-magnitude feature of Section 3.
+
 Inputs only: nothing in this module computes a distance, a ranking, a tile or
 a vote. Both the HIP path and the oracle receive what it returns.
 """
@@ -234,3 +237,22 @@ def make_workload(index: int, nq: int | None = None, n: int | None = None,
                                               0.10, 1.0, rng)
     return Workload(feats, xy, region_of, int(s["r"]), q, offs, truth, s["k"], s["n_reg"],
                     s["agg"], s["name"])
+
+
+def panoramic_signals(n: int, length: int, rng: np.random.Generator) -> np.ndarray:
+    """Stand-ins for 1-D omnidirectional signals, float32 n x length (one value
+    per viewing direction around the camera, such as a column mean of the
+    panorama): a grey level of 128, a smooth periodic profile (white noise
+    circularly smoothed by a Gaussian of width length / 32, centred and scaled
+    to standard deviation 40) and pixel noise of standard deviation 2."""
+    if length < 2:
+        raise ValueError("length must be >= 2")
+    w = max(1.0, length / 32)
+    half = int(min(length // 2, math.ceil(3 * w)))
+    taps = np.exp(-0.5 * (np.arange(-half, half + 1) / w) ** 2)
+    white = rng.standard_normal((n, length))
+    padded = np.concatenate([white[:, length - half:], white, white[:, :half]], axis=1)
+    smooth = lfilter(taps, [1.0], padded, axis=1)[:, 2 * half:]
+    smooth -= smooth.mean(axis=1, keepdims=True)
+    smooth *= 40.0 / np.maximum(smooth.std(axis=1, keepdims=True), 1e-12)
+    return (128.0 + smooth + 2.0 * rng.standard_normal((n, length))).astype(np.float32)

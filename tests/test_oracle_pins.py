@@ -274,3 +274,66 @@ def test_duplicates_across_frames_change_the_estimate():
     res = oracle.localize(feats, xy, np.zeros(7, int), 1, q, [0, 3], 3, 1, (0.5, 1, 0.0, 0))
     assert res["tile"][0].tolist() == [5, 5]
     assert res["pos"][0].tolist() == [2.75, 2.75]
+
+
+# ------------------------------------------------ FFT-magnitude feature pins
+def test_fft_magnitude_hand_case():
+    # x = (1, 2, 3, 4): X_0 = 10, X_1 = -2 + 2i, X_2 = -2 (worked by hand)
+    got = oracle.fft_magnitude([[1.0, 2.0, 3.0, 4.0]], 3)
+    assert np.allclose(got, [[10.0, 2.0 * math.sqrt(2.0), 2.0]], rtol=1e-15, atol=1e-14)
+    # L = 2: X_0 = x0 + x1, X_1 = x0 - x1
+    assert np.allclose(oracle.fft_magnitude([[3.0, -5.0]], 2), [[2.0, 8.0]], rtol=0, atol=1e-14)
+
+
+def test_fft_magnitude_matches_library_transform():
+    """The definition written out agrees with numpy's fast real transform."""
+    rng = np.random.default_rng(7)
+    for L in (2, 3, 8, 12, 64, 512):
+        x = rng.standard_normal((5, L)) * 10
+        d = L // 2 + 1
+        lib = np.abs(np.fft.rfft(x, axis=1))[:, :d]
+        got = oracle.fft_magnitude(x, d)
+        assert np.allclose(got, lib, rtol=0, atol=1e-11 * np.abs(x).sum()), L
+
+
+def test_fft_magnitude_tones_and_constant():
+    """A constant c gives |c| L in bin 0 only; A cos(2 pi m t / L + phi) gives
+    A L / 2 in bin m only (0 < m < L/2)."""
+    L, d = 256, 129
+    t = np.arange(L)
+    const = oracle.fft_magnitude(np.full((1, L), -2.5), d)[0]
+    assert abs(const[0] - 2.5 * L) < 1e-10 and np.all(const[1:] < 1e-10)
+    for m, A, phi in ((1, 3.0, 0.3), (17, 0.5, -1.1), (127, 7.0, 2.0)):
+        tone = oracle.fft_magnitude((A * np.cos(2 * np.pi * m * t / L + phi))[None], d)[0]
+        assert abs(tone[m] - A * L / 2) < 1e-9, m
+        rest = np.delete(tone, m)
+        assert np.all(rest < 1e-9), m
+
+
+def test_fft_magnitude_invariances():
+    """Rotation of the panorama (circular shift), mirror (time reversal) and
+    Parseval's identity over the half spectrum."""
+    rng = np.random.default_rng(11)
+    for L in (8, 96, 512):
+        x = rng.standard_normal((4, L))
+        d = L // 2 + 1
+        f = oracle.fft_magnitude(x, d)
+        for s in (1, L // 3, L - 1):
+            assert np.allclose(oracle.fft_magnitude(np.roll(x, s, axis=1), d), f,
+                               rtol=1e-12, atol=1e-12)
+        mirrored = np.concatenate([x[:, :1], x[:, :0:-1]], axis=1)  # x_{-t mod L}
+        assert np.allclose(oracle.fft_magnitude(mirrored, d), f, rtol=1e-12, atol=1e-12)
+        w = np.full(d, 2.0)
+        w[0] = 1.0
+        if L % 2 == 0:
+            w[-1] = 1.0
+        assert np.allclose((f * f * w).sum(axis=1) / L, (x * x).sum(axis=1), rtol=1e-12)
+
+
+def test_fft_magnitude_rejects_bad_shapes():
+    with pytest.raises(ValueError):
+        oracle.fft_magnitude([[1.0]], 1)
+    with pytest.raises(ValueError):
+        oracle.fft_magnitude([[1.0, 2.0, 3.0, 4.0]], 4)
+    with pytest.raises(ValueError):
+        oracle.fft_magnitude([[1.0, 2.0, 3.0, 4.0]], 0)
