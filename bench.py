@@ -221,6 +221,155 @@ def cpu_baseline(w, gpu_idx, seconds: float):
         hits / (mm * w.k), exact, mm
 
 
+FFT_SOURCE = "paper_2006_08861_amd/csrc/fft.hip"
+FFT_KERNEL = "k_fft_magnitude"
+
+
+def fft_digest() -> str:
+    with open(os.path.join(ROOT, FFT_SOURCE), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def fft_workload_name(nsig: int, length: int, bins: int) -> str:
+    return f"fft-{nsig // 1000}k-L{length}-d{bins}" if nsig % 1000 == 0 else \
+        f"fft-{nsig}-L{length}-d{bins}"
+
+
+def fft_counters_path(name: str) -> str:
+    return os.path.join(ROOT, "profiles", f"counters_fft_{name}.md")
+
+
+def load_fft_traffic(name: str):
+    """HBM bytes per launch of the feature kernel from its committed counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy
+    calibration), or None when there is none or the kernel changed since."""
+    path = fft_counters_path(name)
+    if not os.path.exists(path):
+        return None, "no counter summary for this workload"
+    with open(path) as f:
+        recs = [json.loads(l[len("record: "):]) for l in f if l.startswith("record: ")]
+    if not recs:
+        return None, f"{os.path.relpath(path, ROOT)} holds no record line"
+    rec = recs[-1]
+    if rec["sources"] != fft_digest():
+        return None, "the kernel's source changed since the counters were taken"
+    b = 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+    return b, os.path.relpath(path, ROOT)
+
+
+def fft_counters_summary(a) -> None:
+    """Markdown counter summary of the feature kernel (with the record line
+    load_fft_traffic reads) from four rocprofv3 --pmc CSVs: the FETCH_SIZE and
+    WRITE_SIZE runs of `bench.py --fft` and the copy calibration's."""
+    fetch_csv, write_csv, cf_csv, cw_csv = a.fft_counters
+    name = fft_workload_name(a.fft_signals, a.fft_len, a.fft_bins)
+    fk, nf = per_dispatch_kib(fetch_csv, FFT_KERNEL, "FETCH_SIZE")
+    wk, nw = per_dispatch_kib(write_csv, FFT_KERNEL, "WRITE_SIZE")
+    copy_bytes = a.copy_mib * (1 << 20)
+    copy_kernel = "at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add"
+    cfk, _ = per_dispatch_kib(cf_csv, copy_kernel, "FETCH_SIZE")
+    cwk, _ = per_dispatch_kib(cw_csv, copy_kernel, "WRITE_SIZE")
+    fetch_scale = round(copy_bytes / 1024.0 / cfk, 3)
+    write_scale = round(copy_bytes / 1024.0 / cwk, 3)
+    algo = a.fft_signals * 4 * (a.fft_len + a.fft_bins)
+    traffic = 1024.0 * (fk * fetch_scale + wk * write_scale)
+    rec = dict(kernel=FFT_KERNEL, workload=name, fetch_kib=round(fk, 1), write_kib=round(wk, 1),
+               fetch_scale=fetch_scale, write_scale=write_scale, sources=fft_digest())
+    print(f"# Feature-kernel HBM traffic, {name}\n")
+    print("Commands (from the repository root, one counter per run):\n")
+    print("```")
+    for c in a.commands:
+        print(c)
+    print("```\n")
+    print(f"Copy calibration: a {a.copy_mib} MiB device copy reads {cfk:.0f} KiB by FETCH_SIZE "
+          f"(scale x{fetch_scale}) and writes {cwk:.0f} KiB by WRITE_SIZE (scale x{write_scale}).\n")
+    print("| Kernel | Dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | Bytes per dispatch (scaled) "
+          "| Algorithmic bytes |")
+    print("|---|---|---|---|---|---|")
+    print(f"| `{FFT_KERNEL}` | {min(nf, nw)} | {fk:.1f} | {wk:.1f} | {traffic / 1e6:.2f} MB | "
+          f"{algo / 1e6:.2f} MB |\n")
+    print("record: " + json.dumps(rec))
+
+
+def fft_bench(a) -> None:
+    """Fourier-magnitude features of a database's worth of panoramic signals
+    (default 200,000 signals of 512 samples to 256 bins: the rows of
+    fp32-200k-d256), resident in HBM. A step is one launch over all signals."""
+    import torch
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    from paper_2006_08861_amd import hloc, workload
+
+    nsig, L, d = a.fft_signals, a.fft_len, a.fft_bins
+    name = fft_workload_name(nsig, L, d)
+    dev = torch.device("cuda:0")
+    x_h = workload.panoramic_signals(nsig, L, np.random.default_rng(2006))
+    x = torch.from_numpy(x_h).to(dev)
+    out = torch.empty((nsig, d), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    lib = hloc.load_library()
+    P = ctypes.c_void_p
+    args = (P(x.data_ptr()), nsig, L, d, P(out.data_ptr()), P(stream.cuda_stream))
+
+    def step():
+        rc = lib.hloc_fft_features_async(*args)
+        if rc != 0:
+            raise hloc.HlocError(rc, lib.hloc_last_error().decode())
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(a.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = e0.elapsed_time(e1) / a.steps
+    algo = nsig * 4 * (L + d)
+    achieved = algo / (launch_ms * 1e-3) / 1e9
+    traffic, traffic_src = load_fft_traffic(name)
+
+    # parity on seeded sample rows against the oracle (relative to each
+    # row's largest bin)
+    got = out.cpu().numpy()
+    rows = np.sort(np.random.default_rng(2007).choice(nsig, min(nsig, 512), replace=False))
+    ora = oracle.fft_magnitude(x_h[rows], d)
+    rel = float((np.abs(got[rows] - ora) / ora.max(axis=1, keepdims=True)).max())
+    equal = float(np.mean(got[rows] == ora.astype(np.float32)))
+
+    base = None
+    if not a.no_cpu_baseline:
+        done, t_cpu, m = 0, 0.0, 256
+        with threadpool_limits(limits=1):
+            while t_cpu < a.cpu_seconds:
+                lo = done % nsig
+                t1 = time.perf_counter()
+                oracle.fft_magnitude(x_h[lo:lo + m], d)
+                t_cpu += time.perf_counter() - t1
+                done += len(x_h[lo:lo + m])
+        base = dict(value=done / t_cpu, unit="signals/s", cores=1, kind="oracle",
+                    sample=f"{done} signals of {name} in chunks of {m}, DFT by its definition "
+                           f"(FP64 matrix product), single thread, {t_cpu:.1f} s")
+    print(json.dumps({
+        "metric": "omnidirectional features/s (Fourier magnitude, FP64, rounded to fp32) vs "
+                  "FP64 oracle; HBM GB/s % peak",
+        "value": nsig * a.steps / wall, "unit": "signals/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": wall * 1e3 / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": name, "signals": nsig, "len": L, "bins": d},
+        "roofline": {"bound": "hbm", "kernel": FFT_KERNEL, "achieved": achieved, "peak": 8000.0,
+                     "unit": "GB/s", "frac": achieved / 8000.0, "traffic": traffic,
+                     "traffic_source": traffic_src, "bytes_per_launch": algo,
+                     "avg_launch_ms": launch_ms},
+        "parity": {"sample_rows": int(len(rows)), "max_err_rel_row_max": rel,
+                   "equal_to_rounded_oracle": equal},
+        "cpu_baseline": base}), flush=True)
+
+
 def serve_bench(a) -> None:
     """Poisson arrivals of 1-16 frame requests (k in {8, 16, 32}) at a.serve
     requests/s into the request server for a.serve_seconds; prints one JSON
@@ -345,7 +494,24 @@ def main():
     ap.add_argument("--serve-batch", type=int, default=512, help="frames per batch")
     ap.add_argument("--serve-queue", type=int, default=1 << 16, help="frames waiting at most")
     ap.add_argument("--serve-budget", type=int, default=0, help="HBM bytes for the slots")
+    ap.add_argument("--fft", action="store_true",
+                    help="only time the Fourier-magnitude feature kernel")
+    ap.add_argument("--fft-signals", type=int, default=200_000)
+    ap.add_argument("--fft-len", type=int, default=512)
+    ap.add_argument("--fft-bins", type=int, default=256)
+    ap.add_argument("--fft-counters", nargs=4, metavar="CSV",
+                    help="only print the feature kernel's counter summary from rocprofv3 --pmc "
+                         "CSVs: FETCH_SIZE, WRITE_SIZE, copy FETCH_SIZE, copy WRITE_SIZE")
     a = ap.parse_args()
+    if a.fft_counters:
+        fft_counters_summary(a)
+        return
+    if a.fft:
+        if a.gpus != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        fft_bench(a)
+        return
     if a.serve:
         if a.gpus != 1:
             print("bench.py measures one GPU only", file=sys.stderr)

@@ -358,6 +358,26 @@ int hloc_server_stats(hloc_server *srv, int64_t *out, int32_t n);
  * (NULL is ignored). Must be called before hloc_free_db of its database. */
 void hloc_server_free(hloc_server *srv);
 
+/*
+ * Omnidirectional feature of 1-D panoramic signals (Section 3: the magnitude
+ * of the Fourier transform of the omnidirectional vector, invariant to the
+ * camera's heading): for each signal x (len samples around the full circle)
+ * out[j] = | sum_t x_t exp(-2 pi i j t / len) |, j = 0 .. d-1, computed in
+ * FP64 and rounded once to float32. The rows are ready for hloc_build_db
+ * (database) or as query frames.
+ *   signals  device, nsig x len float32, row-major (finite values)
+ *   nsig     signals (>= 0; 0 does nothing)
+ *   len      power of two in 2 .. 2048
+ *   d        bins kept, 1 .. len/2 + 1 (higher bins mirror these)
+ *   out      device, nsig x d float32, row-major (written)
+ *   stream   hipStream_t to enqueue on (NULL: the null stream); runs on the
+ *            current HIP device; the call returns once the kernel is enqueued.
+ * Needs no database. Errors: EINVAL (sizes out of range, NULL buffers with
+ * nsig > 0; checked before any device call), EDEVICE.
+ */
+int hloc_fft_features_async(const float *signals, int64_t nsig, int32_t len, int32_t d, float *out,
+                            void *stream);
+
 /* Release every resource of the database (NULL is ignored). */
 void hloc_free_db(hloc_db *db);
 

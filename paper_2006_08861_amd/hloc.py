@@ -79,6 +79,7 @@ _SIGNATURES = {
                                         ctypes.POINTER(_F64)]),
     "hloc_server_stats": (ctypes.c_int, [_P, _P, _I32]),
     "hloc_server_free": (None, [_P]),
+    "hloc_fft_features_async": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _P]),
     "hloc_free_db": (None, [_P]),
     "hloc_last_error": (ctypes.c_char_p, []),
 }
@@ -131,6 +132,31 @@ def _is_torch_cuda(x) -> bool:
     except ImportError:
         return False
     return isinstance(x, torch.Tensor) and x.is_cuda
+
+
+def fft_features(signals, d: int, stream=None):
+    """Fourier-magnitude features (hloc_fft_features_async) of nsig x len
+    float32 signals: a CUDA tensor runs on `stream` (default: torch's current
+    stream) and returns a CUDA tensor; a NumPy array is copied to the current
+    device and back and returns a NumPy array."""
+    import torch
+    host = not _is_torch_cuda(signals)
+    x = (torch.from_numpy(np.ascontiguousarray(signals, dtype=np.float32)).cuda() if host
+         else signals.contiguous())
+    if x.dtype != torch.float32 or x.dim() != 2:
+        raise HlocError(EINVAL, "signals must be a 2-D float32 array")
+    nsig, length = x.shape
+    out = torch.empty((nsig, d), dtype=torch.float32, device=x.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(x.device)
+    lib = load_library()
+    with torch.cuda.device(x.device):
+        _check(lib.hloc_fft_features_async(_P(x.data_ptr()), nsig, length, d, _P(out.data_ptr()),
+                                           _P(stream.cuda_stream)))
+    if host:
+        stream.synchronize()
+        return out.cpu().numpy()
+    return out
 
 
 class HlocDB:

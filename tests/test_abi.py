@@ -146,3 +146,17 @@ def test_phase_and_info_counts_match_header():
     n_info = int(re.search(r"Writes min\(n, (\d+)\) values", text).group(1))
     assert len(hloc._INFO_KEYS) == n_info
 
+
+
+def test_fft_features_rejects_bad_arguments():
+    """Sizes are checked before any device call (safe without a GPU)."""
+    lib = _lib()
+    P = ctypes.c_void_p
+    dummy = P(16)  # never dereferenced: every call below fails validation or does nothing
+    for nsig, length, d in ((-1, 8, 2), (4, 3, 2), (4, 1, 1), (4, 4096, 8), (4, 12, 2),
+                            (4, 8, 0), (4, 8, 6), (4, 2, 3)):
+        rc = lib.hloc_fft_features_async(dummy, nsig, length, d, dummy, None)
+        assert rc == hloc.EINVAL, (nsig, length, d)
+        assert lib.hloc_last_error().decode()
+    assert lib.hloc_fft_features_async(None, 4, 8, 5, None, None) == hloc.EINVAL
+    assert lib.hloc_fft_features_async(None, 0, 8, 5, None, None) == hloc.OK
