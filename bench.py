@@ -225,6 +225,12 @@ FFT_SOURCE = "paper_2006_08861_amd/csrc/fft.hip"
 FFT_KERNEL = "k_fft_magnitude"
 
 
+def fft_kernel_name(length: int) -> str:
+    """The kernel a launch of this signal length runs (four-step for L = 128
+    and 512, radix-2 in LDS otherwise)."""
+    return {128: "k_fft_magnitude_sq<8>", 512: "k_fft_magnitude_sq<16>"}.get(length, FFT_KERNEL)
+
+
 def fft_digest() -> str:
     with open(os.path.join(ROOT, FFT_SOURCE), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -263,8 +269,9 @@ def fft_counters_summary(a) -> None:
     WRITE_SIZE runs of `bench.py --fft` and the copy calibration's."""
     fetch_csv, write_csv, cf_csv, cw_csv = a.fft_counters
     name = fft_workload_name(a.fft_signals, a.fft_len, a.fft_bins)
-    fk, nf = per_dispatch_kib(fetch_csv, FFT_KERNEL, "FETCH_SIZE")
-    wk, nw = per_dispatch_kib(write_csv, FFT_KERNEL, "WRITE_SIZE")
+    kname = fft_kernel_name(a.fft_len)
+    fk, nf = per_dispatch_kib(fetch_csv, kname, "FETCH_SIZE")
+    wk, nw = per_dispatch_kib(write_csv, kname, "WRITE_SIZE")
     copy_bytes = a.copy_mib * (1 << 20)
     copy_kernel = "at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add"
     cfk, _ = per_dispatch_kib(cf_csv, copy_kernel, "FETCH_SIZE")
@@ -273,7 +280,7 @@ def fft_counters_summary(a) -> None:
     write_scale = round(copy_bytes / 1024.0 / cwk, 3)
     algo = a.fft_signals * 4 * (a.fft_len + a.fft_bins)
     traffic = 1024.0 * (fk * fetch_scale + wk * write_scale)
-    rec = dict(kernel=FFT_KERNEL, workload=name, fetch_kib=round(fk, 1), write_kib=round(wk, 1),
+    rec = dict(kernel=kname, workload=name, fetch_kib=round(fk, 1), write_kib=round(wk, 1),
                fetch_scale=fetch_scale, write_scale=write_scale, sources=fft_digest())
     print(f"# Feature-kernel HBM traffic, {name}\n")
     print("Commands (from the repository root, one counter per run):\n")
@@ -286,7 +293,7 @@ def fft_counters_summary(a) -> None:
     print("| Kernel | Dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | Bytes per dispatch (scaled) "
           "| Algorithmic bytes |")
     print("|---|---|---|---|---|---|")
-    print(f"| `{FFT_KERNEL}` | {min(nf, nw)} | {fk:.1f} | {wk:.1f} | {traffic / 1e6:.2f} MB | "
+    print(f"| `{kname}` | {min(nf, nw)} | {fk:.1f} | {wk:.1f} | {traffic / 1e6:.2f} MB | "
           f"{algo / 1e6:.2f} MB |\n")
     print("record: " + json.dumps(rec))
 
@@ -361,7 +368,7 @@ def fft_bench(a) -> None:
         "warmup": a.warmup, "ms_per_step": wall * 1e3 / a.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": name, "signals": nsig, "len": L, "bins": d},
-        "roofline": {"bound": "hbm", "kernel": FFT_KERNEL, "achieved": achieved, "peak": 8000.0,
+        "roofline": {"bound": "hbm", "kernel": fft_kernel_name(L), "achieved": achieved, "peak": 8000.0,
                      "unit": "GB/s", "frac": achieved / 8000.0, "traffic": traffic,
                      "traffic_source": traffic_src, "bytes_per_launch": algo,
                      "avg_launch_ms": launch_ms},

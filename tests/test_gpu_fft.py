@@ -60,7 +60,8 @@ def _signals(n, length, seed):
 
 
 @pytest.mark.parametrize("length,d,nsig", [(2, 2, 5), (4, 3, 7), (8, 1, 64), (64, 33, 1000),
-                                           (512, 256, 4099), (512, 257, 300),
+                                           (128, 65, 333), (128, 20, 9), (256, 129, 100),
+                                           (512, 256, 4099), (512, 257, 300), (512, 100, 3),
                                            (1024, 100, 777), (2048, 1025, 257)])
 def test_fft_parity(torch_cuda, length, d, nsig):
     x = _signals(nsig, length, 1000 + length + d)
