@@ -14,7 +14,8 @@
 // signal and 64 / R signals per wave. Lane c loads points R t1 + c (R lanes
 // read 8R contiguous bytes per instruction), transforms them over t1 in
 // registers, multiplies by exp(-2 pi i k1 c / n), and the wave transposes its
-// signals through padded LDS rows; lane c then transforms row k1 = c over t2
+// signals through padded LDS rows (real parts, then imaginary parts: half the
+// LDS of a complex transpose, more blocks per compute unit); lane c then transforms row k1 = c over t2
 // in registers and holds Z_{c + R k2}. The partner Z_{n-j} of its bin
 // j = c + R k2 sits in lane R - c (lane 0: its own registers) and comes by a
 // lane shuffle. The next signals' points are loaded while the current ones
@@ -31,6 +32,66 @@ namespace hloc {
 
 constexpr int kFftMaxLen = 2048;   // LDS per block (2n + 1) * 16 bytes <= 32 KB
 constexpr int kFftBlocksPerCu = 32;  // one wave each; 8 waves per SIMD at 45 VGPRs
+
+constexpr int bit_reverse(int t, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((t >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+__device__ __forceinline__ double2 cmul(double2 w, double2 v) {
+  return make_double2(w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x);
+}
+
+// exp(-2 pi i k / 16), k = 0 .. 7, from cos(pi/8) = sqrt(2 + sqrt 2) / 2,
+// sin(pi/8) = sqrt(2 - sqrt 2) / 2 and cos(pi/4) = sqrt(2) / 2 (40 digits,
+// rounded to double by the compiler).
+constexpr double kC8 = 0.9238795325112867561281831893967882868225;
+constexpr double kS8 = 0.3826834323650897717284599840303988667612;
+constexpr double kH2 = 0.7071067811865475244008443621048490392848;
+__device__ constexpr double w16_re(int k) {
+  return k == 0 ? 1.0 : k == 1 ? kC8 : k == 2 ? kH2 : k == 3 ? kS8 : k == 4 ? 0.0
+       : k == 5 ? -kS8 : k == 6 ? -kH2 : -kC8;
+}
+__device__ constexpr double w16_im(int k) {
+  return k == 0 ? 0.0 : k == 1 ? -kS8 : k == 2 ? -kH2 : k == 3 ? -kC8 : k == 4 ? -1.0
+       : k == 5 ? -kC8 : k == 6 ? -kH2 : -kS8;
+}
+
+// In-register transform of length R = 8 or 16 (bit-reversed input, natural
+// output), radix-2 decimation in time with compile-time twiddles; the
+// twiddles 1 and -i cost no multiply.
+template <int R>
+__device__ __forceinline__ void dft_regs(double2 (&a)[R]) {
+#pragma unroll
+  for (int h = 1; h < R; h <<= 1) {
+#pragma unroll
+    for (int b = 0; b < R / 2; ++b) {
+      const int pos = b & (h - 1);
+      const int i = ((b - pos) << 1) + pos;
+      const int k = pos * (16 / (2 * h));  // exp(-2 pi i pos / 2h) = w16(k)
+      double2 v = a[i + h];
+      if (k == 4)
+        v = make_double2(v.y, -v.x);
+      else if (k != 0)
+        v = cmul(make_double2(w16_re(k), w16_im(k)), v);
+      const double2 u = a[i];
+      a[i] = make_double2(u.x + v.x, u.y + v.y);
+      a[i + h] = make_double2(u.x - v.x, u.y - v.y);
+    }
+  }
+}
+
+// |X_j| from Z_j (A), Z_{n-j} (B) and tw[j], computed as |2 X_j| / 2 from
+// 2 E_j and 2 O_j (scaling by powers of two is exact, so the result is the
+// same as with the halvings applied first).
+__device__ __forceinline__ float unpack_mag(double2 A, double2 B, double2 w) {
+  const double er = A.x + B.x, ei = A.y - B.y;    // 2 E_j
+  const double orr = A.y + B.y, oi = B.x - A.x;   // 2 O_j
+  const double xr = er + (w.x * orr - w.y * oi);
+  const double xi = ei + (w.x * oi + w.y * orr);
+  return (float)(0.5 * sqrt(xr * xr + xi * xi));
+}
 
 __global__ __launch_bounds__(64) void k_fft_magnitude(const float *__restrict__ x, int64_t nsig,
                                                       int len, int log2n, int d,
@@ -70,59 +131,14 @@ __global__ __launch_bounds__(64) void k_fft_magnitude(const float *__restrict__ 
     __syncthreads();
     float *o = out + sig * d;
     for (int j = lane; j < d; j += 64) {
-      const double2 A = a[j & (n - 1)];        // Z_j (Z_n = Z_0)
-      const double2 B = a[(n - j) & (n - 1)];  // Z_{n-j}
-      const double er = 0.5 * (A.x + B.x), ei = 0.5 * (A.y - B.y);  // E_j
-      const double orr = 0.5 * (A.y + B.y), oi = -0.5 * (A.x - B.x);  // O_j
-      const double2 w = tw[j];
-      const double xr = er + (w.x * orr - w.y * oi);
-      const double xi = ei + (w.x * oi + w.y * orr);
-      o[j] = (float)sqrt(xr * xr + xi * xi);
+      o[j] = unpack_mag(a[j & (n - 1)], a[(n - j) & (n - 1)], tw[j]);  // Z_j, Z_{n-j}
     }
   }
-}
-
-constexpr int bit_reverse(int t, int bits) {
-  int r = 0;
-  for (int i = 0; i < bits; ++i) r |= ((t >> i) & 1) << (bits - 1 - i);
-  return r;
-}
-
-__device__ __forceinline__ double2 cmul(double2 w, double2 v) {
-  return make_double2(w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x);
-}
-
-// In-register transform of length R (bit-reversed input, natural output),
-// radix-2 decimation in time; tw[j] = exp(-i pi j / n).
-template <int R, int N>
-__device__ __forceinline__ void dft_regs(double2 (&a)[R], const double2 *tw) {
-#pragma unroll
-  for (int h = 1; h < R; h <<= 1) {
-#pragma unroll
-    for (int b = 0; b < R / 2; ++b) {
-      const int pos = b & (h - 1);
-      const int i = ((b - pos) << 1) + pos;
-      double2 v = a[i + h];
-      if (pos != 0) v = cmul(tw[pos * (N / h)], v);  // exp(-2 pi i pos / 2h)
-      const double2 u = a[i];
-      a[i] = make_double2(u.x + v.x, u.y + v.y);
-      a[i + h] = make_double2(u.x - v.x, u.y - v.y);
-    }
-  }
-}
-
-// |X_j| from Z_j (A), Z_{n-j} (B) and tw[j].
-__device__ __forceinline__ float unpack_mag(double2 A, double2 B, double2 w) {
-  const double er = 0.5 * (A.x + B.x), ei = 0.5 * (A.y - B.y);    // E_j
-  const double orr = 0.5 * (A.y + B.y), oi = -0.5 * (A.x - B.x);  // O_j
-  const double xr = er + (w.x * orr - w.y * oi);
-  const double xi = ei + (w.x * oi + w.y * orr);
-  return (float)sqrt(xr * xr + xi * xi);
 }
 
 template <int R>
 constexpr uint32_t fft_sq_lds_bytes() {
-  return (uint32_t)((R * R + 1) + (64 / R) * R * (R + 1)) * sizeof(double2);
+  return (uint32_t)((R * R + 1) * sizeof(double2) + (64 / R) * R * (R + 1) * sizeof(double));
 }
 
 template <int R>
@@ -135,7 +151,8 @@ __global__ __launch_bounds__(64) void k_fft_magnitude_sq(const float *__restrict
   extern __shared__ double2 lds[];
   double2 *tw = lds;  // tw[j] = exp(-i pi j / N), j = 0 .. N
   const int lane = threadIdx.x, g = lane / R, c = lane % R;
-  double2 *rows = lds + (N + 1) + g * R * (R + 1);  // this signal's R x (R + 1) rows
+  // this signal's R x (R + 1) rows (real parts, then imaginary parts)
+  double *rows = reinterpret_cast<double *>(lds + (N + 1)) + g * R * (R + 1);
   for (int j = lane; j <= N; j += 64) {
     double sn, cs;
     sincospi((double)j / (double)N, &sn, &cs);
@@ -163,7 +180,7 @@ __global__ __launch_bounds__(64) void k_fft_magnitude_sq(const float *__restrict
 #pragma unroll
     for (int t = 0; t < R; ++t)
       a[bit_reverse(t, LG)] = make_double2((double)cur[t].x, (double)cur[t].y);
-    dft_regs<R, N>(a, tw);  // a[k1] = sum_t1 z[R t1 + c] exp(-2 pi i t1 k1 / R)
+    dft_regs<R>(a);  // a[k1] = sum_t1 z[R t1 + c] exp(-2 pi i t1 k1 / R)
 #pragma unroll
     for (int k1 = 1; k1 < R; ++k1) {
       const int m = 2 * k1 * c;  // exp(-2 pi i k1 c / N) = tw[2 k1 c], or -tw[2 k1 c - N]
@@ -171,13 +188,20 @@ __global__ __launch_bounds__(64) void k_fft_magnitude_sq(const float *__restrict
       const double2 v = cmul(w, a[k1]);
       a[k1] = m <= N ? v : make_double2(-v.x, -v.y);
     }
+    double re[R];
 #pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) rows[k1 * (R + 1) + c] = a[k1];
+    for (int k1 = 0; k1 < R; ++k1) rows[k1 * (R + 1) + c] = a[k1].x;
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < R; ++t) a[bit_reverse(t, LG)] = rows[c * (R + 1) + t];
+    for (int t = 0; t < R; ++t) re[t] = rows[c * (R + 1) + t];
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) rows[k1 * (R + 1) + c] = a[k1].y;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < R; ++t) a[bit_reverse(t, LG)] = make_double2(re[t], rows[c * (R + 1) + t]);
     __syncthreads();  // the rows are read out before the next signals write them
-    dft_regs<R, N>(a, tw);  // a[k2] = Z_{c + R k2}
+    dft_regs<R>(a);  // a[k2] = Z_{c + R k2}
     const bool valid = s < nsig;
     float *o = out + s * d;
     const int partner = g * R + ((R - c) & (R - 1));
