@@ -13,6 +13,8 @@
  *     `n_regions` regions (all regions = the paper's exhaustive search).
  *   - Multi-frame requests and 2-D density aggregation: Section 3.1 and
  *     Section 3.2, Algorithm 2.
+ *   - The feature itself, the Fourier magnitude of a 1-D panoramic signal:
+ *     Section 3 (hloc_fft_features_async).
  *
  * Conventions for every call:
  *   - Return value: HLOC_OK (0) or a negative hloc_status. On error the
