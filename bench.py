@@ -22,6 +22,7 @@ sample on the host.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import ctypes
 import csv
 import hashlib
@@ -472,6 +473,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", type=int, default=1, help="index of workload.SHAPES")
     ap.add_argument("--nq", type=int, default=None, help="override the batch size")
+    ap.add_argument("--n-regions", type=int, default=None,
+                    help="override the regions searched per frame (>= the region count: the "
+                         "exhaustive search)")
     ap.add_argument("--precision", choices=("fp32", "bf16", "fp8"), default="fp32",
                     help="fine-screen precision (the rerank is FP64 either way)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -548,6 +552,9 @@ def main():
         return
     t0 = time.perf_counter()
     w = workload.make_workload(a.workload, nq=a.nq)
+    if a.n_regions is not None and a.n_regions != w.n_reg:
+        tag = "exhaustive" if a.n_regions >= w.n_regions_total else f"nreg{a.n_regions}"
+        w = dataclasses.replace(w, n_reg=a.n_regions, name=f"{w.name}-{tag}")
     log(f"[bench] workload {w.name}: n={len(w.feats)} d={w.feats.shape[1]} "
         f"regions={w.n_regions_total} frames={len(w.q)} requests={len(w.req_offsets) - 1} "
         f"({time.perf_counter() - t0:.1f} s)")
@@ -661,6 +668,12 @@ def main():
     if wide_items > 0:
         screen_ms += phases["screen_wide"][0] / max(phases["screen_wide"][1], 1)
     achieved = screen_bytes / (screen_ms * 1e-3) / 1e9
+    # 2 D flops per (frame, row) word: past the dtype's ridge point (all
+    # frames against many rows, as in the exhaustive search) the screen is
+    # bound by the matrix cores, not by HBM
+    screen_flops = 2.0 * info["candidates"] * d
+    screen_dtype = a.precision
+    mfma_bound = screen_flops / screen_bytes > MFMA_PEAK_TFLOPS[screen_dtype] / (HBM_PEAK_GBS / 1e3)
     traffic, traffic_src = load_traffic(w.name, a.precision, db.tiles()["rows_per_item"])
     # the coarse screen is the dense (GEMM-shaped) part: nq x R distances
     coarse_ms = phases["coarse"][0] / max(phases["coarse"][1], 1)
@@ -704,14 +717,25 @@ def main():
         "device_p99_ms": float(np.percentile(lat_dev, 99)),
         "recall_at_k": recall,
         "exact_lists": None if base is None else f"{exact}/{m}",
-        "roofline": {"bound": "hbm",
-                     "kernel": narrow_label(a.precision, db.tiles()["rows_per_item"])
-                               + (" + wide-item kernel" if wide_items > 0 else ""),
-                     "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None if traffic is None else int(traffic),
-                     "traffic_source": traffic_src, "bytes_per_launch": int(screen_bytes),
-                     "avg_launch_ms": screen_ms},
+        "roofline": ({"bound": "mfma",
+                      "kernel": narrow_label(a.precision, db.tiles()["rows_per_item"])
+                                + (" + wide-item kernel" if wide_items > 0 else ""),
+                      "achieved": screen_flops / (screen_ms * 1e-3) / 1e12,
+                      "peak": MFMA_PEAK_TFLOPS[screen_dtype], "unit": "TFLOP/s",
+                      "frac": screen_flops / (screen_ms * 1e-3) / 1e12
+                              / MFMA_PEAK_TFLOPS[screen_dtype],
+                      "traffic": None if traffic is None else int(traffic),
+                      "traffic_source": traffic_src, "flops_per_launch": screen_flops,
+                      "bytes_per_launch": int(screen_bytes), "hbm_gbs": achieved,
+                      "avg_launch_ms": screen_ms} if mfma_bound else
+                     {"bound": "hbm",
+                      "kernel": narrow_label(a.precision, db.tiles()["rows_per_item"])
+                                + (" + wide-item kernel" if wide_items > 0 else ""),
+                      "achieved": achieved,
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                      "traffic": None if traffic is None else int(traffic),
+                      "traffic_source": traffic_src, "bytes_per_launch": int(screen_bytes),
+                      "avg_launch_ms": screen_ms}),
         "stage1_mfma": stage1,
         "phases_ms": {p: v[0] / max(v[1], 1) for p, v in phases.items()},
         "ms_per_step_event_timed": wall_prof * 1e3 / a.steps,

@@ -170,36 +170,39 @@ hipError_t launch_broadcast_ids(const int32_t *ids, int32_t nr, int32_t nq, int3
 // Multi-kernel schedule for large region counts. Per frame: offset of each
 // kept region in the frame's candidate list and its first row, and the list
 // length. Per region: how many frames kept it.
-// Frame f's candidate-list offsets, slot rows and length; counts its regions
-// in cnt.
+// One wave per frame: 64 of its regions at a time, their candidate-list
+// offsets by an inclusive scan of the sizes across the wave (a frame of the
+// exhaustive search keeps every region, so its list is long); the next 64
+// region ids are loaded while the current ones are placed.
 __device__ __forceinline__ void count_frame(const int32_t *__restrict__ regions, int f, int nr,
                                             int R, const int64_t *__restrict__ reg_start,
                                             int32_t *cnt, int32_t *cand_off, int32_t *slot_row,
                                             int32_t *n_cand) {
-  int off = 0;
-  for (int j0 = 0; j0 < nr; j0 += 8) {
-    // ids, then first rows and sizes, then updates: eight loads in flight per step
-    int r[8], r0[8], sz[8];
+  const int lane = threadIdx.x & 63;
+  const int32_t *ids = regions + (int64_t)f * nr;
+  int base = 0;
+  int nxt = lane < nr ? ids[lane] : -1;
+  for (int j0 = 0; j0 < nr; j0 += 64) {
+    const int j = j0 + lane;
+    int r = nxt;
+    if (r >= R) r = -1;
+    nxt = j + 64 < nr ? ids[j + 64] : -1;
+    const int r0 = r >= 0 ? (int)reg_start[r] : 0;
+    const int sz = r >= 0 ? (int)(reg_start[r + 1] - r0) : 0;
+    int inc = sz;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      r[u] = j0 + u < nr ? regions[(int64_t)f * nr + j0 + u] : -1;
-      if (r[u] >= R) r[u] = -1;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      r0[u] = r[u] >= 0 ? (int)reg_start[r[u]] : 0;
-      sz[u] = r[u] >= 0 ? (int)(reg_start[r[u] + 1] - r0[u]) : 0;
+    if (j < nr) {
+      cand_off[(int64_t)f * nr + j] = base + inc - sz;
+      slot_row[(int64_t)f * nr + j] = r0;
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (j0 + u >= nr) break;
-      cand_off[(int64_t)f * nr + j0 + u] = off;
-      slot_row[(int64_t)f * nr + j0 + u] = r0[u];
-      off += sz[u];
-      if (r[u] >= 0) atomicAdd(&cnt[r[u]], 1);
-    }
+    if (r >= 0) atomicAdd(&cnt[r], 1);
+    base += __shfl(inc, 63);
   }
-  n_cand[f] = off;
+  if (lane == 0) n_cand[f] = base;
 }
 
 // With LDS (R <= kHistR) the block counts in LDS and adds each nonzero count
@@ -216,7 +219,7 @@ __global__ void k_sched_count(const int32_t *__restrict__ regions, int nq, int n
     __syncthreads();
   }
   int32_t *cnt = LDS ? s_cnt : rcount;
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);  // one wave per frame
   if (f < nq) count_frame(regions, f, nr, R, reg_start, cnt, cand_off, slot_row, n_cand);
   if (LDS) {
     __syncthreads();
@@ -412,11 +415,12 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
   if (e != hipSuccess) return e;
   const bool hist = R <= kHistR;
   if (nq > 0) {
-    e = hist ? launch_kernel(k_sched_count<true>, dim3((nq + 255) / 256), dim3(256),
+    // one wave per frame, 16 frames per block
+    e = hist ? launch_kernel(k_sched_count<true>, dim3((nq + 15) / 16), dim3(1024),
                              (uint32_t)(R * sizeof(int32_t)), s, regions, nq, nr, R, reg_start,
                              rcount, cand_off, slot_row, n_cand)
-             : launch_kernel(k_sched_count<false>, dim3((nq + 63) / 64), dim3(64), 0, s, regions,
-                             nq, nr, R, reg_start, rcount, cand_off, slot_row, n_cand);
+             : launch_kernel(k_sched_count<false>, dim3((nq + 15) / 16), dim3(1024), 0, s,
+                             regions, nq, nr, R, reg_start, rcount, cand_off, slot_row, n_cand);
     if (e != hipSuccess) return e;
   }
   if ((e = launch_kernel(k_sched_scan, dim3(1), dim3(1024), 0, s, rcount, R, reg_start, T,

@@ -116,6 +116,26 @@ def test_batch_invariance(torch_cuda, fp32_shape):
         np.testing.assert_array_equal(part["xy"].view(np.uint64), full["xy"][sel].view(np.uint64))
 
 
+def test_exhaustive_full_shape(torch_cuda, fp32_shape):
+    """n_regions = R on fp32-200k-d256: every frame against all 200,000 rows
+    (all items wide), 48 frames checked against the oracle's exhaustive
+    search, and bitwise the same lists alone as in the batch."""
+    w, db = fp32_shape
+    R = w.n_regions_total
+    say("[case] exhaustive fp32-200k-d256 x48")
+    q = w.q[:48]
+    out = run_device(torch_cuda, db, q, w.k, R)
+    regs = db.last_regions()
+    ora = oracle.localize(w.feats, w.xy, w.region_of, R, q, np.arange(len(q) + 1), w.k, R,
+                          w.agg)
+    st = judge_frames(out["idx"], out["dist"], regs, ora, w.feats, w.region_of, R, q, w.k)
+    say(f"[ok] {st} info={db.info()}")
+    assert st["recall"] == 1.0
+    one = run_device(torch_cuda, db, q[7:8], w.k, R)
+    np.testing.assert_array_equal(one["idx"][0], out["idx"][7])
+    np.testing.assert_array_equal(one["dist"][0].view(np.uint32), out["dist"][7].view(np.uint32))
+
+
 def test_host_and_device_entry_points_agree(torch_cuda, fp32_shape):
     w, db = fp32_shape
     say("[case] sync host-pointer call vs async device call")
