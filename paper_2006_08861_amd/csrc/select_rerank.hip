@@ -564,24 +564,23 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
           base += __popcll(bal[u]);
         }
       } else {
-        int wcount = 0;
-        for (int b0 = w * 64; b0 < n; b0 += BLOCK) {
-          uint32_t v;
-          wcount += __popcll(__ballot(keep(b0 + lane, v)));
-        }
-        int base = 0;
-        if (lane == 0 && wcount > 0) base = atomicAdd(&sh.krem, wcount);
-        base = __shfl(base, 0);
+        // long lists (the exhaustive search: 200,000 words a frame): one
+        // pass, one atomic per wave and 64 positions that keep any word
+        // (few do), instead of a counting pass and a placing pass
         for (int b0 = w * 64; b0 < n; b0 += BLOCK) {
           uint32_t v;
           const bool k = keep(b0 + lane, v);
           const uint64_t bal = __ballot(k);
-          if (k) {
-            const int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
-            sh.sort_hi[slot] = v;
-            sh.sort_lo[slot] = (uint32_t)(b0 + lane);
+          if (bal) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&sh.krem, __popcll(bal));
+            base = __shfl(base, 0);
+            if (k) {
+              const int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
+              sh.sort_hi[slot] = v;
+              sh.sort_lo[slot] = (uint32_t)(b0 + lane);
+            }
           }
-          base += __popcll(bal);
         }
       }
       __syncthreads();
