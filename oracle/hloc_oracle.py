@@ -211,11 +211,16 @@ def aggregate(cand_rows, xy, cell, top_c, radius, toler_pct):
 
 
 def localize(feats, xy, region_of, n_regions_total, q, req_offsets, k, n_reg, agg, reps=None,
-             regions=None):
+             regions=None, req_frames=None):
     """Whole path: retrieve every frame, pool each request's frames, aggregate.
 
     agg = (cell_m, top_c, radius_m, toler_pct). Returns the retrieve() dict
     plus per-request arrays tile (nreq x 2), pos (nreq x 2) and flags.
+    Request i pools frames req_offsets[i] .. req_offsets[i+1]-1, or, with
+    req_frames, the frames req_frames[req_offsets[i] : req_offsets[i+1]]
+    (indices into q, in that order, repeats pooled again): the sliding
+    window of Section 3.1, where consecutive requests share all but one
+    frame and each frame is retrieved once.
     """
     res = retrieve(feats, region_of, n_regions_total, q, k, n_reg, reps=reps, regions=regions)
     offs = np.asarray(req_offsets, dtype=np.int64)
@@ -224,7 +229,11 @@ def localize(feats, xy, region_of, n_regions_total, q, req_offsets, k, n_reg, ag
     pos = np.zeros((nreq, 2))
     flags = np.zeros(nreq, np.int32)
     for i in range(nreq):
-        pooled = res["idx"][offs[i]:offs[i + 1]].ravel()
+        if req_frames is None:
+            frames = np.arange(offs[i], offs[i + 1])
+        else:
+            frames = np.asarray(req_frames, dtype=np.int64)[offs[i]:offs[i + 1]]
+        pooled = res["idx"][frames].ravel()
         ix, iy, x, y, fl = aggregate(pooled, xy, *agg)
         tile[i], pos[i], flags[i] = (ix, iy), (x, y), fl
     res.update(tile=tile, pos=pos, flags=flags)

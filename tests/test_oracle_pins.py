@@ -276,6 +276,43 @@ def test_duplicates_across_frames_change_the_estimate():
     assert res["pos"][0].tolist() == [2.75, 2.75]
 
 
+def test_window_requests_hand_case():
+    # the duplicates case above as windows over two distinct frames: request
+    # 0 = frames (A, B, B) votes (5,5) 6:3; request 1 = frames (A) alone
+    # votes (0,0); request 2 = (B, A) ties 3:3 and takes (0,0) by (iy, ix)
+    feats = np.array([[0, 0], [0, 0.1], [0, 0.2], [10, 0], [10, 0.1], [10, 0.2], [50, 50]],
+                     dtype=np.float64)
+    xy = np.array([[0.25, 0.25]] * 3 + [[2.75, 2.75]] * 3 + [[40.0, 40.0]])
+    q = np.array([[0, 0.05], [10, 0.05]])
+    res = oracle.localize(feats, xy, np.zeros(7, int), 1, q, [0, 3, 4, 6], 3, 1,
+                          (0.5, 1, 0.0, 0), req_frames=[0, 1, 1, 0, 1, 0])
+    assert res["tile"].tolist() == [[5, 5], [0, 0], [0, 0]]
+
+
+def test_sliding_windows_equal_materialised_requests():
+    # windows of M = 5 consecutive frames over a walk of 40 frames (each
+    # frame retrieved once) give the same estimates as sending every
+    # window's frames again as its own request
+    from paper_2006_08861_amd import workload
+    w = workload.make_workload(0, nq=40)
+    M = 5
+    starts = np.arange(0, len(w.q) - M + 1)
+    frames = np.concatenate([np.arange(s0, s0 + M) for s0 in starts])
+    offs = np.arange(len(starts) + 1) * M
+    agg = (0.3, 10, 3.0, 20)
+    win = oracle.localize(w.feats, w.xy, w.region_of, w.n_regions_total, w.q, offs, w.k,
+                          w.n_reg, agg, req_frames=frames)
+    mat = oracle.localize(w.feats, w.xy, w.region_of, w.n_regions_total, w.q[frames], offs, w.k,
+                          w.n_reg, agg)
+    assert win["tile"].tolist() == mat["tile"].tolist()
+    assert win["flags"].tolist() == mat["flags"].tolist()
+    ident = oracle.localize(w.feats, w.xy, w.region_of, w.n_regions_total, w.q, [0, 7, 40], w.k,
+                            w.n_reg, agg, req_frames=np.arange(40))
+    plain = oracle.localize(w.feats, w.xy, w.region_of, w.n_regions_total, w.q, [0, 7, 40], w.k,
+                            w.n_reg, agg)
+    assert ident["tile"].tolist() == plain["tile"].tolist()
+
+
 # ------------------------------------------------ FFT-magnitude feature pins
 def test_fft_magnitude_hand_case():
     # x = (1, 2, 3, 4): X_0 = 10, X_1 = -2 + 2i, X_2 = -2 (worked by hand)
