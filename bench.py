@@ -378,6 +378,132 @@ def fft_bench(a) -> None:
         "cpu_baseline": base}), flush=True)
 
 
+def windows_bench(a) -> None:
+    """Sliding-window requests over a video along the walk of fp32-200k-d256:
+    T frames (consecutive database rows plus N(0, 0.1^2) noise), one request
+    per window of M consecutive frames (Section 4 uses M = 11). Each frame is
+    retrieved once and every window pools its frames' lists
+    (hloc_query_windows_async); the same windows sent as materialised
+    requests (every window's M frames again) are timed beside it."""
+    import torch
+
+    import oracle
+    from paper_2006_08861_amd import hloc, workload
+
+    w = workload.make_workload(1)
+    rng = np.random.default_rng(2016)
+    T, M = a.windows_frames, a.windows
+    s0 = int(rng.integers(0, len(w.feats) - T))
+    q_h = (w.feats[s0:s0 + T] + 0.1 * rng.standard_normal((T, w.feats.shape[1]))).astype(np.float32)
+    nreq = T - M + 1
+    frames_h = np.concatenate([np.arange(i, i + M) for i in range(nreq)]).astype(np.int32)
+    offs_h = (np.arange(nreq + 1) * M).astype(np.int32)
+    agg = (0.3, 10, 3.0, 20)
+    name = f"{w.name}-video{T}-window{M}"
+    dev = torch.device("cuda:0")
+    db = hloc.HlocDB(w.feats, w.xy)
+    db.set_regions(w.region_of, w.n_regions_total)
+    db.set_aggregation(*agg)
+    k, n_reg = w.k, w.n_reg
+    q, frames, offs = (torch.from_numpy(x).to(dev) for x in (q_h, frames_h, offs_h))
+    qm = q[frames.long()].contiguous()
+    db.reserve(len(frames_h), nreq, k, n_reg)
+    stream = torch.cuda.current_stream(dev)
+    lib = hloc.load_library()
+    P = ctypes.c_void_p
+    o = {"idx": torch.empty((T, k), dtype=torch.int64, device=dev),
+         "dist": torch.empty((T, k), dtype=torch.float32, device=dev),
+         "xy": torch.empty((nreq, 2), dtype=torch.float64, device=dev),
+         "tile": torch.empty((nreq, 2), dtype=torch.int32, device=dev),
+         "flags": torch.empty(nreq, dtype=torch.int32, device=dev)}
+    om = dict(o, idx=torch.empty((len(frames_h), k), dtype=torch.int64, device=dev),
+              dist=torch.empty((len(frames_h), k), dtype=torch.float32, device=dev),
+              xy=torch.empty_like(o["xy"]), tile=torch.empty_like(o["tile"]),
+              flags=torch.empty_like(o["flags"]))
+    outp = lambda d: tuple(P(d[key].data_ptr()) for key in ("idx", "dist", "xy", "tile", "flags"))
+
+    def step_windows():
+        rc = lib.hloc_query_windows_async(db._h, P(q.data_ptr()), T, k, n_reg, P(offs.data_ptr()),
+                                          P(frames.data_ptr()), len(frames_h), nreq, hloc.FP32,
+                                          *outp(o), P(stream.cuda_stream))
+        if rc != 0:
+            raise hloc.HlocError(rc, lib.hloc_last_error().decode())
+
+    def step_materialised():
+        rc = lib.hloc_query_batch_async(db._h, P(qm.data_ptr()), len(frames_h), k, n_reg,
+                                        P(offs.data_ptr()), nreq, hloc.FP32, *outp(om),
+                                        P(stream.cuda_stream))
+        if rc != 0:
+            raise hloc.HlocError(rc, lib.hloc_last_error().decode())
+
+    def timed(step):
+        for _ in range(a.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / a.steps
+
+    t_win = timed(step_windows)
+    t_mat = timed(step_materialised)
+    for key in ("xy", "tile", "flags"):
+        if o[key].cpu().numpy().tobytes() != om[key].cpu().numpy().tobytes():
+            raise RuntimeError(f"windows and materialised requests differ in {key}")
+    # the fine screen of the windows batch, event-timed per dispatch
+    db.profile(True)
+    for _ in range(a.steps):
+        step_windows()
+    torch.cuda.synchronize()
+    phases = db.profile_read()
+    db.profile(False)
+    info = db.info()
+    regions = db.last_regions()
+    sizes = np.bincount(w.region_of, minlength=w.n_regions_total)
+    d = w.feats.shape[1]
+    screen_bytes = int(sizes[np.unique(regions)].sum()) * (4 * d + 4) + info["candidates"] * 4 \
+        + T * 4 * d
+    screen_ms = phases["screen"][0] / max(phases["screen"][1], 1)
+    if info["items"] > info["narrow_items"]:
+        screen_ms += phases["screen_wide"][0] / max(phases["screen_wide"][1], 1)
+    achieved = screen_bytes / (screen_ms * 1e-3) / 1e9
+    # oracle on the first windows (their frames retrieved once), about a.cpu_seconds
+    base, same = None, None
+    if not a.no_cpu_baseline:
+        m, t_cpu, done = 4, 0.0, 0
+        while t_cpu < a.cpu_seconds and m <= nreq:
+            t1 = time.perf_counter()
+            ora = oracle.localize(w.feats, w.xy, w.region_of, w.n_regions_total, q_h[:m + M - 1],
+                                  offs_h[:m + 1], k, n_reg, agg, req_frames=frames_h[:m * M])
+            t_cpu += time.perf_counter() - t1
+            done += m
+            tile = o["tile"].cpu().numpy()[:m]
+            same = (int((tile == ora["tile"]).all(axis=1).sum()), m)
+            m *= 2
+        base = dict(value=done / t_cpu, unit="requests/s", cores=1, kind="oracle",
+                    sample=f"{done} windows of {name} (the first 4, 8, ... windows, each set "
+                           f"retrieving its frames once), single thread, {t_cpu:.1f} s")
+    print(json.dumps({
+        "metric": "sliding-window localization requests/s (frames retrieved once, windows "
+                  "pooled) vs FP64 oracle; HBM GB/s % peak",
+        "value": nreq / t_win, "unit": "requests/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": t_win * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": name, "frames": T, "window": M, "requests": nreq, "k": k,
+                   "n_regions": n_reg, "aggregation": list(agg)},
+        "materialised": {"requests_per_s": nreq / t_mat, "ms_per_step": t_mat * 1e3,
+                         "frames_screened": int(len(frames_h))},
+        "speedup_vs_materialised": t_mat / t_win,
+        "same_tiles_as_oracle": None if same is None else f"{same[0]}/{same[1]}",
+        "roofline": {"bound": "hbm", "kernel": "fine screen (narrow + wide items)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": screen_bytes, "avg_launch_ms": screen_ms},
+        "cpu_baseline": base}), flush=True)
+    db.close()
+
+
 def serve_bench(a) -> None:
     """Poisson arrivals of 1-16 frame requests (k in {8, 16, 32}) at a.serve
     requests/s into the request server for a.serve_seconds; prints one JSON
@@ -505,6 +631,9 @@ def main():
     ap.add_argument("--serve-batch", type=int, default=512, help="frames per batch")
     ap.add_argument("--serve-queue", type=int, default=1 << 16, help="frames waiting at most")
     ap.add_argument("--serve-budget", type=int, default=0, help="HBM bytes for the slots")
+    ap.add_argument("--windows", type=int, default=0, metavar="M",
+                    help="only run sliding-window requests of M frames over a video")
+    ap.add_argument("--windows-frames", type=int, default=256, help="video frames per batch")
     ap.add_argument("--fft", action="store_true",
                     help="only time the Fourier-magnitude feature kernel")
     ap.add_argument("--fft-signals", type=int, default=200_000)
@@ -516,6 +645,12 @@ def main():
     a = ap.parse_args()
     if a.fft_counters:
         fft_counters_summary(a)
+        return
+    if a.windows:
+        if a.gpus != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        windows_bench(a)
         return
     if a.fft:
         if a.gpus != 1:

@@ -161,6 +161,28 @@ int hloc_query_batch_async(hloc_db *db, const float *q, int32_t nq, int32_t k, i
                            void *stream);
 
 /*
+ * Sliding-window requests (Section 3.1: a request carries a frame and its
+ * neighbours, so consecutive requests of a video share all but one frame).
+ * Every frame of the batch is retrieved once; request i pools the results of
+ * the batch frames req_frames[req_offsets[i] .. req_offsets[i+1]-1] (indices
+ * into q, any order, repeats pooled again) and is aggregated as in
+ * hloc_query_batch. Device pointers, enqueued on `stream` like
+ * hloc_query_batch_async.
+ *   req_offsets : nreq + 1 int32 (device), non-decreasing from 0 to n_list.
+ *   req_frames  : n_list int32 (device), each in [0, nq).
+ * Outputs as hloc_query_batch (idx / dist per frame, xy / tile / flags per
+ * request). Malformed offsets or an index outside [0, nq) are detected on the
+ * device: that request gets HLOC_FLAG_BAD_REQUEST.
+ * Errors: EINVAL (NULL lists with nreq > 0, n_list < 0, as hloc_query_batch),
+ * ESTATE, EUNSUPPORTED, ENOMEM, EDEVICE.
+ */
+int hloc_query_windows_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
+                             int32_t n_regions, const int32_t *req_offsets,
+                             const int32_t *req_frames, int32_t n_list, int32_t nreq,
+                             int32_t precision, int64_t *idx, float *dist, double *xy,
+                             int32_t *tile, int32_t *flags, void *stream);
+
+/*
  * Pre-size the workspace for batches up to nq_max frames, nreq_max requests,
  * k_max and n_regions_max, so that later query calls within these limits
  * allocate nothing. Errors: EINVAL, ESTATE, ENOMEM, EDEVICE.

@@ -1,8 +1,12 @@
 // Multi-frame candidate aggregation (Section 3.2, Algorithm 2), one block per
 // request, integer arithmetic throughout:
 //   1. the request's frames pool their k candidates each (or the first
-//      req_k[r] of them; duplicates count, padding -1 is dropped) and every candidate becomes its tile key
-//      (iy, ix) from the precomputed floor(coord / cell) table;
+//      req_k[r] of them; duplicates count, padding -1 is dropped) and every
+//      candidate becomes its tile key (iy, ix) from the precomputed
+//      floor(coord / cell) table. The frames are req_offsets[r] ..
+//      req_offsets[r+1]-1 of the batch, or, with a frame list, the batch
+//      frames that list names there (sliding windows over a video share
+//      frames, each retrieved once: Section 3.1);
 //   2. the keys are sorted; runs give each distinct tile and its count
 //      (the 2-D binning of the location distribution array);
 //   3. tiles are ranked by (count desc, iy asc, ix asc): a tile's position in
@@ -16,6 +20,7 @@
 // one rounded FP64 add and one rounded multiply, so it is reproducible bit
 // for bit from the tile.
 #include "hloc_device.h"
+#include "hloc_host.h"
 #include "hloc_internal.h"
 
 #include <algorithm>
@@ -30,20 +35,27 @@ __device__ __forceinline__ int32_t unflip(uint32_t v) { return (int32_t)(v ^ 0x8
 
 constexpr int kAggSmall = 512;  // pooled candidates up to which a request takes the small kernel
 
+// Optional frame list: request r pools batch frames frames[req_offsets[r] ..
+// req_offsets[r+1]-1] (n entries), NULL = the frames themselves.
+struct FrameList {
+  const int32_t *frames;
+  int32_t n;
+};
+
 // Pooled candidates of request req (0 for an empty or malformed request).
-__device__ __forceinline__ int pooled_of(const AggArgs &a, int req) {
+__device__ __forceinline__ int pooled_of(const AggArgs &a, FrameList fl, int req) {
   const int f0 = a.req_offsets ? a.req_offsets[req] : req;
   const int f1 = a.req_offsets ? a.req_offsets[req + 1] : req + 1;
   const int kr = a.req_k ? a.req_k[req] : a.k;
-  if (f0 < 0 || f1 < f0 || f1 > a.nq || kr < 1 || kr > a.k) return 0;
+  if (f0 < 0 || f1 < f0 || f1 > (fl.frames ? fl.n : a.nq) || kr < 1 || kr > a.k) return 0;
   return (int)min<int64_t>((int64_t)(f1 - f0) * kr, (int64_t)kAggMax + 1);
 }
 
 // Algorithm 2 for one request with LDS lists of CAP entries (the request
 // pools at most CAP candidates, or is malformed).
 template <int CAP>
-__device__ void aggregate_one(const AggArgs &a, int req, uint64_t *lds, int *scratch,
-                              int *s_circle) {
+__device__ void aggregate_one(const AggArgs &a, FrameList fl, int req, uint64_t *lds,
+                              int *scratch, int *s_circle) {
   uint64_t *s_key = lds;           // CAP sorted tile keys
   uint64_t *s_rank = lds + CAP;    // CAP rank keys
   int *s_pos = reinterpret_cast<int *>(lds + 2 * CAP);  // CAP + 1 run starts
@@ -57,8 +69,15 @@ __device__ void aggregate_one(const AggArgs &a, int req, uint64_t *lds, int *scr
     f1 = req + 1;
   }
   const int kr = a.req_k ? a.req_k[req] : a.k;  // candidates pooled per frame
-  const bool bad = f0 < 0 || f1 < f0 || f1 > a.nq || kr < 1 || kr > a.k ||
-                   (int64_t)(f1 - f0) * kr > (int64_t)CAP;
+  bool bad = f0 < 0 || f1 < f0 || f1 > (fl.frames ? fl.n : a.nq) || kr < 1 || kr > a.k ||
+             (int64_t)(f1 - f0) * kr > (int64_t)CAP;
+  if (!bad && fl.frames) {
+    // every listed frame must be one of the batch
+    int out_of_range = 0;
+    for (int i = f0 + threadIdx.x; i < f1; i += blockDim.x)
+      out_of_range |= fl.frames[i] < 0 || fl.frames[i] >= a.nq;
+    bad = __syncthreads_or(out_of_range);
+  }
   if (bad) {
     if (tid == 0) {
       a.tile[2 * req] = 0;
@@ -71,13 +90,13 @@ __device__ void aggregate_one(const AggArgs &a, int req, uint64_t *lds, int *scr
   }
   const int P = (f1 - f0) * kr;
   const int Pp = next_pow2(P > 0 ? P : 1);
-  const int64_t *idx = a.idx + (int64_t)f0 * a.k;
   int valid_local = 0;
   for (int p = tid; p < Pp; p += blockDim.x) {
     uint64_t key = kKeyNone;
     if (p < P) {
       const int fr = p / kr;
-      const int64_t j = idx[(int64_t)fr * a.k + (p - fr * kr)];
+      const int frame = fl.frames ? fl.frames[f0 + fr] : f0 + fr;
+      const int64_t j = a.idx[(int64_t)frame * a.k + (p - fr * kr)];
       if (j >= 0) {
         const int2 t = a.tile_of[j];
         key = ((uint64_t)flip(t.y) << 32) | flip(t.x);
@@ -165,34 +184,35 @@ constexpr size_t agg_lds() {
 // One block per request. Requests pooling more than kAggSmall candidates
 // (up to kAggMax) are listed for k_aggregate_big instead: the small LDS
 // lets many blocks share a compute unit.
-__global__ __launch_bounds__(256) void k_aggregate(AggArgs a) {
+__global__ __launch_bounds__(256) void k_aggregate(AggArgs a, FrameList fl) {
   __shared__ uint64_t lds[agg_lds<kAggSmall>() / sizeof(uint64_t) + 1];
   __shared__ int scratch[16];
   __shared__ int s_circle[64];
   const int req = blockIdx.x;
   if (req >= a.nreq) return;
-  const int P = pooled_of(a, req);
+  const int P = pooled_of(a, fl, req);
   if (P > kAggSmall && P <= kAggMax) {
     if (threadIdx.x == 0) a.big_list[atomicAdd(a.big_count, 1)] = req;
     return;
   }
-  aggregate_one<kAggSmall>(a, req, lds, scratch, s_circle);
+  aggregate_one<kAggSmall>(a, fl, req, lds, scratch, s_circle);
 }
 
 // The listed requests, a persistent grid over them; without a list, request
 // blockIdx.x (every request of a batch that fits one round of blocks).
-__global__ __launch_bounds__(256) void k_aggregate_big(AggArgs a) {
+__global__ __launch_bounds__(256) void k_aggregate_big(AggArgs a, FrameList fl) {
   extern __shared__ uint64_t lds_big[];
   __shared__ int scratch[16];
   __shared__ int s_circle[64];
   if (!a.big_list) {
-    if ((int)blockIdx.x < a.nreq) aggregate_one<kAggMax>(a, blockIdx.x, lds_big, scratch, s_circle);
+    if ((int)blockIdx.x < a.nreq)
+      aggregate_one<kAggMax>(a, fl, blockIdx.x, lds_big, scratch, s_circle);
     return;
   }
   const int n = *a.big_count;
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     __syncthreads();  // the previous request's lists are no longer read
-    aggregate_one<kAggMax>(a, a.big_list[i], lds_big, scratch, s_circle);
+    aggregate_one<kAggMax>(a, fl, a.big_list[i], lds_big, scratch, s_circle);
   }
 }
 
@@ -210,20 +230,26 @@ hipError_t prepare_aggregate_kernels() {
   return e;
 }
 
-hipError_t launch_aggregate(const AggArgs &a, hipStream_t s) {
+hipError_t launch_aggregate_frames(const AggArgs &a, const int32_t *frames, int32_t n_frames,
+                                   hipStream_t s) {
   if (a.nreq <= 0) return hipSuccess;
   if (a.top_c < 1 || a.top_c > 64) return hipErrorInvalidValue;
+  const FrameList fl{frames, frames ? n_frames : 0};
   const int32_t cus = std::max(a.num_cu, 1);
   if (a.nreq <= cus) {
     // one round of blocks: a single launch with the large lists
     AggArgs b = a;
     b.big_list = nullptr;
-    return launch_kernel(k_aggregate_big, dim3(a.nreq), dim3(256), kAggLds, s, b);
+    return launch_kernel(k_aggregate_big, dim3(a.nreq), dim3(256), kAggLds, s, b, fl);
   }
-  hipError_t e = launch_kernel(k_aggregate, dim3(a.nreq), dim3(256), 0, s, a);
+  hipError_t e = launch_kernel(k_aggregate, dim3(a.nreq), dim3(256), 0, s, a, fl);
   if (e != hipSuccess) return e;
   // one resident block per compute unit at most (the lists take 82 KB of LDS)
-  return launch_kernel(k_aggregate_big, dim3(cus), dim3(256), kAggLds, s, a);
+  return launch_kernel(k_aggregate_big, dim3(cus), dim3(256), kAggLds, s, a, fl);
+}
+
+hipError_t launch_aggregate(const AggArgs &a, hipStream_t s) {
+  return launch_aggregate_frames(a, nullptr, 0, s);
 }
 
 }  // namespace hloc

@@ -212,7 +212,7 @@ struct Phaser {
 
 int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req_offsets,
                   const int32_t *req_k, int64_t *idx, float *dist, double *xy, int32_t *tile,
-                  int32_t *flags, hipStream_t s) {
+                  int32_t *flags, hipStream_t s, const int32_t *req_frames, int32_t n_frames) {
   const hloc_db *db = ws->db;
   const bool want_agg = xy || tile || flags;
   CHK(ensure_workspace(ws, p, want_agg && !(xy && tile && flags)));
@@ -398,7 +398,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     ag.big_count = misc + 8;
     ag.num_cu = db->num_cu;
     ph.begin(HLOC_PHASE_AGGREGATE);
-    HIPCHK(launch_aggregate(ag, s));
+    HIPCHK(launch_aggregate_frames(ag, req_frames, n_frames, s));
   }
   return HLOC_OK;
 }
@@ -810,6 +810,24 @@ int hloc_ws_query_async(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int3
   if (!ws) return fail(HLOC_EINVAL, "ws is NULL");
   return query_async(ws, q, nq, k, n_regions, req_offsets, nreq, precision, idx, dist, xy, tile,
                      flags, reinterpret_cast<hipStream_t>(stream));
+}
+
+int hloc_query_windows_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
+                             int32_t n_regions, const int32_t *req_offsets,
+                             const int32_t *req_frames, int32_t n_list, int32_t nreq,
+                             int32_t precision, int64_t *idx, float *dist, double *xy,
+                             int32_t *tile, int32_t *flags, void *stream) {
+  if (!db) return fail(HLOC_EINVAL, "db is NULL");
+  if (nreq > 0 && (!req_offsets || !req_frames))
+    return fail(HLOC_EINVAL, "req_offsets and req_frames must be non-NULL");
+  if (n_list < 0) return fail(HLOC_EINVAL, "n_list must be >= 0 (got %d)", n_list);
+  CHK(check_query_args(db, q, nq, req_offsets, nreq, precision, idx, dist));
+  Plan p;
+  CHK(make_plan(db, nq, k, n_regions, nreq, precision, &p));
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  return enqueue_query(db->ws0, p, q, req_offsets, nullptr, idx, dist, xy, tile, flags,
+                       reinterpret_cast<hipStream_t>(stream), req_frames, n_list);
 }
 
 int hloc_query_batch_async(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t n_regions,

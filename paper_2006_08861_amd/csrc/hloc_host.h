@@ -163,9 +163,16 @@ size_t alloc_size(size_t bytes);
 int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *bytes = nullptr);
 // Enqueues one batch on stream s. req_k (device, nreq entries, or NULL) gives
 // each request's candidates per frame for the aggregation (<= p.k).
+// req_frames (device, n_frames entries, or NULL): request r pools the batch
+// frames req_frames[req_offsets[r] .. req_offsets[r+1]-1] instead of the
+// frames req_offsets[r] .. req_offsets[r+1]-1.
 int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req_offsets,
                   const int32_t *req_k, int64_t *idx, float *dist, double *xy, int32_t *tile,
-                  int32_t *flags, hipStream_t s);
+                  int32_t *flags, hipStream_t s, const int32_t *req_frames = nullptr,
+                  int32_t n_frames = 0);
+// The aggregation of aggregate.hip over a frame list (NULL: contiguous frames).
+hipError_t launch_aggregate_frames(const AggArgs &a, const int32_t *frames, int32_t n_frames,
+                                   hipStream_t s);
 int check_query_args(const hloc_db *db, const float *q, int32_t nq, const int32_t *req_offsets,
                      int32_t nreq, int32_t precision, const int64_t *idx, const float *dist);
 int new_ws(hloc_db *db, hloc_ws **out);

@@ -55,6 +55,8 @@ _SIGNATURES = {
                                         _P]),
     "hloc_query_batch_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _P,
                                               _P, _P, _P, _P]),
+    "hloc_query_windows_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _P, _I32, _I32,
+                                                _I32, _P, _P, _P, _P, _P, _P]),
     "hloc_reserve": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32]),
     "hloc_query_info": (ctypes.c_int, [_P, _P, _I32]),
     "hloc_last_regions": (ctypes.c_int, [_P, _P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
@@ -264,6 +266,38 @@ class HlocDB:
         _check(lib.hloc_query_batch_async(self._h, p(q), nq, k, n_regions, p(offs), nreq, prec,
                                           p(idx), p(dist), p(xy), p(tile), p(flags),
                                           ctypes.c_void_p(s.cuda_stream)))
+        return out
+
+    def query_windows(self, q, k: int, n_regions: int, req_offsets, req_frames,
+                      precision="fp32", stream=None) -> dict:
+        """Sliding-window requests (hloc_query_windows_async): every frame of q
+        retrieved once, request i pooling frames req_frames[req_offsets[i] :
+        req_offsets[i+1]]. q, req_offsets and req_frames may be CUDA tensors
+        or NumPy arrays (copied to the device); returns CUDA tensors."""
+        import torch
+        dev = q.device if _is_torch_cuda(q) else torch.device("cuda", torch.cuda.current_device())
+
+        def on_dev(a, dtype):
+            if _is_torch_cuda(a):
+                return a.to(dtype).contiguous()
+            return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(dev)
+
+        qd = on_dev(q, torch.float32)
+        offs = on_dev(req_offsets, torch.int32)
+        frames = on_dev(req_frames, torch.int32)
+        nq, nreq = int(qd.shape[0]), int(offs.shape[0]) - 1
+        out = {"idx": torch.empty((nq, k), dtype=torch.int64, device=dev),
+               "dist": torch.empty((nq, k), dtype=torch.float32, device=dev),
+               "xy": torch.empty((nreq, 2), dtype=torch.float64, device=dev),
+               "tile": torch.empty((nreq, 2), dtype=torch.int32, device=dev),
+               "flags": torch.empty(nreq, dtype=torch.int32, device=dev)}
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        _check(load_library().hloc_query_windows_async(
+            self._h, _P(qd.data_ptr()), nq, k, n_regions, _P(offs.data_ptr()),
+            _P(frames.data_ptr()), int(frames.shape[0]), nreq, PRECISIONS[precision],
+            *(_P(out[key].data_ptr()) for key in ("idx", "dist", "xy", "tile", "flags")),
+            _P(stream.cuda_stream)))
         return out
 
     def info(self) -> dict:

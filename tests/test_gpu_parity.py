@@ -136,6 +136,60 @@ def test_exhaustive_full_shape(torch_cuda, fp32_shape):
     np.testing.assert_array_equal(one["dist"][0].view(np.uint32), out["dist"][7].view(np.uint32))
 
 
+def test_sliding_windows(torch_cuda):
+    """Windows of M = 11 frames (Section 4's window) over a 120-frame video
+    along the walk, each frame retrieved once (hloc_query_windows_async):
+    frame lists against the oracle, every request against the oracle's
+    estimate, and bitwise against the same windows sent as materialised
+    requests; a list naming a frame outside the batch flags only its request."""
+    torch = torch_cuda
+    w = workload.make_workload(0, nq=8)
+    rng = np.random.default_rng(21)
+    T, M = 120, 11
+    q = (w.feats[3000:3000 + T] + 0.1 * rng.standard_normal((T, w.feats.shape[1]))
+         ).astype(np.float32)
+    starts = np.arange(T - M + 1)
+    frames = np.concatenate([np.arange(s0, s0 + M) for s0 in starts]).astype(np.int32)
+    offs = (np.arange(len(starts) + 1) * M).astype(np.int32)
+    agg = (0.3, 10, 3.0, 20)
+    say(f"[case] sliding windows T={T} M={M}")
+    db = make_db(w.feats, w.xy, w.region_of, w.n_regions_total, agg)
+    out = db.query_windows(q, w.k, w.n_reg, offs, frames)
+    torch.cuda.synchronize()
+    out = {key: v.cpu().numpy() for key, v in out.items()}
+    regs = db.last_regions()
+    ora = oracle.localize(w.feats, w.xy, w.region_of, w.n_regions_total, q, offs, w.k, w.n_reg,
+                          agg, req_frames=frames)
+    st = judge_frames(out["idx"], out["dist"], regs, ora, w.feats, w.region_of,
+                      w.n_regions_total, q, w.k)
+    assert st["recall"] == 1.0
+    same_frames = np.array([set(out["idx"][i].tolist()) == set(ora["idx"][i].tolist())
+                            for i in range(T)])
+    checked = 0
+    for r in range(len(starts)):
+        fr = frames[offs[r]:offs[r + 1]]
+        if not same_frames[fr].all():
+            continue
+        checked += 1
+        assert out["tile"][r].tolist() == ora["tile"][r].tolist(), r
+        assert out["flags"][r] == ora["flags"][r], r
+        assert out["xy"][r].tolist() == ((ora["tile"][r] + 0.5) * agg[0]).tolist(), r
+    say(f"[ok] {st} windows checked {checked}/{len(starts)}")
+    assert checked >= len(starts) - 5
+    mat = run_device(torch, db, q[frames], w.k, w.n_reg, offs)
+    for key in ("tile", "flags"):
+        np.testing.assert_array_equal(mat[key], out[key])
+    np.testing.assert_array_equal(mat["xy"].view(np.uint64), out["xy"].view(np.uint64))
+    bad = frames.copy()
+    bad[2 * M + 3] = T + 5
+    out2 = db.query_windows(q, w.k, w.n_reg, offs, bad)
+    torch.cuda.synchronize()
+    flags2 = out2["flags"].cpu().numpy()
+    assert flags2[2] == hloc.FLAG_BAD_REQUEST
+    np.testing.assert_array_equal(np.delete(flags2, 2), np.delete(out["flags"], 2))
+    db.close()
+
+
 def test_host_and_device_entry_points_agree(torch_cuda, fp32_shape):
     w, db = fp32_shape
     say("[case] sync host-pointer call vs async device call")
