@@ -100,3 +100,51 @@ def test_counter_summary_round_trip(tmp_path, monkeypatch, capsys):
     monkeypatch.setattr(bench, "screen_digest", lambda: "changed")
     b, src = bench.load_traffic("unit", "fp32", 64)
     assert b is None and "changed" in src
+
+
+def test_fft_counter_record_round_trip(tmp_path, monkeypatch, capsys):
+    """The feature kernel's summary: per-dispatch FETCH/WRITE scaled by the
+    copy calibration, read back while the kernel source is unchanged."""
+    name = bench.fft_workload_name(200_000, 512, 256)
+    assert name == "fft-200k-L512-d256"
+    kname = bench.fft_kernel_name(512)
+    assert kname == "k_fft_magnitude_sq<16>" and bench.fft_kernel_name(1024) == "k_fft_magnitude"
+    full = f"void hloc::{kname}(float const*, long, int, float*)"
+    copy = "void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add<float> >"
+    f_csv, w_csv = str(tmp_path / "f.csv"), str(tmp_path / "w.csv")
+    cf_csv, cw_csv = str(tmp_path / "cf.csv"), str(tmp_path / "cw.csv")
+    _csv(f_csv, [dict(Dispatch_Id=i, Kernel_Name=full, Counter_Name="FETCH_SIZE",
+                      Counter_Value=300_000.0) for i in range(3)])
+    _csv(w_csv, [dict(Dispatch_Id=i, Kernel_Name=full, Counter_Name="WRITE_SIZE",
+                      Counter_Value=200_000.0) for i in range(3)])
+    _csv(cf_csv, [dict(Dispatch_Id=0, Kernel_Name=copy, Counter_Name="FETCH_SIZE",
+                       Counter_Value=512.0)])
+    _csv(cw_csv, [dict(Dispatch_Id=0, Kernel_Name=copy, Counter_Name="WRITE_SIZE",
+                       Counter_Value=1024.0)])
+
+    class A:
+        fft_counters = (f_csv, w_csv, cf_csv, cw_csv)
+        fft_signals, fft_len, fft_bins, copy_mib = 200_000, 512, 256, 1
+        commands = ["cmd"]
+
+    bench.fft_counters_summary(A)
+    text = capsys.readouterr().out
+    assert "record: " in text
+    monkeypatch.setattr(bench, "fft_counters_path", lambda n: str(tmp_path / "c.md"))
+    (tmp_path / "c.md").write_text(text)
+    traffic, src = bench.load_fft_traffic(name)
+    assert traffic == 1024.0 * (300_000.0 * 2.0 + 200_000.0 * 1.0)
+    monkeypatch.setattr(bench, "fft_digest", lambda: "another")
+    traffic, src = bench.load_fft_traffic(name)
+    assert traffic is None and "changed" in src
+
+
+def test_committed_fft_record_matches_the_kernel_source():
+    """The committed counters of the feature kernel: about the algorithmic
+    bytes (each signal read once, each bin written once). After a change to
+    the kernel the benchmark reports no traffic until they are taken again."""
+    import pytest
+    traffic, src = bench.load_fft_traffic("fft-200k-L512-d256")
+    if traffic is None:
+        pytest.skip(f"no current counter record: {src}")
+    assert abs(traffic / (200_000 * 4 * (512 + 256)) - 1.0) < 0.01
