@@ -240,6 +240,45 @@ def localize(feats, xy, region_of, n_regions_total, q, req_offsets, k, n_reg, ag
     return res
 
 
+# ------------------------------------------------- per-subspace top-N
+def localize_labels(feats, xy, region_of, n_regions_total, labels, q, req_offsets, k, n_reg,
+                    agg):
+    """Top-N per (frame, subspace) (Section 4 keeps N candidates per walked
+    path: N x M x P of them for a request of M frames over P paths).
+
+    labels: one subspace label per region, in [0, P). For every label p each
+    frame runs the two-stage search restricted to the regions labelled p (the
+    best n_reg of them by (d^2 to the mean, id), then their rows); request i
+    pools, for each of its frames and each label, that frame's k results, and
+    is aggregated as in localize. Returns idx / d2 as P x nq x k and the
+    per-request tile, pos and flags.
+    """
+    f = np.asarray(feats, dtype=np.float64)
+    qs = np.atleast_2d(np.asarray(q, dtype=np.float64))
+    lab = np.asarray(labels, dtype=np.int64)
+    P = int(lab.max()) + 1 if len(lab) else 0
+    reps, nonempty = region_means(f, region_of, n_regions_total)
+    idx = np.full((P, len(qs), k), -1, dtype=np.int64)
+    d2 = np.full((P, len(qs), k), np.inf)
+    for p in range(P):
+        keep = nonempty & (lab == p)
+        if not keep.any():
+            continue
+        lists = [select_regions(qi, reps, keep, n_reg)[0] for qi in qs]
+        res = retrieve(f, region_of, n_regions_total, qs, k, n_reg, regions=lists)
+        idx[p], d2[p] = res["idx"], res["d2"]
+    offs = np.asarray(req_offsets, dtype=np.int64)
+    nreq = len(offs) - 1
+    tile = np.zeros((nreq, 2), np.int64)
+    pos = np.zeros((nreq, 2))
+    flags = np.zeros(nreq, np.int32)
+    for i in range(nreq):
+        pooled = idx[:, offs[i]:offs[i + 1]].transpose(1, 0, 2).ravel()
+        ix, iy, x, y, fl = aggregate(pooled, xy, *agg)
+        tile[i], pos[i], flags[i] = (ix, iy), (x, y), fl
+    return dict(idx=idx, d2=d2, tile=tile, pos=pos, flags=flags)
+
+
 # ------------------------------------------------- omnidirectional feature
 def fft_magnitude(signals, d: int) -> np.ndarray:
     """Rotation-invariant omnidirectional feature (Section 3): the magnitude

@@ -313,6 +313,46 @@ def test_sliding_windows_equal_materialised_requests():
     assert ident["tile"].tolist() == plain["tile"].tolist()
 
 
+def test_labels_single_label_is_localize():
+    w = workload_small()
+    R = w.n_regions_total
+    one = oracle.localize_labels(w.feats, w.xy, w.region_of, R, np.zeros(R, int), w.q,
+                                 w.req_offsets, w.k, w.n_reg, w.agg)
+    plain = oracle.localize(w.feats, w.xy, w.region_of, R, w.q, w.req_offsets, w.k, w.n_reg,
+                            w.agg)
+    assert np.array_equal(one["idx"][0], plain["idx"])
+    assert one["tile"].tolist() == plain["tile"].tolist()
+
+
+def test_labels_equal_sub_databases():
+    # label p's lists are the plain search over a database holding only the
+    # rows of label p's regions (row ids mapped back), and hold only such rows
+    w = workload_small()
+    R = w.n_regions_total
+    labels = (np.arange(R) * 3) // R  # three contiguous runs of regions (paths)
+    res = oracle.localize_labels(w.feats, w.xy, w.region_of, R, labels, w.q, w.req_offsets,
+                                 w.k, w.n_reg, w.agg)
+    for p in range(3):
+        rows = np.nonzero(labels[w.region_of] == p)[0]
+        sub = oracle.retrieve(w.feats[rows], w.region_of[rows], R, w.q, w.k, w.n_reg)
+        mapped = np.where(sub["idx"] >= 0, rows[np.maximum(sub["idx"], 0)], -1)
+        assert np.array_equal(mapped, res["idx"][p]), p
+        got = res["idx"][p][res["idx"][p] >= 0]
+        assert np.all(labels[w.region_of[got]] == p)
+    # a request pools frames x labels x k candidates
+    i = 0
+    f0, f1 = w.req_offsets[i], w.req_offsets[i + 1]
+    pooled = res["idx"][:, f0:f1].transpose(1, 0, 2).ravel()
+    ix, iy, _, _, _ = oracle.aggregate(pooled, w.xy, *w.agg)
+    assert res["tile"][i].tolist() == [ix, iy]
+    assert len(pooled) == (f1 - f0) * 3 * w.k
+
+
+def workload_small():
+    from paper_2006_08861_amd import workload
+    return workload.make_workload(0, nq=24)
+
+
 # ------------------------------------------------ FFT-magnitude feature pins
 def test_fft_magnitude_hand_case():
     # x = (1, 2, 3, 4): X_0 = 10, X_1 = -2 + 2i, X_2 = -2 (worked by hand)
