@@ -504,6 +504,110 @@ def windows_bench(a) -> None:
     db.close()
 
 
+def labels_bench(a) -> None:
+    """Top N per (frame, path) with Section 4's parameters on fp32-200k-d256:
+    the 1,024 regions split into P contiguous runs (walked paths), requests
+    of M = 11 consecutive frames of the batch, N = 15 per frame and path, so
+    a request pools N x M x P = 825 candidates at P = 5."""
+    import torch
+
+    import oracle
+    from paper_2006_08861_amd import hloc, workload
+
+    w = workload.make_workload(1)
+    P, M, k = a.labels, 11, 15
+    R = w.n_regions_total
+    labels = ((np.arange(R) * P) // R).astype(np.int32)
+    nq = (len(w.q) // M) * M
+    q_h = w.q[:nq]
+    offs_h = np.arange(0, nq + 1, M).astype(np.int32)
+    nreq = len(offs_h) - 1
+    agg = (0.3, 10, 3.0, 20)
+    name = f"{w.name}-paths{P}-window{M}-top{k}"
+    dev = torch.device("cuda:0")
+    db = hloc.HlocDB(w.feats, w.xy)
+    db.set_regions(w.region_of, R)
+    db.set_aggregation(*agg)
+    db.set_region_labels(labels, P)
+    db.reserve(nq, nreq, k, w.n_reg)
+    q = torch.from_numpy(q_h).to(dev)
+    offs = torch.from_numpy(offs_h).to(dev)
+    out = {"idx": torch.empty((P, nq, k), dtype=torch.int64, device=dev),
+           "dist": torch.empty((P, nq, k), dtype=torch.float32, device=dev),
+           "xy": torch.empty((nreq, 2), dtype=torch.float64, device=dev),
+           "tile": torch.empty((nreq, 2), dtype=torch.int32, device=dev),
+           "flags": torch.empty(nreq, dtype=torch.int32, device=dev)}
+    stream = torch.cuda.current_stream(dev)
+    lib = hloc.load_library()
+    Pp = ctypes.c_void_p
+    args = (db._h, Pp(q.data_ptr()), nq, k, w.n_reg, Pp(offs.data_ptr()), nreq, hloc.FP32,
+            *(Pp(out[key].data_ptr()) for key in ("idx", "dist", "xy", "tile", "flags")),
+            Pp(stream.cuda_stream))
+
+    def step():
+        rc = lib.hloc_query_labels_async(*args)
+        if rc != 0:
+            raise hloc.HlocError(rc, lib.hloc_last_error().decode())
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / a.steps
+    # fine-screen launches of every label's pass, event-timed; the bytes are
+    # those of the last label's pass (the passes are alike in size)
+    db.profile(True)
+    for _ in range(a.steps):
+        step()
+    torch.cuda.synchronize()
+    phases = db.profile_read()
+    db.profile(False)
+    info = db.info()
+    regions = db.last_regions()
+    sizes = np.bincount(w.region_of, minlength=R)
+    d = w.feats.shape[1]
+    screen_bytes = int(sizes[np.unique(regions)].sum()) * (4 * d + 4) + info["candidates"] * 4 \
+        + nq * 4 * d
+    screen_ms = phases["screen"][0] / max(phases["screen"][1], 1)
+    if info["items"] > info["narrow_items"]:
+        screen_ms += phases["screen_wide"][0] / max(phases["screen_wide"][1], 1)
+    achieved = screen_bytes / (screen_ms * 1e-3) / 1e9
+    base, same = None, None
+    if not a.no_cpu_baseline:
+        m, t_cpu, done = 1, 0.0, 0
+        tile = out["tile"].cpu().numpy()
+        while t_cpu < a.cpu_seconds and m <= nreq:
+            t1 = time.perf_counter()
+            ora = oracle.localize_labels(w.feats, w.xy, w.region_of, R, labels, q_h[:m * M],
+                                         offs_h[:m + 1], k, w.n_reg, agg)
+            t_cpu += time.perf_counter() - t1
+            done += m
+            same = (int((tile[:m] == ora["tile"]).all(axis=1).sum()), m)
+            m *= 2
+        base = dict(value=done / t_cpu, unit="requests/s", cores=1, kind="oracle",
+                    sample=f"{done} requests of {name} (the first 1, 2, 4, ... requests), "
+                           f"single thread, {t_cpu:.1f} s")
+    print(json.dumps({
+        "metric": "localization requests/s with top-N per (frame, path) pooled (N x M x P "
+                  "candidates) vs FP64 oracle; HBM GB/s % peak",
+        "value": nreq / wall, "unit": "requests/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": wall * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": name, "paths": P, "frames_per_request": M, "top_n": k,
+                   "requests": nreq, "frames": nq, "candidates_per_request": k * M * P,
+                   "n_regions": w.n_reg, "aggregation": list(agg)},
+        "same_tiles_as_oracle": None if same is None else f"{same[0]}/{same[1]}",
+        "roofline": {"bound": "hbm", "kernel": "fine screen of one path's pass",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": screen_bytes, "avg_launch_ms": screen_ms},
+        "cpu_baseline": base}), flush=True)
+    db.close()
+
+
 def serve_bench(a) -> None:
     """Poisson arrivals of 1-16 frame requests (k in {8, 16, 32}) at a.serve
     requests/s into the request server for a.serve_seconds; prints one JSON
@@ -631,6 +735,8 @@ def main():
     ap.add_argument("--serve-batch", type=int, default=512, help="frames per batch")
     ap.add_argument("--serve-queue", type=int, default=1 << 16, help="frames waiting at most")
     ap.add_argument("--serve-budget", type=int, default=0, help="HBM bytes for the slots")
+    ap.add_argument("--labels", type=int, default=0, metavar="P",
+                    help="only run top-N per (frame, path) over P paths (N = 15, M = 11)")
     ap.add_argument("--windows", type=int, default=0, metavar="M",
                     help="only run sliding-window requests of M frames over a video")
     ap.add_argument("--windows-frames", type=int, default=256, help="video frames per batch")
@@ -645,6 +751,12 @@ def main():
     a = ap.parse_args()
     if a.fft_counters:
         fft_counters_summary(a)
+        return
+    if a.labels:
+        if a.gpus != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        labels_bench(a)
         return
     if a.windows:
         if a.gpus != 1:

@@ -79,6 +79,7 @@ enum { HLOC_MIRROR_BF16 = 1, HLOC_MIRROR_FP8 = 2 };
 #define HLOC_MAX_K 256               /* k */
 #define HLOC_MAX_REQUEST_CANDIDATES 4096 /* frames of one request x k */
 #define HLOC_MAX_TOP_C 64
+#define HLOC_MAX_LABELS 64           /* subspace labels */
 
 /*
  * Build a database from n feature vectors (Section 3: one omnidirectional
@@ -181,6 +182,34 @@ int hloc_query_windows_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
                              const int32_t *req_frames, int32_t n_list, int32_t nreq,
                              int32_t precision, int64_t *idx, float *dist, double *xy,
                              int32_t *tile, int32_t *flags, void *stream);
+
+/*
+ * Subspace labels (Section 3.1: the database is split into subspaces, such as
+ * the walked paths of Section 4, where the top N candidates of every path are
+ * kept: N x M x P for a request of M frames over P paths). labels: host, one
+ * int32 per region (R of hloc_set_regions), each in [0, n_labels); every
+ * label needs a non-empty region. Copied; hloc_set_regions drops them.
+ * Errors: EINVAL, ESTATE (no regions yet, or a server uses the database),
+ * ENOMEM, EDEVICE.
+ */
+int hloc_set_region_labels(hloc_db *db, const int32_t *labels, int32_t n_labels);
+
+/*
+ * Top k per (frame, label) and the aggregation over all of them: for every
+ * label p, each frame runs the search of hloc_query_batch restricted to the
+ * regions labelled p (the best min(n_regions, regions of p) of them, then their
+ * rows); request i pools, for each of its frames and each label, the k
+ * results (frames x labels x k candidates, at most
+ * HLOC_MAX_REQUEST_CANDIDATES). Device pointers, enqueued on `stream`.
+ *   req_offsets : nreq + 1 int32 (device) as hloc_query_batch, or NULL.
+ *   idx, dist   : n_labels x nq x k (label-major), as hloc_query_batch.
+ *   xy, tile, flags : per request, required when nreq > 0.
+ * Errors: EINVAL, ESTATE (no labels), EUNSUPPORTED, ENOMEM, EDEVICE.
+ */
+int hloc_query_labels_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
+                            int32_t n_regions, const int32_t *req_offsets, int32_t nreq,
+                            int32_t precision, int64_t *idx, float *dist, double *xy,
+                            int32_t *tile, int32_t *flags, void *stream);
 
 /*
  * Pre-size the workspace for batches up to nq_max frames, nreq_max requests,

@@ -212,7 +212,8 @@ struct Phaser {
 
 int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req_offsets,
                   const int32_t *req_k, int64_t *idx, float *dist, double *xy, int32_t *tile,
-                  int32_t *flags, hipStream_t s, const int32_t *req_frames, int32_t n_frames) {
+                  int32_t *flags, hipStream_t s, const int32_t *req_frames, int32_t n_frames,
+                  int32_t label) {
   const hloc_db *db = ws->db;
   const bool want_agg = xy || tile || flags;
   CHK(ensure_workspace(ws, p, want_agg && !(xy && tile && flags)));
@@ -279,6 +280,8 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
       HIPCHK(wide_dense ? launch_screen_wide_f32(sa, p.grid1, db->num_cu, s)
                         : launch_screen_f32(sa, p.grid1, s));
     }
+    if (label >= 0 && db->rlabel)
+      HIPCHK(launch_mask_label(as<uint32_t>(ws->cand1), p.nq, db->R, db->rlabel, label, s));
     ph.begin(HLOC_PHASE_COARSE_SELECT);
     SelRerankArgs ra{};
     ra.cand = as<uint32_t>(ws->cand1);
@@ -448,7 +451,8 @@ void free_ws(hloc_ws *ws) {
                    &ws->agg_tile, &ws->agg_flags, &ws->s_q,     &ws->s_off,   &ws->s_idx,
                    &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags, &ws->q_lp,
                    &ws->q_scale,  &ws->q_err,    &ws->q_lon,   &ws->slot_row,
-                   &ws->c_lp,     &ws->c_scale,  &ws->c_err,   &ws->c_lon,   &ws->agg_big};
+                   &ws->c_lp,     &ws->c_scale,  &ws->c_err,   &ws->c_lon,   &ws->agg_big,
+                   &ws->lab_off,  &ws->lab_list};
   for (WsBuf *b : bufs) free_buf(*b);
   for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
   if (ws->stream) (void)hipStreamDestroy(ws->stream);
@@ -502,6 +506,7 @@ void free_db_data(hloc_db *db) {
   dev_free(db->norm_max);
   dev_free(db->reg_start);
   dev_free(db->nonempty_ids);
+  dev_free(db->rlabel);
   dev_free(db->rep64);
   dev_free(db->rep32);
   dev_free(db->rep_n2);
@@ -648,7 +653,10 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   }
   for (int64_t i = 0; i < n; ++i) inv_cur[db->h_perm[i]] = (int32_t)i;
   for (int64_t i = 0; i < n; ++i) src_row[i] = inv_cur[new_perm[i]];
-  // release the old region data
+  // release the old region data (and the labels of the old regions)
+  dev_free(db->rlabel);
+  db->n_labels = 0;
+  db->h_label_nonempty.clear();
   dev_free(db->reg_start);
   dev_free(db->nonempty_ids);
   dev_free(db->rep64);
@@ -828,6 +836,95 @@ int hloc_query_windows_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   return enqueue_query(db->ws0, p, q, req_offsets, nullptr, idx, dist, xy, tile, flags,
                        reinterpret_cast<hipStream_t>(stream), req_frames, n_list);
+}
+
+int hloc_set_region_labels(hloc_db *db, const int32_t *labels, int32_t n_labels) {
+  if (!db) return fail(HLOC_EINVAL, "db is NULL");
+  if (!db->has_regions) return fail(HLOC_ESTATE, "hloc_set_regions has not been called");
+  if (db->servers > 0) return fail(HLOC_ESTATE, "a request server is using this database");
+  if (!labels) return fail(HLOC_EINVAL, "labels is NULL");
+  if (n_labels < 1 || n_labels > HLOC_MAX_LABELS)
+    return fail(HLOC_EINVAL, "n_labels must be in 1..%d (got %d)", HLOC_MAX_LABELS, n_labels);
+  std::vector<int32_t> nonempty((size_t)n_labels, 0);
+  for (int32_t r = 0; r < db->R; ++r) {
+    if (labels[r] < 0 || labels[r] >= n_labels)
+      return fail(HLOC_EINVAL, "labels[%d] = %d is outside [0, %d)", r, labels[r], n_labels);
+    if (db->h_reg_start[r + 1] > db->h_reg_start[r]) ++nonempty[(size_t)labels[r]];
+  }
+  for (int32_t p = 0; p < n_labels; ++p)
+    if (nonempty[(size_t)p] == 0)
+      return fail(HLOC_EINVAL, "label %d has no non-empty region", p);
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  HIPCHK(hipDeviceSynchronize());  // a batch in flight may read the old labels
+  dev_free(db->rlabel);
+  db->n_labels = 0;
+  // empty regions get label -1: a label's pass masks them with the other
+  // labels' regions (its survivors may outnumber its non-empty regions, and
+  // an empty region's zero representative must not be re-scored as a region)
+  std::vector<int32_t> dev_labels(labels, labels + db->R);
+  for (int32_t r = 0; r < db->R; ++r)
+    if (db->h_reg_start[r + 1] == db->h_reg_start[r]) dev_labels[(size_t)r] = -1;
+  CHK(dev_alloc(&db->rlabel, (size_t)db->R));
+  HIPCHK(hipMemcpy(db->rlabel, dev_labels.data(), (size_t)db->R * sizeof(int32_t),
+                   hipMemcpyHostToDevice));
+  db->h_label_nonempty = nonempty;
+  db->n_labels = n_labels;
+  return HLOC_OK;
+}
+
+int hloc_query_labels_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
+                            int32_t n_regions, const int32_t *req_offsets, int32_t nreq,
+                            int32_t precision, int64_t *idx, float *dist, double *xy,
+                            int32_t *tile, int32_t *flags, void *stream) {
+  if (!db) return fail(HLOC_EINVAL, "db is NULL");
+  if (db->n_labels < 1) return fail(HLOC_ESTATE, "hloc_set_region_labels has not been called");
+  CHK(check_query_args(db, q, nq, req_offsets, nreq, precision, idx, dist));
+  if (nreq > 0 && (!xy || !tile || !flags))
+    return fail(HLOC_EINVAL, "xy, tile and flags must be non-NULL");
+  if (n_regions < 1) return fail(HLOC_EINVAL, "n_regions must be >= 1 (got %d)", n_regions);
+  if (nq == 0 && nreq > 0) return fail(HLOC_EINVAL, "requests need frames (nq is 0)");
+  const int32_t P = db->n_labels;
+  if ((int64_t)nq * P > INT32_MAX) return fail(HLOC_EINVAL, "nq x labels too large");
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hloc_ws *ws = db->ws0;
+  // one search per label, each writing its nq x k slab of idx and dist
+  for (int32_t p = 0; p < P; ++p) {
+    Plan pl;
+    CHK(make_plan(db, nq, k, std::min(n_regions, db->h_label_nonempty[(size_t)p]), nreq,
+                  precision, &pl));
+    CHK(enqueue_query(ws, pl, q, nullptr, nullptr, idx + (int64_t)p * nq * k,
+                      dist + (int64_t)p * nq * k, nullptr, nullptr, nullptr, s, nullptr, 0,
+                      P > 1 ? p : -1));
+  }
+  if (nreq == 0) return HLOC_OK;
+  // every request pools its frames' lists under every label
+  CHK(ensure(ws->lab_off, (size_t)(nreq + 1) * sizeof(int32_t)));
+  CHK(ensure(ws->lab_list, (size_t)std::max<int64_t>((int64_t)nq * P, 1) * sizeof(int32_t)));
+  int32_t *lab_off = as<int32_t>(ws->lab_off), *lab_list = as<int32_t>(ws->lab_list);
+  HIPCHK(launch_label_lists(req_offsets, nreq, nq, P, lab_off, lab_list, s));
+  AggArgs ag{};
+  ag.idx = idx;
+  ag.k = k;
+  ag.nq = nq * P;
+  ag.req_offsets = lab_off;
+  ag.req_k = nullptr;
+  ag.nreq = nreq;
+  ag.tile_of = db->tiles;
+  ag.cell = db->cell;
+  ag.top_c = db->top_c;
+  ag.rho = db->rho;
+  ag.toler_pct = db->pct;
+  ag.xy = xy;
+  ag.tile = tile;
+  ag.flags = flags;
+  ag.big_list = as<int32_t>(ws->agg_big);
+  ag.big_count = as<int32_t>(ws->misc) + 8;  // cleared by the last search's prep
+  ag.num_cu = db->num_cu;
+  HIPCHK(launch_aggregate_frames(ag, lab_list, nq * P, s));
+  return HLOC_OK;
 }
 
 int hloc_query_batch_async(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t n_regions,

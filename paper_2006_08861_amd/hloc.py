@@ -57,6 +57,9 @@ _SIGNATURES = {
                                               _P, _P, _P, _P]),
     "hloc_query_windows_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _P, _I32, _I32,
                                                 _I32, _P, _P, _P, _P, _P, _P]),
+    "hloc_set_region_labels": (ctypes.c_int, [_P, _P, _I32]),
+    "hloc_query_labels_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _P,
+                                               _P, _P, _P, _P]),
     "hloc_reserve": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32]),
     "hloc_query_info": (ctypes.c_int, [_P, _P, _I32]),
     "hloc_last_regions": (ctypes.c_int, [_P, _P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
@@ -266,6 +269,39 @@ class HlocDB:
         _check(lib.hloc_query_batch_async(self._h, p(q), nq, k, n_regions, p(offs), nreq, prec,
                                           p(idx), p(dist), p(xy), p(tile), p(flags),
                                           ctypes.c_void_p(s.cuda_stream)))
+        return out
+
+    def set_region_labels(self, labels, n_labels: int):
+        lab = np.ascontiguousarray(labels, dtype=np.int32)
+        _check(load_library().hloc_set_region_labels(self._h, _np_ptr(lab), n_labels))
+
+    def query_labels(self, q, k: int, n_regions: int, n_labels: int, req_offsets=None,
+                     precision="fp32", stream=None) -> dict:
+        """Top k per (frame, subspace label) and one estimate per request
+        pooling frames x labels x k candidates (hloc_query_labels_async).
+        idx / dist come back as n_labels x nq x k CUDA tensors."""
+        import torch
+        dev = q.device if _is_torch_cuda(q) else torch.device("cuda", torch.cuda.current_device())
+        qd = q.float().contiguous() if _is_torch_cuda(q) else \
+            torch.from_numpy(np.ascontiguousarray(q, dtype=np.float32)).to(dev)
+        nq = int(qd.shape[0])
+        offs = None
+        if req_offsets is not None:
+            offs = req_offsets.to(torch.int32).contiguous() if _is_torch_cuda(req_offsets) else \
+                torch.from_numpy(np.ascontiguousarray(req_offsets, dtype=np.int32)).to(dev)
+        nreq = nq if offs is None else int(offs.shape[0]) - 1
+        out = {"idx": torch.empty((n_labels, nq, k), dtype=torch.int64, device=dev),
+               "dist": torch.empty((n_labels, nq, k), dtype=torch.float32, device=dev),
+               "xy": torch.empty((nreq, 2), dtype=torch.float64, device=dev),
+               "tile": torch.empty((nreq, 2), dtype=torch.int32, device=dev),
+               "flags": torch.empty(nreq, dtype=torch.int32, device=dev)}
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        _check(load_library().hloc_query_labels_async(
+            self._h, _P(qd.data_ptr()), nq, k, n_regions,
+            None if offs is None else _P(offs.data_ptr()), nreq, PRECISIONS[precision],
+            *(_P(out[key].data_ptr()) for key in ("idx", "dist", "xy", "tile", "flags")),
+            _P(stream.cuda_stream)))
         return out
 
     def query_windows(self, q, k: int, n_regions: int, req_offsets, req_frames,

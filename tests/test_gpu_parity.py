@@ -190,6 +190,51 @@ def test_sliding_windows(torch_cuda):
     db.close()
 
 
+@pytest.mark.parametrize("n_reg", [5, 1000])
+def test_subspace_labels(torch_cuda, n_reg):
+    """Top k per (frame, label) over three labels (contiguous runs of regions,
+    like walked paths) and requests of 5 frames pooling frames x labels x k:
+    every list against the oracle's label-restricted search, every request
+    against its estimate; n_regions = 1000 searches every region of each
+    label. One label covering all regions gives the plain query bitwise."""
+    torch = torch_cuda
+    w = workload.make_workload(0, nq=60)
+    R = w.n_regions_total
+    labels = ((np.arange(R) * 3) // R).astype(np.int32)
+    offs = np.arange(0, 61, 5).astype(np.int32)
+    agg = (0.3, 10, 3.0, 20)
+    say(f"[case] labels P=3 n_reg={n_reg}")
+    db = make_db(w.feats, w.xy, w.region_of, R, agg)
+    db.set_region_labels(labels, 3)
+    out = db.query_labels(w.q, w.k, n_reg, 3, offs)
+    torch.cuda.synchronize()
+    out = {key: v.cpu().numpy() for key, v in out.items()}
+    ora = oracle.localize_labels(w.feats, w.xy, w.region_of, R, labels, w.q, offs, w.k, n_reg,
+                                 agg)
+    same = np.zeros((3, len(w.q)), bool)
+    for p in range(3):
+        for i in range(len(w.q)):
+            same[p, i] = set(out["idx"][p, i].tolist()) == set(ora["idx"][p, i].tolist())
+            ok = np.isfinite(ora["d2"][p, i])
+            assert np.all(np.abs(out["dist"][p, i][ok] - ora["d2"][p, i][ok])
+                          <= 1e-5 * ora["d2"][p, i][ok] + 1e-30), (p, i)
+        got = out["idx"][p][out["idx"][p] >= 0]
+        assert np.all(labels[w.region_of[got]] == p)
+    say(f"[ok] lists equal {int(same.sum())}/{same.size}")
+    assert same.sum() >= same.size - 2
+    for r in range(len(offs) - 1):
+        if same[:, offs[r]:offs[r + 1]].all():
+            assert out["tile"][r].tolist() == ora["tile"][r].tolist(), r
+            assert out["flags"][r] == ora["flags"][r], r
+    db.set_region_labels(np.zeros(R, np.int32), 1)
+    one = db.query_labels(w.q, w.k, n_reg, 1, offs)
+    plain = run_device(torch, db, w.q, w.k, n_reg, offs)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(one["idx"][0].cpu().numpy(), plain["idx"])
+    np.testing.assert_array_equal(one["tile"].cpu().numpy(), plain["tile"])
+    db.close()
+
+
 def test_host_and_device_entry_points_agree(torch_cuda, fp32_shape):
     w, db = fp32_shape
     say("[case] sync host-pointer call vs async device call")
