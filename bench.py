@@ -557,8 +557,8 @@ def labels_bench(a) -> None:
         step()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / a.steps
-    # fine-screen launches of every label's pass, event-timed; the bytes are
-    # those of the last label's pass (the passes are alike in size)
+    # the fine screen, event-timed: with n_regions within every path's
+    # regions the paths run as one batch of frames x paths (one screen launch)
     db.profile(True)
     for _ in range(a.steps):
         step()
@@ -600,7 +600,7 @@ def labels_bench(a) -> None:
                    "requests": nreq, "frames": nq, "candidates_per_request": k * M * P,
                    "n_regions": w.n_reg, "aggregation": list(agg)},
         "same_tiles_as_oracle": None if same is None else f"{same[0]}/{same[1]}",
-        "roofline": {"bound": "hbm", "kernel": "fine screen of one path's pass",
+        "roofline": {"bound": "hbm", "kernel": "fine screen (frames x paths in one batch)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": screen_bytes, "avg_launch_ms": screen_ms},

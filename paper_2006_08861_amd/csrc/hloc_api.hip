@@ -213,7 +213,7 @@ struct Phaser {
 int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req_offsets,
                   const int32_t *req_k, int64_t *idx, float *dist, double *xy, int32_t *tile,
                   int32_t *flags, hipStream_t s, const int32_t *req_frames, int32_t n_frames,
-                  int32_t label) {
+                  int32_t label, int32_t label_frames) {
   const hloc_db *db = ws->db;
   const bool want_agg = xy || tile || flags;
   CHK(ensure_workspace(ws, p, want_agg && !(xy && tile && flags)));
@@ -280,8 +280,9 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
       HIPCHK(wide_dense ? launch_screen_wide_f32(sa, p.grid1, db->num_cu, s)
                         : launch_screen_f32(sa, p.grid1, s));
     }
-    if (label >= 0 && db->rlabel)
-      HIPCHK(launch_mask_label(as<uint32_t>(ws->cand1), p.nq, db->R, db->rlabel, label, s));
+    if ((label >= 0 || label_frames > 0) && db->rlabel)
+      HIPCHK(launch_mask_label(as<uint32_t>(ws->cand1), p.nq, db->R, db->rlabel, label,
+                               label_frames, s));
     ph.begin(HLOC_PHASE_COARSE_SELECT);
     SelRerankArgs ra{};
     ra.cand = as<uint32_t>(ws->cand1);
@@ -452,7 +453,7 @@ void free_ws(hloc_ws *ws) {
                    &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags, &ws->q_lp,
                    &ws->q_scale,  &ws->q_err,    &ws->q_lon,   &ws->slot_row,
                    &ws->c_lp,     &ws->c_scale,  &ws->c_err,   &ws->c_lon,   &ws->agg_big,
-                   &ws->lab_off,  &ws->lab_list};
+                   &ws->lab_off,  &ws->lab_list, &ws->lab_q};
   for (WsBuf *b : bufs) free_buf(*b);
   for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
   if (ws->stream) (void)hipStreamDestroy(ws->stream);
@@ -890,14 +891,31 @@ int hloc_query_labels_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hloc_ws *ws = db->ws0;
-  // one search per label, each writing its nq x k slab of idx and dist
-  for (int32_t p = 0; p < P; ++p) {
+  const int32_t min_ne =
+      *std::min_element(db->h_label_nonempty.begin(), db->h_label_nonempty.end());
+  if (P > 1 && n_regions <= min_ne && nq > 0) {
+    // every label has n_regions regions: one batch holding the frames once
+    // per label (frame p * nq + f is frame f under label p) writes the
+    // label-major slabs of idx and dist in one pass
     Plan pl;
-    CHK(make_plan(db, nq, k, std::min(n_regions, db->h_label_nonempty[(size_t)p]), nreq,
-                  precision, &pl));
-    CHK(enqueue_query(ws, pl, q, nullptr, nullptr, idx + (int64_t)p * nq * k,
-                      dist + (int64_t)p * nq * k, nullptr, nullptr, nullptr, s, nullptr, 0,
-                      P > 1 ? p : -1));
+    CHK(make_plan(db, nq * P, k, n_regions, nreq, precision, &pl));
+    const size_t fbytes = (size_t)nq * db->d * sizeof(float);
+    CHK(ensure(ws->lab_q, fbytes * (size_t)P));
+    for (int32_t p = 0; p < P; ++p)
+      HIPCHK(hipMemcpyAsync(static_cast<char *>(ws->lab_q.p) + fbytes * (size_t)p, q, fbytes,
+                            hipMemcpyDeviceToDevice, s));
+    CHK(enqueue_query(ws, pl, as<float>(ws->lab_q), nullptr, nullptr, idx, dist, nullptr,
+                      nullptr, nullptr, s, nullptr, 0, -1, nq));
+  } else {
+    // one search per label, each writing its nq x k slab of idx and dist
+    for (int32_t p = 0; p < P; ++p) {
+      Plan pl;
+      CHK(make_plan(db, nq, k, std::min(n_regions, db->h_label_nonempty[(size_t)p]), nreq,
+                    precision, &pl));
+      CHK(enqueue_query(ws, pl, q, nullptr, nullptr, idx + (int64_t)p * nq * k,
+                        dist + (int64_t)p * nq * k, nullptr, nullptr, nullptr, s, nullptr, 0,
+                        P > 1 ? p : -1));
+    }
   }
   if (nreq == 0) return HLOC_OK;
   // every request pools its frames' lists under every label

@@ -90,7 +90,8 @@ struct hloc_ws {
       items, cand2, agg_xy, agg_tile, agg_flags, q_lp, q_scale, q_err, q_lon, slot_row,
       c_lp, c_scale, c_err, c_lon,  // bf16 frame copy for the coarse screen of fp8 queries
       agg_big,                      // requests for the large-list aggregation kernel
-      lab_off, lab_list;            // frame lists of a query over subspace labels
+      lab_off, lab_list,            // frame lists of a query over subspace labels
+      lab_q;                        // its frames once per label
   hloc::WsBuf s_q, s_off, s_idx, s_dist, s_xy, s_tile, s_flags;  // staging of host-pointer calls
   int32_t last_nq = 0, last_nr = 0, last_kp = 0;
   bool prof_on = false;
@@ -170,13 +171,14 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *byte
 // req_frames (device, n_frames entries, or NULL): request r pools the batch
 // frames req_frames[req_offsets[r] .. req_offsets[r+1]-1] instead of the
 // frames req_offsets[r] .. req_offsets[r+1]-1.
-// label >= 0: the coarse selection keeps only regions with that label.
+// label >= 0: the coarse selection keeps only regions with that label;
+// label_frames > 0: frame f keeps only regions labelled f / label_frames.
 int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req_offsets,
                   const int32_t *req_k, int64_t *idx, float *dist, double *xy, int32_t *tile,
                   int32_t *flags, hipStream_t s, const int32_t *req_frames = nullptr,
-                  int32_t n_frames = 0, int32_t label = -1);
+                  int32_t n_frames = 0, int32_t label = -1, int32_t label_frames = 0);
 hipError_t launch_mask_label(uint32_t *words, int32_t nq, int32_t R, const int32_t *rlabel,
-                             int32_t p, hipStream_t s);
+                             int32_t p, int32_t per, hipStream_t s);
 hipError_t launch_label_lists(const int32_t *req_offsets, int32_t nreq, int32_t nq, int32_t P,
                               int32_t *list_off, int32_t *list, hipStream_t s);
 // The aggregation of aggregate.hip over a frame list (NULL: contiguous frames).

@@ -12,20 +12,25 @@
 namespace hloc {
 
 // words: nq x R coarse screen words (frame-major); those of regions whose
-// label is not p become 0xFFFFFFFF (no candidate).
+// label is not the frame's become 0xFFFFFFFF (no candidate). The frame's
+// label is p, or, with per > 0, frame / per (a batch holding the frames once
+// per label).
 __global__ void k_mask_label(uint32_t *words, int64_t total, int R,
-                             const int32_t *__restrict__ rlabel, int p) {
+                             const int32_t *__restrict__ rlabel, int p, int per) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x)
-    if (rlabel[i % R] != p) words[i] = 0xFFFFFFFFu;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int lab = per > 0 ? (int)((i / R) / per) : p;
+    if (rlabel[i % R] != lab) words[i] = 0xFFFFFFFFu;
+  }
 }
 
 hipError_t launch_mask_label(uint32_t *words, int32_t nq, int32_t R, const int32_t *rlabel,
-                             int32_t p, hipStream_t s) {
+                             int32_t p, int32_t per, hipStream_t s) {
   const int64_t total = (int64_t)nq * R;
   if (total <= 0) return hipSuccess;
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
-  return launch_kernel(k_mask_label, dim3(grid), dim3(256), 0, s, words, total, R, rlabel, p);
+  return launch_kernel(k_mask_label, dim3(grid), dim3(256), 0, s, words, total, R, rlabel, p,
+                       per);
 }
 
 // Frame lists of the labelled query: the results of frame f under label p
