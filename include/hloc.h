@@ -201,13 +201,17 @@ int hloc_set_region_labels(hloc_db *db, const int32_t *labels, int32_t n_labels)
  * rows); request i pools, for each of its frames and each label, the k
  * results (frames x labels x k candidates, at most
  * HLOC_MAX_REQUEST_CANDIDATES). Device pointers, enqueued on `stream`.
+ *   n_labels    : the label count given to hloc_set_region_labels (the
+ *                 caller's outputs are sized by it; a different value is
+ *                 EINVAL, so the kernels never write past them).
  *   req_offsets : nreq + 1 int32 (device) as hloc_query_batch, or NULL.
  *   idx, dist   : n_labels x nq x k (label-major), as hloc_query_batch.
  *   xy, tile, flags : per request, required when nreq > 0.
  * Errors: EINVAL, ESTATE (no labels), EUNSUPPORTED, ENOMEM, EDEVICE.
  */
 int hloc_query_labels_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
-                            int32_t n_regions, const int32_t *req_offsets, int32_t nreq,
+                            int32_t n_regions, int32_t n_labels, const int32_t *req_offsets,
+                            int32_t nreq,
                             int32_t precision, int64_t *idx, float *dist, double *xy,
                             int32_t *tile, int32_t *flags, void *stream);
 
@@ -272,8 +276,13 @@ int hloc_ws_query_info(hloc_ws *ws, int64_t *out, int32_t n);
  * hloc_ws_replay(ws, stream) launches that graph on `stream`: the batch runs
  * again on whatever the captured input buffers hold at that time, writing the
  * captured output buffers. The buffers must stay valid while the graph is in
- * use; capturing again replaces the graph. Errors: EINVAL, ESTATE (replay
- * without capture), EUNSUPPORTED, ENOMEM, EDEVICE.
+ * use; capturing again replaces the graph. The graph holds the addresses of
+ * the workspace's buffers and of the database's arrays: a later call that
+ * grows a buffer of this workspace, or hloc_set_regions,
+ * hloc_set_aggregation or hloc_set_region_labels on its database, drops or
+ * outdates it, and replay then returns ESTATE until the batch is captured
+ * again. Errors: EINVAL, ESTATE (replay without a current capture),
+ * EUNSUPPORTED, ENOMEM, EDEVICE.
  */
 int hloc_ws_capture(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int32_t n_regions,
                     const int32_t *req_offsets, int32_t nreq, int32_t precision, int64_t *idx,

@@ -68,7 +68,7 @@ def region_means(feats: np.ndarray, region_of: np.ndarray, n_regions_total: int)
     Returns (reps, nonempty): reps[r] is (1/s_r) * sum of the rows with
     region_of == r; rows of empty regions are NaN and nonempty[r] is False.
     """
-    f = np.asarray(feats, dtype=np.float64)
+    f = np.asarray(feats)  # float32 values are added to the FP64 sums exactly promoted
     reg = np.asarray(region_of, dtype=np.int64)
     d = f.shape[1]
     sums = np.zeros((n_regions_total, d), dtype=np.float64)
@@ -143,7 +143,9 @@ def retrieve(feats, region_of, n_regions_total, q, k, n_reg, reps=None, regions=
     Returns a dict of per-query arrays: regions (list of id arrays), region_d2,
     gap_r, idx (nq x k), d2 (nq x k, FP64), gap_k, n_cand, band (list).
     """
-    f = np.asarray(feats, dtype=np.float64)
+    # the rows keep their stored type: sq_dist promotes the gathered rows to
+    # FP64 (exact for float32), so a large database is never copied whole
+    f = np.asarray(feats)
     reg = np.asarray(region_of, dtype=np.int64)
     qs = np.atleast_2d(np.asarray(q, dtype=np.float64))
     if reps is None:
@@ -250,23 +252,29 @@ def localize_labels(feats, xy, region_of, n_regions_total, labels, q, req_offset
     frame runs the two-stage search restricted to the regions labelled p (the
     best n_reg of them by (d^2 to the mean, id), then their rows); request i
     pools, for each of its frames and each label, that frame's k results, and
-    is aggregated as in localize. Returns idx / d2 as P x nq x k and the
-    per-request tile, pos and flags.
+    is aggregated as in localize. Returns idx / d2 as P x nq x k, per label
+    the per-frame lists of retrieve (regions, gap_r, gap_k, band) under
+    "per_label", and the per-request tile, pos and flags.
     """
-    f = np.asarray(feats, dtype=np.float64)
+    f = np.asarray(feats)
     qs = np.atleast_2d(np.asarray(q, dtype=np.float64))
     lab = np.asarray(labels, dtype=np.int64)
     P = int(lab.max()) + 1 if len(lab) else 0
     reps, nonempty = region_means(f, region_of, n_regions_total)
     idx = np.full((P, len(qs), k), -1, dtype=np.int64)
     d2 = np.full((P, len(qs), k), np.inf)
+    per_label = []
     for p in range(P):
         keep = nonempty & (lab == p)
         if not keep.any():
+            per_label.append(None)
             continue
-        lists = [select_regions(qi, reps, keep, n_reg)[0] for qi in qs]
-        res = retrieve(f, region_of, n_regions_total, qs, k, n_reg, regions=lists)
+        sel = [select_regions(qi, reps, keep, n_reg) for qi in qs]
+        res = retrieve(f, region_of, n_regions_total, qs, k, n_reg, regions=[s_[0] for s_ in sel])
+        # the coarse gap is the one of the label's own region ranking
+        res["gap_r"] = np.array([s_[2] for s_ in sel])
         idx[p], d2[p] = res["idx"], res["d2"]
+        per_label.append(res)
     offs = np.asarray(req_offsets, dtype=np.int64)
     nreq = len(offs) - 1
     tile = np.zeros((nreq, 2), np.int64)
@@ -276,7 +284,7 @@ def localize_labels(feats, xy, region_of, n_regions_total, labels, q, req_offset
         pooled = idx[:, offs[i]:offs[i + 1]].transpose(1, 0, 2).ravel()
         ix, iy, x, y, fl = aggregate(pooled, xy, *agg)
         tile[i], pos[i], flags[i] = (ix, iy), (x, y), fl
-    return dict(idx=idx, d2=d2, tile=tile, pos=pos, flags=flags)
+    return dict(idx=idx, d2=d2, tile=tile, pos=pos, flags=flags, per_label=per_label)
 
 
 # ------------------------------------------------- omnidirectional feature

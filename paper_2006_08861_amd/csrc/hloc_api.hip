@@ -59,6 +59,12 @@ int ensure(WsBuf &b, size_t bytes) {
   return HLOC_OK;
 }
 
+int ws_ensure(hloc_ws *ws, WsBuf &b, size_t bytes) {
+  if (bytes <= b.cap && b.p) return HLOC_OK;
+  drop_graph(ws);
+  return ensure(b, bytes);
+}
+
 template <class T>
 int dev_alloc(T **p, size_t count) {
   if (hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(count, 1) * sizeof(T)) !=
@@ -136,7 +142,7 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *byte
       *bytes += alloc_size(need);
       return HLOC_OK;
     }
-    return ensure(b, need);
+    return ws_ensure(ws, b, need);
   };
   const int64_t nq = std::max(p.nq, 1), nr = std::max(p.nr, 1);
   CHK(fit(ws->qp, (size_t)nq * db->dp * sizeof(float)));
@@ -654,7 +660,9 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   }
   for (int64_t i = 0; i < n; ++i) inv_cur[db->h_perm[i]] = (int32_t)i;
   for (int64_t i = 0; i < n; ++i) src_row[i] = inv_cur[new_perm[i]];
-  // release the old region data (and the labels of the old regions)
+  // release the old region data (and the labels of the old regions); graphs
+  // captured before hold their addresses
+  ++db->gen;
   dev_free(db->rlabel);
   db->n_labels = 0;
   db->h_label_nonempty.clear();
@@ -768,6 +776,7 @@ int hloc_set_aggregation(hloc_db *db, double cell_m, int32_t top_c, double radiu
   DeviceGuard g(db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   HIPCHK(hipDeviceSynchronize());
+  ++db->gen;  // captured graphs hold the old constants
   db->cell = cell_m;
   db->top_c = top_c;
   db->radius = radius_m;
@@ -858,6 +867,7 @@ int hloc_set_region_labels(hloc_db *db, const int32_t *labels, int32_t n_labels)
   DeviceGuard g(db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   HIPCHK(hipDeviceSynchronize());  // a batch in flight may read the old labels
+  ++db->gen;
   dev_free(db->rlabel);
   db->n_labels = 0;
   // empty regions get label -1: a label's pass masks them with the other
@@ -875,11 +885,14 @@ int hloc_set_region_labels(hloc_db *db, const int32_t *labels, int32_t n_labels)
 }
 
 int hloc_query_labels_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
-                            int32_t n_regions, const int32_t *req_offsets, int32_t nreq,
-                            int32_t precision, int64_t *idx, float *dist, double *xy,
-                            int32_t *tile, int32_t *flags, void *stream) {
+                            int32_t n_regions, int32_t n_labels, const int32_t *req_offsets,
+                            int32_t nreq, int32_t precision, int64_t *idx, float *dist,
+                            double *xy, int32_t *tile, int32_t *flags, void *stream) {
   if (!db) return fail(HLOC_EINVAL, "db is NULL");
   if (db->n_labels < 1) return fail(HLOC_ESTATE, "hloc_set_region_labels has not been called");
+  if (n_labels != db->n_labels)
+    return fail(HLOC_EINVAL, "n_labels %d differs from the %d labels set on the database",
+                n_labels, db->n_labels);
   CHK(check_query_args(db, q, nq, req_offsets, nreq, precision, idx, dist));
   if (nreq > 0 && (!xy || !tile || !flags))
     return fail(HLOC_EINVAL, "xy, tile and flags must be non-NULL");
@@ -900,7 +913,7 @@ int hloc_query_labels_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
     Plan pl;
     CHK(make_plan(db, nq * P, k, n_regions, nreq, precision, &pl));
     const size_t fbytes = (size_t)nq * db->d * sizeof(float);
-    CHK(ensure(ws->lab_q, fbytes * (size_t)P));
+    CHK(ws_ensure(ws, ws->lab_q, fbytes * (size_t)P));
     for (int32_t p = 0; p < P; ++p)
       HIPCHK(hipMemcpyAsync(static_cast<char *>(ws->lab_q.p) + fbytes * (size_t)p, q, fbytes,
                             hipMemcpyDeviceToDevice, s));
@@ -919,8 +932,8 @@ int hloc_query_labels_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
   }
   if (nreq == 0) return HLOC_OK;
   // every request pools its frames' lists under every label
-  CHK(ensure(ws->lab_off, (size_t)(nreq + 1) * sizeof(int32_t)));
-  CHK(ensure(ws->lab_list, (size_t)std::max<int64_t>((int64_t)nq * P, 1) * sizeof(int32_t)));
+  CHK(ws_ensure(ws, ws->lab_off, (size_t)(nreq + 1) * sizeof(int32_t)));
+  CHK(ws_ensure(ws, ws->lab_list, (size_t)std::max<int64_t>((int64_t)nq * P, 1) * sizeof(int32_t)));
   int32_t *lab_off = as<int32_t>(ws->lab_off), *lab_list = as<int32_t>(ws->lab_list);
   HIPCHK(launch_label_lists(req_offsets, nreq, nq, P, lab_off, lab_list, s));
   AggArgs ag{};
@@ -987,12 +1000,15 @@ int hloc_ws_capture(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int32_t 
     return fail(HLOC_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
   }
   ws->graph = graph;
+  ws->graph_gen = db->gen;
   return HLOC_OK;
 }
 
 int hloc_ws_replay(hloc_ws *ws, void *stream) {
   if (!ws) return fail(HLOC_EINVAL, "ws is NULL");
   if (!ws->exec) return fail(HLOC_ESTATE, "no batch has been captured on this workspace");
+  if (ws->graph_gen != ws->db->gen)
+    return fail(HLOC_ESTATE, "the database changed since the batch was captured; capture it again");
   DeviceGuard g(ws->db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   HIPCHK(hipGraphLaunch(ws->exec, reinterpret_cast<hipStream_t>(stream)));
@@ -1011,14 +1027,14 @@ int hloc_query_batch(hloc_db *db, const float *q, int32_t nq, int32_t k, int32_t
   hloc_ws *ws = db->ws0;
   const bool want_agg = xy || tile || flags;
   const int64_t nqk = (int64_t)nq * k;
-  CHK(ensure(ws->s_q, (size_t)std::max<int64_t>((int64_t)nq * db->d, 1) * sizeof(float)));
-  CHK(ensure(ws->s_off, (size_t)(nreq + 1) * sizeof(int32_t)));
-  CHK(ensure(ws->s_idx, (size_t)std::max<int64_t>(nqk, 1) * sizeof(int64_t)));
-  CHK(ensure(ws->s_dist, (size_t)std::max<int64_t>(nqk, 1) * sizeof(float)));
+  CHK(ws_ensure(ws, ws->s_q, (size_t)std::max<int64_t>((int64_t)nq * db->d, 1) * sizeof(float)));
+  CHK(ws_ensure(ws, ws->s_off, (size_t)(nreq + 1) * sizeof(int32_t)));
+  CHK(ws_ensure(ws, ws->s_idx, (size_t)std::max<int64_t>(nqk, 1) * sizeof(int64_t)));
+  CHK(ws_ensure(ws, ws->s_dist, (size_t)std::max<int64_t>(nqk, 1) * sizeof(float)));
   if (want_agg) {
-    CHK(ensure(ws->s_xy, (size_t)std::max(nreq, 1) * 2 * sizeof(double)));
-    CHK(ensure(ws->s_tile, (size_t)std::max(nreq, 1) * 2 * sizeof(int32_t)));
-    CHK(ensure(ws->s_flags, (size_t)std::max(nreq, 1) * sizeof(int32_t)));
+    CHK(ws_ensure(ws, ws->s_xy, (size_t)std::max(nreq, 1) * 2 * sizeof(double)));
+    CHK(ws_ensure(ws, ws->s_tile, (size_t)std::max(nreq, 1) * 2 * sizeof(int32_t)));
+    CHK(ws_ensure(ws, ws->s_flags, (size_t)std::max(nreq, 1) * sizeof(int32_t)));
   }
   hipStream_t s = ws->stream;
   if (nq > 0)

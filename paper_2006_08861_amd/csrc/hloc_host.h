@@ -100,6 +100,7 @@ struct hloc_ws {
   std::vector<hloc::ProfRec> prof;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  uint64_t graph_gen = 0;  // hloc_db::gen when the graph was captured
 };
 
 struct hloc_db {
@@ -143,6 +144,7 @@ struct hloc_db {
   hloc_ws *ws0 = nullptr;  // workspace of the calls that take no workspace
   int32_t user_ws = 0;     // workspaces created by the caller and not yet freed
   int32_t servers = 0;     // request servers over this database not yet freed
+  uint64_t gen = 1;        // bumped whenever arrays or constants a captured graph uses change
 };
 
 namespace hloc {
@@ -158,6 +160,10 @@ void free_buf(WsBuf &b);
 // Grows b to at least bytes (waits for the device first: the old buffer may
 // be in use).
 int ensure(WsBuf &b, size_t bytes);
+// ensure() for a buffer of ws: a reallocation drops the graph captured on ws
+// (it holds the old address).
+int ws_ensure(hloc_ws *ws, WsBuf &b, size_t bytes);
+void drop_graph(hloc_ws *ws);
 int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32_t nreq,
               int32_t precision, Plan *pl);
 // Bytes ensure() allocates for a request of `bytes`.

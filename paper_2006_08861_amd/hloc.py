@@ -58,8 +58,8 @@ _SIGNATURES = {
     "hloc_query_windows_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _P, _I32, _I32,
                                                 _I32, _P, _P, _P, _P, _P, _P]),
     "hloc_set_region_labels": (ctypes.c_int, [_P, _P, _I32]),
-    "hloc_query_labels_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _P,
-                                               _P, _P, _P, _P]),
+    "hloc_query_labels_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _I32,
+                                               _P, _P, _P, _P, _P, _P]),
     "hloc_reserve": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32]),
     "hloc_query_info": (ctypes.c_int, [_P, _P, _I32]),
     "hloc_last_regions": (ctypes.c_int, [_P, _P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
@@ -274,6 +274,7 @@ class HlocDB:
     def set_region_labels(self, labels, n_labels: int):
         lab = np.ascontiguousarray(labels, dtype=np.int32)
         _check(load_library().hloc_set_region_labels(self._h, _np_ptr(lab), n_labels))
+        self.n_labels = int(n_labels)
 
     def query_labels(self, q, k: int, n_regions: int, n_labels: int, req_offsets=None,
                      precision="fp32", stream=None) -> dict:
@@ -298,7 +299,7 @@ class HlocDB:
         if stream is None:
             stream = torch.cuda.current_stream(dev)
         _check(load_library().hloc_query_labels_async(
-            self._h, _P(qd.data_ptr()), nq, k, n_regions,
+            self._h, _P(qd.data_ptr()), nq, k, n_regions, n_labels,
             None if offs is None else _P(offs.data_ptr()), nreq, PRECISIONS[precision],
             *(_P(out[key].data_ptr()) for key in ("idx", "dist", "xy", "tile", "flags")),
             _P(stream.cuda_stream)))

@@ -89,8 +89,8 @@ def test_calls_on_null_database():
     assert lib.hloc_query_windows_async(None, None, 0, 1, 1, None, None, 0, 0, 0, None, None,
                                         None, None, None, None) == hloc.EINVAL
     assert lib.hloc_set_region_labels(None, None, 1) == hloc.EINVAL
-    assert lib.hloc_query_labels_async(None, None, 0, 1, 1, None, 0, 0, None, None, None, None,
-                                       None, None) == hloc.EINVAL
+    assert lib.hloc_query_labels_async(None, None, 0, 1, 1, 1, None, 0, 0, None, None, None,
+                                       None, None, None) == hloc.EINVAL
     out = (ctypes.c_int64 * 6)()
     assert lib.hloc_query_info(None, out, 6) == hloc.EINVAL
     a, b = ctypes.c_int32(), ctypes.c_int32()

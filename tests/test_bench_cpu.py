@@ -26,8 +26,20 @@ def test_cpu_baseline_times_the_oracle():
     w = workload.make_workload(0, nq=6)
     ref = oracle.retrieve(w.feats, w.region_of, w.n_regions_total, w.q, w.k, w.n_reg)
     base, recall, exact, m = bench.cpu_baseline(w, np.asarray(ref["idx"]), 0.2)
-    assert base["kind"] == "oracle" and base["cores"] == 1 and base["value"] > 0
-    assert recall == 1.0 and exact == m and m >= 1
+    assert base["kind"] == "oracle" and base["value"] > 0 and base["single_core_value"] > 0
+    assert base["cores"] == bench.oracle_threads() and 1 <= base["cores"] <= 16
+    assert recall == 1.0 and exact == m and m == len(w.q)
+
+
+def test_cpu_baseline_samples_whole_requests():
+    # above the full-batch size the oracle is timed on the first whole
+    # requests holding at least the sample size
+    w = workload.make_workload(3, nq=40, n=20_000)
+    ref = oracle.retrieve(w.feats, w.region_of, w.n_regions_total, w.q, w.k, w.n_reg)
+    base, recall, exact, m = bench.cpu_baseline(w, np.asarray(ref["idx"]), 0.2,
+                                                sample_frames=20, full_rows=1000)
+    assert m == 24 and "first 3 requests" in base["sample"]
+    assert recall == 1.0 and exact == m
 
 
 def _csv(path, rows):
