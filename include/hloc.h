@@ -228,11 +228,13 @@ int hloc_reserve(hloc_db *db, int32_t nq_max, int32_t nreq_max, int32_t k_max,
  * items of the fine screen, out[1] frames whose coarse selection failed its
  * certificate (so the band of uncertain regions was re-scored in FP64),
  * out[2] frames whose top-k did (the band of uncertain rows), out[3] largest
- * candidate count of a frame, out[4] survivors per frame (k'), out[5] total
- * candidates screened, out[6] narrow work items (regions kept by at most 16
- * frames; out[0] - out[6] are wide items), out[7] frames whose band was too
- * large for one pass and was re-scored in chunks, out[8] rows re-scored in
- * bands over all frames. Writes min(n, 9) values.
+ * count of 16-row candidate blocks of a frame, out[4] survivor rows per
+ * frame (k'), out[5] total candidate rows screened, out[6] narrow work items
+ * (regions kept by at most 16 frames; out[0] - out[6] are wide items),
+ * out[7] frames whose band was too large for one pass and was re-scored in
+ * chunks, out[8] row slots re-scored in bands over all frames (16 per
+ * block), out[9] row slots re-scored in FP64 by the fine stage over all
+ * frames (survivor blocks and bands). Writes min(n, 10) values.
  * Errors: EINVAL, EDEVICE.
  */
 int hloc_query_info(hloc_db *db, int64_t *out, int32_t n);

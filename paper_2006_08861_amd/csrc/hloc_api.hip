@@ -117,7 +117,7 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
   // survivors re-scored in FP64: k + 16 behind the fp32 screen, 4k behind bf16
   p.kp = std::min(precision == HLOC_FP32 ? k + kOversample : std::max(4 * k, k + kOversample),
                   kMaxSurvivors);  // 4k behind the bf16 and fp8 screens
-  p.cap2 = db->h_desc_prefix[p.nr];
+  p.cap2 = p.exhaustive ? db->n_blocks : db->h_desc_blocks[p.nr];
   const int32_t crow = std::min(db->tile_rows, kWideRows);  // the shorter chunks bound the items
   const int64_t maxch = (db->max_region + crow - 1) / crow;
   const int64_t b1 = (int64_t)nq * p.nr * maxch;
@@ -157,6 +157,7 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *byte
   CHK(fit(ws->cand_off, (size_t)nq * nr * sizeof(int32_t)));
   CHK(fit(ws->slot_row, (size_t)nq * nr * sizeof(int32_t)));
   CHK(fit(ws->n_cand, (size_t)nq * sizeof(int32_t)));
+  CHK(fit(ws->n_rows, (size_t)nq * sizeof(int32_t)));
   CHK(fit(ws->misc, 16 * sizeof(int32_t)));
   CHK(fit(ws->rq, (size_t)nq * nr * sizeof(int2)));
   CHK(fit(ws->items, (size_t)std::max<int64_t>(p.items_bound, 1) * sizeof(Item)));
@@ -323,7 +324,8 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
                       as<int32_t>(ws->rcount), as<int32_t>(ws->rfill), as<int32_t>(ws->vord),
                       as<int32_t>(ws->rq_off),
                       as<int32_t>(ws->item_off), cand_off, as<int32_t>(ws->slot_row), n_cand,
-                      misc + 0, as<int2>(ws->rq), as<Item>(ws->items), s));
+                      as<int32_t>(ws->n_rows), misc + 0, as<int2>(ws->rq), as<Item>(ws->items),
+                      s));
   ph.begin(HLOC_PHASE_SCREEN);
   ScreenArgs sb{};
   sb.rows = db->rows;
@@ -353,14 +355,19 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   SelRerankArgs rb{};
   rb.cand = as<uint32_t>(ws->cand2);
   rb.cap = p.cap2;
-  // positions -> rows through the frame's region slots; in the exhaustive
-  // search the slots are every non-empty region in id order, so the position
-  // is the row itself
+  // the fine screen wrote one word per 16-row block: block positions -> rows
+  // through the frame's region slots; in the exhaustive search the slots are
+  // every non-empty region in id order, so the database's block table
+  // serves every frame
+  rb.blocks = 1;
   rb.nslots = p.exhaustive ? 0 : p.nr;
   rb.slot_off = cand_off;
   rb.slot_row = as<int32_t>(ws->slot_row);
+  rb.slot_reg = regions;
+  rb.reg_start = db->reg_start;
+  rb.blk_rows = db->blk_rows;
   rb.n_cand = n_cand;
-  rb.L = p.kp;
+  rb.L = (p.kp + kBlockRows - 1) / kBlockRows;  // survivor blocks: at least k' rows
   rb.m = p.k;
   rb.src32 = db->rows;
   rb.dp = db->dp;
@@ -386,6 +393,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   rb.stat_max = misc + 3;
   rb.stat_chunked = misc + 6;
   rb.stat_band = misc + 7;
+  rb.stat_rows = misc + 9;
   HIPCHK(launch_select_rerank(rb, s));
   ph.end();
   if (want_agg && p.nreq > 0) {
@@ -449,18 +457,24 @@ void drop_graph(hloc_ws *ws) {
   ws->graph = nullptr;
 }
 
-void free_ws(hloc_ws *ws) {
-  if (!ws) return;
-  drop_graph(ws);
+// Every buffer of a workspace.
+template <class F>
+void for_each_buf(hloc_ws *ws, F f) {
   WsBuf *bufs[] = {&ws->vord,     &ws->qp,       &ws->qn2,      &ws->cand1,    &ws->regions, &ws->rcount,
                    &ws->rfill,    &ws->rq_off,   &ws->item_off, &ws->cand_off, &ws->n_cand,
                    &ws->misc,     &ws->rq,       &ws->items,    &ws->cand2,   &ws->agg_xy,
                    &ws->agg_tile, &ws->agg_flags, &ws->s_q,     &ws->s_off,   &ws->s_idx,
                    &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags, &ws->q_lp,
-                   &ws->q_scale,  &ws->q_err,    &ws->q_lon,   &ws->slot_row,
+                   &ws->q_scale,  &ws->q_err,    &ws->q_lon,   &ws->slot_row, &ws->n_rows,
                    &ws->c_lp,     &ws->c_scale,  &ws->c_err,   &ws->c_lon,   &ws->agg_big,
                    &ws->lab_off,  &ws->lab_list, &ws->lab_q};
-  for (WsBuf *b : bufs) free_buf(*b);
+  for (WsBuf *b : bufs) f(*b);
+}
+
+void free_ws(hloc_ws *ws) {
+  if (!ws) return;
+  drop_graph(ws);
+  for_each_buf(ws, [](WsBuf &b) { free_buf(b); });
   for (hipEvent_t e : ws->ev_pool) (void)hipEventDestroy(e);
   if (ws->stream) (void)hipStreamDestroy(ws->stream);
   delete ws;
@@ -517,6 +531,7 @@ void free_db_data(hloc_db *db) {
   dev_free(db->rep64);
   dev_free(db->rep32);
   dev_free(db->rep_n2);
+  dev_free(db->blk_rows);
   if (db->stream) (void)hipStreamDestroy(db->stream);
   db->stream = nullptr;
 }
@@ -546,14 +561,15 @@ int info_of(hloc_ws *ws, int64_t *out, int32_t n) {
   int32_t misc[16] = {0};
   if (ws->misc.p) HIPCHK(hipMemcpy(misc, ws->misc.p, sizeof misc, hipMemcpyDeviceToHost));
   int64_t total = 0;
-  if (ws->last_nq > 0 && ws->n_cand.p) {
+  if (ws->last_nq > 0 && ws->n_rows.p) {
     std::vector<int32_t> nc(ws->last_nq);
-    HIPCHK(hipMemcpy(nc.data(), ws->n_cand.p, nc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(nc.data(), ws->n_rows.p, nc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     for (int32_t v : nc) total += v;
   }
-  const int64_t vals[9] = {misc[0], misc[1], misc[2],     misc[3], ws->last_kp,
-                           total,   misc[4], misc[6], (int64_t)(uint32_t)misc[7]};
-  for (int32_t i = 0; i < std::min(n, 9); ++i) out[i] = vals[i];
+  const int64_t vals[10] = {misc[0], misc[1], misc[2],     misc[3], ws->last_kp,
+                            total,   misc[4], misc[6], (int64_t)(uint32_t)misc[7],
+                            (int64_t)(uint32_t)misc[9]};
+  for (int32_t i = 0; i < std::min(n, 10); ++i) out[i] = vals[i];
   return HLOC_OK;
 }
 
@@ -671,6 +687,7 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   dev_free(db->rep64);
   dev_free(db->rep32);
   dev_free(db->rep_n2);
+  dev_free(db->blk_rows);
   for (LpMirror &m : db->lp) free_lp(m, true);
   db->has_regions = false;
   int rc;
@@ -695,10 +712,18 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   std::vector<int32_t> ids;
   for (int32_t r = 0; r < R; ++r)
     if (sizes[r] > 0) ids.push_back(r);
+  // 16-row blocks of every region in id order (the exhaustive search's
+  // candidate list)
+  std::vector<int2> blk;
+  blk.reserve((size_t)(n / kBlockRows + R));
+  for (int32_t r = 0; r < R; ++r)
+    for (int64_t b = start[r]; b < start[r + 1]; b += kBlockRows)
+      blk.push_back(make_int2((int)b, (int)std::min<int64_t>(kBlockRows, start[r + 1] - b)));
   if ((rc = dev_alloc(&db->reg_start, (size_t)R + 1)) || (rc = dev_alloc(&db->nonempty_ids, ids.size())) ||
       (rc = dev_alloc(&db->rep64, (size_t)R * db->dp)) || (rc = dev_alloc(&db->rep32, (size_t)R * db->dp)) ||
-      (rc = dev_alloc(&db->rep_n2, (size_t)R)))
+      (rc = dev_alloc(&db->rep_n2, (size_t)R)) || (rc = dev_alloc(&db->blk_rows, blk.size())))
     return rc;
+  HIPCHK(hipMemcpy(db->blk_rows, blk.data(), blk.size() * sizeof(int2), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(db->perm, new_perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(db->reg_start, start.data(), (size_t)(R + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(db->nonempty_ids, ids.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -754,7 +779,13 @@ int hloc_set_regions(hloc_db *db, const int32_t *region_of, int32_t n_regions_to
   std::vector<int64_t> desc(sizes);
   std::sort(desc.begin(), desc.end(), std::greater<int64_t>());
   db->h_desc_prefix.assign(R + 1, 0);
-  for (int32_t r = 0; r < R; ++r) db->h_desc_prefix[r + 1] = db->h_desc_prefix[r] + desc[r];
+  db->h_desc_blocks.assign(R + 1, 0);
+  for (int32_t r = 0; r < R; ++r) {
+    db->h_desc_prefix[r + 1] = db->h_desc_prefix[r] + desc[r];
+    // block counts order like the sizes
+    db->h_desc_blocks[r + 1] = db->h_desc_blocks[r] + (desc[r] + kBlockRows - 1) / kBlockRows;
+  }
+  db->n_blocks = (int64_t)blk.size();
   db->max_region = desc.empty() ? 0 : desc[0];
   db->chunks_fine = count_chunks(db, std::min(db->tile_rows, kWideRows));
   db->has_regions = true;

@@ -21,6 +21,18 @@ __device__ __forceinline__ void store_words4(uint32_t *p, uint32_t a, uint32_t b
   *reinterpret_cast<Words4 *>(p) = Words4{{a, b, c, d}};
 }
 
+// Smallest of one frame's 16 screen words of a 16-row block, as the MFMA
+// tile holds them: lane l has frame l % 16 and rows 4 (l / 16) .. + 3 in wd
+// (0xFFFFFFFF for rows past the end). The lanes of one frame exchange across
+// l ^ 16 and l ^ 32, so every lane of the wave must call this; each returns
+// its frame's minimum.
+__device__ __forceinline__ uint32_t block_min16(const uint32_t (&wd)[4]) {
+  uint32_t m = min(min(wd[0], wd[1]), min(wd[2], wd[3]));
+  m = min(m, (uint32_t)__shfl_xor((int)m, 16));
+  m = min(m, (uint32_t)__shfl_xor((int)m, 32));
+  return m;
+}
+
 // Ascending bitonic sort of n (power of two) keys in LDS by the whole block.
 __device__ inline void block_sort_u64(uint64_t *a, int n) {
   for (int size = 2; size <= n; size <<= 1) {

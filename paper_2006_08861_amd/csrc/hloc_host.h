@@ -87,7 +87,7 @@ struct hloc_ws {
   hloc_db *db = nullptr;
   hipStream_t stream = nullptr;  // own stream (graph capture, host-pointer calls)
   hloc::WsBuf qp, qn2, cand1, regions, rcount, rfill, vord, rq_off, item_off, cand_off, n_cand, misc, rq,
-      items, cand2, agg_xy, agg_tile, agg_flags, q_lp, q_scale, q_err, q_lon, slot_row,
+      items, cand2, agg_xy, agg_tile, agg_flags, q_lp, q_scale, q_err, q_lon, slot_row, n_rows,
       c_lp, c_scale, c_err, c_lon,  // bf16 frame copy for the coarse screen of fp8 queries
       agg_big,                      // requests for the large-list aggregation kernel
       lab_off, lab_list,            // frame lists of a query over subspace labels
@@ -129,6 +129,9 @@ struct hloc_db {
   int64_t *reg_start = nullptr;
   std::vector<int64_t> h_reg_start;
   std::vector<int64_t> h_desc_prefix;  // sum of the j largest region sizes, j = 0..R
+  std::vector<int64_t> h_desc_blocks;  // sum of the j largest regions' 16-row block counts
+  int64_t n_blocks = 0;                // 16-row blocks over all regions
+  int2 *blk_rows = nullptr;            // per block, regions in id order: (first row, rows)
   int64_t chunks_fine = 0;             // sum over regions of ceil(size / min(tile_rows, 64))
   int32_t tile_rows = hloc::kRowsFine; // rows per narrow fine work item (multiple of 16, <= 128)
   int32_t tile_blocks = 8;             // blocks per compute unit of the screen launches
@@ -152,7 +155,8 @@ namespace hloc {
 struct Plan {
   int32_t nq, k, nr, L1, kp, nreq, precision;
   bool exhaustive;
-  int64_t cap2, items_bound;
+  int64_t cap2;  // 16-row blocks of a frame's candidate rows at most
+  int64_t items_bound;
   int32_t grid1, grid2;
 };
 

@@ -47,6 +47,11 @@ constexpr int kBlock = 256;         // threads per block of most kernels
 constexpr int kSelectLds = 4096;    // keys held in LDS by the select kernel
 constexpr uint64_t kKeyNone = ~0ull;  // empty slot / no candidate
 constexpr int kMaxSurvivors = 1024;   // want - 1 of the rerank
+// Rows per block of the fine screen's output: for each frame and each 16-row
+// block of its candidate rows (one MFMA tile height; a region's blocks start
+// at its first row, its last block may be shorter) the fine screen writes the
+// smallest screen word of the block.
+constexpr int kBlockRows = 16;
 
 inline int next_pow2_host(int v) {
   int p = 1;
@@ -65,7 +70,11 @@ struct Item {
 };
 
 // Dense or listed screen of rows against padded frames (fp32, or bf16 / fp8
-// copies).
+// copies). Dense mode (the coarse stage) writes every screen word: frame f's
+// word of row j at cand[f * cap + j]. List mode (the fine stage) writes, per
+// frame, the smallest word of each 16-row block of the frame's candidate
+// rows: the b-th block of a region whose blocks start at e.y in frame f's
+// list goes to cand[f * cap + e.y + b].
 struct ScreenArgs {
   const float *rows;      // nrows x dp, row-major
   const void *rows_lp;    // low-precision copy of rows (bf16 / fp8 screens)
@@ -76,8 +85,8 @@ struct ScreenArgs {
   int32_t dp;             // padded row length (multiple of 32)
   const float *qp;        // frames x dp
   const float *qn2;       // frames squared norms
-  uint32_t *cand;         // per frame: cap screen words (float bits of the screen distance)
-  int64_t cap;
+  uint32_t *cand;         // per frame: cap words (float bits of the screen distance)
+  int64_t cap;            // dense: rows; list: 16-row blocks per frame at most
   int32_t rows_per_item;  // T, multiple of 16
   // dense mode: every frame against rows [0, nrows)
   int32_t dense;
@@ -132,8 +141,9 @@ __device__ __forceinline__ WideItem wide_item(const ScreenArgs &a, int it) {
   return w;
 }
 
-// Frame j of a wide item (j < gq) and where its screen words go; e is the
-// frame's rq entry (list items, from wide_entry).
+// Frame j of a wide item (j < gq) and where its output goes: dense items,
+// the word of the chunk's first row; list items, the block word of the
+// chunk's first 16-row block (e is the frame's rq entry, from wide_entry).
 __device__ __forceinline__ void wide_frame(const ScreenArgs &a, const WideItem &w, int j, int2 e,
                                            int *fr, int64_t *off) {
   if (a.dense) {
@@ -141,7 +151,7 @@ __device__ __forceinline__ void wide_frame(const ScreenArgs &a, const WideItem &
     *off = (int64_t)(*fr) * a.cap + w.chunk_row;
   } else {
     *fr = e.x;
-    *off = (int64_t)e.x * a.cap + e.y + w.chunk_row;
+    *off = (int64_t)e.x * a.cap + e.y + w.chunk_row / kBlockRows;
   }
 }
 
@@ -182,21 +192,33 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_broadcast_ids(const int32_t *ids, int32_t nr, int32_t nq, int32_t *regions,
                                 hipStream_t s);
 // Work items into items[0 .. n_items[0]): narrow ones (frames of regions kept
-// by at most kGroup frames) first, n_items[4] of them, then wide ones.
+// by at most kGroup frames) first, n_items[4] of them, then wide ones. Per
+// frame f and kept-region slot j: cand_off[f][j] the first of the slot's
+// 16-row blocks in the frame's block list, slot_row[f][j] the region's first
+// row; n_cand[f] the frame's block count, n_rows[f] its candidate rows. An rq
+// entry is (frame, cand_off of the region in that frame).
 hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t R,
                         const int64_t *reg_start, int32_t T, int32_t *rcount, int32_t *rfill,
                         int32_t *vord, int32_t *rq_off, int32_t *item_off, int32_t *cand_off,
-                        int32_t *slot_row, int32_t *n_cand, int32_t *n_items, int2 *rq,
-                        Item *items, hipStream_t s);
+                        int32_t *slot_row, int32_t *n_cand, int32_t *n_rows, int32_t *n_items,
+                        int2 *rq, Item *items, hipStream_t s);
 
-// Per frame: the L + 1 smallest screen words of cand[f][0 .. n(f)) (n(f) =
+// Per frame: the L + 1 smallest words of cand[f][0 .. n(f)) (n(f) =
 // n_cand ? n_cand[f] : n_fixed; 0xFFFFFFFF entries are skipped; equal words
-// ordered by position), FP64 rerank of the L smallest, top m by (distance,
-// tie id), certificate against the (L + 1)-th, and the FP64 re-score of the
-// band of uncertain candidates when it fails. Candidate positions map to source rows through
-// the frame's region slots (slot j: the rows from slot_row[f][j] on, at
-// positions from slot_off[f][j] on), or are the rows themselves when nslots
-// is 0.
+// ordered by position), FP64 rerank of the rows of the L smallest, top m by
+// (distance, tie id), certificate against the (L + 1)-th, and the FP64
+// re-score of the band of uncertain positions when it fails.
+// A position is one candidate row (the coarse stage: words of
+// representatives), or with `blocks` a 16-row block of the frame's candidate
+// rows whose word is the smallest screen word of its rows (the fine stage):
+// every row of a block is re-scored, and a block's word minus the screen's
+// error bound is a lower bound of the distance of each of its rows, so the
+// certificate holds per block as it does per row.
+// Positions map to source rows through the frame's region slots (slot j: the
+// rows from slot_row[f][j] on, at positions from slot_off[f][j] on; in block
+// mode the slot's region slot_reg[f][j] gives its row count), or, with
+// nslots = 0, are the rows themselves (block mode: blocks of blk_rows, every
+// non-empty region in id order).
 struct SelRerankArgs {
   const uint32_t *cand;
   int64_t cap;
@@ -206,7 +228,11 @@ struct SelRerankArgs {
   int32_t cache;             // words kept in LDS (set by the launcher)
   const int32_t *n_cand;
   int32_t n_fixed;
-  int32_t L;               // survivors re-scored in FP64 (<= kMaxSurvivors)
+  int32_t blocks;            // positions are 16-row blocks
+  const int32_t *slot_reg;   // block mode: nq x nslots region ids
+  const int64_t *reg_start;  // block mode: first row of each region (R + 1)
+  const int2 *blk_rows;      // block mode, nslots = 0: (first row, rows) of each block
+  int32_t L;               // positions re-scored in FP64 (rows: <= kMaxSurvivors)
   int32_t m;               // results per frame (<= 256, <= L)
   const float *src32;      // fp32 source rows (fine stage) or NULL
   const double *src64;     // fp64 source rows (coarse stage) or NULL
@@ -230,6 +256,7 @@ struct SelRerankArgs {
   int32_t *stat_chunked;   // frames whose band was re-scored in several chunks (or NULL)
   int32_t *stat_band;      // sum of the band sizes (or NULL)
   int32_t *stat_max;       // largest candidate count (or NULL)
+  int32_t *stat_rows;      // rows re-scored in FP64, survivors and bands (or NULL)
 };
 hipError_t launch_select_rerank(SelRerankArgs a, hipStream_t s);
 

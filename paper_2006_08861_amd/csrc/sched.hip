@@ -168,19 +168,20 @@ hipError_t launch_broadcast_ids(const int32_t *ids, int32_t nr, int32_t nq, int3
 }
 
 // Multi-kernel schedule for large region counts. Per frame: offset of each
-// kept region in the frame's candidate list and its first row, and the list
-// length. Per region: how many frames kept it.
-// One wave per frame: 64 of its regions at a time, their candidate-list
-// offsets by an inclusive scan of the sizes across the wave (a frame of the
-// exhaustive search keeps every region, so its list is long); the next 64
-// region ids are loaded while the current ones are placed.
+// kept region in the frame's list of 16-row blocks (the fine screen writes
+// one word per block) and its first row, the number of blocks and of rows.
+// Per region: how many frames kept it.
+// One wave per frame: 64 of its regions at a time, their block offsets by an
+// inclusive scan across the wave (a frame of the exhaustive search keeps
+// every region, so its list is long); the next 64 region ids are loaded while
+// the current ones are placed.
 __device__ __forceinline__ void count_frame(const int32_t *__restrict__ regions, int f, int nr,
                                             int R, const int64_t *__restrict__ reg_start,
                                             int32_t *cnt, int32_t *cand_off, int32_t *slot_row,
-                                            int32_t *n_cand) {
+                                            int32_t *n_cand, int32_t *n_rows) {
   const int lane = threadIdx.x & 63;
   const int32_t *ids = regions + (int64_t)f * nr;
-  int base = 0;
+  int base = 0, rows = 0;
   int nxt = lane < nr ? ids[lane] : -1;
   for (int j0 = 0; j0 < nr; j0 += 64) {
     const int j = j0 + lane;
@@ -189,20 +190,26 @@ __device__ __forceinline__ void count_frame(const int32_t *__restrict__ regions,
     nxt = j + 64 < nr ? ids[j + 64] : -1;
     const int r0 = r >= 0 ? (int)reg_start[r] : 0;
     const int sz = r >= 0 ? (int)(reg_start[r + 1] - r0) : 0;
-    int inc = sz;
+    const int nb = (sz + kBlockRows - 1) / kBlockRows;
+    int inc = nb;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int y = __shfl_up(inc, o);
       if (lane >= o) inc += y;
     }
     if (j < nr) {
-      cand_off[(int64_t)f * nr + j] = base + inc - sz;
+      cand_off[(int64_t)f * nr + j] = base + inc - nb;
       slot_row[(int64_t)f * nr + j] = r0;
     }
     if (r >= 0) atomicAdd(&cnt[r], 1);
     base += __shfl(inc, 63);
+    rows += sz;
   }
-  if (lane == 0) n_cand[f] = base;
+  for (int o = 32; o > 0; o >>= 1) rows += __shfl_xor(rows, o);
+  if (lane == 0) {
+    n_cand[f] = base;
+    n_rows[f] = rows;
+  }
 }
 
 // With LDS (R <= kHistR) the block counts in LDS and adds each nonzero count
@@ -212,7 +219,8 @@ __device__ __forceinline__ void count_frame(const int32_t *__restrict__ regions,
 template <bool LDS>
 __global__ void k_sched_count(const int32_t *__restrict__ regions, int nq, int nr, int R,
                               const int64_t *__restrict__ reg_start, int32_t *rcount,
-                              int32_t *cand_off, int32_t *slot_row, int32_t *n_cand) {
+                              int32_t *cand_off, int32_t *slot_row, int32_t *n_cand,
+                              int32_t *n_rows) {
   extern __shared__ int32_t s_cnt[];  // R (LDS mode)
   if (LDS) {
     for (int i = threadIdx.x; i < R; i += blockDim.x) s_cnt[i] = 0;
@@ -220,7 +228,7 @@ __global__ void k_sched_count(const int32_t *__restrict__ regions, int nq, int n
   }
   int32_t *cnt = LDS ? s_cnt : rcount;
   const int f = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);  // one wave per frame
-  if (f < nq) count_frame(regions, f, nr, R, reg_start, cnt, cand_off, slot_row, n_cand);
+  if (f < nq) count_frame(regions, f, nr, R, reg_start, cnt, cand_off, slot_row, n_cand, n_rows);
   if (LDS) {
     __syncthreads();
     for (int i = threadIdx.x; i < R; i += blockDim.x)
@@ -302,7 +310,8 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
                                                       const int64_t *__restrict__ reg_start, int T,
                                                       int32_t *rq_off, int32_t *cand_off,
                                                       int32_t *slot_row, int32_t *n_cand,
-                                                      int32_t *n_items, int2 *rq, Item *items) {
+                                                      int32_t *n_rows, int32_t *n_items, int2 *rq,
+                                                      Item *items) {
   extern __shared__ int s_mem[];
   int *s_fill = s_mem;         // R: frame counts, then fill pointers, then ends
   int *s_vord = s_mem + R;     // R: regions in narrow-then-wide order
@@ -324,9 +333,11 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
   for (int i = tid; i <= R; i += nt) s_rs[i] = (int)reg_start[i];
   for (int i = tid; i < R; i += nt) s_fill[i] = 0;
   __syncthreads();
+  // per frame: block offset of each kept region (16-row blocks), first row,
+  // and the frame's block and row counts
   if (regs) {
     if (tid < nq) {
-      int off = 0;
+      int off = 0, rows = 0;
 #pragma unroll
       for (int u = 0; u < kFusedRegs; ++u) {
         if (u >= nr) break;
@@ -335,15 +346,18 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
         cand_off[(int64_t)tid * nr + u] = off;
         slot_row[(int64_t)tid * nr + u] = r0;
         if (r[u] >= 0) {
-          off += s_rs[r[u] + 1] - r0;
+          const int sz = s_rs[r[u] + 1] - r0;
+          off += (sz + kBlockRows - 1) / kBlockRows;
+          rows += sz;
           atomicAdd(&s_fill[r[u]], 1);
         }
       }
       n_cand[tid] = off;
+      n_rows[tid] = rows;
     }
   } else {
     for (int f = tid; f < nq; f += nt) {
-      int off = 0;
+      int off = 0, rows = 0;
       for (int j = 0; j < nr; ++j) {
         int rj = regions[(int64_t)f * nr + j];
         if (rj >= R) rj = -1;
@@ -351,11 +365,14 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
         cand_off[(int64_t)f * nr + j] = off;
         slot_row[(int64_t)f * nr + j] = r0;
         if (rj >= 0) {
-          off += s_rs[rj + 1] - r0;
+          const int sz = s_rs[rj + 1] - r0;
+          off += (sz + kBlockRows - 1) / kBlockRows;
+          rows += sz;
           atomicAdd(&s_fill[rj], 1);
         }
       }
       n_cand[f] = off;
+      n_rows[f] = rows;
     }
   }
   __syncthreads();
@@ -403,13 +420,13 @@ hipError_t prepare_sched_kernels() {
 hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t R,
                         const int64_t *reg_start, int32_t T, int32_t *rcount, int32_t *rfill,
                         int32_t *vord, int32_t *rq_off, int32_t *item_off, int32_t *cand_off,
-                        int32_t *slot_row, int32_t *n_cand, int32_t *n_items, int2 *rq,
-                        Item *items, hipStream_t s) {
+                        int32_t *slot_row, int32_t *n_cand, int32_t *n_rows, int32_t *n_items,
+                        int2 *rq, Item *items, hipStream_t s) {
   const int64_t pairs = (int64_t)nq * nr;
   if (R <= kFusedMaxR && pairs <= kFusedMaxPairs) {
     return launch_kernel(k_sched_fused, dim3(1), dim3(1024), (uint32_t)fused_lds_bytes(R), s,
                          regions, nq, nr, R, reg_start, T, rq_off, cand_off, slot_row, n_cand,
-                         n_items, rq, items);
+                         n_rows, n_items, rq, items);
   }
   hipError_t e = launch_fill_i32(rcount, R, 0, s);
   if (e != hipSuccess) return e;
@@ -418,9 +435,10 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
     // one wave per frame, 16 frames per block
     e = hist ? launch_kernel(k_sched_count<true>, dim3((nq + 15) / 16), dim3(1024),
                              (uint32_t)(R * sizeof(int32_t)), s, regions, nq, nr, R, reg_start,
-                             rcount, cand_off, slot_row, n_cand)
+                             rcount, cand_off, slot_row, n_cand, n_rows)
              : launch_kernel(k_sched_count<false>, dim3((nq + 15) / 16), dim3(1024), 0, s,
-                             regions, nq, nr, R, reg_start, rcount, cand_off, slot_row, n_cand);
+                             regions, nq, nr, R, reg_start, rcount, cand_off, slot_row, n_cand,
+                             n_rows);
     if (e != hipSuccess) return e;
   }
   if ((e = launch_kernel(k_sched_scan, dim3(1), dim3(1024), 0, s, rcount, R, reg_start, T,

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_screen_f32(ScreenArgs a) {
             base = (int64_t)e.x * a.cap + e.y;
           }
           s_q[tid] = f;
-          s_off[tid] = base + chunk_row;
+          s_off[tid] = base + (DENSE ? chunk_row : chunk_row / kBlockRows);
           s_qn[tid] = a.qn2[f];
         } else {
           s_q[tid] = 0;
@@ -131,24 +131,32 @@ __global__ __launch_bounds__(256) void k_screen_f32(ScreenArgs a) {
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc, 0, 0, 0);
         }
         // lane l holds dot(row 4*(l/16)+r of the block, frame l%16)
-        if (i < gs) {
-          const float qn = s_qn[i];
-          const int64_t off = s_off[i];
+        const float qn = s_qn[i];
+        const int64_t off = s_off[i];
+        uint32_t wd[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = rb * 16 + 4 * g + r;
-            if (row < nrows) {
-              const int64_t grow = row_begin + row;
-              const float rn = a.row_n2[grow];
-              uint32_t word = 0xFFFFFFFFu;
-              if (!__builtin_isinf(rn)) {
-                float dd = (qn + rn) - 2.f * acc[r];
-                dd = dd > 0.f ? dd : 0.f;
-                word = __float_as_uint(dd);
-              }
-              a.cand[off + row] = word;
+        for (int r = 0; r < 4; ++r) {
+          const int row = rb * 16 + 4 * g + r;
+          uint32_t word = 0xFFFFFFFFu;
+          if (row < nrows) {
+            const float rn = a.row_n2[row_begin + row];
+            if (!__builtin_isinf(rn)) {
+              float dd = (qn + rn) - 2.f * acc[r];
+              dd = dd > 0.f ? dd : 0.f;
+              word = __float_as_uint(dd);
             }
           }
+          wd[r] = word;
+        }
+        if (DENSE) {
+          if (i < gs) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (rb * 16 + 4 * g + r < nrows) a.cand[off + rb * 16 + 4 * g + r] = wd[r];
+          }
+        } else {
+          const uint32_t m = block_min16(wd);
+          if (i < gs && g == 0) a.cand[off + rb] = m;
         }
       }
       __syncthreads();
@@ -203,7 +211,7 @@ __global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
       gq = ng & 0xFFFF;
       if (i < gq) {
         fr = ne.x;
-        off = (int64_t)ne.x * a.cap + ne.y + chunk_row;
+        off = (int64_t)ne.x * a.cap + ne.y + chunk_row / kBlockRows;
       }
       if (itn < hi) nx = a.items[itn];
     }
@@ -237,28 +245,33 @@ __global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].z, bv[s].z, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s].w, bv[s].w, acc, 0, 0, 0);
       }
-      if (i < gq) {
-        // the lane's four rows are consecutive words of its frame's list
-        const int row0 = rb * 16 + 4 * g;
-        uint32_t wd[4];
+      // the lane's four rows are consecutive rows of its frame's list
+      const int row0 = rb * 16 + 4 * g;
+      uint32_t wd[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float rn = a.row_n2[row_begin + min(row0 + r, nrows - 1)];
-          uint32_t word = 0xFFFFFFFFu;
-          if (!__builtin_isinf(rn)) {
-            float dd = (qn + rn) - 2.f * acc[r];
-            dd = dd > 0.f ? dd : 0.f;
-            word = __float_as_uint(dd);
+      for (int r = 0; r < 4; ++r) {
+        const float rn = a.row_n2[row_begin + min(row0 + r, nrows - 1)];
+        uint32_t word = 0xFFFFFFFFu;
+        if (row0 + r < nrows && !__builtin_isinf(rn)) {
+          float dd = (qn + rn) - 2.f * acc[r];
+          dd = dd > 0.f ? dd : 0.f;
+          word = __float_as_uint(dd);
+        }
+        wd[r] = word;
+      }
+      if (DENSE) {
+        if (i < gq) {
+          if (row0 + 3 < nrows) {
+            store_words4(a.cand + off + row0, wd[0], wd[1], wd[2], wd[3]);
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (row0 + r < nrows) a.cand[off + row0 + r] = wd[r];
           }
-          wd[r] = word;
         }
-        if (row0 + 3 < nrows) {
-          store_words4(a.cand + off + row0, wd[0], wd[1], wd[2], wd[3]);
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (row0 + r < nrows) a.cand[off + row0 + r] = wd[r];
-        }
+      } else {
+        const uint32_t m = block_min16(wd);
+        if (i < gq && g == 0) a.cand[off + rb] = m;
       }
       if (!DENSE && rb == w && itn < hi) {
         ne = make_int2(0, 0);
@@ -353,7 +366,11 @@ __global__ __launch_bounds__(256) void k_screen_wide(ScreenArgs a) {
       for (int s = 0; s < NS; ++s) bv[s] = qp[4 * s];
       const float qn = a.qn2[fr];
       ce = wide_entry(a, wi, (grp + nw) * kGroup + i);  // the wave's next group
-      for (int rb = 0; rb * 16 < nrows; ++rb) {
+      uint32_t bm[4];  // list items: the frame's block words of the chunk
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        bm[rb] = 0xFFFFFFFFu;
+        if (rb * 16 >= nrows) continue;
         const float4 *rp = s_rows + (rb * 16 + i) * LDR + g;
         v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -364,28 +381,42 @@ __global__ __launch_bounds__(256) void k_screen_wide(ScreenArgs a) {
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv[s].z, acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv[s].w, acc, 0, 0, 0);
         }
-        if (i < gs) {
-          // the lane's four rows are consecutive words of its frame's list
-          const int row0 = rb * 16 + 4 * g;
-          uint32_t wd[4];
+        // the lane's four rows are consecutive rows of its frame's list
+        const int row0 = rb * 16 + 4 * g;
+        uint32_t wd[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const float rn = s_rn[min(row0 + r, 63)];
-            uint32_t word = 0xFFFFFFFFu;
-            if (!__builtin_isinf(rn)) {
-              float dd = (qn + rn) - 2.f * acc[r];
-              dd = dd > 0.f ? dd : 0.f;
-              word = __float_as_uint(dd);
+        for (int r = 0; r < 4; ++r) {
+          const float rn = s_rn[min(row0 + r, 63)];
+          uint32_t word = 0xFFFFFFFFu;
+          if (row0 + r < nrows && !__builtin_isinf(rn)) {
+            float dd = (qn + rn) - 2.f * acc[r];
+            dd = dd > 0.f ? dd : 0.f;
+            word = __float_as_uint(dd);
+          }
+          wd[r] = word;
+        }
+        if (a.dense) {
+          if (i < gs) {
+            if (row0 + 3 < nrows) {
+              store_words4(a.cand + off + row0, wd[0], wd[1], wd[2], wd[3]);
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                if (row0 + r < nrows) a.cand[off + row0 + r] = wd[r];
             }
-            wd[r] = word;
           }
-          if (row0 + 3 < nrows) {
-            store_words4(a.cand + off + row0, wd[0], wd[1], wd[2], wd[3]);
-          } else {
+        } else {
+          bm[rb] = block_min16(wd);
+        }
+      }
+      if (!a.dense && i < gs && g == 0) {
+        const int nrb = (nrows + 15) >> 4;
+        if (nrb == 4) {
+          store_words4(a.cand + off, bm[0], bm[1], bm[2], bm[3]);
+        } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (row0 + r < nrows) a.cand[off + row0 + r] = wd[r];
-          }
+          for (int rb = 0; rb < 4; ++rb)
+            if (rb < nrb) a.cand[off + rb] = bm[rb];
         }
       }
     }

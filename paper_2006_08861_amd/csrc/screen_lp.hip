@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void k_screen_lp(ScreenArgs a) {
       gq = nx.nrows_gq & 0xFFFF;
       if (i < gq) {
         fr = ne.x;
-        off = (int64_t)ne.x * a.cap + ne.y + chunk_row;
+        off = (int64_t)ne.x * a.cap + ne.y + chunk_row / kBlockRows;
       }
       if (itn < hi) nx = a.items[itn];
     }
@@ -278,23 +278,28 @@ __global__ __launch_bounds__(256) void k_screen_lp(ScreenArgs a) {
       v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < NS; ++s) acc = lp_mfma<FMT>(av[s], bv[s], acc);
-      if (i < gq) {
-        // the lane's four rows are consecutive words of its frame's list
-        const int row0 = rb * 16 + 4 * g;
-        uint32_t wd[4];
+      // the lane's four rows are consecutive rows of its frame's list
+      const int row0 = rb * 16 + 4 * g;
+      uint32_t wd[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int grow = row_begin + min(row0 + r, nrows - 1);
-          const float rs = FMT == HLOC_FP8 ? a.row_scale[grow] : 1.f;
-          wd[r] = lp_word<FMT>(qn, a.row_n2[grow], acc[r], qs, rs);
-        }
-        if (row0 + 3 < nrows) {
-          store_words4(a.cand + off + row0, wd[0], wd[1], wd[2], wd[3]);
-        } else {
+      for (int r = 0; r < 4; ++r) {
+        const int grow = row_begin + min(row0 + r, nrows - 1);
+        const float rs = FMT == HLOC_FP8 ? a.row_scale[grow] : 1.f;
+        wd[r] = row0 + r < nrows ? lp_word<FMT>(qn, a.row_n2[grow], acc[r], qs, rs) : 0xFFFFFFFFu;
+      }
+      if (DENSE) {
+        if (i < gq) {
+          if (row0 + 3 < nrows) {
+            store_words4(a.cand + off + row0, wd[0], wd[1], wd[2], wd[3]);
+          } else {
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (row0 + r < nrows) a.cand[off + row0 + r] = wd[r];
+            for (int r = 0; r < 4; ++r)
+              if (row0 + r < nrows) a.cand[off + row0 + r] = wd[r];
+          }
         }
+      } else {
+        const uint32_t m = block_min16(wd);
+        if (i < gq && g == 0) a.cand[off + rb] = m;
       }
       if (!DENSE && rb == w && itn < hi) {
         ne = make_int2(0, 0);
@@ -374,27 +379,46 @@ __global__ __launch_bounds__(256) void k_screen_wide_lp(ScreenArgs a) {
       const float qn = a.qn2[fr];
       const float qs = FMT == HLOC_FP8 ? a.q_scale[fr] : 1.f;
       ce = wide_entry(a, wi, (grp + nw) * kGroup + i);  // the wave's next group
-      for (int rb = 0; rb * 16 < nrows; ++rb) {
+      uint32_t bm[4];  // list items: the frame's block words of the chunk
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        bm[rb] = 0xFFFFFFFFu;
+        if (rb * 16 >= nrows) continue;
         const uint4 *rp = s_rows + (rb * 16 + i) * LDR + g;
         v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < NS; ++s) acc = lp_mfma<FMT>(rp[4 * s], bv[s], acc);
-        if (i < gs) {
-          // the lane's four rows are consecutive words of its frame's list
-          const int row0 = rb * 16 + 4 * g;
-          uint32_t wd[4];
+        // the lane's four rows are consecutive rows of its frame's list
+        const int row0 = rb * 16 + 4 * g;
+        uint32_t wd[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = min(row0 + r, 63);
-            wd[r] = lp_word<FMT>(qn, s_rn[row], acc[r], qs, s_rs[row]);
-          }
-          if (row0 + 3 < nrows) {
-            store_words4(a.cand + off + row0, wd[0], wd[1], wd[2], wd[3]);
-          } else {
+        for (int r = 0; r < 4; ++r) {
+          const int row = min(row0 + r, 63);
+          wd[r] = row0 + r < nrows ? lp_word<FMT>(qn, s_rn[row], acc[r], qs, s_rs[row])
+                                   : 0xFFFFFFFFu;
+        }
+        if (a.dense) {
+          if (i < gs) {
+            if (row0 + 3 < nrows) {
+              store_words4(a.cand + off + row0, wd[0], wd[1], wd[2], wd[3]);
+            } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (row0 + r < nrows) a.cand[off + row0 + r] = wd[r];
+              for (int r = 0; r < 4; ++r)
+                if (row0 + r < nrows) a.cand[off + row0 + r] = wd[r];
+            }
           }
+        } else {
+          bm[rb] = block_min16(wd);
+        }
+      }
+      if (!a.dense && i < gs && g == 0) {
+        const int nrb = (nrows + 15) >> 4;
+        if (nrb == 4) {
+          store_words4(a.cand + off, bm[0], bm[1], bm[2], bm[3]);
+        } else {
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+            if (rb < nrb) a.cand[off + rb] = bm[rb];
         }
       }
     }

@@ -10,9 +10,11 @@
 //      radix select over kDigitBits per pass finds the (L+1)-th word and the
 //      survivors are gathered in position order;
 //   2. rerank: the positions of the L smallest (the survivors) are mapped to
-//      source rows through the frame's region slots, then FP64 direct sum of
-//      (q_i - d_i)^2, ordered by (distance, tie id) with tie id = original row
-//      index (fine stage) or region id (coarse stage);
+//      source rows through the frame's region slots (a position is a row, or
+//      in the fine stage a 16-row block whose word is the smallest of its
+//      rows' screen words, and then each of its rows), then FP64 direct sum
+//      of (q_i - d_i)^2, ordered by (distance, tie id) with tie id = original
+//      row index (fine stage) or region id (coarse stage);
 //   3. certificate: the (L+1)-th word is the best rejected screen distance; if
 //      it minus the screen's error bound does not exceed the m-th reranked
 //      distance, the block also re-scores every rejected candidate within that
@@ -28,6 +30,7 @@ constexpr int kWordCache = 28672;  // screen words of a frame kept in (dynamic) 
 constexpr int kBigFrame = 4096;    // candidate capacity above which a frame gets 1024 threads
 constexpr int kMaxSlots = 1024;    // region slots of a frame kept in (dynamic) LDS
 constexpr uint32_t kWordNone = 0xFFFFFFFFu;  // no candidate at this position
+constexpr uint32_t kNoRow = 0xFFFFFFFFu;     // a block's row slot past its last row
 constexpr int kDigitBits = 12;     // radix digit of the select (two passes cover 24 bits)
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
@@ -201,7 +204,8 @@ __device__ __forceinline__ double wave_sum8_f64(double (&acc)[kRowBatch]) {
 }
 
 // FP64 distances of the frame to source rows sh.srow[s0 .. s1) into
-// sort_hi / sort_lo[s] (distance bits, tie id). Each wave fetches kRowBatch
+// sort_hi / sort_lo[s] (distance bits, tie id); a kNoRow slot gets the key
+// (kKeyNone, 0x80000000 | s), distinct and after every row. Each wave fetches kRowBatch
 // rows at once with the frame slice reused across them; a lane sums its
 // slice of each row in order (4 consecutive values per 256), then
 // wave_sum8_f64 adds the lanes. LEAN (1024-thread blocks, at most 128
@@ -218,7 +222,8 @@ __device__ void rerank_range(const SelRerankArgs &a, SelShared &sh, const float 
 #pragma unroll
     for (int r = 0; r < kRowBatch; ++r) {
       acc[r] = 0.0;
-      row[r] = sh.srow[min(b + r, s1 - 1)];
+      const uint32_t v = sh.srow[min(b + r, s1 - 1)];
+      row[r] = v == kNoRow ? 0u : v;
     }
     for (int c = 0; c <= nch; ++c) {
       const int col = c * 256 + lane * 4;
@@ -276,8 +281,13 @@ __device__ void rerank_range(const SelRerankArgs &a, SelShared &sh, const float 
     const int r = lane >> 3, sidx = b + r;
     if ((lane & 7) == 0 && sidx < s1) {
       const uint32_t rw = sh.srow[sidx];
-      sh.sort_hi[sidx] = (uint64_t)__double_as_longlong(d);
-      sh.sort_lo[sidx] = a.tie_of ? (uint32_t)a.tie_of[rw] : rw;
+      if (rw == kNoRow) {
+        sh.sort_hi[sidx] = kKeyNone;
+        sh.sort_lo[sidx] = 0x80000000u | (uint32_t)sidx;
+      } else {
+        sh.sort_hi[sidx] = (uint64_t)__double_as_longlong(d);
+        sh.sort_lo[sidx] = a.tie_of ? (uint32_t)a.tie_of[rw] : rw;
+      }
     }
   }
 }
@@ -386,6 +396,49 @@ __device__ __forceinline__ uint32_t row_of(const int32_t *s_off, const int32_t *
   return (uint32_t)(s_row[lo] + ((int32_t)p - s_off[lo]));
 }
 
+// Source row of row slot t (< kBlockRows) of block position p, or kNoRow
+// past the block's last row: with region slots, slot j holds its region's
+// blocks at positions s_off[j] .. (rows from s_row[j] on, s_len[j] of them);
+// without, the block table of the exhaustive search.
+__device__ __forceinline__ uint32_t block_row(const SelRerankArgs &a, const int32_t *s_off,
+                                              const int32_t *s_row, const int32_t *s_len,
+                                              int nslots, uint32_t p, int t) {
+  int row0, len;
+  if (nslots == 0) {
+    const int2 br = a.blk_rows[p];
+    row0 = br.x;
+    len = br.y;
+  } else {
+    int lo = 0, hi = nslots;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_off[mid] <= (int32_t)p) lo = mid;
+      else hi = mid;
+    }
+    const int b = (int32_t)p - s_off[lo];
+    row0 = s_row[lo] + b * kBlockRows;
+    len = min(kBlockRows, s_len[lo] - b * kBlockRows);
+  }
+  return t < len ? (uint32_t)(row0 + t) : kNoRow;
+}
+
+// Source rows of positions sel[0 .. cnt) into srow[base ..): one per
+// position, or kBlockRows per block position (kNoRow past a block's end).
+__device__ __forceinline__ void positions_to_rows(const SelRerankArgs &a, SelShared &sh,
+                                                  const int32_t *s_off, const int32_t *s_row,
+                                                  const int32_t *s_len, int nslots, int cnt,
+                                                  int base) {
+  if (a.blocks) {
+    for (int e = threadIdx.x; e < cnt * kBlockRows; e += blockDim.x) {
+      const int i = e / kBlockRows, t = e - i * kBlockRows;
+      sh.srow[base + e] = block_row(a, s_off, s_row, s_len, nslots, sh.sel[i], t);
+    }
+  } else {
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+      sh.srow[base + i] = row_of(s_off, s_row, nslots, sh.sel[i]);
+  }
+}
+
 // Frame of block b in XCD-major order. Blocks go to the 8 XCDs round-robin
 // (b % 8), so XCD x takes the contiguous run of frames starting at
 // x * (n / 8) + min(x, n % 8): the frames of a request, which share most of
@@ -399,15 +452,17 @@ __device__ __forceinline__ int xcd_frame(int b, int n) {
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
   __shared__ SelShared sh;
-  extern __shared__ uint32_t dyn[];  // [slot offsets | slot regions | word cache]
+  extern __shared__ uint32_t dyn[];  // [slot offsets | slot rows | slot sizes | word cache]
   if ((int)blockIdx.x >= a.nq) return;
   const int f = xcd_frame(blockIdx.x, a.nq);
   const int tid = threadIdx.x, w = wave_id(), lane = lane_id();
   const int nw = blockDim.x >> 6;
   const int nslots = a.nslots;
+  const int unit = a.blocks ? kBlockRows : 1;  // row slots per position
   int32_t *s_off = reinterpret_cast<int32_t *>(dyn);
   int32_t *s_row = s_off + nslots;
-  uint32_t *wc = dyn + 2 * nslots;
+  int32_t *s_len = s_row + nslots;
+  uint32_t *wc = dyn + 3 * nslots;
   const uint32_t *words = a.cand + (int64_t)f * a.cap;
   // the first words are requested together with the count (one round trip)
   constexpr int EU = (kEarlyKeys + BLOCK - 1) / BLOCK;
@@ -426,6 +481,10 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
   for (int j = tid; j < nslots; j += blockDim.x) {
     s_off[j] = a.slot_off[(int64_t)f * nslots + j];
     s_row[j] = a.slot_row[(int64_t)f * nslots + j];
+    if (a.blocks) {
+      const int r = a.slot_reg[(int64_t)f * nslots + j];
+      s_len[j] = r >= 0 ? (int)(a.reg_start[r + 1] - a.reg_start[r]) : 0;
+    }
   }
   const int n = a.n_cand ? a.n_cand[f] : a.n_fixed;
   const int C = min(n, a.cache);  // positions [0, C) cached, the rest read from memory
@@ -648,19 +707,21 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
     if (rejected) tpos = sh.krem;
     __syncthreads();
   }
-  for (int s = tid; s < nsurv; s += blockDim.x)
-    sh.srow[s] = row_of(s_off, s_row, nslots, sh.sel[s]);
+  positions_to_rows(a, sh, s_off, s_row, s_len, nslots, nsurv, 0);
   __syncthreads();
-  // FP64 rerank of the survivors, sorted by (distance, tie id)
+  // FP64 rerank of the survivors' rows, sorted by (distance, tie id); row
+  // slots past a block's end sort last
+  const int nrow = nsurv * unit;
   const float *qrow = a.qp + (int64_t)f * a.dp;
-  rerank_range<BLOCK == 1024>(a, sh, qrow, 0, nsurv);
+  rerank_range<BLOCK == 1024>(a, sh, qrow, 0, nrow);
   __syncthreads();
-  sort_pairs(sh, nsurv);
+  sort_pairs(sh, nrow);
   // certificate: a rejected candidate can only beat the m-th reranked
   // distance dm if its screen distance is within the screen's error bound e
   // of dm. If the best rejected one is not beyond dm + e, every rejected
   // candidate up to dm + e (the band) is re-scored too, in chunks if it does
-  // not fit at once.
+  // not fit at once. (In block mode a rejected block's word bounds all of its
+  // rows from below; fewer than m rows so far make dm infinite.)
   if (tid == 0) {
     sh.flag = 0;
     if (rejected && a.m > 0) {
@@ -671,7 +732,8 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
         const double qe = a.q_err[f], ql = a.q_lon[f];
         e += a.lo_coef * (ql * a.lo_dmax + qe * a.lo_nmax + qe * a.lo_dmax);
       }
-      const double dm = __longlong_as_double((long long)sh.sort_hi[a.m - 1]);
+      const uint64_t km = sh.sort_hi[a.m - 1];
+      const double dm = km == kKeyNone ? __builtin_inf() : __longlong_as_double((long long)km);
       const double tau = dm * (1.0 + 1e-12) + e;
       if (!(rejd > tau)) {
         sh.flag = 1;
@@ -679,9 +741,10 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
         if (a.stat_fallback) atomicAdd(a.stat_fallback, 1);
       }
     }
+    if (a.stat_rows) atomicAdd(a.stat_rows, nrow);
   }
   __syncthreads();
-  int have = min(nsurv, a.m);
+  int have = min(nrow, a.m);
   if (sh.flag) {
     // the band: rejected positions (above tw, or equal to tw past the first
     // take_eq) with a word up to tau_w (>= tw)
@@ -696,53 +759,57 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
     if (tid == blockDim.x - 1) sh.krem = incl;
     __syncthreads();
     const int total_band = sh.krem;
-    if (nsurv + total_band <= kMaxSurvivors) {
-      int pos = nsurv + incl - mine;
+    // the survivors' positions are no longer needed: band positions go to
+    // sel[0 ..), their rows behind the sorted survivor rows
+    if (nrow + total_band * unit <= kMaxSurvivors) {
+      int pos = incl - mine;
       for (int i = i0; i < i1; ++i)
         if (in_band(word_at(i), i)) sh.sel[pos++] = (uint32_t)i;
       __syncthreads();
-      for (int s = nsurv + tid; s < nsurv + total_band; s += blockDim.x)
-        sh.srow[s] = row_of(s_off, s_row, nslots, sh.sel[s]);
+      positions_to_rows(a, sh, s_off, s_row, s_len, nslots, total_band, nrow);
       __syncthreads();
-      rerank_range<BLOCK == 1024>(a, sh, qrow, nsurv, nsurv + total_band);
+      rerank_range<BLOCK == 1024>(a, sh, qrow, nrow, nrow + total_band * unit);
       __syncthreads();
-      merge_band(sh, nsurv, total_band, a.m);
-      have = min(nsurv + total_band, a.m);
+      merge_band(sh, nrow, total_band * unit, a.m);
+      have = min(nrow + total_band * unit, a.m);
     } else {
       // a band too large for one pass: re-scored in chunks of up to
-      // kMaxSurvivors - m positions, each merged with the best m so far
-      // (the sorted survivors' first m to begin with). Every candidate that
-      // can still enter the top m has a word up to tau_w, so this is exact.
-      const int m = a.m, chunk = kMaxSurvivors - m, excl = incl - mine;
-      int kept = min(nsurv, m);  // sort_hi / sort_lo[0, kept): the best so far, sorted
+      // kMaxSurvivors - m rows, each merged with the best m so far (the
+      // sorted survivors' first m to begin with). Every candidate that can
+      // still enter the top m has a word up to tau_w, so this is exact.
+      const int m = a.m, chunk = (kMaxSurvivors - m) / unit, excl = incl - mine;
+      int kept = min(nrow, m);  // sort_hi / sort_lo[0, kept): the best so far, sorted
       if (tid == 0 && a.stat_chunked) atomicAdd(a.stat_chunked, 1);
       for (int c0 = 0; c0 < total_band; c0 += chunk) {
         const int cnt = min(chunk, total_band - c0);
         // this thread's band positions ranked [c0, c0 + cnt) in position order
+        __syncthreads();
         if (excl < c0 + cnt && excl + mine > c0) {
           int r = excl;
           for (int i = i0; i < i1 && r < c0 + cnt; ++i) {
             if (in_band(word_at(i), i)) {
-              if (r >= c0) sh.sel[kept + r - c0] = (uint32_t)i;
+              if (r >= c0) sh.sel[r - c0] = (uint32_t)i;
               ++r;
             }
           }
         }
         __syncthreads();
-        for (int t = kept + tid; t < kept + cnt; t += blockDim.x)
-          sh.srow[t] = row_of(s_off, s_row, nslots, sh.sel[t]);
+        positions_to_rows(a, sh, s_off, s_row, s_len, nslots, cnt, kept);
         __syncthreads();
-        rerank_range<BLOCK == 1024>(a, sh, qrow, kept, kept + cnt);
+        rerank_range<BLOCK == 1024>(a, sh, qrow, kept, kept + cnt * unit);
         __syncthreads();
-        merge_band(sh, kept, cnt, m);
-        kept = min(kept + cnt, m);
+        merge_band(sh, kept, cnt * unit, m);
+        kept = min(kept + cnt * unit, m);
       }
       have = kept;
     }
-    if (tid == 0 && a.stat_band) atomicAdd(a.stat_band, total_band);
+    if (tid == 0) {
+      if (a.stat_band) atomicAdd(a.stat_band, total_band * unit);
+      if (a.stat_rows) atomicAdd(a.stat_rows, total_band * unit);
+    }
   }
   for (int i = tid; i < a.m; i += blockDim.x) {
-    const bool ok = i < have;
+    const bool ok = i < have && sh.sort_hi[i] != kKeyNone;
     if (a.reg_out) {
       a.reg_out[(int64_t)f * a.m + i] = ok ? (int32_t)sh.sort_lo[i] : -1;
     } else {
@@ -754,7 +821,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
 }
 
 size_t select_lds_bytes(int nslots, int cache) {
-  return (size_t)(2 * nslots + cache) * sizeof(uint32_t);
+  return (size_t)(3 * nslots + cache) * sizeof(uint32_t);
 }
 
 // LDS limit of the select kernel (word cache and slot table above 64 KB),
@@ -776,8 +843,12 @@ hipError_t prepare_select_kernels() {
 
 hipError_t launch_select_rerank(SelRerankArgs a, hipStream_t s) {
   if (a.nq <= 0) return hipSuccess;
-  if (a.L > kMaxSurvivors || a.L < a.m || a.m > 256) return hipErrorInvalidValue;
+  const int unit = a.blocks ? kBlockRows : 1;
+  if (a.L * unit > kMaxSurvivors || a.L * unit < a.m || a.m > 256) return hipErrorInvalidValue;
   if (a.nslots < 0 || a.nslots > kMaxSlots || (a.nslots > 0 && (!a.slot_off || !a.slot_row)))
+    return hipErrorInvalidValue;
+  if (a.blocks && ((a.nslots > 0 && (!a.slot_reg || !a.reg_start)) ||
+                   (a.nslots == 0 && !a.blk_rows)))
     return hipErrorInvalidValue;
   a.cache = (int32_t)std::min<int64_t>(a.cap, kWordCache);
   // frames with many candidates: the word cache takes most of the LDS, so the

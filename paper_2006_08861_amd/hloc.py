@@ -240,7 +240,8 @@ class HlocDB:
                                     _np_ptr(tile), _np_ptr(flags)))
         return out
 
-    def _query_device(self, q, k, n_regions, req_offsets, prec, aggregate, stream):
+    def _query_device(self, q, k, n_regions, req_offsets, prec, aggregate, stream,
+                      entry="hloc_query_batch_async"):
         import torch
         lib = load_library()
         if q.dtype != torch.float32 or q.dim() != 2 or q.shape[1] != self.d:
@@ -266,9 +267,9 @@ class HlocDB:
         def p(t):
             return None if t is None else ctypes.c_void_p(t.data_ptr())
 
-        _check(lib.hloc_query_batch_async(self._h, p(q), nq, k, n_regions, p(offs), nreq, prec,
-                                          p(idx), p(dist), p(xy), p(tile), p(flags),
-                                          ctypes.c_void_p(s.cuda_stream)))
+        _check(getattr(lib, entry)(self._h, p(q), nq, k, n_regions, p(offs), nreq, prec,
+                                   p(idx), p(dist), p(xy), p(tile), p(flags),
+                                   ctypes.c_void_p(s.cuda_stream)))
         return out
 
     def set_region_labels(self, labels, n_labels: int):
@@ -406,8 +407,8 @@ class HlocDB:
         return out
 
 
-_INFO_KEYS = ("items", "coarse_fallbacks", "fine_fallbacks", "max_candidates", "survivors",
-              "candidates", "narrow_items", "chunked_bands", "band_rows")
+_INFO_KEYS = ("items", "coarse_fallbacks", "fine_fallbacks", "max_blocks", "survivors",
+              "candidates", "narrow_items", "chunked_bands", "band_rows", "rerank_rows")
 
 
 class Workspace:
