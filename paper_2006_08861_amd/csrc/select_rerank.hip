@@ -26,7 +26,7 @@
 
 namespace hloc {
 
-constexpr int kWordCache = 28672;  // screen words of a frame kept in (dynamic) LDS
+constexpr int kWordCache = 27648;  // screen words of a frame kept in (dynamic) LDS
 constexpr int kBigFrame = 4096;    // candidate capacity above which a frame gets 1024 threads
 constexpr int kMaxSlots = 1024;    // region slots of a frame kept in (dynamic) LDS
 constexpr uint32_t kWordNone = 0xFFFFFFFFu;  // no candidate at this position
@@ -820,9 +820,13 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
   }
 }
 
-size_t select_lds_bytes(int nslots, int cache) {
+constexpr size_t select_lds_bytes(int nslots, int cache) {
   return (size_t)(3 * nslots + cache) * sizeof(uint32_t);
 }
+// the static block state plus the largest slot table and word cache fit the
+// LDS one workgroup may hold
+static_assert(sizeof(SelShared) + select_lds_bytes(kMaxSlots, kWordCache) <= (size_t)kLdsPerCu,
+              "select kernel LDS above 160 KB");
 
 // LDS limit of the select kernel (word cache and slot table above 64 KB),
 // set once per device.
