@@ -80,6 +80,7 @@ enum { HLOC_MIRROR_BF16 = 1, HLOC_MIRROR_FP8 = 2 };
 #define HLOC_MAX_REQUEST_CANDIDATES 4096 /* frames of one request x k */
 #define HLOC_MAX_TOP_C 64
 #define HLOC_MAX_LABELS 64           /* subspace labels */
+#define HLOC_STATIC_SCRATCH_BYTES 67108864 /* scratch of hloc_query_batch_static_async (64 MiB) */
 
 /*
  * Build a database from n feature vectors (Section 3: one omnidirectional
@@ -160,6 +161,30 @@ int hloc_query_batch_async(hloc_db *db, const float *q, int32_t nq, int32_t k, i
                            const int32_t *req_offsets, int32_t nreq, int32_t precision,
                            int64_t *idx, float *dist, double *xy, int32_t *tile, int32_t *flags,
                            void *stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as hloc_query_batch_async, same arguments, outputs and errors, with
+ * bitwise the same results, but it allocates nothing. The batch's scratch
+ * memory (frame copies, screen words, schedule, counters) is carved from a
+ * static device array of HLOC_STATIC_SCRATCH_BYTES that every device the
+ * library runs on holds from the first call on that device until the process
+ * ends; only the caller's inputs and outputs are passed in.
+ * Errors as hloc_query_batch_async, plus EINVAL when the batch's scratch
+ * memory would exceed HLOC_STATIC_SCRATCH_BYTES (the message gives the size
+ * needed; e.g. 256 frames against 1,024 regions need about 2 MB) and EDEVICE
+ * when the array's device address cannot be looked up.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents (the kernels clear what must start at zero): calls on one
+ * device whose work overlaps on the GPU race, so enqueue them on one stream
+ * or wait for the previous one first. hloc_query_info does not report on
+ * these calls.
+ */
+int hloc_query_batch_static_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
+                                  int32_t n_regions, const int32_t *req_offsets, int32_t nreq,
+                                  int32_t precision, int64_t *idx, float *dist, double *xy,
+                                  int32_t *tile, int32_t *flags, void *stream);
 
 /*
  * Sliding-window requests (Section 3.1: a request carries a frame and its

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -14,6 +15,13 @@
 #include "hloc_host.h"
 
 using namespace hloc;
+
+// Scratch memory of hloc_query_batch_static_async, which allocates nothing:
+// every device the library runs on holds its own copy of this array until
+// the process ends. On the host the name is only a stand-in, not a device
+// address: host code uses the per-device address from hipGetSymbolAddress
+// (static_scratch below), never the name.
+static __device__ __align__(256) unsigned char scratch[HLOC_STATIC_SCRATCH_BYTES];
 
 namespace hloc {
 thread_local PhaseEvents *g_phase = nullptr;
@@ -134,10 +142,19 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
   return HLOC_OK;
 }
 
-int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *bytes) {
+int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *bytes,
+                     const Carve *carve) {
   const hloc_db *db = ws->db;
-  // with `bytes`: only add up what the buffers would take
+  // with `bytes`: only add up what the buffers would take; with `carve`:
+  // point each buffer into the caller's memory (256-byte aligned, in order)
+  // and add up the bytes used, allocating nothing
   auto fit = [&](WsBuf &b, size_t need) -> int {
+    if (carve) {
+      b.p = static_cast<char *>(carve->base) + *bytes;
+      b.cap = need;
+      *bytes += (need + 255) / 256 * 256;
+      return HLOC_OK;
+    }
     if (bytes) {
       *bytes += alloc_size(need);
       return HLOC_OK;
@@ -552,6 +569,30 @@ int query_async(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int32_t n_re
   DeviceGuard g(db->device);
   if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
   return enqueue_query(ws, p, q, req_offsets, nullptr, idx, dist, xy, tile, flags, s);
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the static scratch array on device `dev` (current),
+// looked up once per device.
+int static_scratch(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(HLOC_EDEVICE, "device %d is beyond the %d devices of the scratch table", dev,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(HLOC_EDEVICE, "address of the static scratch array: %s", hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HLOC_OK;
 }
 
 int info_of(hloc_ws *ws, int64_t *out, int32_t n) {
@@ -996,6 +1037,35 @@ int hloc_query_batch_async(hloc_db *db, const float *q, int32_t nq, int32_t k, i
   if (!db) return fail(HLOC_EINVAL, "db is NULL");
   return query_async(db->ws0, q, nq, k, n_regions, req_offsets, nreq, precision, idx, dist, xy,
                      tile, flags, reinterpret_cast<hipStream_t>(stream));
+}
+
+int hloc_query_batch_static_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
+                                  int32_t n_regions, const int32_t *req_offsets, int32_t nreq,
+                                  int32_t precision, int64_t *idx, float *dist, double *xy,
+                                  int32_t *tile, int32_t *flags, void *stream) {
+  if (!db) return fail(HLOC_EINVAL, "db is NULL");
+  CHK(check_query_args(db, q, nq, req_offsets, nreq, precision, idx, dist));
+  Plan p;
+  CHK(make_plan(db, nq, k, n_regions, nreq, precision, &p));
+  DeviceGuard g(db->device);
+  if (g.err != hipSuccess) return fail(HLOC_EDEVICE, "hipSetDevice failed");
+  void *base = nullptr;
+  CHK(static_scratch(db->device, &base));
+  // a workspace record on the stack whose buffers all point into the array:
+  // the sizing inside enqueue_query then finds every buffer large enough
+  hloc_ws ws;
+  ws.db = db;
+  const bool agg_internal = (xy || tile || flags) && !(xy && tile && flags);
+  size_t used = 0;
+  const Carve carve{base};
+  CHK(ensure_workspace(&ws, p, agg_internal, &used, &carve));
+  if (used > (size_t)HLOC_STATIC_SCRATCH_BYTES)
+    return fail(HLOC_EINVAL,
+                "the batch needs %zu bytes of scratch memory, above the %zu bytes of the static "
+                "array (send fewer frames)",
+                used, (size_t)HLOC_STATIC_SCRATCH_BYTES);
+  return enqueue_query(&ws, p, q, req_offsets, nullptr, idx, dist, xy, tile, flags,
+                       reinterpret_cast<hipStream_t>(stream));
 }
 
 int hloc_ws_capture(hloc_ws *ws, const float *q, int32_t nq, int32_t k, int32_t n_regions,

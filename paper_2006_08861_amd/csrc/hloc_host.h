@@ -172,10 +172,17 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
               int32_t precision, Plan *pl);
 // Bytes ensure() allocates for a request of `bytes`.
 size_t alloc_size(size_t bytes);
+// Memory the workspace buffers are carved from instead of allocated.
+struct Carve {
+  void *base;
+};
 // Sizes every buffer of ws for plan p (agg_internal: the aggregation outputs
 // live in the workspace). With `bytes` set, allocates nothing and adds to
-// *bytes what sizing an empty workspace would allocate.
-int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *bytes = nullptr);
+// *bytes what sizing an empty workspace would allocate; with `carve` too,
+// points every buffer into carve->base from offset *bytes on (each exactly
+// its size, 256-byte aligned) and advances *bytes past them.
+int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *bytes = nullptr,
+                     const Carve *carve = nullptr);
 // Enqueues one batch on stream s. req_k (device, nreq entries, or NULL) gives
 // each request's candidates per frame for the aggregation (<= p.k).
 // req_frames (device, n_frames entries, or NULL): request r pools the batch

@@ -55,6 +55,8 @@ _SIGNATURES = {
                                         _P]),
     "hloc_query_batch_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _I32, _I32, _P, _P,
                                               _P, _P, _P, _P]),
+    "hloc_query_batch_static_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _I32, _I32,
+                                                     _P, _P, _P, _P, _P, _P]),
     "hloc_query_windows_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _P, _I32, _I32,
                                                 _I32, _P, _P, _P, _P, _P, _P]),
     "hloc_set_region_labels": (ctypes.c_int, [_P, _P, _I32]),
@@ -217,6 +219,17 @@ class HlocDB:
         if _is_torch_cuda(q):
             return self._query_device(q, k, n_regions, req_offsets, prec, aggregate, stream)
         return self._query_host(q, k, n_regions, req_offsets, prec, aggregate)
+
+    def query_static(self, q, k: int, n_regions: int, req_offsets=None, precision="fp32",
+                     aggregate: bool = True, stream=None) -> dict:
+        """As query() on CUDA tensors, through hloc_query_batch_static_async:
+        the library allocates no device memory for the batch (its scratch is
+        the library's static array; the output tensors are allocated here)."""
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        if not _is_torch_cuda(q):
+            raise HlocError(EINVAL, "query_static takes a CUDA tensor of frames")
+        return self._query_device(q, k, n_regions, req_offsets, prec, aggregate, stream,
+                                  entry="hloc_query_batch_static_async")
 
     def _query_host(self, q, k, n_regions, req_offsets, prec, aggregate):
         lib = load_library()
