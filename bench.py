@@ -1040,8 +1040,9 @@ def main():
         "ms_per_step_event_timed": wall_prof * 1e3 / a.steps,
         "modes": {"eager_one_stream_ms_per_step": wall_eager * 1e3 / a.steps,
                   f"graphs_{W}_streams_ms_per_step": wall_pipe * 1e3 / a.steps},
-        "fallbacks": {"coarse": info["coarse_fallbacks"], "fine": info["fine_fallbacks"],
-                      "chunked_bands": info["chunked_bands"], "band_rows": info["band_rows"]},
+        "fallbacks": {"coarse": info["coarse_fallbacks"], "coarse_deferred": info["coarse_deferred"],
+                      "fine": info["fine_fallbacks"], "chunked_bands": info["chunked_bands"],
+                      "band_rows": info["band_rows"], "rerank_rows": info["rerank_rows"]},
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

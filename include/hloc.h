@@ -259,7 +259,9 @@ int hloc_reserve(hloc_db *db, int32_t nq_max, int32_t nreq_max, int32_t k_max,
  * out[7] frames whose band was too large for one pass and was re-scored in
  * chunks, out[8] row slots re-scored in bands over all frames (16 per
  * block), out[9] row slots re-scored in FP64 by the fine stage over all
- * frames (survivor blocks and bands). Writes min(n, 10) values.
+ * frames (survivor blocks and bands), out[10] frames whose coarse
+ * selection the fused coarse product's kept candidates could not decide, so
+ * they took the dense coarse screen. Writes min(n, 11) values.
  * Errors: EINVAL, EDEVICE.
  */
 int hloc_query_info(hloc_db *db, int64_t *out, int32_t n);

@@ -125,6 +125,16 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
   // survivors re-scored in FP64: k + 16 behind the fp32 screen, 4k behind bf16
   p.kp = std::min(precision == HLOC_FP32 ? k + kOversample : std::max(4 * k, k + kOversample),
                   kMaxSurvivors);  // 4k behind the bf16 and fp8 screens
+  // bf16 coarse screens (bf16 queries, and fp8 queries when the database
+  // keeps bf16 representatives) on a length the fused product supports
+  p.coarse_keys = !p.exhaustive && precision != HLOC_FP32 && db->lp[HLOC_BF16].reps &&
+                  coarse_gemm_supports(db->dp) && db->R < (1 << 28);
+  if (p.coarse_keys) {
+    const int32_t sp = coarse_gemm_splits(std::max(nq, 1), db->R, db->num_cu);
+    p.creps = (db->R + sp - 1) / sp;
+    p.creps = (p.creps + 31) / 32 * 32;           // whole tiles of 32
+    p.csplits = (db->R + p.creps - 1) / p.creps;  // no empty range
+  }
   p.cap2 = p.exhaustive ? db->n_blocks : db->h_desc_blocks[p.nr];
   const int32_t crow = std::min(db->tile_rows, kWideRows);  // the shorter chunks bound the items
   const int64_t maxch = (db->max_region + crow - 1) / crow;
@@ -164,6 +174,12 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *byte
   const int64_t nq = std::max(p.nq, 1), nr = std::max(p.nr, 1);
   CHK(fit(ws->qp, (size_t)nq * db->dp * sizeof(float)));
   CHK(fit(ws->qn2, (size_t)nq * sizeof(float)));
+  if (p.coarse_keys) {
+    CHK(fit(ws->ckeys, (size_t)nq * p.csplits * kCgKeys * sizeof(uint64_t)));
+    CHK(fit(ws->cslots, (size_t)nq * p.csplits * 4 * kCgKeep * sizeof(uint4)));
+    CHK(fit(ws->cbounds, (size_t)nq * p.csplits * 4 * sizeof(uint64_t)));
+    CHK(fit(ws->cdefer, (size_t)nq * sizeof(int32_t)));
+  }
   if (!p.exhaustive) CHK(fit(ws->cand1, (size_t)nq * db->R * sizeof(uint32_t)));
   CHK(fit(ws->regions, (size_t)nq * nr * sizeof(int32_t)));
   CHK(fit(ws->rcount, (size_t)db->R * sizeof(int32_t)));
@@ -276,7 +292,13 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   const double lo_fp32 = fmt == HLOC_FP8 ? 1.15 : 1.01;
   ph.begin(HLOC_PHASE_COARSE);
   const double coef = (db->dp + 16) * kUnit32 * 1.001;
-  if (!p.exhaustive) {
+  const bool masked = (label >= 0 || label_frames > 0) && db->rlabel;
+  const bool coarse_lp = cfmt && cpm->reps;
+  // The dense coarse stage: every frame's word against every representative,
+  // then the words-mode select (FP64 re-score of the best, certificate).
+  // With a frame list, only the listed frames (those the fused product's
+  // keys could not decide; their count on the device).
+  auto coarse_words = [&](const int32_t *list, const int32_t *count) -> int {
     ScreenArgs sa{};
     sa.rows = db->rep32;
     sa.row_n2 = db->rep_n2;
@@ -289,10 +311,12 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     sa.dense = 1;
     sa.nrows = db->R;
     sa.nq = p.nq;
+    sa.frame_list = list;
+    sa.frame_count = count;
     // large batches: 64 representatives staged in LDS against 256 frames at a
     // time (the wide kernels' dense mode) instead of re-reading them per 16
-    const bool coarse_lp = cfmt && cpm->reps;
-    const bool wide_dense = p.nq >= kWideDenseFrames && (coarse_lp || f32_wide_supports(db->dp));
+    const bool wide_dense =
+        !list && p.nq >= kWideDenseFrames && (coarse_lp || f32_wide_supports(db->dp));
     if (coarse_lp) {
       sa.rows_lp = cpm->reps;
       sa.q_lp = c_lp;
@@ -304,7 +328,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
       HIPCHK(wide_dense ? launch_screen_wide_f32(sa, p.grid1, db->num_cu, s)
                         : launch_screen_f32(sa, p.grid1, s));
     }
-    if ((label >= 0 || label_frames > 0) && db->rlabel)
+    if (masked)
       HIPCHK(launch_mask_label(as<uint32_t>(ws->cand1), p.nq, db->R, db->rlabel, label,
                                label_frames, s));
     ph.begin(HLOC_PHASE_COARSE_SELECT);
@@ -331,7 +355,64 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     ra.nq = p.nq;
     ra.reg_out = regions;
     ra.stat_fallback = misc + 1;
+    ra.frame_list = list;
+    ra.frame_count = count;
     HIPCHK(launch_select_rerank(ra, s));
+    return HLOC_OK;
+  };
+  if (p.coarse_keys) {
+    // one bf16 product of frames and representatives whose epilogue keeps
+    // short key lists; the select re-scores the best in FP64 and certifies,
+    // and the frames it cannot decide from the keys take the dense stage
+    CoarseGemmArgs ca{};
+    ca.reps = cpm->reps;
+    ca.rep_n2 = db->rep_n2;
+    ca.frames = c_lp;
+    ca.qn2 = qn2;
+    ca.R = db->R;
+    ca.nq = p.nq;
+    ca.dp = db->dp;
+    ca.splits = p.csplits;
+    ca.reps_per_split = p.creps;
+    if (masked) {
+      ca.rlabel = db->rlabel;
+      ca.label = label;
+      ca.label_frames = label_frames;
+    }
+    ca.slots = as<uint4>(ws->cslots);
+    ca.keys = as<uint64_t>(ws->ckeys);
+    ca.bounds = as<uint64_t>(ws->cbounds);
+    HIPCHK(launch_coarse_gemm(ca, s));
+    ph.begin(HLOC_PHASE_COARSE_SELECT);
+    SelRerankArgs ra{};
+    ra.keys = ca.keys;
+    ra.cap = (int64_t)p.csplits * kCgKeys;
+    ra.n_fixed = p.csplits * kCgKeys;
+    ra.bounds = ca.bounds;
+    ra.n_bounds = p.csplits * 4;
+    ra.defer_list = as<int32_t>(ws->cdefer);
+    ra.defer_count = misc + 10;  // cleared by the prep kernel
+    ra.L = p.L1;
+    ra.m = p.nr;
+    ra.src64 = db->rep64;
+    ra.dp = db->dp;
+    ra.qp = qp;
+    ra.qn2 = qn2;
+    ra.max_norm = (double)db->h_rep_max * (1.0 + 1e-6);
+    ra.q_err = c_err;
+    ra.q_lon = c_lon;
+    ra.lo_dmax = (double)cpm->rep_err * (1.0 + 1e-6);
+    ra.lo_nmax = (double)cpm->rep_norm * (1.0 + 1e-6);
+    ra.lo_coef = 2.0 * (1.0 + 1e-6);
+    ra.err_coef = coef * 1.01;
+    ra.nq = p.nq;
+    ra.reg_out = regions;
+    ra.stat_fallback = misc + 1;
+    HIPCHK(launch_select_rerank(ra, s));
+    ph.begin(HLOC_PHASE_COARSE);
+    CHK(coarse_words(as<int32_t>(ws->cdefer), misc + 10));
+  } else if (!p.exhaustive) {
+    CHK(coarse_words(nullptr, nullptr));
   } else {
     HIPCHK(launch_broadcast_ids(db->nonempty_ids, p.nr, p.nq, regions, s));
   }
@@ -484,7 +565,8 @@ void for_each_buf(hloc_ws *ws, F f) {
                    &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags, &ws->q_lp,
                    &ws->q_scale,  &ws->q_err,    &ws->q_lon,   &ws->slot_row, &ws->n_rows,
                    &ws->c_lp,     &ws->c_scale,  &ws->c_err,   &ws->c_lon,   &ws->agg_big,
-                   &ws->lab_off,  &ws->lab_list, &ws->lab_q};
+                   &ws->lab_off,  &ws->lab_list, &ws->lab_q,  &ws->ckeys,
+                   &ws->cslots,   &ws->cbounds,  &ws->cdefer};
   for (WsBuf *b : bufs) f(*b);
 }
 
@@ -607,10 +689,10 @@ int info_of(hloc_ws *ws, int64_t *out, int32_t n) {
     HIPCHK(hipMemcpy(nc.data(), ws->n_rows.p, nc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     for (int32_t v : nc) total += v;
   }
-  const int64_t vals[10] = {misc[0], misc[1], misc[2],     misc[3], ws->last_kp,
+  const int64_t vals[11] = {misc[0], misc[1], misc[2],     misc[3], ws->last_kp,
                             total,   misc[4], misc[6], (int64_t)(uint32_t)misc[7],
-                            (int64_t)(uint32_t)misc[9]};
-  for (int32_t i = 0; i < std::min(n, 10); ++i) out[i] = vals[i];
+                            (int64_t)(uint32_t)misc[9], misc[10]};
+  for (int32_t i = 0; i < std::min(n, 11); ++i) out[i] = vals[i];
   return HLOC_OK;
 }
 

@@ -91,7 +91,9 @@ struct hloc_ws {
       c_lp, c_scale, c_err, c_lon,  // bf16 frame copy for the coarse screen of fp8 queries
       agg_big,                      // requests for the large-list aggregation kernel
       lab_off, lab_list,            // frame lists of a query over subspace labels
-      lab_q;                        // its frames once per label
+      lab_q,                        // its frames once per label
+      ckeys, cslots, cbounds,       // key lists of the fused coarse product
+      cdefer;                       // frames its keys could not decide
   hloc::WsBuf s_q, s_off, s_idx, s_dist, s_xy, s_tile, s_flags;  // staging of host-pointer calls
   int32_t last_nq = 0, last_nr = 0, last_kp = 0;
   bool prof_on = false;
@@ -155,6 +157,10 @@ namespace hloc {
 struct Plan {
   int32_t nq, k, nr, L1, kp, nreq, precision;
   bool exhaustive;
+  // the coarse stage as the fused bf16 product (short key lists per frame)
+  // instead of the dense screen's frame x region words
+  bool coarse_keys;
+  int32_t csplits, creps;  // representative ranges and their length
   int64_t cap2;  // 16-row blocks of a frame's candidate rows at most
   int64_t items_bound;
   int32_t grid1, grid2;

@@ -97,6 +97,10 @@ struct ScreenArgs {
   const int32_t *n_items;
   const int2 *rq;         // (frame, offset of the region in the frame's candidate list)
   const int64_t *reg_start;
+  // dense mode over a frame list (NULL: frames 0 .. nq - 1): frames
+  // frame_list[0 .. *frame_count), each writing its own row of cand
+  const int32_t *frame_list;
+  const int32_t *frame_count;
 };
 
 // Work item of the wide screens: a chunk of rows against up to kItemFrames
@@ -203,6 +207,34 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
                         int32_t *slot_row, int32_t *n_cand, int32_t *n_rows, int32_t *n_items,
                         int2 *rq, Item *items, hipStream_t s);
 
+// Coarse screen fused with the start of the selection (coarse_gemm.hip): a
+// bf16 MFMA product of frames and representatives whose epilogue keeps, per
+// (frame, split of the representatives, lane group), the kCgKeep best quads
+// (four consecutive representatives, ranked by their smallest screen word)
+// instead of storing every word.
+constexpr int kCgKeep = 6;                     // quads kept per (frame, split, lane group)
+constexpr int kCgKeys = 4 * kCgKeep * 4;       // keys per (frame, split): 4 lane groups x quads x 4
+struct CoarseGemmArgs {
+  const void *reps;        // R x dp bf16 representatives
+  const float *rep_n2;     // R squared norms (+inf: empty region)
+  const void *frames;      // nq x dp bf16 frames
+  const float *qn2;        // nq squared norms of the fp32 frames
+  int32_t R, nq, dp;
+  int32_t splits;          // representative ranges, one block column each
+  int32_t reps_per_split;  // multiple of 32, splits * reps_per_split >= R
+  const int32_t *rlabel;   // R region labels, or NULL (no label restriction)
+  int32_t label;           // with rlabel and label_frames == 0: every frame's label
+  int32_t label_frames;    // > 0: frame f's label is f / label_frames
+  uint4 *slots;            // nq x splits x 4 x kCgKeep: the words of each kept quad
+  uint64_t *keys;          // nq x splits x kCgKeys: (word << 32 | region), kKeyNone pads
+  uint64_t *bounds;        // nq x splits x 4: per lane list, word << 32 of its last kept
+                           // quad when it dropped any (every dropped region's word is at
+                           // least that), else kKeyNone
+};
+bool coarse_gemm_supports(int32_t dp);
+int32_t coarse_gemm_splits(int32_t nq, int32_t R, int32_t num_cu);
+hipError_t launch_coarse_gemm(CoarseGemmArgs a, hipStream_t s);
+
 // Per frame: the L + 1 smallest words of cand[f][0 .. n(f)) (n(f) =
 // n_cand ? n_cand[f] : n_fixed; 0xFFFFFFFF entries are skipped; equal words
 // ordered by position), FP64 rerank of the rows of the L smallest, top m by
@@ -257,6 +289,21 @@ struct SelRerankArgs {
   int32_t *stat_band;      // sum of the band sizes (or NULL)
   int32_t *stat_max;       // largest candidate count (or NULL)
   int32_t *stat_rows;      // rows re-scored in FP64, survivors and bands (or NULL)
+  // key mode (the coarse stage after the fused coarse product): the frame's
+  // n_fixed candidates are keys (word << 32 | source row, any order), and
+  // n_bounds bounds per frame: every source row missing from the keys has a
+  // key of at least their minimum. A frame whose keys cannot decide the
+  // selection writes nothing: it is appended to defer_list (count in
+  // *defer_count, zero on entry) for the dense screen and words mode.
+  const uint64_t *keys;    // nq x n_fixed, or NULL (words mode)
+  const uint64_t *bounds;  // nq x n_bounds
+  int32_t n_bounds;
+  int32_t *defer_list;     // nq entries
+  int32_t *defer_count;
+  // words mode over a frame list (NULL: block b takes frame b in XCD-major
+  // order): block b < *frame_count takes frame frame_list[b]
+  const int32_t *frame_list;
+  const int32_t *frame_count;
 };
 hipError_t launch_select_rerank(SelRerankArgs a, hipStream_t s);
 
@@ -289,8 +336,10 @@ hipError_t prepare_screen_lp_kernels();
 hipError_t prepare_select_kernels();
 hipError_t prepare_aggregate_kernels();
 hipError_t prepare_sched_kernels();
+hipError_t prepare_coarse_gemm_kernels();
 inline hipError_t prepare_kernels() {
   hipError_t e = prepare_screen_kernels();
+  if (e == hipSuccess) e = prepare_coarse_gemm_kernels();
   if (e == hipSuccess) e = prepare_select_kernels();
   if (e == hipSuccess) e = prepare_sched_kernels();
   if (e == hipSuccess) e = prepare_aggregate_kernels();

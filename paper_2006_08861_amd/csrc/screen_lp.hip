@@ -24,6 +24,7 @@ namespace hloc {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));  // 16-byte piece (native vector)
 
 constexpr float kFp8Max = 448.f;  // largest finite OCP e4m3 value
 
@@ -203,6 +204,20 @@ __device__ __forceinline__ v4f lp_mfma(uint4 a, uint4 b, v4f acc) {
   }
 }
 
+// The same on native vectors (kept in registers across loops).
+template <int FMT>
+__device__ __forceinline__ v4f lp_mfma_v(v4u a, v4u b, v4f acc) {
+  if (FMT == HLOC_BF16) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                   __builtin_bit_cast(v8bf, b), acc, 0, 0, 0);
+  } else {
+    const long a0 = (long)(((uint64_t)a.y << 32) | a.x), a1 = (long)(((uint64_t)a.w << 32) | a.z);
+    const long b0 = (long)(((uint64_t)b.y << 32) | b.x), b1 = (long)(((uint64_t)b.w << 32) | b.z);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, acc, 0, 0, 0);
+  }
+}
+
 // Screen word of a row with squared norm rn against a frame with squared norm
 // qn, from the low-precision dot product (times the two scales for fp8).
 template <int FMT>
@@ -225,9 +240,11 @@ __global__ __launch_bounds__(256) void k_screen_lp(ScreenArgs a) {
   const uint4 *rows = static_cast<const uint4 *>(a.rows_lp);
   const uint4 *frames = static_cast<const uint4 *>(a.q_lp);
   int lo = 0, hi, nchunks = 1;
+  // dense mode: frames 0 .. nq - 1, or the listed ones
+  const int nqd = DENSE && a.frame_list ? *a.frame_count : a.nq;
   if (DENSE) {
     nchunks = (a.nrows + a.rows_per_item - 1) / a.rows_per_item;
-    hi = nchunks * ((a.nq + kGroup - 1) / kGroup);
+    hi = nchunks * ((nqd + kGroup - 1) / kGroup);
   } else {
     hi = a.n_items[4];  // the narrow items: at most kGroup frames each
   }
@@ -248,8 +265,9 @@ __global__ __launch_bounds__(256) void k_screen_lp(ScreenArgs a) {
       row_begin = c * a.rows_per_item;
       chunk_row = row_begin;
       nrows = min(a.rows_per_item, a.nrows - row_begin);
-      gq = min(kGroup, a.nq - grp * kGroup);
+      gq = min(kGroup, nqd - grp * kGroup);
       fr = grp * kGroup + i;
+      if (a.frame_list) fr = i < gq ? a.frame_list[fr] : 0;
       off = (int64_t)fr * a.cap + chunk_row;
     } else {
       row_begin = nx.row_begin;
@@ -425,10 +443,130 @@ __global__ __launch_bounds__(256) void k_screen_wide_lp(ScreenArgs a) {
   }
 }
 
+// Wide list items with the rows held in registers and the frames staged
+// through LDS, 16 at a time, double-buffered (wide items of the bf16 and fp8
+// screens when the padded length gives an even NS).
+// A block of two waves takes one wide item (a chunk of up to 64 rows of one
+// region against its gq frames). Wave w holds rows 32 w .. 32 w + 31 of the
+// chunk as the MFMA A operand (two 16-row tiles over the whole padded
+// length), so each row is read from memory once per item and every LDS read
+// of a frame piece feeds both row tiles (two MFMAs for bf16, four for fp8).
+// While frame group k is multiplied, group k + 1 is read into registers; it
+// is written to the other buffer after the multiply. The epilogue takes, per
+// frame and row tile, the smallest of the tile's 16 screen words (the block
+// word) and stores it at the frame's block position.
+template <int FMT, int NS>
+__global__ __launch_bounds__(128) void k_screen_wide_rs(ScreenArgs a) {
+  constexpr int ROWU4 = 4 * NS;                 // 16-byte pieces per row
+  constexpr int LDF = ROWU4 + 1;                // padded frame row in LDS
+  constexpr int TPF = 8;                        // threads per staged frame
+  static_assert(ROWU4 % TPF == 0, "whole pieces per thread");
+  constexpr int PERF = ROWU4 / TPF;             // pieces per thread per group
+  extern __shared__ v4u s_fr[];                 // 2 x kGroup x LDF
+  __shared__ int2 s_e[2][kGroup];
+  __shared__ float s_qn[2][kGroup], s_qs[2][kGroup];
+  const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+  const int i = lane & 15, g = lane >> 4;
+  const v4u *rows = static_cast<const v4u *>(a.rows_lp);
+  const v4u *frames = static_cast<const v4u *>(a.q_lp);
+  int lo;
+  const int hi = wide_range(a, &lo);
+  // staging: thread t loads pieces (t % TPF) + TPF u of frame t / TPF
+  const int sj = tid / TPF, sc = tid % TPF;
+  for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
+    const WideItem wi = wide_item(a, it);
+    const int nrows = wi.nrows, gq = wi.gq;
+    // the wave's rows (clamped to the chunk's last row; words of rows past
+    // it are no candidates)
+    v4u av[2][NS];
+    float rn[2][4], rs[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int rl = min(32 * w + 16 * h + i, nrows - 1);
+      const v4u *rp = rows + (int64_t)(wi.row_begin + rl) * ROWU4 + g;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) av[h][s] = rp[4 * s];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 32 * w + 16 * h + 4 * g + r;
+        const int grow = wi.row_begin + min(row, nrows - 1);
+        rn[h][r] = row < nrows ? a.row_n2[grow] : __builtin_inff();
+        rs[h][r] = FMT == HLOC_FP8 ? a.row_scale[grow] : 1.f;
+      }
+    }
+    const int ng = (gq + kGroup - 1) / kGroup;
+    v4u pv[PERF];
+    int2 pe = make_int2(0, 0);
+    float pqn = 0.f, pqs = 1.f;
+#define HLOC_RS_FETCH(K)                                                         \
+  {                                                                              \
+    const int jj = (K) * kGroup + sj;                                            \
+    pe = jj < gq ? a.rq[wi.q0 + jj] : make_int2(0, 0);                           \
+    const v4u *fp = frames + (int64_t)pe.x * ROWU4 + sc;                         \
+    _Pragma("unroll") for (int u = 0; u < PERF; ++u) pv[u] = fp[TPF * u];        \
+    if (sc == 0) {                                                               \
+      pqn = a.qn2[pe.x];                                                         \
+      pqs = FMT == HLOC_FP8 ? a.q_scale[pe.x] : 1.f;                             \
+    }                                                                            \
+  }
+#define HLOC_RS_STAGE(BUF)                                                       \
+  {                                                                              \
+    _Pragma("unroll") for (int u = 0; u < PERF; ++u)                             \
+        s_fr[((BUF) * kGroup + sj) * LDF + sc + TPF * u] = pv[u];                \
+    if (sc == 0) {                                                               \
+      s_e[BUF][sj] = pe;                                                         \
+      s_qn[BUF][sj] = pqn;                                                       \
+      s_qs[BUF][sj] = pqs;                                                       \
+    }                                                                            \
+  }
+    __syncthreads();  // the previous item's last group is no longer read
+    HLOC_RS_FETCH(0)
+    HLOC_RS_STAGE(0)
+    __syncthreads();
+    for (int k = 0; k < ng; ++k) {
+      const int buf = k & 1;
+      if (k + 1 < ng) HLOC_RS_FETCH(k + 1)
+      v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+      const v4u *bp = s_fr + (buf * kGroup + i) * LDF + g;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const v4u b = bp[4 * s];
+        acc[0] = lp_mfma_v<FMT>(av[0][s], b, acc[0]);
+        acc[1] = lp_mfma_v<FMT>(av[1][s], b, acc[1]);
+      }
+      const int2 e = s_e[buf][i];
+      const float qn = s_qn[buf][i], qs = s_qs[buf][i];
+      const bool fok = k * kGroup + i < gq;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (32 * w + 16 * h >= nrows) continue;  // (uniform over the wave)
+        uint32_t wd[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          wd[r] = __builtin_isinf(rn[h][r]) ? 0xFFFFFFFFu
+                                            : lp_word<FMT>(qn, rn[h][r], acc[h][r], qs, rs[h][r]);
+        const uint32_t m = block_min16(wd);
+        if (fok && g == 0)
+          a.cand[(int64_t)e.x * a.cap + e.y + wi.chunk_row / kBlockRows + 2 * w + h] = m;
+      }
+      if (k + 1 < ng) HLOC_RS_STAGE(buf ^ 1)
+      __syncthreads();
+    }
+#undef HLOC_RS_FETCH
+#undef HLOC_RS_STAGE
+  }
+}
+
 template <int NS>
 size_t wide_lp_lds_bytes() {
   return (size_t)64 * (4 * NS + 1) * sizeof(uint4);
 }
+
+template <int NS>
+constexpr size_t wide_rs_lds_bytes() {
+  return (size_t)2 * kGroup * (4 * NS + 1) * sizeof(v4u);
+}
+constexpr int kRsBlocksPerCu = 4;  // blocks per compute unit if the occupancy query fails
 
 // Pieces per lane for a padded length: bf16 rows take dp / 32, fp8 rows
 // dp / 64 (0: no kernel for this length).
@@ -447,6 +585,26 @@ bool lp_screen_supports(int32_t fmt, int32_t dp) { return lp_pieces(fmt, dp) > 0
 
 template <int FMT, int NS>
 hipError_t launch_lp_ns(const ScreenArgs &a, int32_t grid, int32_t wide_cu, hipStream_t s) {
+  if constexpr (NS % 2 == 0) {
+    if (wide_cu > 0 && !a.dense) {
+      // as many blocks as the compute units hold at once (registers and LDS)
+      static int per_cu = 0;
+      if (per_cu == 0) {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &occ, reinterpret_cast<const void *>(&k_screen_wide_rs<FMT, NS>), 128,
+                wide_rs_lds_bytes<NS>()) != hipSuccess || occ < 1) {
+          (void)hipGetLastError();
+          occ = kRsBlocksPerCu;
+        }
+        per_cu = occ;
+      }
+      const int64_t resident = (int64_t)wide_cu * per_cu;
+      return launch_kernel(k_screen_wide_rs<FMT, NS>,
+                           dim3((int32_t)std::min<int64_t>(grid, resident)), dim3(128),
+                           (uint32_t)wide_rs_lds_bytes<NS>(), s, a);
+    }
+  }
   if (wide_cu > 0) {
     const int64_t resident =
         (int64_t)wide_cu * std::max<int64_t>(1, kLdsPerCu / wide_lp_lds_bytes<NS>());

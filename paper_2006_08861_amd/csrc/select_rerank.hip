@@ -427,8 +427,11 @@ __device__ __forceinline__ uint32_t block_row(const SelRerankArgs &a, const int3
 __device__ __forceinline__ void positions_to_rows(const SelRerankArgs &a, SelShared &sh,
                                                   const int32_t *s_off, const int32_t *s_row,
                                                   const int32_t *s_len, int nslots, int cnt,
-                                                  int base) {
-  if (a.blocks) {
+                                                  int base, const uint32_t *krow) {
+  if (krow) {
+    // key mode: the source row is the low half of the position's key
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) sh.srow[base + i] = krow[sh.sel[i]];
+  } else if (a.blocks) {
     for (int e = threadIdx.x; e < cnt * kBlockRows; e += blockDim.x) {
       const int i = e / kBlockRows, t = e - i * kBlockRows;
       sh.srow[base + e] = block_row(a, s_off, s_row, s_len, nslots, sh.sel[i], t);
@@ -454,7 +457,8 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
   __shared__ SelShared sh;
   extern __shared__ uint32_t dyn[];  // [slot offsets | slot rows | slot sizes | word cache]
   if ((int)blockIdx.x >= a.nq) return;
-  const int f = xcd_frame(blockIdx.x, a.nq);
+  if (a.frame_list && (int)blockIdx.x >= *a.frame_count) return;
+  const int f = a.frame_list ? a.frame_list[blockIdx.x] : xcd_frame(blockIdx.x, a.nq);
   const int tid = threadIdx.x, w = wave_id(), lane = lane_id();
   const int nw = blockDim.x >> 6;
   const int nslots = a.nslots;
@@ -463,10 +467,10 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
   int32_t *s_row = s_off + nslots;
   int32_t *s_len = s_row + nslots;
   uint32_t *wc = dyn + 3 * nslots;
-  const uint32_t *words = a.cand + (int64_t)f * a.cap;
+  const uint32_t *words = a.keys ? nullptr : a.cand + (int64_t)f * a.cap;
   // the first words are requested together with the count (one round trip)
   constexpr int EU = (kEarlyKeys + BLOCK - 1) / BLOCK;
-  const int early = (int)min<int64_t>(a.cap, kEarlyKeys);
+  const int early = a.keys ? 0 : (int)min<int64_t>(a.cap, kEarlyKeys);
   uint32_t ew[EU];
 #pragma unroll
   for (int u = 0; u < EU; ++u) {
@@ -487,7 +491,10 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
     }
   }
   const int n = a.n_cand ? a.n_cand[f] : a.n_fixed;
-  const int C = min(n, a.cache);  // positions [0, C) cached, the rest read from memory
+  // positions [0, C) cached, the rest read from memory (key mode: all, with
+  // the keys' source rows behind the words)
+  const int C = a.keys ? n : min(n, a.cache);
+  uint32_t *krow = a.keys ? wc + n : nullptr;
   const float qn2 = a.qn2[f];
   if (tid == 0 && a.stat_max) atomicMax(a.stat_max, n);
   auto word_at = [&](int i) -> uint32_t { return i < C ? wc[i] : words[i]; };
@@ -503,39 +510,71 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
       vmax = max(vmax, v);
     }
   };
-#pragma unroll
-  for (int u = 0; u < EU; ++u) account(u * BLOCK + tid, ew[u]);
-  for (int base = EU * BLOCK; base < n; base += 8 * blockDim.x) {
-    uint32_t v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = base + u * blockDim.x + tid;
-      v[u] = i < n ? words[i] : kWordNone;
+  uint64_t bmin = kKeyNone;  // key mode: smallest bound
+  if (a.keys) {
+    const uint64_t *kf = a.keys + (int64_t)f * n;
+    for (int i = tid; i < n; i += blockDim.x) {
+      const uint64_t kk = kf[i];
+      account(i, (uint32_t)(kk >> 32));
+      krow[i] = (uint32_t)kk;
     }
+    const uint64_t *bf = a.bounds + (int64_t)f * a.n_bounds;
+    for (int i = tid; i < a.n_bounds; i += blockDim.x) bmin = bf[i] < bmin ? bf[i] : bmin;
+  } else {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) account(base + u * blockDim.x + tid, v[u]);
+    for (int u = 0; u < EU; ++u) account(u * BLOCK + tid, ew[u]);
+    for (int base = EU * BLOCK; base < n; base += 8 * blockDim.x) {
+      uint32_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = base + u * blockDim.x + tid;
+        v[u] = i < n ? words[i] : kWordNone;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) account(base + u * blockDim.x + tid, v[u]);
+    }
   }
   nv_local = wave_sum_i32(nv_local);
   vmin = wave_min_u32(vmin);
   vmax = wave_max_u32(vmax);
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t y = (uint64_t)__shfl_xor((long long)bmin, o);
+    bmin = y < bmin ? y : bmin;
+  }
   if (lane == 0) {
     sh.red_i[w] = nv_local;
     sh.red_u[w] = vmin;
     sh.red_v[w] = vmax;
+    sh.red_k[w] = bmin;
   }
   __syncthreads();
   int nvalid = 0;
   vmin = 0xFFFFFFFFu;
   vmax = 0u;
+  uint64_t bound = kKeyNone;
   for (int i = 0; i < nw; ++i) {
     nvalid += sh.red_i[i];
     vmin = min(vmin, sh.red_u[i]);
     vmax = max(vmax, sh.red_v[i]);
+    bound = sh.red_k[i] < bound ? sh.red_k[i] : bound;
   }
   __syncthreads();
   const int L = a.L;
   const int nsurv = min(L, nvalid);
   const bool rejected = nvalid > L;
+  // key mode: every source row missing from the keys has a word of at least
+  // bw (the smallest of the frame's bounds); what the selection needs must
+  // lie below it, else the frame is deferred to the dense screen
+  const uint32_t bw = (uint32_t)(bound >> 32);
+  // the frame goes to the dense screen instead (key mode, uniform over the
+  // block); every later decision keeps that rule
+  auto defer = [&]() {
+    if (tid == 0) a.defer_list[atomicAdd(a.defer_count, 1)] = f;
+  };
+  if (bound != kKeyNone && !rejected) {
+    defer();
+    return;
+  }
   // The L smallest (word, position) pairs become the survivors and the
   // (L+1)-th, (tw, tpos), the best rejected one: every rejected position has
   // a word above tw, or tw and a position from tpos on.
@@ -707,7 +746,12 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
     if (rejected) tpos = sh.krem;
     __syncthreads();
   }
-  positions_to_rows(a, sh, s_off, s_row, s_len, nslots, nsurv, 0);
+  // key mode: the (L+1)-th word must not exceed what a list may have dropped
+  if (rejected && bound != kKeyNone && tw > bw) {
+    defer();
+    return;
+  }
+  positions_to_rows(a, sh, s_off, s_row, s_len, nslots, nsurv, 0, krow);
   __syncthreads();
   // FP64 rerank of the survivors' rows, sorted by (distance, tie id); row
   // slots past a block's end sort last
@@ -738,14 +782,21 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
       if (!(rejd > tau)) {
         sh.flag = 1;
         sh.word = __float_as_uint(__double2float_ru(tau));
-        if (a.stat_fallback) atomicAdd(a.stat_fallback, 1);
+        // key mode: a band reaching words the lists may have dropped is not
+        // complete in the keys (flag 2: the frame is deferred)
+        if (bound != kKeyNone && sh.word >= bw) sh.flag = 2;
+        else if (a.stat_fallback) atomicAdd(a.stat_fallback, 1);
       }
     }
     if (a.stat_rows) atomicAdd(a.stat_rows, nrow);
   }
   __syncthreads();
   int have = min(nrow, a.m);
-  if (sh.flag) {
+  if (sh.flag == 2) {
+    defer();
+    return;
+  }
+  if (sh.flag == 1) {
     // the band: rejected positions (above tw, or equal to tw past the first
     // take_eq) with a word up to tau_w (>= tw)
     const uint32_t tau_w = sh.word;
@@ -766,7 +817,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
       for (int i = i0; i < i1; ++i)
         if (in_band(word_at(i), i)) sh.sel[pos++] = (uint32_t)i;
       __syncthreads();
-      positions_to_rows(a, sh, s_off, s_row, s_len, nslots, total_band, nrow);
+      positions_to_rows(a, sh, s_off, s_row, s_len, nslots, total_band, nrow, krow);
       __syncthreads();
       rerank_range<BLOCK == 1024>(a, sh, qrow, nrow, nrow + total_band * unit);
       __syncthreads();
@@ -794,7 +845,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
           }
         }
         __syncthreads();
-        positions_to_rows(a, sh, s_off, s_row, s_len, nslots, cnt, kept);
+        positions_to_rows(a, sh, s_off, s_row, s_len, nslots, cnt, kept, krow);
         __syncthreads();
         rerank_range<BLOCK == 1024>(a, sh, qrow, kept, kept + cnt * unit);
         __syncthreads();
@@ -849,12 +900,21 @@ hipError_t launch_select_rerank(SelRerankArgs a, hipStream_t s) {
   if (a.nq <= 0) return hipSuccess;
   const int unit = a.blocks ? kBlockRows : 1;
   if (a.L * unit > kMaxSurvivors || a.L * unit < a.m || a.m > 256) return hipErrorInvalidValue;
+  if (a.frame_list && !a.frame_count) return hipErrorInvalidValue;
   if (a.nslots < 0 || a.nslots > kMaxSlots || (a.nslots > 0 && (!a.slot_off || !a.slot_row)))
     return hipErrorInvalidValue;
   if (a.blocks && ((a.nslots > 0 && (!a.slot_reg || !a.reg_start)) ||
                    (a.nslots == 0 && !a.blk_rows)))
     return hipErrorInvalidValue;
-  a.cache = (int32_t)std::min<int64_t>(a.cap, kWordCache);
+  if (a.keys) {
+    // key mode: every word and its source row cached, no slots, rows
+    if (a.nslots != 0 || a.blocks || !a.bounds || a.n_bounds < 1 || a.cap != a.n_fixed ||
+        2 * (int64_t)a.cap > kWordCache || !a.defer_list || !a.defer_count || a.frame_list)
+      return hipErrorInvalidValue;
+    a.cache = (int32_t)(2 * a.cap);
+  } else {
+    a.cache = (int32_t)std::min<int64_t>(a.cap, kWordCache);
+  }
   // frames with many candidates: the word cache takes most of the LDS, so the
   // block is alone on its compute unit; 1024 threads use all of it
   if (a.cap > kBigFrame)

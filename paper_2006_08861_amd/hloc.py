@@ -421,7 +421,8 @@ class HlocDB:
 
 
 _INFO_KEYS = ("items", "coarse_fallbacks", "fine_fallbacks", "max_blocks", "survivors",
-              "candidates", "narrow_items", "chunked_bands", "band_rows", "rerank_rows")
+              "candidates", "narrow_items", "chunked_bands", "band_rows", "rerank_rows",
+              "coarse_deferred")
 
 
 class Workspace:

@@ -410,6 +410,73 @@ def test_identical_representatives_fall_back(torch_cuda):
         assert info["coarse_fallbacks"] == 5
 
 
+@pytest.mark.parametrize("n_same", [16, 120])
+def test_fused_coarse_equal_means(torch_cuda, n_same):
+    """The fused bf16 coarse product keeps, per frame and lane group, the 6
+    best quads (representatives 4 q .. 4 q + 3), lane group g seeing the
+    quads 4 g .. 4 g + 3 of every 16 representatives. n_same regions (ids
+    0 .. n_same - 1) hold the same rows, so their means tie for the best.
+    With 16 (one tied quad per group) the band of the kept keys settles the
+    tie (coarse fallback); with 120 (7 or 8 tied quads per group, more than
+    it keeps) the keys cannot decide and the frame is deferred to the dense
+    coarse screen. Either way the lowest ids win, as in the fp32 path
+    (bitwise) and the oracle."""
+    rng = np.random.default_rng(11)
+    d, rows = 64, 30
+    base = rng.standard_normal((rows, d)).astype(np.float32)
+    other = (rng.standard_normal((60 * 20, d)) + 2.0).astype(np.float32)
+    feats = np.concatenate([np.tile(base, (n_same, 1)), other])
+    region_of = np.concatenate([np.repeat(np.arange(n_same), rows),
+                                n_same + np.arange(60 * 20) // 20]).astype(np.int32)
+    R = n_same + 60
+    xy = rng.uniform(0, 20, size=(len(feats), 2))
+    q = (base[:5] + 0.01).astype(np.float32)
+    outs = {}
+    for precision in ("fp32", "bf16"):
+        st, info, out = check_all(torch_cuda, feats, xy, region_of, R, q, 6, 3,
+                                  name=f"{n_same} equal means, {precision} screens",
+                                  precision=precision)
+        outs[precision] = out
+        assert st["recall"] == 1.0
+        if precision == "bf16":
+            if n_same == 16:
+                assert info["coarse_fallbacks"] == 5 and info["coarse_deferred"] == 0
+            else:
+                assert info["coarse_deferred"] == 5
+    for key in ("idx", "dist", "tile", "flags", "xy"):
+        assert outs["fp32"][key].tobytes() == outs["bf16"][key].tobytes(), key
+
+
+@pytest.mark.parametrize("n_reg", [5, 1000])
+def test_subspace_labels_bf16(torch_cuda, n_reg):
+    """Label queries through the bf16 screens (the fused coarse product then
+    masks the regions of other labels itself): bitwise the fp32 screens'
+    results, which test_subspace_labels judges against the oracle."""
+    torch = torch_cuda
+    w = workload.make_workload(0, nq=60)
+    R = w.n_regions_total
+    P = 3
+    labels = ((np.arange(R) * P) // R).astype(np.int32)
+    offs = np.arange(0, 61, 5).astype(np.int32)
+    agg = (0.3, 10, 3.0, 20)
+    say(f"[case] labels P={P} n_reg={n_reg}, bf16 vs fp32 screens")
+    db = make_db(w.feats, w.xy, w.region_of, R, agg, mirrors=hloc.MIRROR_BF16)
+    db.set_region_labels(labels, P)
+    res = {}
+    for precision in ("fp32", "bf16"):
+        out = db.query_labels(w.q, w.k, n_reg, P, offs, precision=precision)
+        torch.cuda.synchronize()
+        res[precision] = {key: v.cpu().numpy() for key, v in out.items()}
+    say(f"[ok] info {db.info()}")
+    for key in ("idx", "dist", "tile", "flags", "xy"):
+        assert res["fp32"][key].tobytes() == res["bf16"][key].tobytes(), key
+    got = res["bf16"]["idx"]
+    for p in range(P):
+        g = got[p][got[p] >= 0]
+        assert np.all(labels[w.region_of[g]] == p)
+    db.close()
+
+
 def test_user_representatives_and_relayout(torch_cuda):
     rng, feats, xy, region_of = _random_db(8, 2500, 48, 25)
     reps = rng.standard_normal((25, 48)).astype(np.float32)
