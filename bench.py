@@ -57,7 +57,7 @@ SCREEN_SOURCES = ("paper_2006_08861_amd/csrc/screen_f32.hip",
 # name prefixes of the narrow-item list kernels (their names end in ", false>":
 # not dense) and of the wide-item kernels
 SCREEN_KERNELS = {"fp32": "k_screen_blk<", "bf16": "k_screen_lp<1, ", "fp8": "k_screen_lp<2, "}
-WIDE_KERNELS = {"fp32": "k_screen_wide<", "bf16": "k_screen_wide_lp<1, ", "fp8": "k_screen_wide_lp<2, "}
+WIDE_KERNELS = {"fp32": "k_screen_wide<", "bf16": "k_screen_wide_rs<1, ", "fp8": "k_screen_wide_rs<2, "}
 MIRRORS = {"fp32": lambda h: 0, "bf16": lambda h: h.MIRROR_BF16, "fp8": lambda h: h.MIRROR_FP8}
 DTYPES = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}
 
@@ -976,7 +976,11 @@ def main():
     # fp8 queries screen the representatives in bf16 (bf16 copies are kept
     # beside an fp8 mirror)
     s1_dtype = "bf16" if a.precision == "fp8" else a.precision
-    stage1 = {"kernel": "coarse screen (" + ("wide" if nq >= 512 else "narrow") + " kernel, dense)",
+    # bf16 coarse screens run as the fused product with its key lists (the
+    # frames it defers are timed apart, in the coarse_defer phase)
+    fused = s1_dtype == "bf16" and d % 64 == 0 and d <= 512
+    stage1 = {"kernel": "k_coarse_gemm<NS, false> (bf16 product, kept-quad epilogue)" if fused
+              else "coarse screen (" + ("wide" if nq >= 512 else "narrow") + " kernel, dense)",
               "dtype": s1_dtype, "flops": s1_flops, "avg_launch_ms": coarse_ms, "achieved": s1_tf,
               "peak": MFMA_PEAK_TFLOPS[s1_dtype], "unit": "TFLOP/s",
               "frac": s1_tf / MFMA_PEAK_TFLOPS[s1_dtype]}

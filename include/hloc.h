@@ -57,7 +57,7 @@ typedef enum {
  * HLOC_FP8 from OCP e4m3 copies with one fp32 scale per vector (max |v| / 448;
  * database built with HLOC_MIRROR_FP8; padded length a multiple of 64).
  * Whatever the screen, the returned top-k is decided by an FP64 rerank of the
- * survivors (k + 16 of them behind fp32, 4k behind bf16 and fp8) and the
+ * survivors (k + 16 of them behind fp32, 3k behind bf16 and fp8) and the
  * regions by an FP64 re-score of the best n_regions + 8, each with a
  * certificate: candidates the screen's error bound cannot exclude are
  * re-scored too, so the result is the same for every precision (a looser
@@ -331,6 +331,9 @@ int hloc_ws_replay(hloc_ws *ws, void *stream);
  *                        more than 16 frames)
  *   HLOC_PHASE_SELECT    per-frame select, FP64 rerank, certificate, exact fallback
  *   HLOC_PHASE_AGGREGATE aggregation of each request
+ *   HLOC_PHASE_COARSE_DEFER dense coarse screen and select of the frames the
+ *                        fused coarse product's kept candidates could not
+ *                        decide (bf16 coarse screens)
  * (kernels of a phase dispatched with start/stop events). It covers the
  * default workspace. hloc_profile(db, 1) clears the record and starts
  * recording for later query calls; hloc_profile(db, 0) stops. hloc_profile_read() waits for the device,
@@ -347,7 +350,8 @@ enum {
   HLOC_PHASE_AGGREGATE = 5,
   HLOC_PHASE_SCREEN_WIDE = 6,
   HLOC_PHASE_COARSE_SELECT = 7,
-  HLOC_NUM_PHASES = 8
+  HLOC_PHASE_COARSE_DEFER = 8,
+  HLOC_NUM_PHASES = 9
 };
 int hloc_profile(hloc_db *db, int32_t enable);
 int hloc_profile_read(hloc_db *db, double *ms, int64_t *calls, int32_t n);

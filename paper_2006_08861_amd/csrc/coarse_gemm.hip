@@ -82,6 +82,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int r0 = split * a.reps_per_split;
   const int r1 = min(a.R, r0 + a.reps_per_split);
   const int ntiles = (r1 - r0 + kCgTile - 1) / kCgTile;
+  // tiles in a spread order, tile(t) = t * stride mod ntiles with the stride
+  // coprime to ntiles (about 5/8 of it): the lists see the whole range early
+  // and fill with good quads. In index order the distances along the walk
+  // fall toward a frame's own place, and nearly every quad before it would
+  // be inserted.
+  int stride = 1;
+  if (ntiles > 2) {
+    stride = (ntiles * 5 / 8) | 1;
+    for (;;) {
+      int x = stride, y = ntiles;
+      while (y) {
+        const int t = x % y;
+        x = y;
+        y = t;
+      }
+      if (x == 1) break;
+      stride += 2;
+    }
+  }
 
   const v4u *reps = reinterpret_cast<const v4u *>(a.reps);
   const v4u *frames = reinterpret_cast<const v4u *>(a.frames);
@@ -120,7 +139,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   int plab = 0;
 #define HLOC_CG_FETCH(T)                                                       \
   {                                                                            \
-    const int fb = r0 + (T) * kCgTile;                                         \
+    const int fb = r0 + (int)(((int64_t)(T) * stride) % ntiles) * kCgTile;     \
     _Pragma("unroll") for (int u = 0; u < PER; ++u) {                          \
       const int e = tid + u * 256, row = e / ROWU4, c = e - row * ROWU4;       \
       pv[u] = reps[(int64_t)min(fb + row, r1 - 1) * ROWU4 + c];                \
@@ -170,7 +189,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       acc[1][1] = cg_mfma(a1, bv[1][s], acc[1][1]);
     }
     // epilogue: per (row half h, frame group j) the lane's quad of words
-    const int base = r0 + t * kCgTile;
+    const int base = r0 + (int)(((int64_t)t * stride) % ntiles) * kCgTile;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int row0 = h * kGroup + 4 * g;

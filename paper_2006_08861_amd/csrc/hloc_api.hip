@@ -122,9 +122,9 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
                   "n_regions >= %d to search every region",
                   n_regions, kMaxSurvivors - kRegionMargin, db->R_nonempty, db->R_nonempty);
   }
-  // survivors re-scored in FP64: k + 16 behind the fp32 screen, 4k behind bf16
-  p.kp = std::min(precision == HLOC_FP32 ? k + kOversample : std::max(4 * k, k + kOversample),
-                  kMaxSurvivors);  // 4k behind the bf16 and fp8 screens
+  // survivors re-scored in FP64: k + 16 behind the fp32 screen, 3k behind bf16
+  p.kp = std::min(precision == HLOC_FP32 ? k + kOversample : std::max(3 * k, k + kOversample),
+                  kMaxSurvivors);  // 3k behind the bf16 and fp8 screens
   // bf16 coarse screens (bf16 queries, and fp8 queries when the database
   // keeps bf16 representatives) on a length the fused product supports
   p.coarse_keys = !p.exhaustive && precision != HLOC_FP32 && db->lp[HLOC_BF16].reps &&
@@ -139,7 +139,7 @@ int make_plan(const hloc_db *db, int32_t nq, int32_t k, int32_t n_regions, int32
   const int32_t crow = std::min(db->tile_rows, kWideRows);  // the shorter chunks bound the items
   const int64_t maxch = (db->max_region + crow - 1) / crow;
   const int64_t b1 = (int64_t)nq * p.nr * maxch;
-  const int64_t b2 = db->chunks_fine * (((int64_t)nq + kItemFrames - 1) / kItemFrames);
+  const int64_t b2 = db->chunks_fine * (((int64_t)nq + kListFrames - 1) / kListFrames);
   p.items_bound = std::min(b1, b2);
   if (p.items_bound > INT32_MAX || (int64_t)nq * p.cap2 > ((int64_t)1 << 40))
     return fail(HLOC_EINVAL, "batch too large for one call (nq %d)", nq);
@@ -331,7 +331,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     if (masked)
       HIPCHK(launch_mask_label(as<uint32_t>(ws->cand1), p.nq, db->R, db->rlabel, label,
                                label_frames, s));
-    ph.begin(HLOC_PHASE_COARSE_SELECT);
+    if (!list) ph.begin(HLOC_PHASE_COARSE_SELECT);
     SelRerankArgs ra{};
     ra.cand = as<uint32_t>(ws->cand1);
     ra.cap = db->R;
@@ -409,7 +409,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
     ra.reg_out = regions;
     ra.stat_fallback = misc + 1;
     HIPCHK(launch_select_rerank(ra, s));
-    ph.begin(HLOC_PHASE_COARSE);
+    ph.begin(HLOC_PHASE_COARSE_DEFER);
     CHK(coarse_words(as<int32_t>(ws->cdefer), misc + 10));
   } else if (!p.exhaustive) {
     CHK(coarse_words(nullptr, nullptr));
@@ -418,7 +418,10 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   }
   ph.begin(HLOC_PHASE_SCHED);
   int32_t *cand_off = as<int32_t>(ws->cand_off), *n_cand = as<int32_t>(ws->n_cand);
-  HIPCHK(launch_sched(regions, p.nq, p.nr, db->R, db->reg_start, db->tile_rows,
+  // wide regions: chunks the wide kernel of this screen takes
+  const int32_t wide_rows = fmt && lp_wide_rs(fmt, db->dp) ? kWideRowsRs
+                                                            : std::min(db->tile_rows, kWideRows);
+  HIPCHK(launch_sched(regions, p.nq, p.nr, db->R, db->reg_start, db->tile_rows, wide_rows,
                       as<int32_t>(ws->rcount), as<int32_t>(ws->rfill), as<int32_t>(ws->vord),
                       as<int32_t>(ws->rq_off),
                       as<int32_t>(ws->item_off), cand_off, as<int32_t>(ws->slot_row), n_cand,

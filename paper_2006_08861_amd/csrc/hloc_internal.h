@@ -40,8 +40,10 @@ inline hipError_t launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t lds, h
 
 constexpr int kGroup = 16;          // frames per MFMA column block of the screen
 constexpr int kLdsPerCu = 160 * 1024;  // LDS of one compute unit (gfx950)
-constexpr int kItemFrames = 256;    // frames per screen work item (wide items)
+constexpr int kItemFrames = 256;    // frames per dense work item of the wide kernels
+constexpr int kListFrames = 1024;   // frames per wide list item (rows re-read once per this many)
 constexpr int kWideRows = 64;       // rows per wide work item (the LDS stage of the wide kernels)
+constexpr int kWideRowsRs = 128;    // rows per wide item of the register-row kernels (bf16, fp8)
 constexpr int kMaxItemRows = 128;   // rows per narrow work item at most
 constexpr int kBlock = 256;         // threads per block of most kernels
 constexpr int kSelectLds = 4096;    // keys held in LDS by the select kernel
@@ -61,7 +63,7 @@ inline int next_pow2_host(int v) {
 
 // One unit of fine-screen work: rows [row_begin, row_begin + nrows) of one
 // region (absolute row indices; chunk_row = offset of the chunk inside its
-// region) against frames rq[q0 .. q0 + gq), gq <= kItemFrames.
+// region) against frames rq[q0 .. q0 + gq), gq <= kListFrames.
 struct Item {
   int32_t row_begin;
   int32_t chunk_row;
@@ -103,7 +105,7 @@ struct ScreenArgs {
   const int32_t *frame_count;
 };
 
-// Work item of the wide screens: a chunk of rows against up to kItemFrames
+// Work item of the wide screens: a chunk of rows against up to kListFrames
 // frames, either list item it of the narrow-then-wide order, or dense item it
 // (chunk it % nchunks of all rows against frames from (it / nchunks) *
 // kItemFrames).
@@ -180,6 +182,9 @@ hipError_t launch_screen_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipS
 hipError_t launch_screen_wide_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, int32_t num_cu,
                                  hipStream_t s);
 bool lp_screen_supports(int32_t fmt, int32_t dp);
+// The wide list items of this low-precision screen hold kWideRowsRs rows
+// (the register-row kernel) instead of min(T, kWideRows).
+bool lp_wide_rs(int32_t fmt, int32_t dp);
 // Low-precision copy of n rows (fp8: with a scale per row); maxima of the
 // per-row norms of the rounding error and of the rounded row.
 hipError_t launch_rows_to_lp(int32_t fmt, const float *src, int64_t n, int32_t dp, void *dst,
@@ -202,7 +207,8 @@ hipError_t launch_broadcast_ids(const int32_t *ids, int32_t nr, int32_t nq, int3
 // row; n_cand[f] the frame's block count, n_rows[f] its candidate rows. An rq
 // entry is (frame, cand_off of the region in that frame).
 hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t R,
-                        const int64_t *reg_start, int32_t T, int32_t *rcount, int32_t *rfill,
+                        const int64_t *reg_start, int32_t T, int32_t W, int32_t *rcount,
+                        int32_t *rfill,
                         int32_t *vord, int32_t *rq_off, int32_t *item_off, int32_t *cand_off,
                         int32_t *slot_row, int32_t *n_cand, int32_t *n_rows, int32_t *n_items,
                         int2 *rq, Item *items, hipStream_t s);

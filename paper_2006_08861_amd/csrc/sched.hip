@@ -1,14 +1,14 @@
 // Scheduling of the fine screen: the frame -> regions lists chosen by the
 // coarse stage are inverted into region -> frames lists, and every touched
-// region is cut into chunks of T rows (at most kWideRows for wide regions)
-// crossed with groups of up to kItemFrames frames. This takes the place of the paper's
+// region is cut into chunks of T rows (W rows for wide regions)
+// crossed with groups of up to kListFrames frames. This takes the place of the paper's
 // one-stream-per-subspace launch (Section 3.1): uneven regions become many
 // equal-sized work items for persistent screen kernels, and every count lives
 // in device memory (no host round trip).
 //
 // Items come in two classes. A region kept by at most kGroup frames gives
 // narrow items (one MFMA column block of frames); a region kept by more
-// frames gives wide items of up to kItemFrames frames, screened by a kernel
+// frames gives wide items of up to kListFrames frames, screened by a kernel
 // that reads each row once for all of them. Narrow items are numbered first:
 // items [0, n_items[4]) are narrow, [n_items[4], n_items[0]) wide. Regions
 // are laid out in that order (narrow regions by id, then wide regions by id)
@@ -45,30 +45,30 @@ __device__ __forceinline__ int owner_slot(const int32_t *iof, int R, int t) {
   return lo;
 }
 
-// Rows per chunk of a region kept by g frames: T for narrow regions, at most
-// kWideRows (the wide kernels' LDS stage) for wide ones.
-__device__ __forceinline__ int chunk_rows(int g, int T) {
-  return g <= kGroup ? T : min(T, kWideRows);
+// Rows per chunk of a region kept by g frames: T for narrow regions, W (what
+// the wide kernel of the screen takes) for wide ones.
+__device__ __forceinline__ int chunk_rows(int g, int T, int W) {
+  return g <= kGroup ? T : W;
 }
 
-__device__ __forceinline__ int items_of(int g, int64_t rows, int T) {
-  const int C = chunk_rows(g, T);
-  return g > 0 ? (int)((rows + C - 1) / C) * ((g + kItemFrames - 1) / kItemFrames) : 0;
+__device__ __forceinline__ int items_of(int g, int64_t rows, int T, int W) {
+  const int C = chunk_rows(g, T, W);
+  return g > 0 ? (int)((rows + C - 1) / C) * ((g + kListFrames - 1) / kListFrames) : 0;
 }
 
 // Work item t of a region whose rows are [r0, r0 + rows) and whose frames are
 // rq[q_begin, q_end): chunk-major, frame groups inner, so consecutive items
 // re-read the same rows.
 __device__ __forceinline__ Item make_item(int t, int item_begin, int q_begin, int q_end, int r0,
-                                          int rows, int T) {
-  const int g = q_end - q_begin, ngr = (g + kItemFrames - 1) / kItemFrames;
-  const int C = chunk_rows(g, T);
+                                          int rows, int T, int W) {
+  const int g = q_end - q_begin, ngr = (g + kListFrames - 1) / kListFrames;
+  const int C = chunk_rows(g, T, W);
   const int local = t - item_begin, c = local / ngr, b = local - c * ngr;
   Item it;
   it.row_begin = r0 + c * C;
   it.chunk_row = c * C;
-  it.q0 = q_begin + b * kItemFrames;
-  it.nrows_gq = (min(C, rows - c * C) << 16) | min(kItemFrames, g - b * kItemFrames);
+  it.q0 = q_begin + b * kListFrames;
+  it.nrows_gq = (min(C, rows - c * C) << 16) | min(kListFrames, g - b * kListFrames);
   return it;
 }
 
@@ -80,7 +80,7 @@ __device__ __forceinline__ Item make_item(int t, int item_begin, int q_begin, in
 // reg_start: first row of each region (R + 1 entries, device or LDS).
 template <class RS>
 __device__ void sched_scan(const int32_t *count, int R, const RS *__restrict__ reg_start,
-                           int T, int32_t *rq_off, int32_t *vord, int32_t *iof,
+                           int T, int W, int32_t *rq_off, int32_t *vord, int32_t *iof,
                            int32_t *n_items, int32_t *fill, int *s_red) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int per = (R + nt - 1) / nt;
@@ -89,7 +89,7 @@ __device__ void sched_scan(const int32_t *count, int R, const RS *__restrict__ r
   int v[4] = {0, 0, 0, 0};
   for (int r = r0; r < r1; ++r) {
     const int g = count[r];
-    const int m = items_of(g, reg_start[r + 1] - reg_start[r], T);
+    const int m = items_of(g, reg_start[r + 1] - reg_start[r], T, W);
     v[0] += g;
     if (g <= kGroup) {
       v[1] += m;
@@ -125,7 +125,7 @@ __device__ void sched_scan(const int32_t *count, int R, const RS *__restrict__ r
   int pa = inc[0] - v[0], pbn = inc[1] - v[1], pbw = inc[2] - v[2], pcn = inc[3] - v[3];
   for (int r = r0; r < r1; ++r) {
     const int g = count[r];
-    const int m = items_of(g, reg_start[r + 1] - reg_start[r], T);
+    const int m = items_of(g, reg_start[r + 1] - reg_start[r], T, W);
     rq_off[r] = pa;
     if (fill) fill[r] = pa;
     pa += g;
@@ -238,12 +238,12 @@ __global__ void k_sched_count(const int32_t *__restrict__ regions, int nq, int n
 
 // One block: the scans of sched_scan over the region counts; clears rfill.
 __global__ __launch_bounds__(1024) void k_sched_scan(const int32_t *__restrict__ rcount, int R,
-                                                     const int64_t *__restrict__ reg_start, int T,
+                                                     const int64_t *__restrict__ reg_start, int T, int W,
                                                      int32_t *rq_off, int32_t *vord,
                                                      int32_t *iof, int32_t *n_items,
                                                      int32_t *rfill) {
   __shared__ int s_red[72];
-  sched_scan(rcount, R, reg_start, T, rq_off, vord, iof, n_items, nullptr, s_red);
+  sched_scan(rcount, R, reg_start, T, W, rq_off, vord, iof, n_items, nullptr, s_red);
   for (int r = threadIdx.x; r < R; r += blockDim.x) rfill[r] = 0;
 }
 
@@ -281,13 +281,14 @@ __global__ void k_sched_scatter(const int32_t *__restrict__ regions, int nq, int
 __global__ void k_sched_items(int R, const int32_t *__restrict__ vord,
                               const int32_t *__restrict__ iof,
                               const int32_t *__restrict__ rq_off,
-                              const int64_t *__restrict__ reg_start, int T, Item *items) {
+                              const int64_t *__restrict__ reg_start, int T, int W, Item *items) {
   const int n = iof[R];
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     const int k = owner_slot(iof, R, t);
     const int r = vord[k];
     const int64_t r0 = reg_start[r];
-    items[t] = make_item(t, iof[k], rq_off[r], rq_off[r + 1], (int)r0, (int)(reg_start[r + 1] - r0), T);
+    items[t] = make_item(t, iof[k], rq_off[r], rq_off[r + 1], (int)r0, (int)(reg_start[r + 1] - r0), T,
+                         W);
   }
 }
 
@@ -307,7 +308,7 @@ size_t fused_lds_bytes(int R) { return (size_t)(4 * R + 2) * sizeof(int); }
 
 __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict__ regions, int nq,
                                                       int nr, int R,
-                                                      const int64_t *__restrict__ reg_start, int T,
+                                                      const int64_t *__restrict__ reg_start, int T, int W,
                                                       int32_t *rq_off, int32_t *cand_off,
                                                       int32_t *slot_row, int32_t *n_cand,
                                                       int32_t *n_rows, int32_t *n_items, int2 *rq,
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
   }
   __syncthreads();
   // counts -> fill pointers (each thread reads and rewrites only its own range)
-  sched_scan(s_fill, R, s_rs, T, rq_off, s_vord, s_iof, n_items, s_fill, s_red);
+  sched_scan(s_fill, R, s_rs, T, W, rq_off, s_vord, s_iof, n_items, s_fill, s_red);
   __syncthreads();
   if (regs) {
     if (tid < nq) {
@@ -407,7 +408,7 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
     const int k = owner_slot(s_iof, R, t);
     const int rr = s_vord[k];
     const int q0 = rr > 0 ? s_fill[rr - 1] : 0;
-    items[t] = make_item(t, s_iof[k], q0, s_fill[rr], s_rs[rr], s_rs[rr + 1] - s_rs[rr], T);
+    items[t] = make_item(t, s_iof[k], q0, s_fill[rr], s_rs[rr], s_rs[rr + 1] - s_rs[rr], T, W);
   }
 }
 
@@ -418,14 +419,15 @@ hipError_t prepare_sched_kernels() {
 }
 
 hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t R,
-                        const int64_t *reg_start, int32_t T, int32_t *rcount, int32_t *rfill,
+                        const int64_t *reg_start, int32_t T, int32_t W, int32_t *rcount,
+                        int32_t *rfill,
                         int32_t *vord, int32_t *rq_off, int32_t *item_off, int32_t *cand_off,
                         int32_t *slot_row, int32_t *n_cand, int32_t *n_rows, int32_t *n_items,
                         int2 *rq, Item *items, hipStream_t s) {
   const int64_t pairs = (int64_t)nq * nr;
   if (R <= kFusedMaxR && pairs <= kFusedMaxPairs) {
     return launch_kernel(k_sched_fused, dim3(1), dim3(1024), (uint32_t)fused_lds_bytes(R), s,
-                         regions, nq, nr, R, reg_start, T, rq_off, cand_off, slot_row, n_cand,
+                         regions, nq, nr, R, reg_start, T, W, rq_off, cand_off, slot_row, n_cand,
                          n_rows, n_items, rq, items);
   }
   hipError_t e = launch_fill_i32(rcount, R, 0, s);
@@ -441,7 +443,7 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
                              n_rows);
     if (e != hipSuccess) return e;
   }
-  if ((e = launch_kernel(k_sched_scan, dim3(1), dim3(1024), 0, s, rcount, R, reg_start, T,
+  if ((e = launch_kernel(k_sched_scan, dim3(1), dim3(1024), 0, s, rcount, R, reg_start, T, W,
                          rq_off, vord, item_off, n_items, rfill)) != hipSuccess)
     return e;
   if (pairs > 0) {
@@ -453,7 +455,7 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
     if (e != hipSuccess) return e;
   }
   return launch_kernel(k_sched_items, dim3(1024), dim3(256), 0, s, R, vord, item_off, rq_off,
-                       reg_start, T, items);
+                       reg_start, T, W, items);
 }
 
 }  // namespace hloc

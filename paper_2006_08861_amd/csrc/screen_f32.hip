@@ -3,8 +3,8 @@
 // Squared L2 distance of each frame to each candidate row, written as
 // |q|^2 + |d|^2 - 2 q.d with the dot products on the matrix cores (the
 // comparison of a frame with every row of a subspace, Section 3.1 /
-// Algorithm 1). A block of four waves takes one work item: up to kItemFrames
-// frames, 16 at a time (one MFMA column block), against a chunk of rows; each
+// Algorithm 1). A block of four waves takes one work item: up to kListFrames
+// frames (kItemFrames in dense mode), 16 at a time (one MFMA column block), against a chunk of rows; each
 // wave walks 16-row blocks of the chunk. Lane l holds row (l % 16) and the k-slice
 // 4 * (l / 16) + 16 s + {0..3}, so one 16-byte load feeds four MFMAs and the
 // 16 rows of a block are read as 64-byte runs. The frame operand uses the
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(256) void k_screen_blk(ScreenArgs a) {
 }
 
 // Wide list items: a 64-row chunk of a region kept by more than kGroup frames,
-// against up to kItemFrames of them. The block stages the chunk's rows and
+// against up to kListFrames of them. The block stages the chunk's rows and
 // norms in LDS once; each wave takes a 16-frame group at a time, holds that
 // group's frame operand in registers and runs it against the four 16-row
 // blocks read from LDS. Every row is read from memory once per item and every

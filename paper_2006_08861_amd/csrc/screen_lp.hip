@@ -445,35 +445,44 @@ __global__ __launch_bounds__(256) void k_screen_wide_lp(ScreenArgs a) {
 
 // Wide list items with the rows held in registers and the frames staged
 // through LDS, 16 at a time, double-buffered (wide items of the bf16 and fp8
-// screens when the padded length gives an even NS).
-// A block of two waves takes one wide item (a chunk of up to 64 rows of one
-// region against its gq frames). Wave w holds rows 32 w .. 32 w + 31 of the
-// chunk as the MFMA A operand (two 16-row tiles over the whole padded
+// screens when the padded length gives NS % 4 == 0).
+// A block of four waves takes one wide item (a chunk of up to 128 rows of
+// one region against its gq frames). Wave w holds rows 32 w .. 32 w + 31 of
+// the chunk as the MFMA A operand (two 16-row tiles over the whole padded
 // length), so each row is read from memory once per item and every LDS read
 // of a frame piece feeds both row tiles (two MFMAs for bf16, four for fp8).
 // While frame group k is multiplied, group k + 1 is read into registers; it
 // is written to the other buffer after the multiply. The epilogue takes, per
 // frame and row tile, the smallest of the tile's 16 screen words (the block
 // word) and stores it at the frame's block position.
+// Items are dealt to the XCDs in contiguous runs (blocks go to the eight
+// XCDs round-robin): the chunks of one region, which stage the same frames,
+// run on one XCD and find them in its L2.
 template <int FMT, int NS>
-__global__ __launch_bounds__(128) void k_screen_wide_rs(ScreenArgs a) {
+__global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
   constexpr int ROWU4 = 4 * NS;                 // 16-byte pieces per row
   constexpr int LDF = ROWU4 + 1;                // padded frame row in LDS
-  constexpr int TPF = 8;                        // threads per staged frame
+  constexpr int TPF = 256 / kGroup;             // threads staging one frame
   static_assert(ROWU4 % TPF == 0, "whole pieces per thread");
   constexpr int PERF = ROWU4 / TPF;             // pieces per thread per group
   extern __shared__ v4u s_fr[];                 // 2 x kGroup x LDF
-  __shared__ int2 s_e[2][kGroup];
-  __shared__ float s_qn[2][kGroup], s_qs[2][kGroup];
+  // the item's frames: rq entries, squared norms, scales (read once per item)
+  __shared__ int2 s_e[kListFrames];
+  __shared__ float s_qn[kListFrames], s_qs[kListFrames];
   const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
   const int i = lane & 15, g = lane >> 4;
   const v4u *rows = static_cast<const v4u *>(a.rows_lp);
   const v4u *frames = static_cast<const v4u *>(a.q_lp);
   int lo;
   const int hi = wide_range(a, &lo);
+  // this block's run of items: XCD x = b % 8 owns [x span, (x + 1) span)
+  constexpr int kXcd = 8;
+  const int nb = gridDim.x / kXcd, x = blockIdx.x % kXcd, jb = blockIdx.x / kXcd;
+  const int span = (hi - lo + kXcd - 1) / kXcd;
+  const int it0 = lo + x * span, it1 = min(hi, it0 + span);
   // staging: thread t loads pieces (t % TPF) + TPF u of frame t / TPF
   const int sj = tid / TPF, sc = tid % TPF;
-  for (int it = lo + blockIdx.x; it < hi; it += gridDim.x) {
+  for (int it = it0 + jb; it < it1; it += nb) {
     const WideItem wi = wide_item(a, it);
     const int nrows = wi.nrows, gq = wi.gq;
     // the wave's rows (clamped to the chunk's last row; words of rows past
@@ -496,30 +505,38 @@ __global__ __launch_bounds__(128) void k_screen_wide_rs(ScreenArgs a) {
     }
     const int ng = (gq + kGroup - 1) / kGroup;
     v4u pv[PERF];
-    int2 pe = make_int2(0, 0);
-    float pqn = 0.f, pqs = 1.f;
 #define HLOC_RS_FETCH(K)                                                         \
   {                                                                              \
-    const int jj = (K) * kGroup + sj;                                            \
-    pe = jj < gq ? a.rq[wi.q0 + jj] : make_int2(0, 0);                           \
-    const v4u *fp = frames + (int64_t)pe.x * ROWU4 + sc;                         \
+    const v4u *fp = frames + (int64_t)s_e[(K) * kGroup + sj].x * ROWU4 + sc;     \
     _Pragma("unroll") for (int u = 0; u < PERF; ++u) pv[u] = fp[TPF * u];        \
-    if (sc == 0) {                                                               \
-      pqn = a.qn2[pe.x];                                                         \
-      pqs = FMT == HLOC_FP8 ? a.q_scale[pe.x] : 1.f;                             \
-    }                                                                            \
   }
 #define HLOC_RS_STAGE(BUF)                                                       \
   {                                                                              \
     _Pragma("unroll") for (int u = 0; u < PERF; ++u)                             \
         s_fr[((BUF) * kGroup + sj) * LDF + sc + TPF * u] = pv[u];                \
-    if (sc == 0) {                                                               \
-      s_e[BUF][sj] = pe;                                                         \
-      s_qn[BUF][sj] = pqn;                                                       \
-      s_qs[BUF][sj] = pqs;                                                       \
-    }                                                                            \
   }
-    __syncthreads();  // the previous item's last group is no longer read
+    __syncthreads();  // the previous item's frames are no longer read
+    // the item's frame entries (frames past gq: frame 0, never stored),
+    // all requested at once
+    {
+      constexpr int U = kListFrames / 256;
+      int2 e[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = u * 256 + tid;
+        e[u] = j < gq ? a.rq[wi.q0 + j] : make_int2(0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = u * 256 + tid;
+        if (j < ng * kGroup) {
+          s_e[j] = e[u];
+          s_qn[j] = a.qn2[e[u].x];
+          s_qs[j] = FMT == HLOC_FP8 ? a.q_scale[e[u].x] : 1.f;
+        }
+      }
+    }
+    __syncthreads();
     HLOC_RS_FETCH(0)
     HLOC_RS_STAGE(0)
     __syncthreads();
@@ -534,17 +551,15 @@ __global__ __launch_bounds__(128) void k_screen_wide_rs(ScreenArgs a) {
         acc[0] = lp_mfma_v<FMT>(av[0][s], b, acc[0]);
         acc[1] = lp_mfma_v<FMT>(av[1][s], b, acc[1]);
       }
-      const int2 e = s_e[buf][i];
-      const float qn = s_qn[buf][i], qs = s_qs[buf][i];
+      const int2 e = s_e[k * kGroup + i];
+      const float qn = s_qn[k * kGroup + i], qs = s_qs[k * kGroup + i];
       const bool fok = k * kGroup + i < gq;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         if (32 * w + 16 * h >= nrows) continue;  // (uniform over the wave)
         uint32_t wd[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          wd[r] = __builtin_isinf(rn[h][r]) ? 0xFFFFFFFFu
-                                            : lp_word<FMT>(qn, rn[h][r], acc[h][r], qs, rs[h][r]);
+        for (int r = 0; r < 4; ++r) wd[r] = lp_word<FMT>(qn, rn[h][r], acc[h][r], qs, rs[h][r]);
         const uint32_t m = block_min16(wd);
         if (fok && g == 0)
           a.cand[(int64_t)e.x * a.cap + e.y + wi.chunk_row / kBlockRows + 2 * w + h] = m;
@@ -566,7 +581,7 @@ template <int NS>
 constexpr size_t wide_rs_lds_bytes() {
   return (size_t)2 * kGroup * (4 * NS + 1) * sizeof(v4u);
 }
-constexpr int kRsBlocksPerCu = 4;  // blocks per compute unit if the occupancy query fails
+constexpr int kRsBlocksPerCu = 2;  // blocks per compute unit if the occupancy query fails
 
 // Pieces per lane for a padded length: bf16 rows take dp / 32, fp8 rows
 // dp / 64 (0: no kernel for this length).
@@ -583,25 +598,30 @@ int lp_pieces(int32_t fmt, int32_t dp) {
 
 bool lp_screen_supports(int32_t fmt, int32_t dp) { return lp_pieces(fmt, dp) > 0; }
 
+bool lp_wide_rs(int32_t fmt, int32_t dp) {
+  const int ns = lp_pieces(fmt, dp);
+  return ns > 0 && ns % 4 == 0;
+}
+
 template <int FMT, int NS>
 hipError_t launch_lp_ns(const ScreenArgs &a, int32_t grid, int32_t wide_cu, hipStream_t s) {
-  if constexpr (NS % 2 == 0) {
+  if constexpr (NS % 4 == 0) {
     if (wide_cu > 0 && !a.dense) {
       // as many blocks as the compute units hold at once (registers and LDS)
       static int per_cu = 0;
       if (per_cu == 0) {
         int occ = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &occ, reinterpret_cast<const void *>(&k_screen_wide_rs<FMT, NS>), 128,
+                &occ, reinterpret_cast<const void *>(&k_screen_wide_rs<FMT, NS>), 256,
                 wide_rs_lds_bytes<NS>()) != hipSuccess || occ < 1) {
           (void)hipGetLastError();
           occ = kRsBlocksPerCu;
         }
         per_cu = occ;
       }
-      const int64_t resident = (int64_t)wide_cu * per_cu;
-      return launch_kernel(k_screen_wide_rs<FMT, NS>,
-                           dim3((int32_t)std::min<int64_t>(grid, resident)), dim3(128),
+      // every block resident at once, a multiple of the eight XCDs
+      const int64_t resident = std::max<int64_t>(8, (int64_t)wide_cu * per_cu / 8 * 8);
+      return launch_kernel(k_screen_wide_rs<FMT, NS>, dim3((int32_t)resident), dim3(256),
                            (uint32_t)wide_rs_lds_bytes<NS>(), s, a);
     }
   }

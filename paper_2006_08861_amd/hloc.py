@@ -396,7 +396,7 @@ class HlocDB:
         return dict(t, source="tuned")
 
     PHASES = ("prep", "coarse", "sched", "screen", "select", "aggregate", "screen_wide",
-              "coarse_select")
+              "coarse_select", "coarse_defer")
 
     def profile(self, enable: bool = True):
         """Start (clearing) or stop the per-phase event record."""
