@@ -419,9 +419,10 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   ph.begin(HLOC_PHASE_SCHED);
   int32_t *cand_off = as<int32_t>(ws->cand_off), *n_cand = as<int32_t>(ws->n_cand);
   // wide regions: chunks the wide kernel of this screen takes
-  const int32_t wide_rows = fmt && lp_wide_rs(fmt, db->dp) ? kWideRowsRs
-                                                            : std::min(db->tile_rows, kWideRows);
+  const bool rs = fmt && lp_wide_rs(fmt, db->dp);
+  const int32_t wide_rows = rs ? kWideRowsRs : std::min(db->tile_rows, kWideRows);
   HIPCHK(launch_sched(regions, p.nq, p.nr, db->R, db->reg_start, db->tile_rows, wide_rows,
+                      rs ? kWideRunsRs : 1,
                       as<int32_t>(ws->rcount), as<int32_t>(ws->rfill), as<int32_t>(ws->vord),
                       as<int32_t>(ws->rq_off),
                       as<int32_t>(ws->item_off), cand_off, as<int32_t>(ws->slot_row), n_cand,

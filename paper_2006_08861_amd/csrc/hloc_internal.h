@@ -43,7 +43,9 @@ constexpr int kLdsPerCu = 160 * 1024;  // LDS of one compute unit (gfx950)
 constexpr int kItemFrames = 256;    // frames per dense work item of the wide kernels
 constexpr int kListFrames = 1024;   // frames per wide list item (rows re-read once per this many)
 constexpr int kWideRows = 64;       // rows per wide work item (the LDS stage of the wide kernels)
-constexpr int kWideRowsRs = 128;    // rows per wide item of the register-row kernels (bf16, fp8)
+constexpr int kWideRowsRs = 128;    // rows per run of the register-row kernels (bf16, fp8)
+constexpr int kWideRunsRs = 16;     // runs of kWideRowsRs rows per wide item at most
+constexpr int kWideSteps = 32;      // (run, 16-frame group) steps a multi-run wide item aims at
 constexpr int kMaxItemRows = 128;   // rows per narrow work item at most
 constexpr int kBlock = 256;         // threads per block of most kernels
 constexpr int kSelectLds = 4096;    // keys held in LDS by the select kernel
@@ -182,8 +184,9 @@ hipError_t launch_screen_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, hipS
 hipError_t launch_screen_wide_lp(int32_t fmt, const ScreenArgs &a, int32_t grid, int32_t num_cu,
                                  hipStream_t s);
 bool lp_screen_supports(int32_t fmt, int32_t dp);
-// The wide list items of this low-precision screen hold kWideRowsRs rows
-// (the register-row kernel) instead of min(T, kWideRows).
+// The wide list items of this low-precision screen go to the register-row
+// kernel: up to kWideRunsRs runs of kWideRowsRs rows each, instead of
+// min(T, kWideRows) rows.
 bool lp_wide_rs(int32_t fmt, int32_t dp);
 // Low-precision copy of n rows (fp8: with a scale per row); maxima of the
 // per-row norms of the rounding error and of the rounded row.
@@ -205,9 +208,11 @@ hipError_t launch_broadcast_ids(const int32_t *ids, int32_t nr, int32_t nq, int3
 // frame f and kept-region slot j: cand_off[f][j] the first of the slot's
 // 16-row blocks in the frame's block list, slot_row[f][j] the region's first
 // row; n_cand[f] the frame's block count, n_rows[f] its candidate rows. An rq
-// entry is (frame, cand_off of the region in that frame).
+// entry is (frame, cand_off of the region in that frame). Narrow chunks hold
+// T rows; wide chunks W rows, or with WM > 1 up to WM runs of W rows.
 hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t R,
-                        const int64_t *reg_start, int32_t T, int32_t W, int32_t *rcount,
+                        const int64_t *reg_start, int32_t T, int32_t W, int32_t WM,
+                        int32_t *rcount,
                         int32_t *rfill,
                         int32_t *vord, int32_t *rq_off, int32_t *item_off, int32_t *cand_off,
                         int32_t *slot_row, int32_t *n_cand, int32_t *n_rows, int32_t *n_items,

@@ -1,7 +1,7 @@
 // Scheduling of the fine screen: the frame -> regions lists chosen by the
 // coarse stage are inverted into region -> frames lists, and every touched
-// region is cut into chunks of T rows (W rows for wide regions)
-// crossed with groups of up to kListFrames frames. This takes the place of the paper's
+// region is cut into chunks of T rows (for wide regions W rows, or a few runs
+// of W rows) crossed with groups of up to kListFrames frames. This takes the place of the paper's
 // one-stream-per-subspace launch (Section 3.1): uneven regions become many
 // equal-sized work items for persistent screen kernels, and every count lives
 // in device memory (no host round trip).
@@ -46,13 +46,19 @@ __device__ __forceinline__ int owner_slot(const int32_t *iof, int R, int t) {
 }
 
 // Rows per chunk of a region kept by g frames: T for narrow regions, W (what
-// the wide kernel of the screen takes) for wide ones.
-__device__ __forceinline__ int chunk_rows(int g, int T, int W) {
-  return g <= kGroup ? T : W;
+// the wide kernel of the screen takes) for wide ones. With WM > 1 a wide
+// chunk is up to WM runs of W rows (the register-row kernels take such an
+// item run by run with its frames staged once), as many as bring the item to
+// about kWideSteps (W rows, kGroup frames) steps: items of few frame groups
+// then carry enough work to hide their set-up.
+__device__ __forceinline__ int chunk_rows(int g, int T, int W, int WM) {
+  if (g <= kGroup) return T;
+  const int groups = (min(g, kListFrames) + kGroup - 1) / kGroup;
+  return W * max(1, min(WM, (kWideSteps + groups - 1) / groups));
 }
 
-__device__ __forceinline__ int items_of(int g, int64_t rows, int T, int W) {
-  const int C = chunk_rows(g, T, W);
+__device__ __forceinline__ int items_of(int g, int64_t rows, int T, int W, int WM) {
+  const int C = chunk_rows(g, T, W, WM);
   return g > 0 ? (int)((rows + C - 1) / C) * ((g + kListFrames - 1) / kListFrames) : 0;
 }
 
@@ -60,9 +66,9 @@ __device__ __forceinline__ int items_of(int g, int64_t rows, int T, int W) {
 // rq[q_begin, q_end): chunk-major, frame groups inner, so consecutive items
 // re-read the same rows.
 __device__ __forceinline__ Item make_item(int t, int item_begin, int q_begin, int q_end, int r0,
-                                          int rows, int T, int W) {
+                                          int rows, int T, int W, int WM) {
   const int g = q_end - q_begin, ngr = (g + kListFrames - 1) / kListFrames;
-  const int C = chunk_rows(g, T, W);
+  const int C = chunk_rows(g, T, W, WM);
   const int local = t - item_begin, c = local / ngr, b = local - c * ngr;
   Item it;
   it.row_begin = r0 + c * C;
@@ -80,7 +86,7 @@ __device__ __forceinline__ Item make_item(int t, int item_begin, int q_begin, in
 // reg_start: first row of each region (R + 1 entries, device or LDS).
 template <class RS>
 __device__ void sched_scan(const int32_t *count, int R, const RS *__restrict__ reg_start,
-                           int T, int W, int32_t *rq_off, int32_t *vord, int32_t *iof,
+                           int T, int W, int WM, int32_t *rq_off, int32_t *vord, int32_t *iof,
                            int32_t *n_items, int32_t *fill, int *s_red) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int per = (R + nt - 1) / nt;
@@ -89,7 +95,7 @@ __device__ void sched_scan(const int32_t *count, int R, const RS *__restrict__ r
   int v[4] = {0, 0, 0, 0};
   for (int r = r0; r < r1; ++r) {
     const int g = count[r];
-    const int m = items_of(g, reg_start[r + 1] - reg_start[r], T, W);
+    const int m = items_of(g, reg_start[r + 1] - reg_start[r], T, W, WM);
     v[0] += g;
     if (g <= kGroup) {
       v[1] += m;
@@ -125,7 +131,7 @@ __device__ void sched_scan(const int32_t *count, int R, const RS *__restrict__ r
   int pa = inc[0] - v[0], pbn = inc[1] - v[1], pbw = inc[2] - v[2], pcn = inc[3] - v[3];
   for (int r = r0; r < r1; ++r) {
     const int g = count[r];
-    const int m = items_of(g, reg_start[r + 1] - reg_start[r], T, W);
+    const int m = items_of(g, reg_start[r + 1] - reg_start[r], T, W, WM);
     rq_off[r] = pa;
     if (fill) fill[r] = pa;
     pa += g;
@@ -238,12 +244,12 @@ __global__ void k_sched_count(const int32_t *__restrict__ regions, int nq, int n
 
 // One block: the scans of sched_scan over the region counts; clears rfill.
 __global__ __launch_bounds__(1024) void k_sched_scan(const int32_t *__restrict__ rcount, int R,
-                                                     const int64_t *__restrict__ reg_start, int T, int W,
+                                                     const int64_t *__restrict__ reg_start, int T, int W, int WM,
                                                      int32_t *rq_off, int32_t *vord,
                                                      int32_t *iof, int32_t *n_items,
                                                      int32_t *rfill) {
   __shared__ int s_red[72];
-  sched_scan(rcount, R, reg_start, T, W, rq_off, vord, iof, n_items, nullptr, s_red);
+  sched_scan(rcount, R, reg_start, T, W, WM, rq_off, vord, iof, n_items, nullptr, s_red);
   for (int r = threadIdx.x; r < R; r += blockDim.x) rfill[r] = 0;
 }
 
@@ -281,14 +287,14 @@ __global__ void k_sched_scatter(const int32_t *__restrict__ regions, int nq, int
 __global__ void k_sched_items(int R, const int32_t *__restrict__ vord,
                               const int32_t *__restrict__ iof,
                               const int32_t *__restrict__ rq_off,
-                              const int64_t *__restrict__ reg_start, int T, int W, Item *items) {
+                              const int64_t *__restrict__ reg_start, int T, int W, int WM, Item *items) {
   const int n = iof[R];
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     const int k = owner_slot(iof, R, t);
     const int r = vord[k];
     const int64_t r0 = reg_start[r];
     items[t] = make_item(t, iof[k], rq_off[r], rq_off[r + 1], (int)r0, (int)(reg_start[r + 1] - r0), T,
-                         W);
+                         W, WM);
   }
 }
 
@@ -308,7 +314,7 @@ size_t fused_lds_bytes(int R) { return (size_t)(4 * R + 2) * sizeof(int); }
 
 __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict__ regions, int nq,
                                                       int nr, int R,
-                                                      const int64_t *__restrict__ reg_start, int T, int W,
+                                                      const int64_t *__restrict__ reg_start, int T, int W, int WM,
                                                       int32_t *rq_off, int32_t *cand_off,
                                                       int32_t *slot_row, int32_t *n_cand,
                                                       int32_t *n_rows, int32_t *n_items, int2 *rq,
@@ -378,7 +384,7 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
   }
   __syncthreads();
   // counts -> fill pointers (each thread reads and rewrites only its own range)
-  sched_scan(s_fill, R, s_rs, T, W, rq_off, s_vord, s_iof, n_items, s_fill, s_red);
+  sched_scan(s_fill, R, s_rs, T, W, WM, rq_off, s_vord, s_iof, n_items, s_fill, s_red);
   __syncthreads();
   if (regs) {
     if (tid < nq) {
@@ -408,7 +414,7 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
     const int k = owner_slot(s_iof, R, t);
     const int rr = s_vord[k];
     const int q0 = rr > 0 ? s_fill[rr - 1] : 0;
-    items[t] = make_item(t, s_iof[k], q0, s_fill[rr], s_rs[rr], s_rs[rr + 1] - s_rs[rr], T, W);
+    items[t] = make_item(t, s_iof[k], q0, s_fill[rr], s_rs[rr], s_rs[rr + 1] - s_rs[rr], T, W, WM);
   }
 }
 
@@ -419,7 +425,7 @@ hipError_t prepare_sched_kernels() {
 }
 
 hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t R,
-                        const int64_t *reg_start, int32_t T, int32_t W, int32_t *rcount,
+                        const int64_t *reg_start, int32_t T, int32_t W, int32_t WM, int32_t *rcount,
                         int32_t *rfill,
                         int32_t *vord, int32_t *rq_off, int32_t *item_off, int32_t *cand_off,
                         int32_t *slot_row, int32_t *n_cand, int32_t *n_rows, int32_t *n_items,
@@ -427,7 +433,7 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
   const int64_t pairs = (int64_t)nq * nr;
   if (R <= kFusedMaxR && pairs <= kFusedMaxPairs) {
     return launch_kernel(k_sched_fused, dim3(1), dim3(1024), (uint32_t)fused_lds_bytes(R), s,
-                         regions, nq, nr, R, reg_start, T, W, rq_off, cand_off, slot_row, n_cand,
+                         regions, nq, nr, R, reg_start, T, W, WM, rq_off, cand_off, slot_row, n_cand,
                          n_rows, n_items, rq, items);
   }
   hipError_t e = launch_fill_i32(rcount, R, 0, s);
@@ -443,7 +449,7 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
                              n_rows);
     if (e != hipSuccess) return e;
   }
-  if ((e = launch_kernel(k_sched_scan, dim3(1), dim3(1024), 0, s, rcount, R, reg_start, T, W,
+  if ((e = launch_kernel(k_sched_scan, dim3(1), dim3(1024), 0, s, rcount, R, reg_start, T, W, WM,
                          rq_off, vord, item_off, n_items, rfill)) != hipSuccess)
     return e;
   if (pairs > 0) {
@@ -455,7 +461,7 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
     if (e != hipSuccess) return e;
   }
   return launch_kernel(k_sched_items, dim3(1024), dim3(256), 0, s, R, vord, item_off, rq_off,
-                       reg_start, T, W, items);
+                       reg_start, T, W, WM, items);
 }
 
 }  // namespace hloc

@@ -446,15 +446,19 @@ __global__ __launch_bounds__(256) void k_screen_wide_lp(ScreenArgs a) {
 // Wide list items with the rows held in registers and the frames staged
 // through LDS, 16 at a time, double-buffered (wide items of the bf16 and fp8
 // screens when the padded length gives NS % 4 == 0).
-// A block of four waves takes one wide item (a chunk of up to 128 rows of
-// one region against its gq frames). Wave w holds rows 32 w .. 32 w + 31 of
-// the chunk as the MFMA A operand (two 16-row tiles over the whole padded
-// length), so each row is read from memory once per item and every LDS read
-// of a frame piece feeds both row tiles (two MFMAs for bf16, four for fp8).
-// While frame group k is multiplied, group k + 1 is read into registers; it
-// is written to the other buffer after the multiply. The epilogue takes, per
-// frame and row tile, the smallest of the tile's 16 screen words (the block
-// word) and stores it at the frame's block position.
+// A block of four waves takes one wide item: up to kWideRunsRs runs of 128
+// rows of one region against the item's gq frames. For each run, wave w
+// holds rows 32 w .. 32 w + 31 as the MFMA A operand (two 16-row tiles over
+// the whole padded length), so each row is read from memory once per item
+// and every LDS read of a frame piece feeds both row tiles (two MFMAs for
+// bf16, four for fp8). The item's frame entries are staged in LDS once; its
+// frame groups then stream through the two buffers run after run: while one
+// (run, group) step is multiplied, the next step's group is read into
+// registers (across a run boundary that is group 0 again) and written to the
+// other buffer after the multiply. At a run's last group the next run's rows
+// are requested as soon as the multiply has consumed the current ones.
+// The epilogue takes, per frame and row tile, the smallest of the tile's 16
+// screen words (the block word) and stores it at the frame's block position.
 // Items are dealt to the XCDs in contiguous runs (blocks go to the eight
 // XCDs round-robin): the chunks of one region, which stage the same frames,
 // run on one XCD and find them in its L2.
@@ -485,25 +489,30 @@ __global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
   for (int it = it0 + jb; it < it1; it += nb) {
     const WideItem wi = wide_item(a, it);
     const int nrows = wi.nrows, gq = wi.gq;
-    // the wave's rows (clamped to the chunk's last row; words of rows past
-    // it are no candidates)
+    const int nrun = (nrows + kWideRowsRs - 1) / kWideRowsRs;
     v4u av[2][NS];
     float rn[2][4], rs[2][4];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int rl = min(32 * w + 16 * h + i, nrows - 1);
-      const v4u *rp = rows + (int64_t)(wi.row_begin + rl) * ROWU4 + g;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) av[h][s] = rp[4 * s];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 32 * w + 16 * h + 4 * g + r;
-        const int grow = wi.row_begin + min(row, nrows - 1);
-        rn[h][r] = row < nrows ? a.row_n2[grow] : __builtin_inff();
-        rs[h][r] = FMT == HLOC_FP8 ? a.row_scale[grow] : 1.f;
-      }
-    }
+    // the wave's rows of run C (clamped to the item's last row; words of rows
+    // past it are no candidates), then their norms and scales
+#define HLOC_RS_ROWS(C)                                                          \
+  _Pragma("unroll") for (int h = 0; h < 2; ++h) {                                \
+    const int rl = min((C) * kWideRowsRs + 32 * w + 16 * h + i, nrows - 1);      \
+    const v4u *rp = rows + (int64_t)(wi.row_begin + rl) * ROWU4 + g;             \
+    _Pragma("unroll") for (int s = 0; s < NS; ++s) av[h][s] = rp[4 * s];         \
+  }
+#define HLOC_RS_NORMS(C)                                                         \
+  _Pragma("unroll") for (int h = 0; h < 2; ++h) {                                \
+    _Pragma("unroll") for (int r = 0; r < 4; ++r) {                              \
+      const int row = (C) * kWideRowsRs + 32 * w + 16 * h + 4 * g + r;           \
+      const int grow = wi.row_begin + min(row, nrows - 1);                       \
+      rn[h][r] = row < nrows ? a.row_n2[grow] : __builtin_inff();                \
+      rs[h][r] = FMT == HLOC_FP8 ? a.row_scale[grow] : 1.f;                      \
+    }                                                                            \
+  }
+    HLOC_RS_ROWS(0)
+    HLOC_RS_NORMS(0)
     const int ng = (gq + kGroup - 1) / kGroup;
+    const int nst = nrun * ng;  // (run, group) steps, groups inner
     v4u pv[PERF];
 #define HLOC_RS_FETCH(K)                                                         \
   {                                                                              \
@@ -540,9 +549,12 @@ __global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
     HLOC_RS_FETCH(0)
     HLOC_RS_STAGE(0)
     __syncthreads();
-    for (int k = 0; k < ng; ++k) {
-      const int buf = k & 1;
-      if (k + 1 < ng) HLOC_RS_FETCH(k + 1)
+    int c = 0, k = 0;  // run and group of step st
+    for (int st = 0; st < nst; ++st) {
+      const int buf = st & 1;
+      const bool more = st + 1 < nst;
+      const bool run_end = k + 1 == ng;
+      if (more) HLOC_RS_FETCH(run_end ? 0 : k + 1)
       v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
       const v4u *bp = s_fr + (buf * kGroup + i) * LDF + g;
 #pragma unroll
@@ -551,22 +563,33 @@ __global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
         acc[0] = lp_mfma_v<FMT>(av[0][s], b, acc[0]);
         acc[1] = lp_mfma_v<FMT>(av[1][s], b, acc[1]);
       }
+      // the next run's rows, once the multiply has read this run's
+      if (run_end && more) HLOC_RS_ROWS(c + 1)
       const int2 e = s_e[k * kGroup + i];
       const float qn = s_qn[k * kGroup + i], qs = s_qs[k * kGroup + i];
       const bool fok = k * kGroup + i < gq;
+      const int blk = (wi.chunk_row + c * kWideRowsRs) / kBlockRows;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        if (32 * w + 16 * h >= nrows) continue;  // (uniform over the wave)
+        if (c * kWideRowsRs + 32 * w + 16 * h >= nrows) continue;  // (uniform over the wave)
         uint32_t wd[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) wd[r] = lp_word<FMT>(qn, rn[h][r], acc[h][r], qs, rs[h][r]);
         const uint32_t m = block_min16(wd);
-        if (fok && g == 0)
-          a.cand[(int64_t)e.x * a.cap + e.y + wi.chunk_row / kBlockRows + 2 * w + h] = m;
+        if (fok && g == 0) a.cand[(int64_t)e.x * a.cap + e.y + blk + 2 * w + h] = m;
       }
-      if (k + 1 < ng) HLOC_RS_STAGE(buf ^ 1)
+      if (run_end && more) HLOC_RS_NORMS(c + 1)
+      if (more) HLOC_RS_STAGE(buf ^ 1)
       __syncthreads();
+      if (run_end) {
+        k = 0;
+        ++c;
+      } else {
+        ++k;
+      }
     }
+#undef HLOC_RS_ROWS
+#undef HLOC_RS_NORMS
 #undef HLOC_RS_FETCH
 #undef HLOC_RS_STAGE
   }
