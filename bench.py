@@ -649,9 +649,11 @@ def labels_bench(a) -> None:
 
 
 def serve_bench(a) -> None:
-    """Poisson arrivals of 1-16 frame requests (k in {8, 16, 32}) at a.serve
-    requests/s into the request server for a.serve_seconds; prints one JSON
-    line with the completed rate and the submit-to-completion latency."""
+    """Poisson arrivals of 1-16 frame requests (k in {8, 16, 32}) into the
+    request server, at each rate of a.serve (requests/s, comma-separated) for
+    a.serve_seconds; one database, a fresh server per rate; prints one JSON
+    line per rate with the completed rate, the submit-to-completion latency
+    and the refused requests."""
     import queue
     import threading
 
@@ -666,74 +668,75 @@ def serve_bench(a) -> None:
     db = hloc.HlocDB(w.feats, w.xy, mirrors=MIRRORS[a.precision](hloc))
     db.set_regions(w.region_of, w.n_regions_total)
     db.set_aggregation(*w.agg)
-    srv = hloc.Server(db, k=32, n_regions=w.n_reg, precision=a.precision,
-                      max_batch_frames=a.serve_batch, max_slots=a.workspaces,
-                      max_queue_frames=a.serve_queue, hbm_budget_bytes=a.serve_budget)
-    rng = np.random.default_rng(77)
     offs = w.req_offsets
     npool = len(offs) - 1
-    n_req = int(a.serve * a.serve_seconds)
-    arrivals = np.cumsum(rng.exponential(1.0 / a.serve, n_req))
-    pick = rng.integers(0, npool, n_req)
-    ks = rng.choice([8, 16, 32], n_req)
     pool = [np.ascontiguousarray(w.q[offs[r]:offs[r + 1]]) for r in range(npool)]
-    # warm-up: one request of every size through every slot
-    for f in range(1, 17):
-        r = next(i for i in range(npool) if offs[i + 1] - offs[i] >= f)
-        t = srv.submit(pool[r][:f], 32)
-        srv.wait(t, f, 32)
-    tickets = queue.Queue()
-    lat, refused = [], [0]
-    done_frames = [0]
+    for rate in (float(v) for v in str(a.serve).split(",")):
+        srv = hloc.Server(db, k=32, n_regions=w.n_reg, precision=a.precision,
+                          max_batch_frames=a.serve_batch, max_slots=a.workspaces,
+                          max_queue_frames=a.serve_queue, hbm_budget_bytes=a.serve_budget)
+        rng = np.random.default_rng(77)
+        n_req = int(rate * a.serve_seconds)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+        pick = rng.integers(0, npool, n_req)
+        ks = rng.choice([8, 16, 32], n_req)
+        # warm-up: one request of every size
+        for f in range(1, 17):
+            r = next(i for i in range(npool) if offs[i + 1] - offs[i] >= f)
+            t = srv.submit(pool[r][:f], 32)
+            srv.wait(t, f, 32)
+        tickets = queue.Queue()
+        lat, refused = [], [0]
+        done_frames = [0]
 
-    def waiter():
-        while True:
-            item = tickets.get()
-            if item is None:
-                return
-            t, nf, k = item
-            out = srv.wait(t, nf, k)
-            lat.append(out["latency_ms"])
-            done_frames[0] += nf
+        def waiter():
+            while True:
+                item = tickets.get()
+                if item is None:
+                    return
+                t, nf, k = item
+                out = srv.wait(t, nf, k)
+                lat.append(out["latency_ms"])
+                done_frames[0] += nf
 
-    th = threading.Thread(target=waiter)
-    th.start()
-    start = time.perf_counter()
-    for i in range(n_req):
-        due = start + arrivals[i]
-        while True:
-            now = time.perf_counter()
-            if now >= due:
-                break
-            if due - now > 3e-4:
-                time.sleep(due - now - 2e-4)
-        frames = pool[pick[i]]
-        try:
-            t = srv.submit(frames, int(ks[i]))
-        except hloc.HlocError as e:
-            if e.code != hloc.EBUSY:
-                raise
-            refused[0] += 1
-            continue
-        tickets.put((t, len(frames), int(ks[i])))
-    tickets.put(None)
-    th.join()
-    wall = time.perf_counter() - start
-    st = srv.stats()
-    srv.close()
+        th = threading.Thread(target=waiter)
+        th.start()
+        start = time.perf_counter()
+        for i in range(n_req):
+            due = start + arrivals[i]
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+                if due - now > 3e-4:
+                    time.sleep(due - now - 2e-4)
+            frames = pool[pick[i]]
+            try:
+                t = srv.submit(frames, int(ks[i]))
+            except hloc.HlocError as e:
+                if e.code != hloc.EBUSY:
+                    raise
+                refused[0] += 1
+                continue
+            tickets.put((t, len(frames), int(ks[i])))
+        tickets.put(None)
+        th.join()
+        wall = time.perf_counter() - start
+        st = srv.stats()
+        srv.close()
+        lat = np.array(lat)
+        print(json.dumps({
+            "metric": "served localization requests/s (Poisson arrivals, 1-16 frames, k 8/16/32)",
+            "offered_req_per_s": rate, "value": len(lat) / wall, "unit": "requests/s",
+            "frames_per_s": done_frames[0] / wall, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "refused": refused[0], "seconds": wall,
+            "dtype": DTYPES[a.precision], "data": "synthetic",
+            "config": {"workload": w.name, "n": int(len(w.feats)), "d": int(w.feats.shape[1]),
+                       "regions": int(w.n_regions_total), "n_regions": int(w.n_reg),
+                       "max_batch_frames": a.serve_batch, "slots": st["slots"],
+                       "hbm_budget_bytes": a.serve_budget},
+            "server": st}), flush=True)
     db.close()
-    lat = np.array(lat)
-    print(json.dumps({
-        "metric": "served localization requests/s (Poisson arrivals, 1-16 frames, k 8/16/32)",
-        "offered_req_per_s": a.serve, "value": len(lat) / wall, "unit": "requests/s",
-        "frames_per_s": done_frames[0] / wall, "p50_ms": float(np.percentile(lat, 50)),
-        "p99_ms": float(np.percentile(lat, 99)), "refused": refused[0], "seconds": wall,
-        "dtype": DTYPES[a.precision], "data": "synthetic",
-        "config": {"workload": w.name, "n": int(len(w.feats)), "d": int(w.feats.shape[1]),
-                   "regions": int(w.n_regions_total), "n_regions": int(w.n_reg),
-                   "max_batch_frames": a.serve_batch, "slots": st["slots"],
-                   "hbm_budget_bytes": a.serve_budget},
-        "server": st}), flush=True)
 
 
 def main():
@@ -770,8 +773,9 @@ def main():
     ap.add_argument("--commands", nargs="*", default=[], help="commands quoted in the summary")
     ap.add_argument("--counters-append", action="store_true",
                     help="print only the section of one more tile choice (appended to a summary)")
-    ap.add_argument("--serve", type=float, default=0.0, metavar="REQ_PER_S",
-                    help="only run the request server under Poisson arrivals at this rate")
+    ap.add_argument("--serve", default="", metavar="REQ_PER_S[,...]",
+                    help="only run the request server under Poisson arrivals at these rates "
+                         "(requests/s, comma-separated: one line each)")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-n", type=int, default=None, help="database rows (default: 4M)")
     ap.add_argument("--serve-batch", type=int, default=512, help="frames per batch")
@@ -816,6 +820,7 @@ def main():
         if a.gpus != 1:
             print("bench.py measures one GPU only", file=sys.stderr)
             sys.exit(2)
+        a.precision = a.precision or "fp32"
         serve_bench(a)
         return
     if a.counters_summary:

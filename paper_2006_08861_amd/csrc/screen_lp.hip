@@ -455,8 +455,13 @@ __global__ __launch_bounds__(256) void k_screen_wide_lp(ScreenArgs a) {
 // frame groups then stream through the two buffers run after run: while one
 // (run, group) step is multiplied, the next step's group is read into
 // registers (across a run boundary that is group 0 again) and written to the
-// other buffer after the multiply. At a run's last group the next run's rows
-// are requested as soon as the multiply has consumed the current ones.
+// other buffer after the multiply. The last step of a run requests the next
+// run's rows as soon as its multiply has read the current ones; it is
+// written apart from the run's other steps so that no other step has row
+// loads in flight, and the multiply of a step never waits for the next
+// step's frame group. An item's set-up requests its entries, then its first
+// frame group, its first run and the entries' norms together; the next
+// item's descriptor is requested one item ahead.
 // The epilogue takes, per frame and row tile, the smallest of the tile's 16
 // screen words (the block word) and stores it at the frame's block position.
 // Items are dealt to the XCDs in contiguous runs (blocks go to the eight
@@ -469,6 +474,7 @@ __global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
   constexpr int TPF = 256 / kGroup;             // threads staging one frame
   static_assert(ROWU4 % TPF == 0, "whole pieces per thread");
   constexpr int PERF = ROWU4 / TPF;             // pieces per thread per group
+  constexpr int U = kListFrames / 256;          // item entries per thread
   extern __shared__ v4u s_fr[];                 // 2 x kGroup x LDF
   // the item's frames: rq entries, squared norms, scales (read once per item)
   __shared__ int2 s_e[kListFrames];
@@ -486,37 +492,38 @@ __global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
   const int it0 = lo + x * span, it1 = min(hi, it0 + span);
   // staging: thread t loads pieces (t % TPF) + TPF u of frame t / TPF
   const int sj = tid / TPF, sc = tid % TPF;
+  Item nxt = it0 + jb < it1 ? a.items[it0 + jb] : Item{};
   for (int it = it0 + jb; it < it1; it += nb) {
-    const WideItem wi = wide_item(a, it);
-    const int nrows = wi.nrows, gq = wi.gq;
+    const Item cur = nxt;
+    if (it + nb < it1) nxt = a.items[it + nb];
+    const int row_begin = cur.row_begin, chunk_row = cur.chunk_row, q0 = cur.q0;
+    const int nrows = cur.nrows_gq >> 16, gq = cur.nrows_gq & 0xFFFF;
     const int nrun = (nrows + kWideRowsRs - 1) / kWideRowsRs;
+    const int ng = (gq + kGroup - 1) / kGroup;
+    const int nst = nrun * ng;  // (run, group) steps, groups inner
     v4u av[2][NS];
     float rn[2][4], rs[2][4];
+    v4u pv[PERF];
     // the wave's rows of run C (clamped to the item's last row; words of rows
     // past it are no candidates), then their norms and scales
 #define HLOC_RS_ROWS(C)                                                          \
   _Pragma("unroll") for (int h = 0; h < 2; ++h) {                                \
     const int rl = min((C) * kWideRowsRs + 32 * w + 16 * h + i, nrows - 1);      \
-    const v4u *rp = rows + (int64_t)(wi.row_begin + rl) * ROWU4 + g;             \
+    const v4u *rp = rows + (int64_t)(row_begin + rl) * ROWU4 + g;                \
     _Pragma("unroll") for (int s = 0; s < NS; ++s) av[h][s] = rp[4 * s];         \
   }
 #define HLOC_RS_NORMS(C)                                                         \
   _Pragma("unroll") for (int h = 0; h < 2; ++h) {                                \
     _Pragma("unroll") for (int r = 0; r < 4; ++r) {                              \
       const int row = (C) * kWideRowsRs + 32 * w + 16 * h + 4 * g + r;           \
-      const int grow = wi.row_begin + min(row, nrows - 1);                       \
+      const int grow = row_begin + min(row, nrows - 1);                          \
       rn[h][r] = row < nrows ? a.row_n2[grow] : __builtin_inff();                \
       rs[h][r] = FMT == HLOC_FP8 ? a.row_scale[grow] : 1.f;                      \
     }                                                                            \
   }
-    HLOC_RS_ROWS(0)
-    HLOC_RS_NORMS(0)
-    const int ng = (gq + kGroup - 1) / kGroup;
-    const int nst = nrun * ng;  // (run, group) steps, groups inner
-    v4u pv[PERF];
-#define HLOC_RS_FETCH(K)                                                         \
+#define HLOC_RS_FETCH_FRAME(FR)                                                  \
   {                                                                              \
-    const v4u *fp = frames + (int64_t)s_e[(K) * kGroup + sj].x * ROWU4 + sc;     \
+    const v4u *fp = frames + (int64_t)(FR) * ROWU4 + sc;                         \
     _Pragma("unroll") for (int u = 0; u < PERF; ++u) pv[u] = fp[TPF * u];        \
   }
 #define HLOC_RS_STAGE(BUF)                                                       \
@@ -524,73 +531,80 @@ __global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
     _Pragma("unroll") for (int u = 0; u < PERF; ++u)                             \
         s_fr[((BUF) * kGroup + sj) * LDF + sc + TPF * u] = pv[u];                \
   }
-    __syncthreads();  // the previous item's frames are no longer read
-    // the item's frame entries (frames past gq: frame 0, never stored),
-    // all requested at once
+    __syncthreads();  // the previous item's entries and frames are no longer read
     {
-      constexpr int U = kListFrames / 256;
+      // the item's frame entries (frames past gq: frame 0, never stored) and
+      // the frame of this thread's piece of the first group
+      const int2 ef = sj < gq ? a.rq[q0 + sj] : make_int2(0, 0);
       int2 e[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = u * 256 + tid;
-        e[u] = j < gq ? a.rq[wi.q0 + j] : make_int2(0, 0);
+        e[u] = j < gq ? a.rq[q0 + j] : make_int2(0, 0);
       }
+      // the first group, the first run and the entries' norms together
+      HLOC_RS_FETCH_FRAME(ef.x)
+      float qv[U], sv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        qv[u] = a.qn2[e[u].x];
+        sv[u] = FMT == HLOC_FP8 ? a.q_scale[e[u].x] : 1.f;
+      }
+      HLOC_RS_ROWS(0)
+      HLOC_RS_NORMS(0)
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = u * 256 + tid;
         if (j < ng * kGroup) {
           s_e[j] = e[u];
-          s_qn[j] = a.qn2[e[u].x];
-          s_qs[j] = FMT == HLOC_FP8 ? a.q_scale[e[u].x] : 1.f;
+          s_qn[j] = qv[u];
+          s_qs[j] = sv[u];
         }
       }
+      HLOC_RS_STAGE(0)
     }
     __syncthreads();
-    HLOC_RS_FETCH(0)
-    HLOC_RS_STAGE(0)
-    __syncthreads();
-    int c = 0, k = 0;  // run and group of step st
-    for (int st = 0; st < nst; ++st) {
-      const int buf = st & 1;
-      const bool more = st + 1 < nst;
-      const bool run_end = k + 1 == ng;
-      if (more) HLOC_RS_FETCH(run_end ? 0 : k + 1)
-      v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
-      const v4u *bp = s_fr + (buf * kGroup + i) * LDF + g;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const v4u b = bp[4 * s];
-        acc[0] = lp_mfma_v<FMT>(av[0][s], b, acc[0]);
-        acc[1] = lp_mfma_v<FMT>(av[1][s], b, acc[1]);
-      }
-      // the next run's rows, once the multiply has read this run's
-      if (run_end && more) HLOC_RS_ROWS(c + 1)
-      const int2 e = s_e[k * kGroup + i];
-      const float qn = s_qn[k * kGroup + i], qs = s_qs[k * kGroup + i];
-      const bool fok = k * kGroup + i < gq;
-      const int blk = (wi.chunk_row + c * kWideRowsRs) / kBlockRows;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (c * kWideRowsRs + 32 * w + 16 * h >= nrows) continue;  // (uniform over the wave)
-        uint32_t wd[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) wd[r] = lp_word<FMT>(qn, rn[h][r], acc[h][r], qs, rs[h][r]);
-        const uint32_t m = block_min16(wd);
-        if (fok && g == 0) a.cand[(int64_t)e.x * a.cap + e.y + blk + 2 * w + h] = m;
-      }
-      if (run_end && more) HLOC_RS_NORMS(c + 1)
-      if (more) HLOC_RS_STAGE(buf ^ 1)
-      __syncthreads();
-      if (run_end) {
-        k = 0;
-        ++c;
-      } else {
-        ++k;
-      }
+    // one (run c, group K) step; LAST: the run's last group
+#define HLOC_RS_STEP(K, LAST)                                                    \
+  {                                                                              \
+    const int buf = st & 1;                                                      \
+    const bool more = st + 1 < nst;                                              \
+    if (more) HLOC_RS_FETCH_FRAME(s_e[((LAST) ? 0 : (K) + 1) * kGroup + sj].x)   \
+    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};             \
+    const v4u *bp = s_fr + (buf * kGroup + i) * LDF + g;                         \
+    _Pragma("unroll") for (int s = 0; s < NS; ++s) {                             \
+      const v4u b = bp[4 * s];                                                   \
+      acc[0] = lp_mfma_v<FMT>(av[0][s], b, acc[0]);                              \
+      acc[1] = lp_mfma_v<FMT>(av[1][s], b, acc[1]);                              \
+    }                                                                            \
+    if ((LAST) && more) HLOC_RS_ROWS(c + 1)                                      \
+    const int2 e = s_e[(K) * kGroup + i];                                        \
+    const float qn = s_qn[(K) * kGroup + i], qs = s_qs[(K) * kGroup + i];        \
+    const bool fok = (K) * kGroup + i < gq;                                      \
+    const int blk = (chunk_row + c * kWideRowsRs) / kBlockRows;                  \
+    _Pragma("unroll") for (int h = 0; h < 2; ++h) {                              \
+      if (c * kWideRowsRs + 32 * w + 16 * h < nrows) { /* (uniform) */           \
+        uint32_t wd[4];                                                          \
+        _Pragma("unroll") for (int r = 0; r < 4; ++r)                            \
+            wd[r] = lp_word<FMT>(qn, rn[h][r], acc[h][r], qs, rs[h][r]);         \
+        const uint32_t m = block_min16(wd);                                      \
+        if (fok && g == 0) a.cand[(int64_t)e.x * a.cap + e.y + blk + 2 * w + h] = m; \
+      }                                                                          \
+    }                                                                            \
+    if ((LAST) && more) HLOC_RS_NORMS(c + 1)                                     \
+    if (more) HLOC_RS_STAGE(buf ^ 1)                                             \
+    __syncthreads();                                                             \
+    ++st;                                                                        \
+  }
+    int st = 0;  // steps done
+    for (int c = 0; c < nrun; ++c) {
+      for (int k = 0; k + 1 < ng; ++k) HLOC_RS_STEP(k, false)
+      HLOC_RS_STEP(ng - 1, true)
     }
+#undef HLOC_RS_STEP
 #undef HLOC_RS_ROWS
 #undef HLOC_RS_NORMS
-#undef HLOC_RS_FETCH
+#undef HLOC_RS_FETCH_FRAME
 #undef HLOC_RS_STAGE
   }
 }

@@ -172,6 +172,7 @@ constexpr int kRowBatch = 8;    // survivor rows fetched together by one wave
 constexpr int kEarlyKeys = 2048;  // keys requested before the count is known
 constexpr int kRankSort = 256;  // entries up to which sort_pairs ranks instead of merging
 constexpr int kCollectRounds = 8;  // positions per lane held in registers by the collect
+constexpr bool kPairChunks = false;  // block kernel: two 256-value chunks of fp32 rows per round trip
 
 // Sums over the wave of kRowBatch (8) values per lane at once: three halving
 // exchanges (lanes 32 apart swap half of their values, then 16, then 8 apart)
@@ -203,93 +204,145 @@ __device__ __forceinline__ double wave_sum8_f64(double (&acc)[kRowBatch]) {
   return v;
 }
 
-// FP64 distances of the frame to source rows sh.srow[s0 .. s1) into
-// sort_hi / sort_lo[s] (distance bits, tie id); a kNoRow slot gets the key
-// (kKeyNone, 0x80000000 | s), distinct and after every row. Each wave fetches kRowBatch
-// rows at once with the frame slice reused across them; a lane sums its
-// slice of each row in order (4 consecutive values per 256), then
-// wave_sum8_f64 adds the lanes. LEAN (1024-thread blocks, at most 128
-// VGPRs) fetches the FP64 rows in two halves; the sums are the same.
-template <bool LEAN>
-__device__ void rerank_range(const SelRerankArgs &a, SelShared &sh, const float *qrow, int s0,
-                             int s1) {
-  const int w = wave_id(), lane = lane_id(), nw = blockDim.x >> 6;
+// FP64 partial sums of this lane for kRowBatch source rows: the sum of
+// (q_i - d_i)^2 over the lane's values, chunk by chunk of 256 values (4
+// consecutive per lane), in column order; wave_sum8_f64 then adds the lanes.
+// With PAIR, fp32 rows of a length that is a multiple of 512 are fetched two
+// chunks per round trip (more registers); otherwise one chunk at a time, and
+// LEAN (1024-thread blocks, at most 128 VGPRs) fetches FP64 rows in halves.
+// The sums are the same either way.
+template <bool LEAN, bool PAIR>
+__device__ __forceinline__ void rerank_batch(const SelRerankArgs &a, const float *qrow,
+                                             const uint32_t (&row)[kRowBatch],
+                                             double (&acc)[kRowBatch]) {
+  const int lane = lane_id();
   const int nch = a.dp >> 8;    // chunks of 256 values: 4 per lane
   const int tail = a.dp & 255;  // remaining values (multiple of 16)
-  for (int b = s0 + w * kRowBatch; b < s1; b += nw * kRowBatch) {
-    double acc[kRowBatch];
-    uint32_t row[kRowBatch];
 #pragma unroll
-    for (int r = 0; r < kRowBatch; ++r) {
-      acc[r] = 0.0;
-      const uint32_t v = sh.srow[min(b + r, s1 - 1)];
-      row[r] = v == kNoRow ? 0u : v;
-    }
-    for (int c = 0; c <= nch; ++c) {
-      const int col = c * 256 + lane * 4;
-      if (c == nch && (tail == 0 || col >= a.dp)) break;
-      const float4 y = *reinterpret_cast<const float4 *>(qrow + col);
-      const double y0 = y.x, y1 = y.y, y2 = y.z, y3 = y.w;
-      if (a.src32) {
-        float4 v[kRowBatch];
+  for (int r = 0; r < kRowBatch; ++r) acc[r] = 0.0;
+  if (PAIR && a.src32 && (a.dp & 511) == 0) {
+    for (int c = 0; c < nch; c += 2) {
+      const int col0 = c * 256 + lane * 4, col1 = col0 + 256;
+      float4 y[2], v[2][kRowBatch];
+      y[0] = *reinterpret_cast<const float4 *>(qrow + col0);
+      y[1] = *reinterpret_cast<const float4 *>(qrow + col1);
 #pragma unroll
-        for (int r = 0; r < kRowBatch; ++r)
-          v[r] = *reinterpret_cast<const float4 *>(a.src32 + (int64_t)row[r] * a.dp + col);
+      for (int r = 0; r < kRowBatch; ++r) {
+        const float *rp = a.src32 + (int64_t)row[r] * a.dp;
+        v[0][r] = *reinterpret_cast<const float4 *>(rp + col0);
+        v[1][r] = *reinterpret_cast<const float4 *>(rp + col1);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double y0 = y[h].x, y1 = y[h].y, y2 = y[h].z, y3 = y[h].w;
 #pragma unroll
         for (int r = 0; r < kRowBatch; ++r) {
           double t;
-          t = y0 - (double)v[r].x; acc[r] = fma(t, t, acc[r]);
-          t = y1 - (double)v[r].y; acc[r] = fma(t, t, acc[r]);
-          t = y2 - (double)v[r].z; acc[r] = fma(t, t, acc[r]);
-          t = y3 - (double)v[r].w; acc[r] = fma(t, t, acc[r]);
-        }
-      } else if (LEAN) {
-#pragma unroll
-        for (int hf = 0; hf < 2; ++hf) {
-          double2 v[kRowBatch];
-#pragma unroll
-          for (int r = 0; r < kRowBatch; ++r)
-            v[r] = reinterpret_cast<const double2 *>(a.src64 + (int64_t)row[r] * a.dp + col)[hf];
-          const double ya = hf ? y2 : y0, yb = hf ? y3 : y1;
-          __builtin_amdgcn_sched_barrier(0);  // keep the halves apart (register budget)
-#pragma unroll
-          for (int r = 0; r < kRowBatch; ++r) {
-            double t;
-            t = ya - v[r].x; acc[r] = fma(t, t, acc[r]);
-            t = yb - v[r].y; acc[r] = fma(t, t, acc[r]);
-          }
-        }
-      } else {
-        double2 v[kRowBatch][2];
-#pragma unroll
-        for (int r = 0; r < kRowBatch; ++r) {
-          const double2 *rp = reinterpret_cast<const double2 *>(a.src64 + (int64_t)row[r] * a.dp + col);
-          v[r][0] = rp[0];
-          v[r][1] = rp[1];
-        }
-#pragma unroll
-        for (int r = 0; r < kRowBatch; ++r) {
-          double t;
-          t = y0 - v[r][0].x; acc[r] = fma(t, t, acc[r]);
-          t = y1 - v[r][0].y; acc[r] = fma(t, t, acc[r]);
-          t = y2 - v[r][1].x; acc[r] = fma(t, t, acc[r]);
-          t = y3 - v[r][1].y; acc[r] = fma(t, t, acc[r]);
+          t = y0 - (double)v[h][r].x; acc[r] = fma(t, t, acc[r]);
+          t = y1 - (double)v[h][r].y; acc[r] = fma(t, t, acc[r]);
+          t = y2 - (double)v[h][r].z; acc[r] = fma(t, t, acc[r]);
+          t = y3 - (double)v[h][r].w; acc[r] = fma(t, t, acc[r]);
         }
       }
     }
-    const double d = wave_sum8_f64(acc);
-    const int r = lane >> 3, sidx = b + r;
-    if ((lane & 7) == 0 && sidx < s1) {
-      const uint32_t rw = sh.srow[sidx];
-      if (rw == kNoRow) {
-        sh.sort_hi[sidx] = kKeyNone;
-        sh.sort_lo[sidx] = 0x80000000u | (uint32_t)sidx;
-      } else {
-        sh.sort_hi[sidx] = (uint64_t)__double_as_longlong(d);
-        sh.sort_lo[sidx] = a.tie_of ? (uint32_t)a.tie_of[rw] : rw;
+    return;
+  }
+  for (int c = 0; c <= nch; ++c) {
+    const int col = c * 256 + lane * 4;
+    if (c == nch && (tail == 0 || col >= a.dp)) break;
+    const float4 y = *reinterpret_cast<const float4 *>(qrow + col);
+    const double y0 = y.x, y1 = y.y, y2 = y.z, y3 = y.w;
+    if (a.src32) {
+      float4 v[kRowBatch];
+#pragma unroll
+      for (int r = 0; r < kRowBatch; ++r)
+        v[r] = *reinterpret_cast<const float4 *>(a.src32 + (int64_t)row[r] * a.dp + col);
+#pragma unroll
+      for (int r = 0; r < kRowBatch; ++r) {
+        double t;
+        t = y0 - (double)v[r].x; acc[r] = fma(t, t, acc[r]);
+        t = y1 - (double)v[r].y; acc[r] = fma(t, t, acc[r]);
+        t = y2 - (double)v[r].z; acc[r] = fma(t, t, acc[r]);
+        t = y3 - (double)v[r].w; acc[r] = fma(t, t, acc[r]);
+      }
+    } else if (LEAN) {
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+        double2 v[kRowBatch];
+#pragma unroll
+        for (int r = 0; r < kRowBatch; ++r)
+          v[r] = reinterpret_cast<const double2 *>(a.src64 + (int64_t)row[r] * a.dp + col)[hf];
+        const double ya = hf ? y2 : y0, yb = hf ? y3 : y1;
+        __builtin_amdgcn_sched_barrier(0);  // keep the halves apart (register budget)
+#pragma unroll
+        for (int r = 0; r < kRowBatch; ++r) {
+          double t;
+          t = ya - v[r].x; acc[r] = fma(t, t, acc[r]);
+          t = yb - v[r].y; acc[r] = fma(t, t, acc[r]);
+        }
+      }
+    } else {
+      double2 v[kRowBatch][2];
+#pragma unroll
+      for (int r = 0; r < kRowBatch; ++r) {
+        const double2 *rp = reinterpret_cast<const double2 *>(a.src64 + (int64_t)row[r] * a.dp + col);
+        v[r][0] = rp[0];
+        v[r][1] = rp[1];
+      }
+#pragma unroll
+      for (int r = 0; r < kRowBatch; ++r) {
+        double t;
+        t = y0 - v[r][0].x; acc[r] = fma(t, t, acc[r]);
+        t = y1 - v[r][0].y; acc[r] = fma(t, t, acc[r]);
+        t = y2 - v[r][1].x; acc[r] = fma(t, t, acc[r]);
+        t = y3 - v[r][1].y; acc[r] = fma(t, t, acc[r]);
       }
     }
   }
+}
+
+// FP64 distances of the frame to source rows srow[s0 .. s1) into
+// sort_hi / sort_lo[s] (distance bits, tie id); a kNoRow slot gets the key
+// (kKeyNone, 0x80000000 | s), distinct and after every row. The calling
+// wave takes the batches of kRowBatch rows starting at first, step apart;
+// the tie ids are requested with the row values.
+template <bool LEAN, bool PAIR>
+__device__ void rerank_rows(const SelRerankArgs &a, const float *qrow, const uint32_t *srow,
+                            uint64_t *sort_hi, uint32_t *sort_lo, int s1, int first, int step) {
+  const int lane = lane_id();
+  for (int b = first; b < s1; b += step) {
+    uint32_t row[kRowBatch];
+#pragma unroll
+    for (int r = 0; r < kRowBatch; ++r) {
+      const uint32_t v = srow[min(b + r, s1 - 1)];
+      row[r] = v == kNoRow ? 0u : v;
+    }
+    // lanes 8 r .. 8 r + 7 end up holding row r's total
+    const int sidx = b + (lane >> 3);
+    const uint32_t rw = (lane & 7) == 0 && sidx < s1 ? srow[sidx] : kNoRow;
+    const uint32_t tie = rw != kNoRow && a.tie_of ? (uint32_t)a.tie_of[rw] : rw;
+    double acc[kRowBatch];
+    rerank_batch<LEAN, PAIR>(a, qrow, row, acc);
+    const double d = wave_sum8_f64(acc);
+    if ((lane & 7) == 0 && sidx < s1) {
+      if (rw == kNoRow) {
+        sort_hi[sidx] = kKeyNone;
+        sort_lo[sidx] = 0x80000000u | (uint32_t)sidx;
+      } else {
+        sort_hi[sidx] = (uint64_t)__double_as_longlong(d);
+        sort_lo[sidx] = tie;
+      }
+    }
+  }
+}
+
+// The block's waves share rows [s0, s1) of sh.srow, kRowBatch at a time.
+template <bool LEAN>
+__device__ void rerank_range(const SelRerankArgs &a, SelShared &sh, const float *qrow, int s0,
+                             int s1) {
+  const int w = wave_id(), nw = blockDim.x >> 6;
+  rerank_rows<LEAN, kPairChunks && !LEAN>(a, qrow, sh.srow, sh.sort_hi, sh.sort_lo, s1,
+                                          s0 + w * kRowBatch, nw * kRowBatch);
 }
 
 // Sorts sort_hi / sort_lo[0, cnt) ascending; the pairs are distinct (the
@@ -871,6 +924,207 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
   }
 }
 
+// Key mode in one wave per frame: the coarse stage after the fused coarse
+// product when a frame has at most kWaveKeys keys. Its keys are few (the
+// kept quads of each lane group and split), so a whole block per frame would
+// mostly wait at barriers; here each wave takes one frame on its own (four
+// frames per block, no block barrier) and follows the rules of
+// k_select_rerank's key mode: the L smallest (word, position) pairs survive,
+// the (L+1)-th decides the deferral and the certificate, the FP64 distances
+// come from the same per-row arithmetic (rerank_rows), and the band is
+// re-scored the same way, so the regions are the ones the block kernel
+// would return. A band beyond kWaveRows rows defers the frame to the dense
+// screen (exact as well).
+constexpr int kWaveKeys = 256;  // keys per frame held by one wave (4 per lane)
+constexpr int kWaveRows = 64;   // rows re-scored per frame by one wave
+constexpr int kWaveFrames = 4;  // frames (waves) per block
+struct WaveSel {
+  uint32_t krow[kWaveKeys];     // source row of each key
+  uint64_t sort_hi[kWaveRows];  // FP64 distance bits
+  uint32_t sort_lo[kWaveRows];  // tie ids
+  uint32_t srow[kWaveRows];     // rows to re-score
+};
+
+// Orders the wave's LDS accesses before and after (no block barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t y = (uint64_t)__shfl_xor((long long)v, o);
+    v = y < v ? y : v;
+  }
+  return v;
+}
+
+// Sorts sort_hi / sort_lo[0, cnt) (cnt <= 64, distinct pairs) by rank: lane t
+// counts the entries ordered before entry t.
+__device__ __forceinline__ void wave_sort_pairs(WaveSel &sh, int cnt) {
+  const int lane = lane_id();
+  uint64_t hi = kKeyNone;
+  uint32_t lo = 0xFFFFFFFFu;
+  int rank = 0;
+  if (lane < cnt) {
+    hi = sh.sort_hi[lane];
+    lo = sh.sort_lo[lane];
+    for (int j = 0; j < cnt; ++j) {
+      const uint64_t yh = sh.sort_hi[j];
+      const uint32_t yl = sh.sort_lo[j];
+      rank += (yh < hi) | ((yh == hi) & (yl < lo));
+    }
+  }
+  wave_sync();
+  if (lane < cnt) {
+    sh.sort_hi[rank] = hi;
+    sh.sort_lo[rank] = lo;
+  }
+  wave_sync();
+}
+
+__global__ __launch_bounds__(64 * kWaveFrames) void k_select_keys(SelRerankArgs a) {
+  __shared__ WaveSel s_all[kWaveFrames];
+  const int w = wave_id(), lane = lane_id();
+  const int ng = (a.nq + kWaveFrames - 1) / kWaveFrames;
+  const int f = xcd_frame((int)blockIdx.x, ng) * kWaveFrames + w;
+  if (f >= a.nq) return;  // (the whole wave; no block barrier follows)
+  WaveSel &sh = s_all[w];
+  const int n = a.n_fixed, L = a.L, m = a.m;
+  constexpr int KPL = kWaveKeys / 64;  // keys per lane
+  // the keys and bounds, requested together
+  const uint64_t *kf = a.keys + (int64_t)f * n;
+  uint64_t kk[KPL];
+#pragma unroll
+  for (int u = 0; u < KPL; ++u) {
+    const int i = u * 64 + lane;
+    kk[u] = i < n ? kf[i] : kKeyNone;
+  }
+  uint64_t bound = kKeyNone;
+  for (int i = lane; i < a.n_bounds; i += 64) {
+    const uint64_t b = a.bounds[(int64_t)f * a.n_bounds + i];
+    bound = b < bound ? b : bound;
+  }
+  const float qn2 = a.qn2[f];
+  if (lane == 0 && a.stat_max) atomicMax(a.stat_max, n);
+  // entries (word << 32 | position) of the valid keys (kKeyNone otherwise)
+  uint64_t ent[KPL];
+  int nv = 0;
+#pragma unroll
+  for (int u = 0; u < KPL; ++u) {
+    const int i = u * 64 + lane;
+    const uint32_t wd = (uint32_t)(kk[u] >> 32);
+    const bool valid = i < n && wd != kWordNone;
+    ent[u] = valid ? ((uint64_t)wd << 32) | (uint32_t)i : kKeyNone;
+    sh.krow[i] = (uint32_t)kk[u];
+    nv += valid;
+  }
+  const int nvalid = wave_sum_i32(nv);
+  bound = wave_min_u64(bound);
+  const bool rejected = nvalid > L;
+  const uint32_t bw = (uint32_t)(bound >> 32);
+  auto defer = [&]() {
+    if (lane == 0) a.defer_list[atomicAdd(a.defer_count, 1)] = f;
+  };
+  if (bound != kKeyNone && !rejected) {
+    defer();
+    return;
+  }
+  // the survivors in (word, position) order: the wave minimum, taken out of
+  // its lane, nsurv times; then the word tw of the best rejected pair
+  // without taking it out
+  const int nsurv = min(L, nvalid);
+  wave_sync();  // krow written
+  for (int t = 0; t < nsurv; ++t) {
+    uint64_t lm = ent[0];
+#pragma unroll
+    for (int u = 1; u < KPL; ++u) lm = ent[u] < lm ? ent[u] : lm;
+    const uint64_t mn = wave_min_u64(lm);
+#pragma unroll
+    for (int u = 0; u < KPL; ++u)
+      if (ent[u] == mn) ent[u] = kKeyNone;
+    if (lane == 0) sh.srow[t] = sh.krow[(uint32_t)mn];
+  }
+  uint32_t tw = kWordNone;
+  if (rejected) {
+    uint64_t lm = ent[0];
+#pragma unroll
+    for (int u = 1; u < KPL; ++u) lm = ent[u] < lm ? ent[u] : lm;
+    tw = (uint32_t)(wave_min_u64(lm) >> 32);
+  }
+  if (rejected && bound != kKeyNone && tw > bw) {
+    defer();
+    return;
+  }
+  wave_sync();  // srow written
+  const float *qrow = a.qp + (int64_t)f * a.dp;
+  const int nrow = nsurv;
+  rerank_rows<false, false>(a, qrow, sh.srow, sh.sort_hi, sh.sort_lo, nrow, 0, kRowBatch);
+  wave_sync();
+  wave_sort_pairs(sh, nrow);
+  // certificate (the block kernel's, every lane alike)
+  bool band = false;
+  uint32_t tau_w = 0;
+  if (rejected && m > 0) {
+    const double rejd = (double)__uint_as_float(tw);
+    const double qn = sqrt((double)qn2) * (1.0 + 1e-6);
+    double e = a.err_coef * (qn + a.max_norm) * (qn + a.max_norm);
+    if (a.q_err) {
+      const double qe = a.q_err[f], ql = a.q_lon[f];
+      e += a.lo_coef * (ql * a.lo_dmax + qe * a.lo_nmax + qe * a.lo_dmax);
+    }
+    const uint64_t km = sh.sort_hi[m - 1];
+    const double dm = km == kKeyNone ? __builtin_inf() : __longlong_as_double((long long)km);
+    const double tau = dm * (1.0 + 1e-12) + e;
+    if (!(rejd > tau)) {
+      band = true;
+      tau_w = __float_as_uint(__double2float_ru(tau));
+      // a band reaching words the lists may have dropped is not complete
+      if (bound != kKeyNone && tau_w >= bw) {
+        defer();
+        return;
+      }
+    }
+  }
+  if (lane == 0 && a.stat_rows) atomicAdd(a.stat_rows, nrow);
+  int have = min(nrow, m);
+  if (band) {
+    // the band: the pairs not taken out with a word up to tau_w (all of
+    // them are at or after (tw, tpos)); their rows behind the survivors'
+    int cnt[KPL], tot = 0;
+#pragma unroll
+    for (int u = 0; u < KPL; ++u) {
+      const bool in = ent[u] != kKeyNone && (uint32_t)(ent[u] >> 32) <= tau_w;
+      const uint64_t bal = __ballot(in);
+      cnt[u] = in ? tot + __popcll(bal & ((1ull << lane) - 1ull)) : -1;
+      tot += __popcll(bal);
+    }
+    if (nrow + tot > kWaveRows) {
+      defer();
+      return;
+    }
+#pragma unroll
+    for (int u = 0; u < KPL; ++u)
+      if (cnt[u] >= 0) sh.srow[nrow + cnt[u]] = sh.krow[(uint32_t)ent[u]];
+    wave_sync();
+    rerank_rows<false, false>(a, qrow, sh.srow, sh.sort_hi, sh.sort_lo, nrow + tot, nrow, kRowBatch);
+    wave_sync();
+    wave_sort_pairs(sh, nrow + tot);
+    have = min(nrow + tot, m);
+    if (lane == 0) {
+      if (a.stat_fallback) atomicAdd(a.stat_fallback, 1);
+      if (a.stat_band) atomicAdd(a.stat_band, tot);
+      if (a.stat_rows) atomicAdd(a.stat_rows, tot);
+    }
+  }
+  for (int i = lane; i < m; i += 64) {
+    const bool ok = i < have && sh.sort_hi[i] != kKeyNone;
+    a.reg_out[(int64_t)f * m + i] = ok ? (int32_t)sh.sort_lo[i] : -1;
+  }
+}
+
 constexpr size_t select_lds_bytes(int nslots, int cache) {
   return (size_t)(3 * nslots + cache) * sizeof(uint32_t);
 }
@@ -915,6 +1169,11 @@ hipError_t launch_select_rerank(SelRerankArgs a, hipStream_t s) {
   } else {
     a.cache = (int32_t)std::min<int64_t>(a.cap, kWordCache);
   }
+  // key mode with few keys per frame (the coarse stage of large batches):
+  // one wave per frame
+  if (a.keys && a.reg_out && a.n_fixed <= kWaveKeys && a.L <= kWaveRows)
+    return launch_kernel(k_select_keys, dim3((unsigned)((a.nq + kWaveFrames - 1) / kWaveFrames)),
+                         dim3(64 * kWaveFrames), 0, s, a);
   // frames with many candidates: the word cache takes most of the LDS, so the
   // block is alone on its compute unit; 1024 threads use all of it
   if (a.cap > kBigFrame)

@@ -203,6 +203,45 @@ def test_full_multiframe_shape(torch_cuda, db_2m):
     assert same >= n - st["tie_excused"] - st["region_excused"]
 
 
+def test_full_exhaustive_shape(torch_cuda, db_2m):
+    """bf16-2m-d512 searched exhaustively (n_regions = every region, the
+    paper's whole-database search): 2,048 frames against all 2,000,000 rows,
+    k 16; the bf16 screen against the plain fp32 one bit for bit, and sampled
+    frames against the oracle's brute force over every row (12 frames: each
+    costs the oracle tens of GB and seconds, so two at a time)."""
+    w, db, reps = db_2m
+    R = w.n_regions_total
+    say(f"[case] bf16-2m-d512 x{len(w.q)} exhaustive (n_regions {R}), bf16 / fp32 screens")
+    q = torch_cuda.from_numpy(w.q).to("cuda:0")
+    offs = torch_cuda.from_numpy(w.req_offsets.astype(np.int32)).to("cuda:0")
+    res = {}
+    for prec in ("bf16", "fp32"):
+        t0 = time.perf_counter()
+        out = db.query(q, w.k, R, offs, precision=prec)
+        torch_cuda.cuda.synchronize()
+        res[prec] = {key: v.cpu().numpy() for key, v in out.items()}
+        say(f"[gpu] exhaustive {prec}: {time.perf_counter() - t0:.2f} s (first call), "
+            f"info {db.info()}")
+    for key in ("idx", "dist", "xy", "tile", "flags"):
+        assert res["bf16"][key].tobytes() == res["fp32"][key].tobytes(), f"exhaustive: {key}"
+    frames = np.sort(np.random.default_rng(5).choice(len(w.q), 12, replace=False))
+    t0 = time.perf_counter()
+
+    def job(i):
+        return oracle.retrieve(w.feats, w.region_of, R, w.q[i:i + 1], w.k, R, reps=reps)
+
+    with ThreadPoolExecutor(2) as ex:
+        parts = list(ex.map(job, frames.tolist()))
+    ora = {key: (np.concatenate([p[key] for p in parts]) if not isinstance(parts[0][key], list)
+                 else [v for p in parts for v in p[key]]) for key in parts[0]}
+    say(f"[oracle] {len(frames)} frames by brute force in {time.perf_counter() - t0:.1f} s")
+    st = judge_frames(res["bf16"]["idx"][frames], res["bf16"]["dist"][frames], None, ora,
+                      w.feats, w.region_of, R, w.q[frames], w.k, reps=reps)
+    say(f"[ok] bf16-2m-d512 exhaustive: {st}")
+    assert st["frames"] == len(frames)
+    assert st["recall"] >= 1.0 - st["tie_excused"] / st["frames"]
+
+
 def test_full_serving_shape(torch_cuda, db_4m):
     """serve-4m-d256: 4,096 requests of 1-16 frames in one batch, k 32, on
     the 4M x 256 database; fp32, bf16 and fp8 screens bit for bit, whole
