@@ -189,6 +189,7 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *byte
   CHK(fit(ws->item_off, (size_t)(db->R + 1) * sizeof(int32_t)));
   CHK(fit(ws->cand_off, (size_t)nq * nr * sizeof(int32_t)));
   CHK(fit(ws->slot_row, (size_t)nq * nr * sizeof(int32_t)));
+  CHK(fit(ws->slot_len, (size_t)nq * nr * sizeof(int32_t)));
   CHK(fit(ws->n_cand, (size_t)nq * sizeof(int32_t)));
   CHK(fit(ws->n_rows, (size_t)nq * sizeof(int32_t)));
   CHK(fit(ws->misc, 16 * sizeof(int32_t)));
@@ -425,7 +426,8 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
                       rs ? kWideRunsRs : 1,
                       as<int32_t>(ws->rcount), as<int32_t>(ws->rfill), as<int32_t>(ws->vord),
                       as<int32_t>(ws->rq_off),
-                      as<int32_t>(ws->item_off), cand_off, as<int32_t>(ws->slot_row), n_cand,
+                      as<int32_t>(ws->item_off), cand_off, as<int32_t>(ws->slot_row),
+                      as<int32_t>(ws->slot_len), n_cand,
                       as<int32_t>(ws->n_rows), misc + 0, as<int2>(ws->rq), as<Item>(ws->items),
                       s));
   ph.begin(HLOC_PHASE_SCREEN);
@@ -465,8 +467,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   rb.nslots = p.exhaustive ? 0 : p.nr;
   rb.slot_off = cand_off;
   rb.slot_row = as<int32_t>(ws->slot_row);
-  rb.slot_reg = regions;
-  rb.reg_start = db->reg_start;
+  rb.slot_len = as<int32_t>(ws->slot_len);
   rb.blk_rows = db->blk_rows;
   rb.n_cand = n_cand;
   rb.L = (p.kp + kBlockRows - 1) / kBlockRows;  // survivor blocks: at least k' rows
@@ -567,7 +568,7 @@ void for_each_buf(hloc_ws *ws, F f) {
                    &ws->misc,     &ws->rq,       &ws->items,    &ws->cand2,   &ws->agg_xy,
                    &ws->agg_tile, &ws->agg_flags, &ws->s_q,     &ws->s_off,   &ws->s_idx,
                    &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags, &ws->q_lp,
-                   &ws->q_scale,  &ws->q_err,    &ws->q_lon,   &ws->slot_row, &ws->n_rows,
+                   &ws->q_scale,  &ws->q_err,    &ws->q_lon,   &ws->slot_row, &ws->slot_len, &ws->n_rows,
                    &ws->c_lp,     &ws->c_scale,  &ws->c_err,   &ws->c_lon,   &ws->agg_big,
                    &ws->lab_off,  &ws->lab_list, &ws->lab_q,  &ws->ckeys,
                    &ws->cslots,   &ws->cbounds,  &ws->cdefer};

@@ -207,7 +207,8 @@ hipError_t launch_broadcast_ids(const int32_t *ids, int32_t nr, int32_t nq, int3
 // by at most kGroup frames) first, n_items[4] of them, then wide ones. Per
 // frame f and kept-region slot j: cand_off[f][j] the first of the slot's
 // 16-row blocks in the frame's block list, slot_row[f][j] the region's first
-// row; n_cand[f] the frame's block count, n_rows[f] its candidate rows. An rq
+// row, slot_len[f][j] its rows; n_cand[f] the frame's block count, n_rows[f]
+// its candidate rows. An rq
 // entry is (frame, cand_off of the region in that frame). Narrow chunks hold
 // T rows; wide chunks W rows, or with WM > 1 up to WM runs of W rows.
 hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t R,
@@ -215,7 +216,8 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
                         int32_t *rcount,
                         int32_t *rfill,
                         int32_t *vord, int32_t *rq_off, int32_t *item_off, int32_t *cand_off,
-                        int32_t *slot_row, int32_t *n_cand, int32_t *n_rows, int32_t *n_items,
+                        int32_t *slot_row, int32_t *slot_len, int32_t *n_cand, int32_t *n_rows,
+                        int32_t *n_items,
                         int2 *rq, Item *items, hipStream_t s);
 
 // Coarse screen fused with the start of the selection (coarse_gemm.hip): a
@@ -259,7 +261,7 @@ hipError_t launch_coarse_gemm(CoarseGemmArgs a, hipStream_t s);
 // certificate holds per block as it does per row.
 // Positions map to source rows through the frame's region slots (slot j: the
 // rows from slot_row[f][j] on, at positions from slot_off[f][j] on; in block
-// mode the slot's region slot_reg[f][j] gives its row count), or, with
+// mode slot_len[f][j] is the slot's row count), or, with
 // nslots = 0, are the rows themselves (block mode: blocks of blk_rows, every
 // non-empty region in id order).
 struct SelRerankArgs {
@@ -272,8 +274,7 @@ struct SelRerankArgs {
   const int32_t *n_cand;
   int32_t n_fixed;
   int32_t blocks;            // positions are 16-row blocks
-  const int32_t *slot_reg;   // block mode: nq x nslots region ids
-  const int64_t *reg_start;  // block mode: first row of each region (R + 1)
+  const int32_t *slot_len;   // block mode: nq x nslots rows of each slot's region
   const int2 *blk_rows;      // block mode, nslots = 0: (first row, rows) of each block
   int32_t L;               // positions re-scored in FP64 (rows: <= kMaxSurvivors)
   int32_t m;               // results per frame (<= 256, <= L)

@@ -184,7 +184,7 @@ hipError_t launch_broadcast_ids(const int32_t *ids, int32_t nr, int32_t nq, int3
 __device__ __forceinline__ void count_frame(const int32_t *__restrict__ regions, int f, int nr,
                                             int R, const int64_t *__restrict__ reg_start,
                                             int32_t *cnt, int32_t *cand_off, int32_t *slot_row,
-                                            int32_t *n_cand, int32_t *n_rows) {
+                                            int32_t *slot_len, int32_t *n_cand, int32_t *n_rows) {
   const int lane = threadIdx.x & 63;
   const int32_t *ids = regions + (int64_t)f * nr;
   int base = 0, rows = 0;
@@ -206,6 +206,7 @@ __device__ __forceinline__ void count_frame(const int32_t *__restrict__ regions,
     if (j < nr) {
       cand_off[(int64_t)f * nr + j] = base + inc - nb;
       slot_row[(int64_t)f * nr + j] = r0;
+      slot_len[(int64_t)f * nr + j] = sz;
     }
     if (r >= 0) atomicAdd(&cnt[r], 1);
     base += __shfl(inc, 63);
@@ -225,7 +226,8 @@ __device__ __forceinline__ void count_frame(const int32_t *__restrict__ regions,
 template <bool LDS>
 __global__ void k_sched_count(const int32_t *__restrict__ regions, int nq, int nr, int R,
                               const int64_t *__restrict__ reg_start, int32_t *rcount,
-                              int32_t *cand_off, int32_t *slot_row, int32_t *n_cand,
+                              int32_t *cand_off, int32_t *slot_row, int32_t *slot_len,
+                              int32_t *n_cand,
                               int32_t *n_rows) {
   extern __shared__ int32_t s_cnt[];  // R (LDS mode)
   if (LDS) {
@@ -234,7 +236,8 @@ __global__ void k_sched_count(const int32_t *__restrict__ regions, int nq, int n
   }
   int32_t *cnt = LDS ? s_cnt : rcount;
   const int f = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);  // one wave per frame
-  if (f < nq) count_frame(regions, f, nr, R, reg_start, cnt, cand_off, slot_row, n_cand, n_rows);
+  if (f < nq)
+    count_frame(regions, f, nr, R, reg_start, cnt, cand_off, slot_row, slot_len, n_cand, n_rows);
   if (LDS) {
     __syncthreads();
     for (int i = threadIdx.x; i < R; i += blockDim.x)
@@ -316,7 +319,8 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
                                                       int nr, int R,
                                                       const int64_t *__restrict__ reg_start, int T, int W, int WM,
                                                       int32_t *rq_off, int32_t *cand_off,
-                                                      int32_t *slot_row, int32_t *n_cand,
+                                                      int32_t *slot_row, int32_t *slot_len,
+                                                      int32_t *n_cand,
                                                       int32_t *n_rows, int32_t *n_items, int2 *rq,
                                                       Item *items) {
   extern __shared__ int s_mem[];
@@ -352,6 +356,7 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
         co[u] = off;
         cand_off[(int64_t)tid * nr + u] = off;
         slot_row[(int64_t)tid * nr + u] = r0;
+        slot_len[(int64_t)tid * nr + u] = r[u] >= 0 ? s_rs[r[u] + 1] - r0 : 0;
         if (r[u] >= 0) {
           const int sz = s_rs[r[u] + 1] - r0;
           off += (sz + kBlockRows - 1) / kBlockRows;
@@ -371,6 +376,7 @@ __global__ __launch_bounds__(1024) void k_sched_fused(const int32_t *__restrict_
         const int r0 = rj >= 0 ? s_rs[rj] : 0;
         cand_off[(int64_t)f * nr + j] = off;
         slot_row[(int64_t)f * nr + j] = r0;
+        slot_len[(int64_t)f * nr + j] = rj >= 0 ? s_rs[rj + 1] - r0 : 0;
         if (rj >= 0) {
           const int sz = s_rs[rj + 1] - r0;
           off += (sz + kBlockRows - 1) / kBlockRows;
@@ -428,13 +434,14 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
                         const int64_t *reg_start, int32_t T, int32_t W, int32_t WM, int32_t *rcount,
                         int32_t *rfill,
                         int32_t *vord, int32_t *rq_off, int32_t *item_off, int32_t *cand_off,
-                        int32_t *slot_row, int32_t *n_cand, int32_t *n_rows, int32_t *n_items,
+                        int32_t *slot_row, int32_t *slot_len, int32_t *n_cand, int32_t *n_rows,
+                        int32_t *n_items,
                         int2 *rq, Item *items, hipStream_t s) {
   const int64_t pairs = (int64_t)nq * nr;
   if (R <= kFusedMaxR && pairs <= kFusedMaxPairs) {
     return launch_kernel(k_sched_fused, dim3(1), dim3(1024), (uint32_t)fused_lds_bytes(R), s,
-                         regions, nq, nr, R, reg_start, T, W, WM, rq_off, cand_off, slot_row, n_cand,
-                         n_rows, n_items, rq, items);
+                         regions, nq, nr, R, reg_start, T, W, WM, rq_off, cand_off, slot_row,
+                         slot_len, n_cand, n_rows, n_items, rq, items);
   }
   hipError_t e = launch_fill_i32(rcount, R, 0, s);
   if (e != hipSuccess) return e;
@@ -443,10 +450,10 @@ hipError_t launch_sched(const int32_t *regions, int32_t nq, int32_t nr, int32_t 
     // one wave per frame, 16 frames per block
     e = hist ? launch_kernel(k_sched_count<true>, dim3((nq + 15) / 16), dim3(1024),
                              (uint32_t)(R * sizeof(int32_t)), s, regions, nq, nr, R, reg_start,
-                             rcount, cand_off, slot_row, n_cand, n_rows)
+                             rcount, cand_off, slot_row, slot_len, n_cand, n_rows)
              : launch_kernel(k_sched_count<false>, dim3((nq + 15) / 16), dim3(1024), 0, s,
-                             regions, nq, nr, R, reg_start, rcount, cand_off, slot_row, n_cand,
-                             n_rows);
+                             regions, nq, nr, R, reg_start, rcount, cand_off, slot_row, slot_len,
+                             n_cand, n_rows);
     if (e != hipSuccess) return e;
   }
   if ((e = launch_kernel(k_sched_scan, dim3(1), dim3(1024), 0, s, rcount, R, reg_start, T, W, WM,

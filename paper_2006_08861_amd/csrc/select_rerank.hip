@@ -345,15 +345,81 @@ __device__ void rerank_range(const SelRerankArgs &a, SelShared &sh, const float 
                                           s0 + w * kRowBatch, nw * kRowBatch);
 }
 
+// Sorts hi / lo[0, cnt), cnt <= kWaveSort, by (hi, lo) in one wave: lane l
+// holds entries l and l + 64 (empty ones past cnt) and a bitonic network
+// exchanges them through shuffles, no barrier.
+constexpr int kWaveSort = 128;
+__device__ __forceinline__ bool pair_less(uint64_t ah, uint32_t al, uint64_t bh, uint32_t bl) {
+  return ah < bh || (ah == bh && al < bl);
+}
+__device__ void wave_sort_pairs128(uint64_t *hi, uint32_t *lo, int cnt) {
+  const int lane = lane_id();
+  uint64_t h[2];
+  uint32_t l[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = lane + 64 * u;
+    h[u] = e < cnt ? hi[e] : kKeyNone;
+    l[u] = e < cnt ? lo[e] : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int k = 2; k <= kWaveSort; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j == 64) {
+        // partners in one lane (k = 128: ascending)
+        if (pair_less(h[1], l[1], h[0], l[0])) {
+          const uint64_t th = h[0];
+          const uint32_t tl = l[0];
+          h[0] = h[1];
+          l[0] = l[1];
+          h[1] = th;
+          l[1] = tl;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const uint64_t ph = (uint64_t)__shfl_xor((long long)h[u], j);
+          const uint32_t pl = (uint32_t)__shfl_xor((int)l[u], j);
+          const int e = lane + 64 * u;
+          // the lower element of an ascending pair (or the upper one of a
+          // descending pair) keeps the smaller
+          const bool keep_min = ((lane & j) == 0) == ((e & k) == 0);
+          const bool p_less = pair_less(ph, pl, h[u], l[u]);
+          if (keep_min == p_less) {
+            h[u] = ph;
+            l[u] = pl;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = lane + 64 * u;
+    if (e < cnt) {
+      hi[e] = h[u];
+      lo[e] = l[u];
+    }
+  }
+}
+
 // Sorts sort_hi / sort_lo[0, cnt) ascending; the pairs are distinct (the
 // second member is a candidate position or the tie id of a distinct row).
-// Up to kRankSort entries: G threads per entry (G consecutive lanes, G =
+// Up to kWaveSort entries: wave_sort_pairs128 in the first wave. Up to
+// kRankSort entries: G threads per entry (G consecutive lanes, G =
 // blockDim / next_pow2(cnt), at most 64) each count the entries of a slice
 // that order before it, the lanes add their counts and the entry is stored
 // at that rank. Above, a bitonic merge in LDS over the entries padded to a
 // power of two with empty ones.
 __device__ void sort_pairs(SelShared &sh, int cnt) {
   const int tid = threadIdx.x;
+  if (cnt <= kWaveSort) {
+    __syncthreads();
+    if (tid < 64) wave_sort_pairs128(sh.sort_hi, sh.sort_lo, cnt);
+    __syncthreads();
+    return;
+  }
   if (cnt <= kRankSort && cnt <= (int)blockDim.x) {
     __syncthreads();
     const int G = min(64, (int)blockDim.x / next_pow2(max(cnt, 1)));
@@ -539,8 +605,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
     s_off[j] = a.slot_off[(int64_t)f * nslots + j];
     s_row[j] = a.slot_row[(int64_t)f * nslots + j];
     if (a.blocks) {
-      const int r = a.slot_reg[(int64_t)f * nslots + j];
-      s_len[j] = r >= 0 ? (int)(a.reg_start[r + 1] - a.reg_start[r]) : 0;
+      s_len[j] = a.slot_len[(int64_t)f * nslots + j];
     }
   }
   const int n = a.n_cand ? a.n_cand[f] : a.n_fixed;
@@ -1157,7 +1222,7 @@ hipError_t launch_select_rerank(SelRerankArgs a, hipStream_t s) {
   if (a.frame_list && !a.frame_count) return hipErrorInvalidValue;
   if (a.nslots < 0 || a.nslots > kMaxSlots || (a.nslots > 0 && (!a.slot_off || !a.slot_row)))
     return hipErrorInvalidValue;
-  if (a.blocks && ((a.nslots > 0 && (!a.slot_reg || !a.reg_start)) ||
+  if (a.blocks && ((a.nslots > 0 && !a.slot_len) ||
                    (a.nslots == 0 && !a.blk_rows)))
     return hipErrorInvalidValue;
   if (a.keys) {
