@@ -648,6 +648,71 @@ def labels_bench(a) -> None:
     db.close()
 
 
+def streams_bench(a) -> None:
+    """Sliding windows across calls (hloc_query_streams_async) on
+    fp32-200k-d256: a.streams_n video streams along the walk (consecutive
+    rows plus N(0, 0.1^2) noise), each call bringing one new frame per
+    stream; every frame's window is the frame and the a.streams - 1 before it
+    in its stream, kept on the device between calls. Value: window estimates
+    (frames) per second over a.steps calls."""
+    import torch
+
+    from paper_2006_08861_amd import hloc, workload
+
+    w = workload.make_workload(1)
+    S, M = a.streams_n, a.streams
+    T = a.warmup + a.steps
+    rng = np.random.default_rng(2016)
+    starts = rng.integers(0, len(w.feats) - T, S)
+    d = w.feats.shape[1]
+    q_h = np.stack([w.feats[starts + t] for t in range(T)]).astype(np.float32)
+    q_h += (0.1 * rng.standard_normal(q_h.shape)).astype(np.float32)
+    agg = (0.3, 10, 3.0, 20)
+    dev = torch.device("cuda:0")
+    db = hloc.HlocDB(w.feats, w.xy)
+    db.set_regions(w.region_of, w.n_regions_total)
+    db.set_aggregation(*agg)
+    k, n_reg = w.k, w.n_reg
+    st = hloc.Streams(db, S, M, k, max_frames=S)
+    q = torch.from_numpy(q_h).to(dev)
+    offs = torch.arange(S + 1, dtype=torch.int32, device=dev)
+    sid = torch.arange(S, dtype=torch.int32, device=dev)
+    o = {"idx": torch.empty((S, k), dtype=torch.int64, device=dev),
+         "dist": torch.empty((S, k), dtype=torch.float32, device=dev),
+         "xy": torch.empty((S, 2), dtype=torch.float64, device=dev),
+         "tile": torch.empty((S, 2), dtype=torch.int32, device=dev),
+         "flags": torch.empty(S, dtype=torch.int32, device=dev)}
+    lib = hloc.load_library()
+    P = ctypes.c_void_p
+    stream = torch.cuda.current_stream(dev)
+    outp = tuple(P(o[key].data_ptr()) for key in ("idx", "dist", "xy", "tile", "flags"))
+
+    def call(t):
+        rc = lib.hloc_query_streams_async(st._h, P(q[t].data_ptr()), S, n_reg, hloc.FP32,
+                                          P(offs.data_ptr()), P(sid.data_ptr()), S, *outp,
+                                          P(stream.cuda_stream))
+        if rc != 0:
+            raise hloc.HlocError(rc, lib.hloc_last_error().decode())
+
+    for t in range(a.warmup):
+        call(t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(a.warmup, T):
+        call(t)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st.close()
+    db.close()
+    print(json.dumps({
+        "metric": "window estimates/s (sliding windows across calls, one new frame per stream "
+                  "per call)",
+        "value": S * a.steps / wall, "unit": "frames/s", "ms_per_call": wall * 1e3 / a.steps,
+        "steps": a.steps, "warmup": a.warmup, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{w.name}-streams{S}-window{M}", "streams": S, "window": M,
+                   "k": k, "n_regions": n_reg}}), flush=True)
+
+
 def serve_bench(a) -> None:
     """Poisson arrivals of 1-16 frame requests (k in {8, 16, 32}) into the
     request server, at each rate of a.serve (requests/s, comma-separated) for
@@ -786,6 +851,9 @@ def main():
     ap.add_argument("--windows", type=int, default=0, metavar="M",
                     help="only run sliding-window requests of M frames over a video")
     ap.add_argument("--windows-frames", type=int, default=256, help="video frames per batch")
+    ap.add_argument("--streams", type=int, default=0, metavar="M",
+                    help="only run sliding windows of M frames across calls (hloc_streams)")
+    ap.add_argument("--streams-n", type=int, default=256, help="video streams (one frame each per call)")
     ap.add_argument("--fft", action="store_true",
                     help="only time the Fourier-magnitude feature kernel")
     ap.add_argument("--fft-signals", type=int, default=200_000)
@@ -815,6 +883,12 @@ def main():
             print("bench.py measures one GPU only", file=sys.stderr)
             sys.exit(2)
         fft_bench(a)
+        return
+    if a.streams:
+        if a.gpus != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        streams_bench(a)
         return
     if a.serve:
         if a.gpus != 1:

@@ -209,6 +209,48 @@ int hloc_query_windows_async(hloc_db *db, const float *q, int32_t nq, int32_t k,
                              int32_t *tile, int32_t *flags, void *stream);
 
 /*
+ * Sliding windows across calls (Section 3.1: the request for frame q_m
+ * carries the frames before it; M = 11 in Section 4). A video stream sends
+ * each frame once: the library keeps, per stream, the top-k lists of its
+ * last window - 1 frames on the device, and the estimate of a new frame
+ * pools its own list with those (its window), so every frame is retrieved
+ * once however many windows it belongs to.
+ *
+ * hloc_streams_create: state for n_streams streams (ids 0 .. n_streams - 1),
+ * windows of `window` frames (window x k <= HLOC_MAX_REQUEST_CANDIDATES), k
+ * candidates per frame and at most max_frames new frames per call; device
+ * memory about (n_streams (window - 1) + max_frames) k 8 bytes. Every stream
+ * starts empty. The state holds a workspace of db until hloc_streams_free.
+ * hloc_streams_reset forgets every stream's frames (waits for the device).
+ *
+ * hloc_query_streams_async: new frames q (nq x d, device) in nseg segments:
+ * segment g is frames seg_offsets[g] .. seg_offsets[g+1]-1 of stream
+ * seg_stream[g], in capture order (device arrays of nseg + 1 and nseg
+ * int32; a stream in at most one segment per call). Per new frame: its top-k
+ * (idx / dist, nq x k, or both NULL) and the estimate of its window (xy,
+ * tile, flags, nq entries): the frame and the frames before it in its stream,
+ * from this call and earlier calls, at most `window` of them, aggregated as
+ * in hloc_query_batch. Afterwards each stream in the call keeps its last
+ * window - 1 frames. A segment whose stream is out of range, repeated in the
+ * call, or whose offsets are malformed is ignored (its frames get
+ * HLOC_FLAG_BAD_REQUEST and its stream is left as it was), as are frames
+ * outside every segment. Enqueued on `stream`; calls on one state must be
+ * ordered (one stream, or waited for). Every frame of the batch is retrieved
+ * with n_regions and precision as in hloc_query_batch.
+ * Errors: EINVAL (sizes, NULL pointers, nq > max_frames, window x k too
+ * large), ENOMEM, ESTATE, EUNSUPPORTED, EDEVICE.
+ */
+typedef struct hloc_streams hloc_streams;
+int hloc_streams_create(hloc_db *db, int32_t n_streams, int32_t window, int32_t k,
+                        int32_t max_frames, hloc_streams **out);
+int hloc_streams_reset(hloc_streams *st);
+void hloc_streams_free(hloc_streams *st);
+int hloc_query_streams_async(hloc_streams *st, const float *q, int32_t nq, int32_t n_regions,
+                             int32_t precision, const int32_t *seg_offsets,
+                             const int32_t *seg_stream, int32_t nseg, int64_t *idx, float *dist,
+                             double *xy, int32_t *tile, int32_t *flags, void *stream);
+
+/*
  * Subspace labels (Section 3.1: the database is split into subspaces, such as
  * the walked paths of Section 4, where the top N candidates of every path are
  * kept: N x M x P for a request of M frames over P paths). labels: host, one

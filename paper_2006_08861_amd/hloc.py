@@ -59,6 +59,11 @@ _SIGNATURES = {
                                                      _P, _P, _P, _P, _P, _P]),
     "hloc_query_windows_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _P, _I32, _I32,
                                                 _I32, _P, _P, _P, _P, _P, _P]),
+    "hloc_streams_create": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, ctypes.POINTER(_P)]),
+    "hloc_streams_reset": (ctypes.c_int, [_P]),
+    "hloc_streams_free": (None, [_P]),
+    "hloc_query_streams_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _P, _I32, _P, _P,
+                                                _P, _P, _P, _P]),
     "hloc_set_region_labels": (ctypes.c_int, [_P, _P, _I32]),
     "hloc_query_labels_async": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32, _I32,
                                                _P, _P, _P, _P, _P, _P]),
@@ -497,6 +502,66 @@ class Workspace:
 
 _SERVER_STATS = ("slots", "slot_bytes", "batches", "requests", "frames", "max_batch_frames",
                  "queued_frames", "peak_queued_frames", "max_in_flight", "refused")
+
+
+class Streams:
+    """Sliding windows across calls (hloc_streams): per video stream the
+    top-k lists of its last window - 1 frames stay on the device, and each
+    new frame's estimate pools its window."""
+
+    def __init__(self, db: HlocDB, n_streams: int, window: int, k: int, max_frames: int):
+        self.db, self.k, self.window = db, k, window
+        h = _P()
+        _check(load_library().hloc_streams_create(db._h, n_streams, window, k, max_frames,
+                                                  ctypes.byref(h)))
+        self._h = h
+
+    def query(self, q, seg_offsets, seg_stream, n_regions: int, precision="fp32",
+              stream=None) -> dict:
+        """New frames q in segments (frames seg_offsets[g] : seg_offsets[g+1]
+        of stream seg_stream[g], in capture order); CUDA tensors or NumPy
+        arrays (copied to the device). Returns CUDA tensors: idx, dist per
+        frame and xy, tile, flags of each frame's window."""
+        import torch
+        dev = q.device if _is_torch_cuda(q) else torch.device("cuda", torch.cuda.current_device())
+
+        def on_dev(a, dtype):
+            if _is_torch_cuda(a):
+                return a.to(dtype).contiguous()
+            return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(dev)
+
+        qd = on_dev(q, torch.float32)
+        offs = on_dev(seg_offsets, torch.int32)
+        sid = on_dev(seg_stream, torch.int32)
+        nq, nseg = int(qd.shape[0]), int(sid.shape[0])
+        out = {"idx": torch.empty((nq, self.k), dtype=torch.int64, device=dev),
+               "dist": torch.empty((nq, self.k), dtype=torch.float32, device=dev),
+               "xy": torch.empty((nq, 2), dtype=torch.float64, device=dev),
+               "tile": torch.empty((nq, 2), dtype=torch.int32, device=dev),
+               "flags": torch.empty(nq, dtype=torch.int32, device=dev)}
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        _check(load_library().hloc_query_streams_async(
+            self._h, _P(qd.data_ptr()), nq, n_regions, PRECISIONS[precision],
+            _P(offs.data_ptr()), _P(sid.data_ptr()), nseg,
+            *(_P(out[key].data_ptr()) for key in ("idx", "dist", "xy", "tile", "flags")),
+            _P(stream.cuda_stream)))
+        return out
+
+    def reset(self):
+        _check(load_library().hloc_streams_reset(self._h))
+
+    def close(self):
+        """Frees the state (before the database is closed)."""
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().hloc_streams_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -190,6 +190,95 @@ def test_sliding_windows(torch_cuda):
     db.close()
 
 
+def test_streams_across_calls(torch_cuda):
+    """Sliding windows of M = 11 across calls (hloc_streams): two video
+    streams of 60 frames sent in three calls of uneven pieces, each frame
+    once. Every frame's list against the oracle, every window's estimate
+    against the oracle's for that window (the frame and up to 10 before it in
+    its stream) and bit for bit against the same windows sent in one batch as
+    materialised requests. A stream repeated in a call and an out-of-range
+    stream are flagged and leave the history as it was; a reset empties it."""
+    torch = torch_cuda
+    w = workload.make_workload(0, nq=8)
+    rng = np.random.default_rng(23)
+    T, M, S = 60, 11, 2
+    d = w.feats.shape[1]
+    videos = [(w.feats[3000 + 2500 * s:3000 + 2500 * s + T + 1]
+               + 0.1 * rng.standard_normal((T + 1, d))).astype(np.float32) for s in range(S)]
+    agg = (0.3, 10, 3.0, 20)
+    R = w.n_regions_total
+    say(f"[case] streams across calls: {S} videos x {T} frames, M={M}")
+    db = make_db(w.feats, w.xy, w.region_of, R, agg)
+    st = hloc.Streams(db, n_streams=4, window=M, k=w.k, max_frames=64)
+
+    def send(call):
+        q = np.concatenate([videos[s][a:b] for s, a, b in call])
+        offs = np.cumsum([0] + [b - a for s, a, b in call]).astype(np.int32)
+        sid = np.array([s for s, a, b in call], np.int32)
+        out = st.query(q, offs, sid, w.n_reg)
+        torch.cuda.synchronize()
+        return {key: v.cpu().numpy() for key, v in out.items()}
+
+    got = {}
+    for call in ([(0, 0, 25), (1, 0, 7)], [(1, 7, 41), (0, 25, 30)], [(0, 30, 60), (1, 41, 60)]):
+        out = send(call)
+        j = 0
+        for s, a, b in call:
+            for t in range(a, b):
+                got[(s, t)] = {key: out[key][j] for key in out}
+                j += 1
+    allq = np.concatenate([v[:T] for v in videos])  # frame (s, t) at s T + t
+    frames, offs = [], [0]
+    for s in range(S):
+        for t in range(T):
+            frames += [s * T + u for u in range(max(0, t - M + 1), t + 1)]
+            offs.append(len(frames))
+    frames, offs = np.asarray(frames, np.int32), np.asarray(offs, np.int32)
+    ora = oracle.localize(w.feats, w.xy, w.region_of, R, allq, offs, w.k, w.n_reg, agg,
+                          req_frames=frames)
+    keys = [(s, t) for s in range(S) for t in range(T)]
+    idx = np.stack([got[kk]["idx"] for kk in keys])
+    dist = np.stack([got[kk]["dist"] for kk in keys])
+    st_ = judge_frames(idx, dist, None, ora, w.feats, w.region_of, R, allq, w.k)
+    assert st_["recall"] == 1.0
+    same = np.array([set(idx[i].tolist()) == set(ora["idx"][i].tolist()) for i in range(len(keys))])
+    checked = 0
+    for r, kk in enumerate(keys):
+        if not same[frames[offs[r]:offs[r + 1]]].all():
+            continue
+        checked += 1
+        assert got[kk]["tile"].tolist() == ora["tile"][r].tolist(), kk
+        assert got[kk]["flags"] == ora["flags"][r], kk
+    say(f"[ok] {st_} windows checked {checked}/{len(keys)}")
+    assert checked >= len(keys) - 5
+    mat = run_device(torch, db, allq[frames], w.k, w.n_reg, offs)
+    for r, kk in enumerate(keys):
+        assert mat["tile"][r].tolist() == got[kk]["tile"].tolist(), kk
+        assert mat["flags"][r] == got[kk]["flags"], kk
+        assert mat["xy"][r].tobytes() == got[kk]["xy"].tobytes(), kk
+    # a repeated stream and an out-of-range one: flagged, histories unchanged
+    bad = send([(0, T, T + 1), (0, T, T + 1), (3, 0, 1)][:2])
+    assert (bad["flags"] == hloc.FLAG_BAD_REQUEST).all()
+    q_bad = np.concatenate([videos[0][T:T + 1]])
+    out = st.query(q_bad, np.array([0, 1], np.int32), np.array([7], np.int32), w.n_reg)
+    torch.cuda.synchronize()
+    assert out["flags"].cpu().numpy()[0] == hloc.FLAG_BAD_REQUEST
+    # frame T of stream 0: its window is frames T - 10 .. T of video 0
+    last = send([(0, T, T + 1)])
+    q_last = np.concatenate([videos[0][T - M + 1:T + 1]])
+    ref = run_device(torch, db, q_last, w.k, w.n_reg, np.array([0, M], np.int32))
+    assert last["tile"][0].tolist() == ref["tile"][0].tolist()
+    assert last["xy"][0].tobytes() == ref["xy"][0].tobytes()
+    assert last["flags"][0] == ref["flags"][0]
+    # after a reset a frame's window is the frame alone
+    st.reset()
+    one = send([(1, 5, 6)])
+    ref1 = run_device(torch, db, videos[1][5:6], w.k, w.n_reg, np.array([0, 1], np.int32))
+    assert one["xy"][0].tobytes() == ref1["xy"][0].tobytes()
+    st.close()
+    db.close()
+
+
 @pytest.mark.parametrize("n_reg", [5, 1000])
 def test_subspace_labels(torch_cuda, n_reg):
     """Top k per (frame, label) over three labels (contiguous runs of regions,
