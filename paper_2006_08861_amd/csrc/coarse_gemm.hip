@@ -137,9 +137,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   v4u pv[PER];
   float prn = 0.f;
   int plab = 0;
-#define HLOC_CG_FETCH(T)                                                       \
+  // tile t of the order is tile (t stride) mod ntiles: cur_t for the tile
+  // multiplied, nxt_t for the one fetched (stride < ntiles, so one step is
+  // one conditional subtraction)
+  int cur_t = 0, nxt_t = 0;
+  auto advance = [&](int x) {
+    x += stride;
+    return x >= ntiles ? x - ntiles : x;
+  };
+#define HLOC_CG_FETCH()                                                        \
   {                                                                            \
-    const int fb = r0 + (int)(((int64_t)(T) * stride) % ntiles) * kCgTile;     \
+    const int fb = r0 + nxt_t * kCgTile;                                       \
     _Pragma("unroll") for (int u = 0; u < PER; ++u) {                          \
       const int e = tid + u * 256, row = e / ROWU4, c = e - row * ROWU4;       \
       pv[u] = reps[(int64_t)min(fb + row, r1 - 1) * ROWU4 + c];                \
@@ -162,7 +170,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 
   if (ntiles > 0) {
-    HLOC_CG_FETCH(0)
+    HLOC_CG_FETCH()
     HLOC_CG_STAGE(0)
   }
   // every load so far has landed (the frame operand above all), so the
@@ -171,7 +179,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   __syncthreads();
   for (int t = 0; t < ntiles; ++t) {
     const int buf = t & 1;
-    if (t + 1 < ntiles) HLOC_CG_FETCH(t + 1)  // in flight while this tile is multiplied
+    if (t + 1 < ntiles) {
+      nxt_t = advance(nxt_t);
+      HLOC_CG_FETCH()  // in flight while this tile is multiplied
+    }
     v4f acc[2][2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -189,7 +200,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       acc[1][1] = cg_mfma(a1, bv[1][s], acc[1][1]);
     }
     // epilogue: per (row half h, frame group j) the lane's quad of words
-    const int base = r0 + (int)(((int64_t)t * stride) % ntiles) * kCgTile;
+    const int base = r0 + cur_t * kCgTile;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int row0 = h * kGroup + 4 * g;
@@ -224,6 +235,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
     if (t + 1 < ntiles) HLOC_CG_STAGE(buf ^ 1)  // last read before the previous barrier
     __syncthreads();
+    cur_t = advance(cur_t);
   }
 #undef HLOC_CG_FETCH
 #undef HLOC_CG_STAGE

@@ -28,8 +28,13 @@ __device__ __forceinline__ void store_words4(uint32_t *p, uint32_t a, uint32_t b
 // its frame's minimum.
 __device__ __forceinline__ uint32_t block_min16(const uint32_t (&wd)[4]) {
   uint32_t m = min(min(wd[0], wd[1]), min(wd[2], wd[3]));
-  m = min(m, (uint32_t)__shfl_xor((int)m, 16));
-  m = min(m, (uint32_t)__shfl_xor((int)m, 32));
+  // gfx950 lane swaps (VALU, no LDS): v_permlane16_swap hands each lane the
+  // values of its lane and of lane ^ 16 (one in each result), then
+  // v_permlane32_swap those of lane and lane ^ 32
+  const auto p16 = __builtin_amdgcn_permlane16_swap(m, m, false, false);
+  m = min((uint32_t)p16[0], (uint32_t)p16[1]);
+  const auto p32 = __builtin_amdgcn_permlane32_swap(m, m, false, false);
+  m = min((uint32_t)p32[0], (uint32_t)p32[1]);
   return m;
 }
 
