@@ -21,6 +21,30 @@ __device__ __forceinline__ void store_words4(uint32_t *p, uint32_t a, uint32_t b
   *reinterpret_cast<Words4 *>(p) = Words4{{a, b, c, d}};
 }
 
+// The value of lane l ^ 32 (resp. l ^ 16) through the gfx950 lane swaps:
+// v_permlane32_swap gives each lane the values of lanes l % 32 and
+// l % 32 + 32 (v_permlane16_swap: of its row pair), one in each result.
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t v) {
+  const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return (lane_id() & 32) ? (uint32_t)p[0] : (uint32_t)p[1];
+}
+__device__ __forceinline__ uint32_t lane_xor16(uint32_t v) {
+  const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return (lane_id() & 16) ? (uint32_t)p[0] : (uint32_t)p[1];
+}
+__device__ __forceinline__ double lane_xor_f64(double v, int o) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  uint32_t lo = (uint32_t)b, hi = (uint32_t)(b >> 32);
+  if (o == 32) {
+    lo = lane_xor32(lo);
+    hi = lane_xor32(hi);
+  } else {
+    lo = lane_xor16(lo);
+    hi = lane_xor16(hi);
+  }
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // Smallest of one frame's 16 screen words of a 16-row block, as the MFMA
 // tile holds them: lane l has frame l % 16 and rows 4 (l / 16) .. + 3 in wd
 // (0xFFFFFFFF for rows past the end). The lanes of one frame exchange across

@@ -33,16 +33,24 @@ constexpr uint32_t kWordNone = 0xFFFFFFFFu;  // no candidate at this position
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;     // a block's row slot past its last row
 constexpr int kDigitBits = 12;     // radix digit of the select (two passes cover 24 bits)
 
+// Wave reductions: the exchanges 32 and 16 lanes apart through the lane
+// swaps (VALU), the rest through shuffles.
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
+  v = min(v, lane_xor32(v));
+  v = min(v, lane_xor16(v));
+  for (int o = 8; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
   return v;
 }
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+  v = max(v, lane_xor32(v));
+  v = max(v, lane_xor16(v));
+  for (int o = 8; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
   return v;
 }
 __device__ __forceinline__ int wave_sum_i32(int v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  v += (int)lane_xor32((uint32_t)v);
+  v += (int)lane_xor16((uint32_t)v);
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
 
@@ -187,7 +195,7 @@ __device__ __forceinline__ void halve_rows(double (&acc)[kRowBatch], int lane) {
   for (int r = 0; r < H; ++r) {
     const double keep = up ? acc[r + H] : acc[r];
     const double send = up ? acc[r] : acc[r + H];
-    acc[r] = keep + __shfl_xor(send, O);
+    acc[r] = keep + (O >= 16 ? lane_xor_f64(send, O) : __shfl_xor(send, O));
   }
 }
 
