@@ -192,6 +192,7 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *byte
   CHK(fit(ws->slot_len, (size_t)nq * nr * sizeof(int32_t)));
   CHK(fit(ws->n_cand, (size_t)nq * sizeof(int32_t)));
   CHK(fit(ws->n_rows, (size_t)nq * sizeof(int32_t)));
+  CHK(fit(ws->fstat, (size_t)nq * sizeof(int4)));
   CHK(fit(ws->misc, 16 * sizeof(int32_t)));
   CHK(fit(ws->rq, (size_t)nq * nr * sizeof(int2)));
   CHK(fit(ws->items, (size_t)std::max<int64_t>(p.items_bound, 1) * sizeof(Item)));
@@ -492,11 +493,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   rb.nq = p.nq;
   rb.idx_out = idx;
   rb.dist_out = dist;
-  rb.stat_fallback = misc + 2;
-  rb.stat_max = misc + 3;
-  rb.stat_chunked = misc + 6;
-  rb.stat_band = misc + 7;
-  rb.stat_rows = misc + 9;
+  rb.frame_stat = as<int4>(ws->fstat);
   HIPCHK(launch_select_rerank(rb, s));
   ph.end();
   if (want_agg && p.nreq > 0) {
@@ -568,7 +565,7 @@ void for_each_buf(hloc_ws *ws, F f) {
                    &ws->misc,     &ws->rq,       &ws->items,    &ws->cand2,   &ws->agg_xy,
                    &ws->agg_tile, &ws->agg_flags, &ws->s_q,     &ws->s_off,   &ws->s_idx,
                    &ws->s_dist,   &ws->s_xy,     &ws->s_tile,   &ws->s_flags, &ws->q_lp,
-                   &ws->q_scale,  &ws->q_err,    &ws->q_lon,   &ws->slot_row, &ws->slot_len, &ws->n_rows,
+                   &ws->q_scale,  &ws->q_err,    &ws->q_lon,   &ws->slot_row, &ws->slot_len, &ws->n_rows, &ws->fstat,
                    &ws->c_lp,     &ws->c_scale,  &ws->c_err,   &ws->c_lon,   &ws->agg_big,
                    &ws->lab_off,  &ws->lab_list, &ws->lab_q,  &ws->ckeys,
                    &ws->cslots,   &ws->cbounds,  &ws->cdefer};
@@ -688,15 +685,26 @@ int info_of(hloc_ws *ws, int64_t *out, int32_t n) {
   HIPCHK(hipDeviceSynchronize());
   int32_t misc[16] = {0};
   if (ws->misc.p) HIPCHK(hipMemcpy(misc, ws->misc.p, sizeof misc, hipMemcpyDeviceToHost));
-  int64_t total = 0;
+  int64_t total = 0, fine_fb = 0, max_n = 0, chunked = 0, band = 0, rows = 0;
   if (ws->last_nq > 0 && ws->n_rows.p) {
     std::vector<int32_t> nc(ws->last_nq);
     HIPCHK(hipMemcpy(nc.data(), ws->n_rows.p, nc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     for (int32_t v : nc) total += v;
   }
-  const int64_t vals[11] = {misc[0], misc[1], misc[2],     misc[3], ws->last_kp,
-                            total,   misc[4], misc[6], (int64_t)(uint32_t)misc[7],
-                            (int64_t)(uint32_t)misc[9], misc[10]};
+  if (ws->last_nq > 0 && ws->fstat.p) {
+    // the fine select's per-frame records of the last batch
+    std::vector<int4> fs(ws->last_nq);
+    HIPCHK(hipMemcpy(fs.data(), ws->fstat.p, fs.size() * sizeof(int4), hipMemcpyDeviceToHost));
+    for (const int4 &r : fs) {
+      max_n = std::max<int64_t>(max_n, r.x);
+      rows += r.y;
+      band += r.z;
+      fine_fb += r.w & 1;
+      chunked += (r.w >> 1) & 1;
+    }
+  }
+  const int64_t vals[11] = {misc[0], misc[1], fine_fb, max_n,   ws->last_kp, total,
+                            misc[4], chunked, band,    rows,    misc[10]};
   for (int32_t i = 0; i < std::min(n, 11); ++i) out[i] = vals[i];
   return HLOC_OK;
 }

@@ -88,6 +88,7 @@ struct hloc_ws {
   hipStream_t stream = nullptr;  // own stream (graph capture, host-pointer calls)
   hloc::WsBuf qp, qn2, cand1, regions, rcount, rfill, vord, rq_off, item_off, cand_off, n_cand, misc, rq,
       items, cand2, agg_xy, agg_tile, agg_flags, q_lp, q_scale, q_err, q_lon, slot_row, slot_len, n_rows,
+      fstat,                        // fine select's per-frame statistics
       c_lp, c_scale, c_err, c_lon,  // bf16 frame copy for the coarse screen of fp8 queries
       agg_big,                      // requests for the large-list aggregation kernel
       lab_off, lab_list,            // frame lists of a query over subspace labels

@@ -296,11 +296,12 @@ struct SelRerankArgs {
   int64_t *idx_out;        // fine: nq x m original indices
   float *dist_out;         // fine: nq x m
   int32_t *reg_out;        // coarse: nq x m region ids
-  int32_t *stat_fallback;  // frames whose certificate failed (band re-scored)
-  int32_t *stat_chunked;   // frames whose band was re-scored in several chunks (or NULL)
-  int32_t *stat_band;      // sum of the band sizes (or NULL)
-  int32_t *stat_max;       // largest candidate count (or NULL)
-  int32_t *stat_rows;      // rows re-scored in FP64, survivors and bands (or NULL)
+  int32_t *stat_fallback;  // count of frames whose certificate failed (or NULL)
+  // per frame, written once by the frame's block or wave (or NULL): candidate
+  // count, rows re-scored in FP64 (survivors and band), band rows, flags (1:
+  // the certificate failed and the band was re-scored, 2: in several chunks).
+  // Plain stores: one counter shared by every frame would serialise at L2.
+  int4 *frame_stat;
   // key mode (the coarse stage after the fused coarse product): the frame's
   // n_fixed candidates are keys (word << 32 | source row, any order), and
   // n_bounds bounds per frame: every source row missing from the keys has a

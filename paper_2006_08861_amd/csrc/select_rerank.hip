@@ -622,7 +622,6 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
   const int C = a.keys ? n : min(n, a.cache);
   uint32_t *krow = a.keys ? wc + n : nullptr;
   const float qn2 = a.qn2[f];
-  if (tid == 0 && a.stat_max) atomicMax(a.stat_max, n);
   auto word_at = [&](int i) -> uint32_t { return i < C ? wc[i] : words[i]; };
 
   int nv_local = 0;
@@ -914,7 +913,6 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
         else if (a.stat_fallback) atomicAdd(a.stat_fallback, 1);
       }
     }
-    if (a.stat_rows) atomicAdd(a.stat_rows, nrow);
   }
   __syncthreads();
   int have = min(nrow, a.m);
@@ -922,6 +920,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
     defer();
     return;
   }
+  int band_rows = 0, fflags = 0;
   if (sh.flag == 1) {
     // the band: rejected positions (above tw, or equal to tw past the first
     // take_eq) with a word up to tau_w (>= tw)
@@ -956,7 +955,7 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
       // still enter the top m has a word up to tau_w, so this is exact.
       const int m = a.m, chunk = (kMaxSurvivors - m) / unit, excl = incl - mine;
       int kept = min(nrow, m);  // sort_hi / sort_lo[0, kept): the best so far, sorted
-      if (tid == 0 && a.stat_chunked) atomicAdd(a.stat_chunked, 1);
+      fflags |= 2;
       for (int c0 = 0; c0 < total_band; c0 += chunk) {
         const int cnt = min(chunk, total_band - c0);
         // this thread's band positions ranked [c0, c0 + cnt) in position order
@@ -980,11 +979,10 @@ __global__ __launch_bounds__(BLOCK) void k_select_rerank(SelRerankArgs a) {
       }
       have = kept;
     }
-    if (tid == 0) {
-      if (a.stat_band) atomicAdd(a.stat_band, total_band * unit);
-      if (a.stat_rows) atomicAdd(a.stat_rows, total_band * unit);
-    }
+    band_rows = total_band * unit;
+    fflags |= 1;
   }
+  if (tid == 0 && a.frame_stat) a.frame_stat[f] = make_int4(n, nrow + band_rows, band_rows, fflags);
   for (int i = tid; i < a.m; i += blockDim.x) {
     const bool ok = i < have && sh.sort_hi[i] != kKeyNone;
     if (a.reg_out) {
@@ -1081,7 +1079,6 @@ __global__ __launch_bounds__(64 * kWaveFrames) void k_select_keys(SelRerankArgs 
     bound = b < bound ? b : bound;
   }
   const float qn2 = a.qn2[f];
-  if (lane == 0 && a.stat_max) atomicMax(a.stat_max, n);
   // entries (word << 32 | position) of the valid keys (kKeyNone otherwise)
   uint64_t ent[KPL];
   int nv = 0;
@@ -1161,8 +1158,7 @@ __global__ __launch_bounds__(64 * kWaveFrames) void k_select_keys(SelRerankArgs 
       }
     }
   }
-  if (lane == 0 && a.stat_rows) atomicAdd(a.stat_rows, nrow);
-  int have = min(nrow, m);
+  int have = min(nrow, m), band_rows = 0;
   if (band) {
     // the band: the pairs not taken out with a word up to tau_w (all of
     // them are at or after (tw, tpos)); their rows behind the survivors'
@@ -1186,12 +1182,11 @@ __global__ __launch_bounds__(64 * kWaveFrames) void k_select_keys(SelRerankArgs 
     wave_sync();
     wave_sort_pairs(sh, nrow + tot);
     have = min(nrow + tot, m);
-    if (lane == 0) {
-      if (a.stat_fallback) atomicAdd(a.stat_fallback, 1);
-      if (a.stat_band) atomicAdd(a.stat_band, tot);
-      if (a.stat_rows) atomicAdd(a.stat_rows, tot);
-    }
+    band_rows = tot;
+    if (lane == 0 && a.stat_fallback) atomicAdd(a.stat_fallback, 1);
   }
+  if (lane == 0 && a.frame_stat)
+    a.frame_stat[f] = make_int4(n, nrow + band_rows, band_rows, band ? 1 : 0);
   for (int i = lane; i < m; i += 64) {
     const bool ok = i < have && sh.sort_hi[i] != kKeyNone;
     a.reg_out[(int64_t)f * m + i] = ok ? (int32_t)sh.sort_lo[i] : -1;
