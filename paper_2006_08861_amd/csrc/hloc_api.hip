@@ -193,7 +193,7 @@ int ensure_workspace(hloc_ws *ws, const Plan &p, bool agg_internal, size_t *byte
   CHK(fit(ws->n_cand, (size_t)nq * sizeof(int32_t)));
   CHK(fit(ws->n_rows, (size_t)nq * sizeof(int32_t)));
   CHK(fit(ws->fstat, (size_t)nq * sizeof(int4)));
-  CHK(fit(ws->misc, 16 * sizeof(int32_t)));
+  CHK(fit(ws->misc, kMiscInts * sizeof(int32_t)));
   CHK(fit(ws->rq, (size_t)nq * nr * sizeof(int2)));
   CHK(fit(ws->items, (size_t)std::max<int64_t>(p.items_bound, 1) * sizeof(Item)));
   CHK(fit(ws->cand2, (size_t)nq * std::max<int64_t>(p.cap2, 1) * sizeof(uint32_t)));
@@ -264,7 +264,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   ws->last_kp = p.kp;
   int32_t *misc = as<int32_t>(ws->misc);
   if (p.nq == 0) {
-    HIPCHK(launch_fill_i32(misc, 16, 0, s));
+    HIPCHK(launch_fill_i32(misc, kMiscInts, 0, s));
     return HLOC_OK;
   }
   float *qp = as<float>(ws->qp), *qn2 = as<float>(ws->qn2);
@@ -444,6 +444,7 @@ int enqueue_query(hloc_ws *ws, const Plan &p, const float *q, const int32_t *req
   sb.dense = 0;
   sb.items = as<Item>(ws->items);
   sb.n_items = misc + 0;
+  sb.item_ctr = misc + kMiscItemCtr;
   sb.rq = as<int2>(ws->rq);
   sb.reg_start = db->reg_start;
   if (fmt) {

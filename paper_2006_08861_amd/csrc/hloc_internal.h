@@ -105,6 +105,9 @@ struct ScreenArgs {
   // frame_list[0 .. *frame_count), each writing its own row of cand
   const int32_t *frame_list;
   const int32_t *frame_count;
+  // register-row wide screen: 8 item counters, zero on entry, one per XCD
+  // span of the items (NULL: each block takes a fixed share of its span)
+  int32_t *item_ctr;
 };
 
 // Work item of the wide screens: a chunk of rows against up to kListFrames
@@ -169,9 +172,16 @@ __device__ __forceinline__ int2 wide_entry(const ScreenArgs &a, const WideItem &
   return !a.dense && j < w.gq ? a.rq[w.q0 + j] : make_int2(0, 0);
 }
 
-// Padded copy and squared norm of each frame; block 0 also clears zero16[0..16).
+// Per-batch counters of a workspace (cleared by the prep kernel): [0] items,
+// [1] coarse fallbacks, [4] narrow items, [8] large aggregation lists, [10]
+// deferred coarse frames, [16, 24) the wide screen's item counters.
+constexpr int kMiscInts = 32;
+constexpr int kMiscItemCtr = 16;
+
+// Padded copy and squared norm of each frame; block 0 also clears
+// zero[0 .. kMiscInts).
 hipError_t launch_prep_queries(const float *q, int32_t nq, int32_t d, int32_t dp, float *qp,
-                               float *qn2, int32_t *zero16, hipStream_t s);
+                               float *qn2, int32_t *zero, hipStream_t s);
 // Dense screen, or the narrow list items (every list item where no register
 // kernel exists for the padded length); then the wide list items.
 hipError_t launch_screen_f32(const ScreenArgs &a, int32_t grid, hipStream_t s);

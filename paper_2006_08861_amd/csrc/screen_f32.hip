@@ -23,8 +23,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_prep_queries(const float *__restrict__ q, int nq, int d,
                                                       int dp, float *__restrict__ qp,
                                                       float *__restrict__ qn2,
-                                                      int32_t *__restrict__ zero16) {
-  if (blockIdx.x == 0 && threadIdx.x < 16 && zero16) zero16[threadIdx.x] = 0;
+                                                      int32_t *__restrict__ zero) {
+  if (blockIdx.x == 0 && threadIdx.x < kMiscInts && zero) zero[threadIdx.x] = 0;
   const int f = blockIdx.x * 4 + wave_id();
   const int lane = lane_id();
   if (f >= nq) return;
@@ -41,10 +41,10 @@ __global__ __launch_bounds__(256) void k_prep_queries(const float *__restrict__ 
 }
 
 hipError_t launch_prep_queries(const float *q, int32_t nq, int32_t d, int32_t dp, float *qp,
-                               float *qn2, int32_t *zero16, hipStream_t s) {
+                               float *qn2, int32_t *zero, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
   return launch_kernel(k_prep_queries, dim3((nq + 3) / 4), dim3(256), 0, s, q, nq, d, dp, qp, qn2,
-                       zero16);
+                       zero);
 }
 
 template <bool DENSE>

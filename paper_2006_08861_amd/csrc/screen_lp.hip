@@ -492,10 +492,42 @@ __global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
   const int it0 = lo + x * span, it1 = min(hi, it0 + span);
   // staging: thread t loads pieces (t % TPF) + TPF u of frame t / TPF
   const int sj = tid / TPF, sc = tid % TPF;
-  Item nxt = it0 + jb < it1 ? a.items[it0 + jb] : Item{};
-  for (int it = it0 + jb; it < it1; it += nb) {
+  // With item counters the blocks of XCD x take the items of x's span in
+  // order, one counter increment each, then those left in the other spans
+  // (x + 1, x + 2, ... mod 8), so no block idles while items remain; thread
+  // 0 takes the next item at an item's start and the block reads it after
+  // the item's first barrier (two slots by item parity: the slot thread 0
+  // writes was last read before the previous item's set-up barrier). Without
+  // them block jb of XCD x takes items it0 + jb, + nb, ...
+  const bool dyn = a.item_ctr != nullptr;
+  __shared__ int s_nx[2];
+  int xs = 0;  // spans thread 0 has emptied
+  auto grab = [&]() -> int {
+    while (xs < kXcd) {
+      const int xx = x + xs < kXcd ? x + xs : x + xs - kXcd;
+      const int b0 = lo + xx * span, b1 = min(hi, b0 + span);
+      const int j = atomicAdd(a.item_ctr + xx, 1);
+      if (b0 + j < b1) return b0 + j;
+      ++xs;
+    }
+    return hi;
+  };
+  int it = it0 + jb, lim = it1;
+  if (dyn) {
+    if (tid == 0) s_nx[0] = grab();
+    __syncthreads();
+    it = s_nx[0];
+    lim = hi;
+  }
+  Item nxt = it < lim ? a.items[it] : Item{};
+  for (int par = 1; it < lim; par ^= 1) {
     const Item cur = nxt;
-    if (it + nb < it1) nxt = a.items[it + nb];
+    int itn = it + nb;
+    if (dyn) {
+      if (tid == 0) s_nx[par] = grab();
+    } else if (itn < lim) {
+      nxt = a.items[itn];
+    }
     const int row_begin = cur.row_begin, chunk_row = cur.chunk_row, q0 = cur.q0;
     const int nrows = cur.nrows_gq >> 16, gq = cur.nrows_gq & 0xFFFF;
     const int nrun = (nrows + kWideRowsRs - 1) / kWideRowsRs;
@@ -532,6 +564,10 @@ __global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
         s_fr[((BUF) * kGroup + sj) * LDF + sc + TPF * u] = pv[u];                \
   }
     __syncthreads();  // the previous item's entries and frames are no longer read
+    if (dyn) {
+      itn = s_nx[par];
+      if (itn < lim) nxt = a.items[itn];
+    }
     {
       // the item's frame entries (frames past gq: frame 0, never stored) and
       // the frame of this thread's piece of the first group
@@ -606,6 +642,7 @@ __global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
 #undef HLOC_RS_NORMS
 #undef HLOC_RS_FETCH_FRAME
 #undef HLOC_RS_STAGE
+    it = itn;
   }
 }
 
