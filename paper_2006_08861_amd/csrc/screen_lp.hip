@@ -467,6 +467,8 @@ __global__ __launch_bounds__(256) void k_screen_wide_lp(ScreenArgs a) {
 // Items are dealt to the XCDs in contiguous runs (blocks go to the eight
 // XCDs round-robin): the chunks of one region, which stage the same frames,
 // run on one XCD and find them in its L2.
+constexpr int kRsAhead = 4;  // frame pieces in flight ahead of the multiplies
+
 template <int FMT, int NS>
 __global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
   constexpr int ROWU4 = 4 * NS;                 // 16-byte pieces per row
@@ -608,10 +610,18 @@ __global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
     if (more) HLOC_RS_FETCH_FRAME(s_e[((LAST) ? 0 : (K) + 1) * kGroup + sj].x)   \
     v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};             \
     const v4u *bp = s_fr + (buf * kGroup + i) * LDF + g;                         \
+    /* frame pieces read kRsAhead steps ahead of their multiplies, the */       \
+    /* order pinned: the first reads, then per k step two multiplies and */     \
+    /* the next read */                                                          \
+    v4u bq[NS];                                                                  \
+    _Pragma("unroll") for (int s = 0; s < kRsAhead && s < NS; ++s) bq[s] = bp[4 * s]; \
+    __builtin_amdgcn_sched_group_barrier(0x100, kRsAhead < NS ? kRsAhead : NS, 0); \
     _Pragma("unroll") for (int s = 0; s < NS; ++s) {                             \
-      const v4u b = bp[4 * s];                                                   \
-      acc[0] = lp_mfma_v<FMT>(av[0][s], b, acc[0]);                              \
-      acc[1] = lp_mfma_v<FMT>(av[1][s], b, acc[1]);                              \
+      if (s + kRsAhead < NS) bq[s + kRsAhead] = bp[4 * (s + kRsAhead)];          \
+      acc[0] = lp_mfma_v<FMT>(av[0][s], bq[s], acc[0]);                          \
+      acc[1] = lp_mfma_v<FMT>(av[1][s], bq[s], acc[1]);                          \
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);                         \
+      if (s + kRsAhead < NS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  \
     }                                                                            \
     if ((LAST) && more) HLOC_RS_ROWS(c + 1)                                      \
     const int2 e = s_e[(K) * kGroup + i];                                        \
