@@ -70,9 +70,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   constexpr int LDR = ROWU4 + 1;     // pieces per LDS row, one of padding
   constexpr int PER = kCgTile * ROWU4 / 256;  // pieces per thread per tile
   static_assert(kCgTile * ROWU4 % 256 == 0, "whole pieces per thread");
+  static_assert(kCgTile <= 256 && (kCgTile & (kCgTile - 1)) == 0, "tile norms by tid bits");
   extern __shared__ v4u s_tile[];  // 2 x kCgTile x LDR
-  __shared__ float s_rn[2][kCgTile];
-  __shared__ int s_lab[LAB ? 2 : 1][kCgTile];
+  // (one slot per thread: every thread stores its fetched norm and label,
+  // the first kCgTile slots are the tile's)
+  __shared__ float s_rn[2][256];
+  __shared__ int s_lab[LAB ? 2 : 1][256];
 
   const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
   const int i = lane & 15, g = lane >> 4;
@@ -152,9 +155,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const int e = tid + u * 256, row = e / ROWU4, c = e - row * ROWU4;       \
       pv[u] = reps[(int64_t)min(fb + row, r1 - 1) * ROWU4 + c];                \
     }                                                                          \
-    if (tid < kCgTile) {                                                       \
-      prn = fb + tid < r1 ? a.rep_n2[fb + tid] : __builtin_inff();             \
-      if (LAB) plab = a.rlabel[min(fb + tid, r1 - 1)];                         \
+    {                                                                          \
+      const int rr = fb + (tid & (kCgTile - 1));                               \
+      const float n2 = a.rep_n2[min(rr, r1 - 1)];                              \
+      prn = rr < r1 ? n2 : __builtin_inff();                                   \
+      if (LAB) plab = a.rlabel[min(rr, r1 - 1)];                               \
     }                                                                          \
   }
 #define HLOC_CG_STAGE(BUF)                                                     \
@@ -163,10 +168,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const int e = tid + u * 256, row = e / ROWU4, c = e - row * ROWU4;       \
       s_tile[((BUF) * kCgTile + row) * LDR + c] = pv[u];                        \
     }                                                                          \
-    if (tid < kCgTile) {                                                       \
-      s_rn[BUF][tid] = prn;                                                    \
-      if (LAB) s_lab[LAB ? (BUF) : 0][tid] = plab;                             \
-    }                                                                          \
+    s_rn[BUF][tid] = prn;                                                      \
+    if (LAB) s_lab[LAB ? (BUF) : 0][tid] = plab;                               \
   }
 
   if (ntiles > 0) {
@@ -177,12 +180,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   // waits inside the loop concern only the next tile's rows
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  // Every iteration fetches and stages a tile (after the last, tile
+  // advance(...) again, never read): with no conditional path the loads
+  // are always consumed by the stage, and no wait at the next tile's start
+  // holds the epilogue's slot stores.
   for (int t = 0; t < ntiles; ++t) {
     const int buf = t & 1;
-    if (t + 1 < ntiles) {
-      nxt_t = advance(nxt_t);
-      HLOC_CG_FETCH()  // in flight while this tile is multiplied
-    }
+    nxt_t = advance(nxt_t);
+    HLOC_CG_FETCH()  // in flight while this tile is multiplied
     v4f acc[2][2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -233,7 +238,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
       }
     }
-    if (t + 1 < ntiles) HLOC_CG_STAGE(buf ^ 1)  // last read before the previous barrier
+    HLOC_CG_STAGE(buf ^ 1)  // last read before the previous barrier
     __syncthreads();
     cur_t = advance(cur_t);
   }
