@@ -54,6 +54,22 @@ __device__ __forceinline__ int wave_sum_i32(int v) {
   return v;
 }
 
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    uint64_t y;
+    if (o >= 16) {
+      const uint32_t lo = o == 32 ? lane_xor32((uint32_t)v) : lane_xor16((uint32_t)v);
+      const uint32_t hi = o == 32 ? lane_xor32((uint32_t)(v >> 32)) : lane_xor16((uint32_t)(v >> 32));
+      y = ((uint64_t)hi << 32) | lo;
+    } else {
+      y = (uint64_t)__shfl_xor((long long)v, o);
+    }
+    v = y < v ? y : v;
+  }
+  return v;
+}
+
 struct SelShared {
   uint32_t sel[kMaxSurvivors + 1];  // candidate positions of the survivors (+ band)
   uint32_t srow[kMaxSurvivors];     // their source rows
@@ -1021,15 +1037,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint64_t y = (uint64_t)__shfl_xor((long long)v, o);
-    v = y < v ? y : v;
-  }
-  return v;
 }
 
 // Sorts sort_hi / sort_lo[0, cnt) (cnt <= 64, distinct pairs) by rank: lane t
