@@ -887,6 +887,40 @@ def test_band_in_chunks(torch_cuda, precision):
     assert info["chunked_bands"] > 0 and info["band_rows"] > 1024
 
 
+def test_statistics_follow_the_last_batch(torch_cuda):
+    # the fine select writes one statistics record per frame and the info
+    # call sums those of the last batch: after a large batch with chunked
+    # bands, a small batch reports exactly what it reports on a fresh
+    # database, and the counts are consistent with each other
+    rng = np.random.default_rng(25)
+    n, d = 6000, 64
+    base = rng.standard_normal(d)
+    feats = (base + 0.02 * rng.standard_normal((n, d))).astype(np.float32)
+    region_of = (np.arange(n) // 1500).astype(np.int32)
+    xy = rng.uniform(0, 40, size=(n, 2))
+    big = (base + 0.02 * rng.standard_normal((40, d))).astype(np.float32)
+    small = feats[[17, 2222, 4100]] + 1e-3 * rng.standard_normal((3, d)).astype(np.float32)
+    keys = ("fine_fallbacks", "max_blocks", "chunked_bands", "band_rows", "rerank_rows",
+            "candidates")
+    fresh = make_db(feats, xy, region_of, 4, mirrors=hloc.MIRROR_FP8)
+    run_device(torch_cuda, fresh, small, 16, 2, precision="fp8")
+    want = fresh.info()
+    fresh.close()
+    db = make_db(feats, xy, region_of, 4, mirrors=hloc.MIRROR_FP8)
+    run_device(torch_cuda, db, big, 16, 2, precision="fp8")
+    first = db.info()
+    run_device(torch_cuda, db, small, 16, 2, precision="fp8")
+    got = db.info()
+    say(f"[ok] large batch {first}; small batch {got}")
+    assert first["chunked_bands"] > 0
+    for info, nq in ((first, len(big)), (got, len(small))):
+        assert info["chunked_bands"] <= info["fine_fallbacks"] <= nq
+        assert info["band_rows"] <= info["rerank_rows"]
+        assert 0 < info["max_blocks"]
+    assert {k: got[k] for k in keys} == {k: want[k] for k in keys}
+    db.close()
+
+
 # ------------------------------------------------------------- tiles and the tuner
 def test_tiles_do_not_change_results(torch_cuda, tmp_path):
     # the fine-screen tiles change the work items, never the results
