@@ -58,7 +58,7 @@ typedef enum {
  * database built with HLOC_MIRROR_FP8; padded length a multiple of 64).
  * Whatever the screen, the returned top-k is decided by an FP64 rerank of the
  * survivors (k + 16 of them behind fp32, 3k behind bf16 and fp8) and the
- * regions by an FP64 re-score of the best n_regions + 8, each with a
+ * regions by an FP64 re-score of the best n_regions + 4, each with a
  * certificate: candidates the screen's error bound cannot exclude are
  * re-scored too, so the result is the same for every precision (a looser
  * bound only costs more re-scoring). */

@@ -46,7 +46,7 @@ struct WsBuf {
   size_t cap = 0;
 };
 
-constexpr int kRegionMargin = 8;    // extra regions re-scored in FP64 by the coarse stage
+constexpr int kRegionMargin = 4;    // extra regions re-scored in FP64 by the coarse stage
 constexpr int kOversample = 16;     // extra rows re-scored in FP64 by the fine stage
 constexpr int kRowsCoarse = 64;     // rows (representatives) per coarse work item
 constexpr int kRowsFine = 64;       // rows per fine work item

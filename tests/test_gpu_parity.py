@@ -483,7 +483,7 @@ def test_duplicate_rows_break_ties_by_index_and_fall_back(torch_cuda):
 
 def test_identical_representatives_fall_back(torch_cuda):
     # sixteen regions holding the same rows have identical means, more than
-    # the coarse shortlist (n_regions + 8) can hold: the coarse certificate
+    # the coarse shortlist (n_regions + 4) can hold: the coarse certificate
     # fails and the exact pass keeps the lowest region ids
     rng = np.random.default_rng(7)
     base = rng.standard_normal((50, 16)).astype(np.float32)
