@@ -468,7 +468,6 @@ __global__ __launch_bounds__(256) void k_screen_wide_lp(ScreenArgs a) {
 // XCDs round-robin): the chunks of one region, which stage the same frames,
 // run on one XCD and find them in its L2.
 constexpr int kRsAhead = 4;  // frame pieces in flight ahead of the multiplies
-constexpr int kRsDynItems = 4;  // items per block from which blocks take items from counters
 
 template <int FMT, int NS>
 __global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
@@ -502,9 +501,7 @@ __global__ __launch_bounds__(256) void k_screen_wide_rs(ScreenArgs a) {
   // the item's first barrier (two slots by item parity: the slot thread 0
   // writes was last read before the previous item's set-up barrier). Without
   // them block jb of XCD x takes items it0 + jb, + nb, ...
-  // (counters only for launches of many items per block: with few, most
-  // blocks would only add to every counter and leave)
-  const bool dyn = a.item_ctr != nullptr && hi - lo >= kRsDynItems * (int)gridDim.x;
+  const bool dyn = a.item_ctr != nullptr;
   __shared__ int s_nx[2];
   int xs = 0;  // spans thread 0 has emptied
   auto grab = [&]() -> int {
