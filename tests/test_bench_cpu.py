@@ -160,3 +160,20 @@ def test_committed_fft_record_matches_the_kernel_source():
     if traffic is None:
         pytest.skip(f"no current counter record: {src}")
     assert abs(traffic / (200_000 * 4 * (512 + 256)) - 1.0) < 0.01
+
+
+def test_committed_screen_records_cover_the_tuner_tiles():
+    """The committed fine-screen counters of the benchmark's default workload
+    hold a record for every rows-per-item tile the tuner may choose, each
+    between the algorithmic bytes of the batch (2.09 GB: every kept row's
+    bf16 copy and norm, the frames, the block words) and twice that. After a
+    change to the screen sources the benchmark reports no traffic until they
+    are taken again."""
+    import pytest
+    algorithmic = 2.0896e9
+    for rows in (32, 64, 96, 128):
+        traffic, src = bench.load_traffic("fp8-2m-d512-8frame", "bf16", rows)
+        if traffic is None and "changed" in src:
+            pytest.skip(f"no current counter record: {src}")
+        assert traffic is not None, (rows, src)
+        assert algorithmic <= traffic <= 2.0 * algorithmic, (rows, traffic)
